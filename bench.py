@@ -1,0 +1,190 @@
+"""Benchmark of the Klinkenberg lattice Boltzmann hot path on one MI355X.
+
+One "step" is one fused D2Q9 stream + Klinkenberg + velocity + BGK/Guo
+collide sweep over the whole lattice (one kernel launch).  The workload is
+the two-component heterogeneous medium of Sec. IV.B scaled up: 4096 x 4096
+nodes, 64 seeded overlapping discs (radius 40-200 nodes, eps 0.2,
+k 1e-4) in a matrix (eps 0.5, k 1e-2), local Kn with base 0.05 in the
+matrix, pressure-driven along x (rho_in/rho_out = 1.01), periodic in y.
+Inputs are generated and uploaded before the timed region; the timed region
+is K sweeps on the lattice's stream, bracketed by HIP events.
+
+Prints ONE JSON line.  Headline value: FP32-storage MLUPS.  Also reported:
+FP16- and BF16-storage MLUPS on the same workload, the HBM roofline of the
+sweep kernel, and the FP64 CPU oracle timed on a bounded sample on the
+host (``cpu_baseline``).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS + HBM GB/s (% of peak), FP32 vs FP16-storage; adjoint-grad time/forward"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per node and step (populations read once and written
+# once, three FP32 medium fields read): FP32 9*4*2 + 12 = 84, FP16/BF16
+# 9*2*2 + 12 = 48.  The density plane of the storage layout (FP32 read +
+# write, 8 B) is overhead on top of these and is not counted.
+ALG_BYTES = {"f32": 84, "f16": 48, "bf16": 48}
+LAYOUT_BYTES = {"f32": 92, "f16": 56, "bf16": 56}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def time_storage(case, storage, steps, warmup, device):
+    import torch
+    from paper_1411_7051_amd.lattice import Lattice
+
+    lat = Lattice(case.eps, case.k, case.kn0, device=device, storage=storage,
+                  **case.params)
+    lat.step(warmup)
+    torch.cuda.synchronize(device)
+    stream = lat.stream
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    lat.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize(device)
+    ms = t0.elapsed_time(t1)
+    kapp = lat.apparent_permeability()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    nodes = case.nodes
+    mlups = nodes * steps / (ms * 1e-3) / 1e6
+    ms_step = ms / steps
+    return {
+        "storage": storage,
+        "mlups": mlups,
+        "ms_per_step": ms_step,
+        "alg_GBps": mlups * ALG_BYTES[storage] / 1e3,
+        "layout_GBps": mlups * LAYOUT_BYTES[storage] / 1e3,
+        "k_app_after": kapp,
+    }
+
+
+def cpu_baseline(case, target_s=15.0):
+    """The FP64 oracle, single-threaded, on a 384 x 384 window of the same
+    medium (same fields and boundary conditions), as many steps as fit in
+    about ``target_s`` seconds."""
+    import numpy as np
+
+    import oracle
+    from paper_1411_7051_amd import inputs
+
+    oracle.build(force=False)
+    n = 384
+    sub = inputs.Case(np.ascontiguousarray(case.eps[:n, :n]),
+                      np.ascontiguousarray(case.k[:n, :n]),
+                      np.ascontiguousarray(case.kn0[:n, :n]), case.params)
+    lat = oracle.Lattice(sub.eps, sub.k, sub.kn0, **sub.params)
+    t = time.perf_counter()
+    lat.step(2)
+    probe = time.perf_counter() - t
+    steps = max(2, int(target_s / max(probe / 2, 1e-6)))
+    t = time.perf_counter()
+    lat.step(steps)
+    dt = time.perf_counter() - t
+    return {
+        "value": n * n * steps / dt / 1e6,
+        "unit": "MLUPS",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{n}x{n} window of the same medium, {steps} FP64 steps in {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--n", type=int, default=4096, help="lattice side")
+    ap.add_argument("--storages", default="f32,f16,bf16")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sweep would shard as x-slabs with halo exchange; not built).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1411_7051_amd import inputs
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    t = time.perf_counter()
+    case = inputs.discs(n=args.n, seed=2)
+    log(f"inputs: {case.nodes} nodes in {time.perf_counter() - t:.1f} s")
+
+    runs = {}
+    for st in args.storages.split(","):
+        r = time_storage(case, st, args.steps, args.warmup, dev)
+        log(f"{st}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.4f} ms/step, "
+            f"{r['alg_GBps']:.0f} GB/s algorithmic")
+        runs[st] = r
+    head = runs.get("f32") or next(iter(runs.values()))
+    st = head["storage"]
+    achieved = head["alg_GBps"]
+    roof = {
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": None,
+        "kernel": f"sweep_kernel<{st}> (pressure x, periodic y)",
+        "bytes_per_node": ALG_BYTES[st],
+        "layout_bytes_per_node": LAYOUT_BYTES[st],
+    }
+    cpu = None if args.no_cpu else cpu_baseline(case)
+    if cpu:
+        log(f"cpu oracle: {cpu['value']:.2f} MLUPS ({cpu['sample']})")
+    out = {
+        "metric": METRIC,
+        "value": head["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f32": "f32", "f16": "f16-storage/f32-math",
+                  "bf16": "bf16-storage/f32-math"}[st],
+        "data": "synthetic",
+        "config": {
+            "workload": f"discs{args.n}: {args.n}x{args.n} two-component medium, 64 seeded "
+                        "discs (r 40-200, eps 0.2, k 1e-4) in a matrix (eps 0.5, k 1e-2), "
+                        "local Kn base 0.05, pressure-driven x (1.01/1.0), periodic y, tau 0.8",
+            "nodes": case.nodes,
+            "storage": st,
+            "parallelism": "single GPU",
+        },
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "storage_runs": runs,
+        "adjoint": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

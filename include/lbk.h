@@ -1,0 +1,145 @@
+/*
+ * lbk.h -- C ABI of the MI355X (gfx950) Klinkenberg lattice Boltzmann library.
+ *
+ * The library advances the generalized lattice Boltzmann model of Chen et
+ * al. (arXiv:1411.7051) for gas flow in tight porous media: a D2Q9 BGK
+ * stream-and-collide sweep per time step (Eq. 12) with Guo's porous
+ * equilibrium and forcing (Eqs. 14-15), moments and explicit velocity
+ * (Eqs. 16-17), and the apparent permeability k_a = k f_c(Kn) of Eq. 3 with
+ * the second-order Beskok-Karniadakis/Civan factor (Eqs. 6-7) evaluated at
+ * a local Knudsen number Kn = kn0 * rho_ref / rho (Eq. 5 with Eq. 10:
+ * the mean free path scales as 1/p).  The force is Eq. 8, or Eq. 2 when the
+ * Forchheimer function f_eps is non-zero.
+ *
+ * Conventions
+ *  - Lattice units: dx = dt = 1, c = 1, cs^2 = 1/3, nu = (tau - 1/2)/3.
+ *  - Field arrays are row-major [ny][nx], x fastest, float32, unpadded.
+ *  - k = +inf marks a node with no Darcy drag (free fluid, Sec. III);
+ *    eps = 0 marks an impermeable node (infinite drag, zero velocity).
+ *  - Walls are half-way bounce-back; a pressure boundary imposes rho_in on
+ *    column 0 and rho_out on column nx-1 by non-equilibrium extrapolation
+ *    from the neighbouring column (Sec. IV.A: pressure-driven plates).
+ *  - Every call is asynchronous on the HIP stream given at create, except
+ *    those that return host scalars, which synchronize that stream.
+ *  - Every function returns an lbk_status; on error lbk_last_error() holds a
+ *    message for the calling thread.  No exception crosses the ABI.
+ *  - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef LBK_H
+#define LBK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lbk_status {
+    LBK_OK = 0,
+    LBK_ERR_INVALID_ARG = -1, /* bad description, field value or pointer */
+    LBK_ERR_DEVICE = -2,      /* HIP runtime error or no gfx950 device */
+    LBK_ERR_OOM = -3,         /* workspace too small */
+    LBK_ERR_NONFINITE = -4,   /* a NaN or Inf appeared in the state */
+    LBK_ERR_UNSUPPORTED = -5  /* combination not implemented */
+} lbk_status;
+
+typedef enum lbk_bc {
+    LBK_BC_PERIODIC = 0,
+    LBK_BC_WALL = 1,    /* half-way bounce-back (no-slip plates, Sec. IV.A) */
+    LBK_BC_PRESSURE = 2 /* x only: rho_in at x = 0, rho_out at x = nx-1 */
+} lbk_bc;
+
+/* Element type of the nine stored population planes.  The collide
+ * arithmetic is FP32 for every storage type. */
+typedef enum lbk_storage {
+    LBK_F32 = 0,
+    LBK_F16 = 1, /* with a power-of-two scale managed by the library */
+    LBK_BF16 = 2
+} lbk_storage;
+
+/* Run description (Sec. IV: plates, heterogeneous media, fractured shale). */
+typedef struct lbk_desc {
+    int32_t nx, ny;      /* lattice size; nx >= 3 with pressure boundaries */
+    int32_t bc_x, bc_y;  /* lbk_bc; bc_y may not be LBK_BC_PRESSURE */
+    int32_t storage;     /* lbk_storage */
+    int32_t kn_local;    /* 1: Kn = kn0 * rho_ref / rho; 0: Kn = kn0 */
+    int32_t init;        /* 0: rest at rho0; 1: rest on the linear density
+                            ramp rho_in -> rho_out along x */
+    int32_t check_every; /* lbk_step checks the state for NaN/Inf (and, for
+                            FP16, re-centres the scale) every this many
+                            steps; 0 = never */
+    double tau;          /* BGK relaxation time (Eq. 12), > 1/2 */
+    double gx, gy;       /* external acceleration G (Eqs. 2, 8) */
+    double f_eps;        /* Forchheimer geometric function (Eq. 2); 0 = Eq. 8 */
+    double rho_in, rho_out; /* pressure-boundary densities */
+    double rho0;         /* initial density for a start at rest */
+    double rho_ref;      /* density at which kn0 is quoted */
+} lbk_desc;
+
+typedef struct lbk_lattice lbk_lattice;
+
+/* Fill *d with defaults: periodic, FP32, tau 0.8, rho 1, no force. */
+lbk_status lbk_desc_default(lbk_desc *d);
+
+/* Bytes of device workspace lbk_create needs for this description. */
+lbk_status lbk_workspace_size(const lbk_desc *d, size_t *bytes);
+
+/* Create a lattice.  eps, k, kn0: [ny][nx] float32 arrays in host or device
+ * memory (kn0 may be NULL, meaning 0); they are copied and validated
+ * (0 <= eps <= 1, k > 0 or +inf, kn0 >= 0 and finite) before the call
+ * returns.  workspace: caller-owned device memory of ws_bytes >=
+ * lbk_workspace_size(), 256-byte aligned, which must outlive the handle.
+ * stream: a hipStream_t (NULL = the null stream).  On failure *out is NULL
+ * and nothing is left allocated.  The state starts at rest (init). */
+lbk_status lbk_create(const lbk_desc *d, const float *eps, const float *k,
+                      const float *kn0, void *workspace, size_t ws_bytes,
+                      void *stream, lbk_lattice **out);
+
+/* Release the handle (not the workspace).  NULL is accepted. */
+lbk_status lbk_destroy(lbk_lattice *lat);
+
+/* Advance n >= 0 time steps of Eq. 12 (one fused sweep launch per step). */
+lbk_status lbk_step(lbk_lattice *lat, int64_t n);
+
+/* Number of steps taken since create (or since the loaded state). */
+lbk_status lbk_time(const lbk_lattice *lat, int64_t *t);
+
+/* Macroscopic read-out at the current time (Eqs. 16-17 on the post-stream
+ * populations, after the boundary override): density and velocity as
+ * [ny][nx] float32 into device buffers; any pointer may be NULL. */
+lbk_status lbk_read_macroscopic(lbk_lattice *lat, float *rho, float *ux,
+                                float *uy);
+
+/* The current post-collision populations f*_i, reconstructed in FP64 as
+ * [9][ny][nx] into a device buffer (direction order of Eq. 13). */
+lbk_status lbk_read_populations(lbk_lattice *lat, double *f);
+
+/* Global (apparent) permeability of the whole domain by Darcy's law
+ * (Sec. IV.A): nu <u_x> / G_x for a body-force drive;
+ * eps_b nu (nx-1) <rho u_x> / (cs^2 (rho_in - rho_out)) for a pressure
+ * drive, eps_b being the mean porosity of the two pressure columns.
+ * Means over every node, accumulated in FP64.  Synchronizes the stream. */
+lbk_status lbk_apparent_permeability(lbk_lattice *lat, double *k_app);
+
+/* FP64 diagnostics: total mass sum f*, x mass flux sum rho u_x, and the
+ * residual ||u - u_prev|| / ||u|| against the velocity of the previous
+ * lbk_diagnostics call on this handle (+inf on the first call).  Any
+ * pointer may be NULL.  Synchronizes the stream. */
+lbk_status lbk_diagnostics(lbk_lattice *lat, double *mass, double *flux_x,
+                           double *residual);
+
+/* Size of a saved state; save copies the state (and the step count) to
+ * host or device memory, load restores it into a handle created with the
+ * same description.  Both are asynchronous on the stream. */
+lbk_status lbk_state_size(const lbk_lattice *lat, size_t *bytes);
+lbk_status lbk_save_state(lbk_lattice *lat, void *dst);
+lbk_status lbk_load_state(lbk_lattice *lat, const void *src);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *lbk_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBK_H */

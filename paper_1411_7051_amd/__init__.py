@@ -1,1 +1,19 @@
-"""MI355X-native Klinkenberg lattice Boltzmann hot path (arXiv:1411.7051)."""
+"""MI355X-native hot path of the generalized lattice Boltzmann model for gas
+flow through tight porous media with Klinkenberg's effect (Chen et al.,
+arXiv:1411.7051).
+
+The fused D2Q9 sweep and its read-outs are HIP kernels for gfx950 behind the
+C ABI of ``include/lbk.h`` (``liblbk.so``, built by ``build.py``);
+``Lattice`` is a thin ctypes binding over it.  ``inputs`` draws the seeded
+synthetic media.
+"""
+from . import inputs  # noqa: F401
+
+__all__ = ["Lattice", "inputs", "make_desc", "workspace_bytes"]
+
+
+def __getattr__(name):
+    if name in ("Lattice", "make_desc", "workspace_bytes"):
+        from . import lattice
+        return getattr(lattice, name)
+    raise AttributeError(name)

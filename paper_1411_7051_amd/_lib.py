@@ -1,0 +1,97 @@
+"""ctypes declarations of the C ABI in ``include/lbk.h``.
+
+Argument marshalling only: every step of the method runs in the HIP
+library.  Loading fails loudly when ``liblbk.so`` has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbk.so")
+
+LBK_OK = 0
+STATUS = {
+    0: "LBK_OK",
+    -1: "LBK_ERR_INVALID_ARG",
+    -2: "LBK_ERR_DEVICE",
+    -3: "LBK_ERR_OOM",
+    -4: "LBK_ERR_NONFINITE",
+    -5: "LBK_ERR_UNSUPPORTED",
+}
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+
+
+class LbkError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Desc(ctypes.Structure):
+    """``lbk_desc``."""
+
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+        ("storage", ctypes.c_int32), ("kn_local", ctypes.c_int32),
+        ("init", ctypes.c_int32), ("check_every", ctypes.c_int32),
+        ("tau", ctypes.c_double),
+        ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+        ("f_eps", ctypes.c_double),
+        ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
+        ("rho0", ctypes.c_double), ("rho_ref", ctypes.c_double),
+    ]
+
+
+# Every symbol include/lbk.h declares, with (restype, argtypes).
+_P = ctypes.c_void_p
+_SIG = {
+    "lbk_desc_default": (ctypes.c_int, [ctypes.POINTER(Desc)]),
+    "lbk_workspace_size": (ctypes.c_int, [ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_size_t)]),
+    "lbk_create": (ctypes.c_int, [ctypes.POINTER(Desc), _P, _P, _P, _P, ctypes.c_size_t, _P,
+                                  ctypes.POINTER(_P)]),
+    "lbk_destroy": (ctypes.c_int, [_P]),
+    "lbk_step": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "lbk_time": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "lbk_read_macroscopic": (ctypes.c_int, [_P, _P, _P, _P]),
+    "lbk_read_populations": (ctypes.c_int, [_P, _P]),
+    "lbk_apparent_permeability": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "lbk_diagnostics": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]),
+    "lbk_state_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "lbk_save_state": (ctypes.c_int, [_P, _P]),
+    "lbk_load_state": (ctypes.c_int, [_P, _P]),
+    "lbk_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load ``liblbk.so`` (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"HIP library {LIB_PATH} is not built; run __graft_entry__.build() "
+                "(hipcc --offload-arch=gfx950)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIG.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def symbols():
+    return list(_SIG)
+
+
+def check(status: int) -> None:
+    if status != LBK_OK:
+        msg = load().lbk_last_error()
+        raise LbkError(status, msg.decode() if msg else "")

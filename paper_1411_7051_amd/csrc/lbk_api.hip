@@ -1,0 +1,509 @@
+// lbk_api.hip -- host side of the C ABI declared in include/lbk.h: argument
+// validation, workspace carve-up, launch sequencing on the caller's stream,
+// FP64 diagnostics and state save/load.  No kernels live here.
+#include "../../include/lbk.h"
+#include "lbk_kernels.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+using namespace lbk;
+
+namespace {
+
+thread_local std::string g_err;
+
+lbk_status fail(lbk_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+lbk_status fail(lbk_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(LBK_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));             \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t elem_size(int storage) { return storage == LBK_F32 ? 4 : 2; }
+
+// Byte offsets of every region in the workspace.
+struct Layout {
+    int pitch;
+    int64_t plane;       // elements per plane
+    size_t rho[2], h[2]; // two time levels
+    size_t eps, drag, kn0, uxp, uyp;
+    size_t partials, results;
+    size_t total;
+    int blocks;
+};
+
+Layout layout_of(const lbk_desc &d)
+{
+    Layout L{};
+    L.pitch = (int)align_up((size_t)d.nx, 64);
+    L.plane = (int64_t)L.pitch * d.ny;
+    const size_t f32 = (size_t)L.plane * 4, hT = (size_t)L.plane * elem_size(d.storage);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes, 256);
+        return at;
+    };
+    for (int l = 0; l < 2; ++l) {
+        L.rho[l] = take(f32);
+        L.h[l] = take(9 * hT);
+    }
+    L.eps = take(f32);
+    L.drag = take(f32);
+    L.kn0 = take(f32);
+    L.uxp = take(f32);
+    L.uyp = take(f32);
+    Geom g{d.nx, d.ny, L.pitch, L.plane};
+    L.blocks = launch_of(g).blocks;
+    L.partials = take((size_t)8 * L.blocks * sizeof(double));
+    L.results = take(8 * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+lbk_status check_desc(const lbk_desc *d)
+{
+    if (!d)
+        return fail(LBK_ERR_INVALID_ARG, "desc is NULL");
+    if (d->nx < 1 || d->ny < 1)
+        return fail(LBK_ERR_INVALID_ARG, "nx, ny must be >= 1 (got %d, %d)", d->nx, d->ny);
+    if ((int64_t)align_up((size_t)d->nx, 64) * d->ny > (int64_t)1 << 30)
+        return fail(LBK_ERR_UNSUPPORTED, "lattice of %d x %d exceeds 2^30 nodes", d->nx, d->ny);
+    if (d->bc_x < 0 || d->bc_x > 2 || d->bc_y < 0 || d->bc_y > 1)
+        return fail(LBK_ERR_INVALID_ARG, "bc_x must be 0..2 and bc_y 0..1 (got %d, %d)",
+                    d->bc_x, d->bc_y);
+    if (d->storage < 0 || d->storage > 2)
+        return fail(LBK_ERR_INVALID_ARG, "storage must be 0..2 (got %d)", d->storage);
+    if (!(d->tau > 0.5) || !isfinite(d->tau))
+        return fail(LBK_ERR_INVALID_ARG, "tau must be > 1/2 (got %g)", d->tau);
+    if (!isfinite(d->gx) || !isfinite(d->gy) || !isfinite(d->f_eps) || d->f_eps < 0)
+        return fail(LBK_ERR_INVALID_ARG, "gx, gy, f_eps must be finite, f_eps >= 0");
+    if (d->bc_x == LBK_BC_PRESSURE) {
+        if (d->nx < 3)
+            return fail(LBK_ERR_INVALID_ARG, "pressure boundaries need nx >= 3");
+    }
+    if ((d->bc_x == LBK_BC_PRESSURE || d->init == 1) &&
+        (!(d->rho_in > 0) || !(d->rho_out > 0) || !isfinite(d->rho_in) || !isfinite(d->rho_out)))
+        return fail(LBK_ERR_INVALID_ARG, "rho_in, rho_out must be positive and finite");
+    if (d->init != 0 && d->init != 1)
+        return fail(LBK_ERR_INVALID_ARG, "init must be 0 or 1");
+    if (d->init == 0 && (!(d->rho0 > 0) || !isfinite(d->rho0)))
+        return fail(LBK_ERR_INVALID_ARG, "rho0 must be positive and finite");
+    if (!(d->rho_ref > 0) || !isfinite(d->rho_ref))
+        return fail(LBK_ERR_INVALID_ARG, "rho_ref must be positive and finite");
+    if (d->check_every < 0)
+        return fail(LBK_ERR_INVALID_ARG, "check_every must be >= 0");
+    return LBK_OK;
+}
+
+// Split a double into hi + lo floats with hi + lo == v to ~2^-48 relative.
+void split(double v, float &hi, float &lo)
+{
+    hi = (float)v;
+    lo = (float)(v - (double)hi);
+}
+
+} // namespace
+
+struct lbk_lattice {
+    lbk_desc d;
+    Layout L;
+    Geom g;
+    Physics ph;
+    Medium m;
+    hipStream_t stream;
+    char *ws;
+    int cur;       // time level holding the current state
+    int64_t t;     // steps taken
+    int scale_exp; // FP16: stored = h * 2^scale_exp
+    bool have_prev;
+    double eps_b;  // mean porosity of the two pressure columns
+    double *host;  // pinned scratch for results (8 doubles)
+    int64_t since_check;
+
+    StateV state(int l) const
+    {
+        return StateV{reinterpret_cast<float *>(ws + L.rho[l]),
+                      static_cast<void *>(ws + L.h[l])};
+    }
+    float s() const { return ldexpf(1.0f, scale_exp); }
+    float inv_s() const { return ldexpf(1.0f, -scale_exp); }
+    double *partials() const { return reinterpret_cast<double *>(ws + L.partials); }
+    double *results() const { return reinterpret_cast<double *>(ws + L.results); }
+};
+
+namespace {
+
+// Run a reduction's finish kernel and copy `slots` doubles to lat->host.
+lbk_status fetch(lbk_lattice *lat, int slots, unsigned max_mask)
+{
+    HIP_TRY(launch_finish(lat->partials(), slots, lat->L.blocks, max_mask, lat->results(),
+                          lat->stream));
+    HIP_TRY(hipMemcpyAsync(lat->host, lat->results(), slots * sizeof(double),
+                           hipMemcpyDeviceToHost, lat->stream));
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    return LBK_OK;
+}
+
+// NaN/Inf check of the current state; for FP16 also re-centre the scale so
+// the largest stored magnitude sits near 2^12 (exact power-of-two rescale).
+lbk_status check_state(lbk_lattice *lat)
+{
+    StateV s = lat->state(lat->cur);
+    HIP_TRY(launch_state_sums(lat->d.storage, s, lat->g, lat->inv_s(), lat->partials(),
+                              lat->stream));
+    lbk_status st = fetch(lat, ST_SLOTS, 1u << ST_HMAX);
+    if (st != LBK_OK)
+        return st;
+    if (lat->host[ST_BAD] != 0.0 || !isfinite(lat->host[ST_MASS]))
+        return fail(LBK_ERR_NONFINITE, "non-finite value in the state after %lld steps",
+                    (long long)lat->t);
+    if (lat->d.storage == LBK_F16 && lat->host[ST_HMAX] > 0.0) {
+        int e;
+        frexp(lat->host[ST_HMAX] * ldexp(1.0, lat->scale_exp), &e); // stored max in [2^(e-1), 2^e)
+        const int target = 13;                                       // max in [2^12, 2^13)
+        if (e > 14 || e < 10) {
+            int k = target - e;
+            if (lat->scale_exp + k > 100)
+                k = 100 - lat->scale_exp;
+            if (k != 0) {
+                HIP_TRY(launch_rescale(lat->d.storage, s, lat->g, k, lat->stream));
+                lat->scale_exp += k;
+            }
+        }
+    }
+    return LBK_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+lbk_status lbk_desc_default(lbk_desc *d)
+{
+    if (!d)
+        return fail(LBK_ERR_INVALID_ARG, "desc is NULL");
+    memset(d, 0, sizeof *d);
+    d->nx = d->ny = 1;
+    d->bc_x = d->bc_y = LBK_BC_PERIODIC;
+    d->storage = LBK_F32;
+    d->kn_local = 1;
+    d->init = 0;
+    d->check_every = 0;
+    d->tau = 0.8;
+    d->rho_in = d->rho_out = d->rho0 = d->rho_ref = 1.0;
+    return LBK_OK;
+}
+
+lbk_status lbk_workspace_size(const lbk_desc *d, size_t *bytes)
+{
+    lbk_status s = check_desc(d);
+    if (s != LBK_OK)
+        return s;
+    if (!bytes)
+        return fail(LBK_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = layout_of(*d).total;
+    return LBK_OK;
+}
+
+lbk_status lbk_create(const lbk_desc *d, const float *eps, const float *k, const float *kn0,
+                      void *workspace, size_t ws_bytes, void *stream, lbk_lattice **out)
+{
+    if (!out)
+        return fail(LBK_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    lbk_status s = check_desc(d);
+    if (s != LBK_OK)
+        return s;
+    if (!eps || !k)
+        return fail(LBK_ERR_INVALID_ARG, "eps and k are required");
+    if (!workspace || ((uintptr_t)workspace & 255u))
+        return fail(LBK_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
+    Layout L = layout_of(*d);
+    if (ws_bytes < L.total)
+        return fail(LBK_ERR_OOM, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
+    int dev = -1;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return fail(LBK_ERR_DEVICE, "no HIP device");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(LBK_ERR_DEVICE, "device %s is not gfx950", prop.gcnArchName);
+
+    lbk_lattice *lat = new (std::nothrow) lbk_lattice();
+    if (!lat)
+        return fail(LBK_ERR_OOM, "host allocation failed");
+    lat->d = *d;
+    lat->L = L;
+    lat->g = Geom{d->nx, d->ny, L.pitch, L.plane};
+    lat->stream = static_cast<hipStream_t>(stream);
+    lat->ws = static_cast<char *>(workspace);
+    lat->cur = 0;
+    lat->t = 0;
+    lat->scale_exp = d->storage == LBK_F16 ? 20 : 0;
+    lat->have_prev = false;
+    lat->since_check = 0;
+    if (hipHostMalloc((void **)&lat->host, 8 * sizeof(double), hipHostMallocDefault) !=
+        hipSuccess) {
+        delete lat;
+        return fail(LBK_ERR_DEVICE, "pinned host allocation failed");
+    }
+    auto cleanup = [&](lbk_status st) {
+        (void)hipHostFree(lat->host);
+        delete lat;
+        return st;
+    };
+
+    const double nu = (d->tau - 0.5) / 3.0;
+    Physics &ph = lat->ph;
+    ph.omega = (float)(1.0 / d->tau);
+    ph.guo = (float)(1.0 - 0.5 / d->tau);
+    ph.gx = (float)d->gx;
+    ph.gy = (float)d->gy;
+    ph.feps = (float)d->f_eps;
+    ph.inv_nu = (float)(1.0 / nu);
+    ph.rho_ref = (float)d->rho_ref;
+    split(d->rho_in, ph.rin_hi, ph.rin_lo);
+    split(d->rho_out, ph.rout_hi, ph.rout_lo);
+    ph.kn_local = d->kn_local ? 1 : 0;
+
+    char *ws = lat->ws;
+    float *pe = reinterpret_cast<float *>(ws + L.eps);
+    float *pd = reinterpret_cast<float *>(ws + L.drag);
+    float *pk = reinterpret_cast<float *>(ws + L.kn0);
+    lat->m = Medium{pe, pd, pk};
+    const size_t row = (size_t)d->nx * sizeof(float), prow = (size_t)L.pitch * sizeof(float);
+    hipStream_t st = lat->stream;
+    auto hip_ok = [&](hipError_t e, const char *what) {
+        if (e == hipSuccess)
+            return true;
+        fail(LBK_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+        return false;
+    };
+    if (!hip_ok(hipMemsetAsync(ws, 0, L.total, st), "clear workspace") ||
+        !hip_ok(hipMemcpy2DAsync(pe, prow, eps, row, row, d->ny, hipMemcpyDefault, st), "eps") ||
+        !hip_ok(hipMemcpy2DAsync(pd, prow, k, row, row, d->ny, hipMemcpyDefault, st), "k") ||
+        (kn0 && !hip_ok(hipMemcpy2DAsync(pk, prow, kn0, row, row, d->ny, hipMemcpyDefault, st),
+                        "kn0")) ||
+        !hip_ok(launch_fields(lat->g, pe, pd, pk, nu, lat->partials(), st), "fields kernel"))
+        return cleanup(LBK_ERR_DEVICE);
+    if ((s = fetch(lat, FLD_SLOTS, 0)) != LBK_OK)
+        return cleanup(s);
+    if (lat->host[FLD_BAD] != 0.0)
+        return cleanup(fail(LBK_ERR_INVALID_ARG,
+                            "%.0f field values out of range (need 0<=eps<=1, k>0 or +inf, "
+                            "kn0>=0 finite)",
+                            lat->host[FLD_BAD]));
+    // mean porosity of the pressure columns (for the global permeability)
+    lat->eps_b = 0.0;
+    if (d->bc_x == LBK_BC_PRESSURE) {
+        float *col = nullptr;
+        if (hipHostMalloc((void **)&col, 2 * (size_t)d->ny * sizeof(float),
+                          hipHostMallocDefault) != hipSuccess)
+            return cleanup(fail(LBK_ERR_DEVICE, "pinned host allocation failed"));
+        bool ok =
+            hip_ok(hipMemcpy2DAsync(col, sizeof(float), pe, prow, sizeof(float), d->ny,
+                                    hipMemcpyDeviceToHost, st), "eps column") &&
+            hip_ok(hipMemcpy2DAsync(col + d->ny, sizeof(float), pe + d->nx - 1, prow,
+                                    sizeof(float), d->ny, hipMemcpyDeviceToHost, st),
+                   "eps column") &&
+            hip_ok(hipStreamSynchronize(st), "sync");
+        double sum = 0.0;
+        for (int i = 0; ok && i < 2 * d->ny; ++i)
+            sum += col[i];
+        (void)hipHostFree(col);
+        if (!ok)
+            return cleanup(LBK_ERR_DEVICE);
+        lat->eps_b = sum / (2.0 * d->ny);
+    }
+    if (!hip_ok(launch_init_state(d->storage, lat->state(0), lat->g, d->init, d->rho0,
+                                  d->rho_in, d->rho_out, lat->s(), st), "init kernel") ||
+        !hip_ok(hipStreamSynchronize(st), "sync"))
+        return cleanup(LBK_ERR_DEVICE);
+    *out = lat;
+    return LBK_OK;
+}
+
+lbk_status lbk_destroy(lbk_lattice *lat)
+{
+    if (!lat)
+        return LBK_OK;
+    (void)hipHostFree(lat->host);
+    delete lat;
+    return LBK_OK;
+}
+
+lbk_status lbk_step(lbk_lattice *lat, int64_t n)
+{
+    if (!lat)
+        return fail(LBK_ERR_INVALID_ARG, "lattice is NULL");
+    if (n < 0)
+        return fail(LBK_ERR_INVALID_ARG, "n must be >= 0");
+    const lbk_desc &d = lat->d;
+    for (int64_t i = 0; i < n; ++i) {
+        const int nxt = lat->cur ^ 1;
+        HIP_TRY(launch_sweep(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->state(nxt),
+                             lat->g, lat->m, lat->ph, lat->s(), lat->inv_s(), lat->stream));
+        lat->cur = nxt;
+        ++lat->t;
+        if (d.check_every > 0 && ++lat->since_check >= d.check_every) {
+            lat->since_check = 0;
+            lbk_status s = check_state(lat);
+            if (s != LBK_OK)
+                return s;
+        }
+    }
+    return LBK_OK;
+}
+
+lbk_status lbk_time(const lbk_lattice *lat, int64_t *t)
+{
+    if (!lat || !t)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    *t = lat->t;
+    return LBK_OK;
+}
+
+lbk_status lbk_read_macroscopic(lbk_lattice *lat, float *rho, float *ux, float *uy)
+{
+    if (!lat)
+        return fail(LBK_ERR_INVALID_ARG, "lattice is NULL");
+    const lbk_desc &d = lat->d;
+    HIP_TRY(launch_macro(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->g, lat->m,
+                         lat->ph, lat->inv_s(), rho, ux, uy, nullptr, nullptr, lat->partials(),
+                         lat->stream));
+    return LBK_OK;
+}
+
+lbk_status lbk_read_populations(lbk_lattice *lat, double *f)
+{
+    if (!lat || !f)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    HIP_TRY(launch_populations(lat->d.storage, lat->state(lat->cur), lat->g, lat->inv_s(), f,
+                               lat->stream));
+    return LBK_OK;
+}
+
+static lbk_status macro_sums(lbk_lattice *lat, bool residual)
+{
+    const lbk_desc &d = lat->d;
+    char *ws = lat->ws;
+    float *uxp = residual ? reinterpret_cast<float *>(ws + lat->L.uxp) : nullptr;
+    float *uyp = residual ? reinterpret_cast<float *>(ws + lat->L.uyp) : nullptr;
+    HIP_TRY(launch_macro(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->g, lat->m,
+                         lat->ph, lat->inv_s(), nullptr, nullptr, nullptr, uxp, uyp,
+                         lat->partials(), lat->stream));
+    return fetch(lat, MAC_SLOTS, 0);
+}
+
+lbk_status lbk_apparent_permeability(lbk_lattice *lat, double *k_app)
+{
+    if (!lat || !k_app)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    lbk_status s = macro_sums(lat, false);
+    if (s != LBK_OK)
+        return s;
+    const lbk_desc &d = lat->d;
+    const double n = (double)d.nx * d.ny, nu = (d.tau - 0.5) / 3.0;
+    if (d.bc_x == LBK_BC_PRESSURE)
+        *k_app = lat->eps_b * nu * (d.nx - 1) * (lat->host[MAC_FLUX] / n) /
+                 ((1.0 / 3.0) * (d.rho_in - d.rho_out));
+    else
+        *k_app = nu * (lat->host[MAC_UX] / n) / d.gx;
+    return LBK_OK;
+}
+
+lbk_status lbk_diagnostics(lbk_lattice *lat, double *mass, double *flux_x, double *residual)
+{
+    if (!lat)
+        return fail(LBK_ERR_INVALID_ARG, "lattice is NULL");
+    lbk_status s = macro_sums(lat, true);
+    if (s != LBK_OK)
+        return s;
+    const double flux = lat->host[MAC_FLUX];
+    const double res = lat->have_prev ? sqrt(lat->host[MAC_DU2] / lat->host[MAC_U2]) : INFINITY;
+    lat->have_prev = true;
+    if (flux_x)
+        *flux_x = flux;
+    if (residual)
+        *residual = res;
+    if (mass) {
+        HIP_TRY(launch_state_sums(lat->d.storage, lat->state(lat->cur), lat->g, lat->inv_s(),
+                                  lat->partials(), lat->stream));
+        if ((s = fetch(lat, ST_SLOTS, 1u << ST_HMAX)) != LBK_OK)
+            return s;
+        *mass = lat->host[ST_MASS];
+    }
+    return LBK_OK;
+}
+
+// Saved state: a 64-byte header (magic, step count, FP16 scale exponent,
+// sizes) followed by the density plane and the nine deviation planes.
+static const uint64_t kMagic = 0x6c626b7374617465ull; // "lbkstate"
+
+lbk_status lbk_state_size(const lbk_lattice *lat, size_t *bytes)
+{
+    if (!lat || !bytes)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    *bytes = 64 + (lat->L.h[0] - lat->L.rho[0]) + 9 * (size_t)lat->L.plane *
+                                                     elem_size(lat->d.storage);
+    return LBK_OK;
+}
+
+lbk_status lbk_save_state(lbk_lattice *lat, void *dst)
+{
+    if (!lat || !dst)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    size_t bytes;
+    lbk_state_size(lat, &bytes);
+    int64_t hdr[8] = {(int64_t)kMagic, lat->t, lat->scale_exp, (int64_t)bytes,
+                      lat->d.nx,       lat->d.ny, lat->d.storage, 0};
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    HIP_TRY(hipMemcpy(dst, hdr, sizeof hdr, hipMemcpyDefault));
+    HIP_TRY(hipMemcpyAsync(static_cast<char *>(dst) + 64, lat->ws + lat->L.rho[lat->cur],
+                           bytes - 64, hipMemcpyDefault, lat->stream));
+    return LBK_OK;
+}
+
+lbk_status lbk_load_state(lbk_lattice *lat, const void *src)
+{
+    if (!lat || !src)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    size_t bytes;
+    lbk_state_size(lat, &bytes);
+    int64_t hdr[8];
+    HIP_TRY(hipStreamSynchronize(lat->stream));
+    HIP_TRY(hipMemcpy(hdr, src, sizeof hdr, hipMemcpyDefault));
+    if (hdr[0] != (int64_t)kMagic || hdr[3] != (int64_t)bytes || hdr[4] != lat->d.nx ||
+        hdr[5] != lat->d.ny || hdr[6] != lat->d.storage)
+        return fail(LBK_ERR_INVALID_ARG, "state does not match this lattice");
+    HIP_TRY(hipMemcpyAsync(lat->ws + lat->L.rho[lat->cur], static_cast<const char *>(src) + 64,
+                           bytes - 64, hipMemcpyDefault, lat->stream));
+    lat->t = hdr[1];
+    lat->scale_exp = (int)hdr[2];
+    lat->have_prev = false;
+    return LBK_OK;
+}
+
+const char *lbk_last_error(void) { return g_err.c_str(); }
+
+} // extern "C"

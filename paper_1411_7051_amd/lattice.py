@@ -1,0 +1,178 @@
+"""Python face of the C ABI: ``Lattice`` wraps one ``lbk_lattice`` handle.
+
+PyTorch supplies the device workspace and the stream (torch's current
+stream of the lattice's device); all of the method runs in ``liblbk.so``.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import Desc, check
+
+PERIODIC, WALL, PRESSURE = 0, 1, 2
+
+
+def make_desc(nx, ny, tau=0.8, gx=0.0, gy=0.0, f_eps=0.0, bc_x=PERIODIC,
+              bc_y=PERIODIC, rho_in=1.0, rho_out=1.0, rho0=1.0, rho_ref=1.0,
+              kn_local=1, init=0, storage="f32", check_every=0) -> Desc:
+    lib = _lib.load()
+    d = Desc()
+    check(lib.lbk_desc_default(ctypes.byref(d)))
+    d.nx, d.ny = int(nx), int(ny)
+    d.tau, d.gx, d.gy, d.f_eps = float(tau), float(gx), float(gy), float(f_eps)
+    d.bc_x, d.bc_y = int(bc_x), int(bc_y)
+    d.rho_in, d.rho_out, d.rho0 = float(rho_in), float(rho_out), float(rho0)
+    d.rho_ref, d.kn_local, d.init = float(rho_ref), int(kn_local), int(init)
+    d.storage = _lib.STORAGE[storage] if isinstance(storage, str) else int(storage)
+    d.check_every = int(check_every)
+    return d
+
+
+def workspace_bytes(desc: Desc) -> int:
+    n = ctypes.c_size_t()
+    check(_lib.load().lbk_workspace_size(ctypes.byref(desc), ctypes.byref(n)))
+    return int(n.value)
+
+
+def _field(a, device) -> torch.Tensor:
+    if isinstance(a, torch.Tensor):
+        t = a.detach().to(device=device, dtype=torch.float32)
+    else:
+        t = torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+    return t.contiguous()
+
+
+class Lattice:
+    """A D2Q9 Klinkenberg lattice on one GPU.
+
+    ``eps``, ``k``, ``kn0``: [ny][nx] arrays (numpy or torch); ``k`` may be
+    +inf.  Keyword parameters are those of ``lbk_desc`` (tau, gx, gy, f_eps,
+    bc_x, bc_y, rho_in, rho_out, rho0, rho_ref, kn_local, init, storage,
+    check_every)."""
+
+    def __init__(self, eps, k, kn0=None, device: Optional[torch.device] = None,
+                 **params):
+        if device is None:
+            device = torch.device("cuda", torch.cuda.current_device())
+        self.device = torch.device(device)
+        lib = _lib.load()
+        e = _field(eps, self.device)
+        kk = _field(k, self.device)
+        if e.dim() != 2 or e.shape != kk.shape:
+            raise ValueError("eps and k must be 2-D of one shape")
+        self.ny, self.nx = e.shape
+        kn = None if kn0 is None else _field(kn0, self.device)
+        if kn is not None and kn.shape != e.shape:
+            raise ValueError("kn0 must match eps")
+        self.params = dict(params)
+        self.desc = make_desc(self.nx, self.ny, **params)
+        nbytes = workspace_bytes(self.desc)
+        self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib.lbk_create(ctypes.byref(self.desc), e.data_ptr(), kk.data_ptr(),
+                                 None if kn is None else kn.data_ptr(),
+                                 self._ws.data_ptr(), nbytes, self.stream.cuda_stream,
+                                 ctypes.byref(h)))
+        self._h = h
+
+    # -- lifetime
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.load().lbk_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _handle(self):
+        if self._h is None:
+            raise RuntimeError("lattice is closed")
+        return self._h
+
+    # -- stepping
+    def step(self, n: int = 1) -> "Lattice":
+        check(_lib.load().lbk_step(self._handle(), int(n)))
+        return self
+
+    @property
+    def time(self) -> int:
+        t = ctypes.c_int64()
+        check(_lib.load().lbk_time(self._handle(), ctypes.byref(t)))
+        return int(t.value)
+
+    # -- read-out
+    def macroscopic(self):
+        """(rho, ux, uy) as [ny][nx] float32 device tensors."""
+        out = [torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+               for _ in range(3)]
+        check(_lib.load().lbk_read_macroscopic(self._handle(), *[o.data_ptr() for o in out]))
+        return tuple(out)
+
+    def populations(self) -> torch.Tensor:
+        """Post-collision populations f*_i as a [9][ny][nx] float64 tensor."""
+        f = torch.empty((9, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        check(_lib.load().lbk_read_populations(self._handle(), f.data_ptr()))
+        return f
+
+    def apparent_permeability(self) -> float:
+        v = ctypes.c_double()
+        check(_lib.load().lbk_apparent_permeability(self._handle(), ctypes.byref(v)))
+        return float(v.value)
+
+    def diagnostics(self):
+        """(mass, x mass flux, residual vs the previous call)."""
+        m, q, r = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        check(_lib.load().lbk_diagnostics(self._handle(), ctypes.byref(m), ctypes.byref(q),
+                                          ctypes.byref(r)))
+        return float(m.value), float(q.value), float(r.value)
+
+    # -- checkpoint / resume
+    def state_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        check(_lib.load().lbk_state_size(self._handle(), ctypes.byref(n)))
+        return int(n.value)
+
+    def save_state(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        check(_lib.load().lbk_save_state(self._handle(), out.data_ptr()))
+        return out
+
+    def load_state(self, src: torch.Tensor) -> None:
+        if src.numel() * src.element_size() < self.state_bytes():
+            raise ValueError("state buffer too small")
+        check(_lib.load().lbk_load_state(self._handle(), src.contiguous().data_ptr()))
+
+    def run_to_steady(self, every: int = 100, tol: float = 1e-9, max_steps: int = 10**7,
+                      patience: int = 10):
+        """Step in blocks of ``every`` until the velocity residual
+        ||u - u_prev|| / ||u|| between blocks falls below ``tol``, or stops
+        decreasing for ``patience`` blocks (the FP32 floor).  Returns
+        (steps, residual, reason)."""
+        self.diagnostics()
+        best, stall, steps = math.inf, 0, 0
+        while steps < max_steps:
+            self.step(every)
+            steps += every
+            _, _, r = self.diagnostics()
+            if r < tol:
+                return steps, r, "tol"
+            if r < best:
+                best, stall = r, 0
+            else:
+                stall += 1
+                if stall >= patience:
+                    return steps, r, "plateau"
+        return steps, r, "max_steps"

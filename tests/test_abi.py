@@ -1,0 +1,104 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol
+include/lbk.h declares, and rejects bad descriptions without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1411_7051_amd import _lib
+from paper_1411_7051_amd.lattice import make_desc, workspace_bytes
+
+HEADER = os.path.join(os.path.dirname(__file__), "..", "include", "lbk.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbk_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared() == sorted(_lib.symbols())
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def test_desc_struct_layout():
+    # 8 int32 then 8 doubles: 32 + 64 bytes, no padding
+    assert ctypes.sizeof(_lib.Desc) == 96
+
+
+def test_workspace_size_scales_with_lattice():
+    small = workspace_bytes(make_desc(64, 32))
+    big = workspace_bytes(make_desc(128, 64))
+    assert big > 3 * small
+    f16 = workspace_bytes(make_desc(1024, 512, storage="f16"))
+    f32 = workspace_bytes(make_desc(1024, 512, storage="f32"))
+    assert f16 < f32
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(tau=0.5), "tau"),
+    (dict(tau=float("nan")), "tau"),
+    (dict(bc_x=3), "bc_x"),
+    (dict(bc_y=2), "bc_y"),
+    (dict(storage=7), "storage"),
+    (dict(bc_x=2, rho_in=-1.0), "rho_in"),
+    (dict(init=1, rho_out=0.0), "rho_in"),
+    (dict(init=5), "init"),
+    (dict(rho_ref=0.0), "rho_ref"),
+    (dict(check_every=-1), "check_every"),
+    (dict(f_eps=-1.0), "f_eps"),
+])
+def test_invalid_descriptions_rejected(kw, msg):
+    d = make_desc(16, 8, **kw)
+    with pytest.raises(_lib.LbkError) as e:
+        workspace_bytes(d)
+    assert e.value.status == -1 and msg in str(e.value)
+
+
+def test_pressure_needs_three_columns():
+    with pytest.raises(_lib.LbkError):
+        workspace_bytes(make_desc(2, 8, bc_x=2))
+
+
+def test_too_large_rejected():
+    with pytest.raises(_lib.LbkError) as e:
+        workspace_bytes(make_desc(65536, 65536))
+    assert e.value.status == -5
+
+
+def test_null_arguments_rejected():
+    lib = _lib.load()
+    assert lib.lbk_step(None, 1) == -1
+    assert lib.lbk_destroy(None) == 0
+    out = ctypes.c_void_p()
+    d = make_desc(16, 8)
+    # missing fields are rejected before any device work
+    assert lib.lbk_create(ctypes.byref(d), None, None, None, None, 0, None,
+                          ctypes.byref(out)) == -1
+    assert out.value is None
+    assert b"eps and k" in lib.lbk_last_error()
+
+
+def test_create_without_gpu_reports_device_error():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import numpy as np
+    lib = _lib.load()
+    d = make_desc(16, 8)
+    n = workspace_bytes(d)
+    buf = np.zeros(n + 256, dtype=np.uint8)
+    base = buf.ctypes.data
+    ws = (base + 255) // 256 * 256
+    f = np.ones((8, 16), dtype=np.float32)
+    out = ctypes.c_void_p()
+    st = lib.lbk_create(ctypes.byref(d), f.ctypes.data, f.ctypes.data, None, ws, n, None,
+                        ctypes.byref(out))
+    assert st == -2 and out.value is None

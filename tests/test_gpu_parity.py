@@ -1,0 +1,196 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP32 storage: velocity relative L2 <= 1e-5 against the oracle after the same
+number of steps on the same seeded inputs; populations compared element by
+element.  Sizes span several 256-wide blocks with a ragged tail."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1411_7051_amd import inputs
+from paper_1411_7051_amd.lattice import Lattice
+
+pytestmark = pytest.mark.gpu
+
+VEL_TOL = 1e-5  # relative L2 on velocity, FP32 path vs FP64 oracle
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = torch.device("cuda", 0)
+    torch.cuda.set_device(d)
+    return d
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def gpu_run(dev, case, steps, **extra):
+    lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params, **extra)
+    lat.step(steps)
+    return lat
+
+
+def macro_np(lat):
+    return [t.double().cpu().numpy() for t in lat.macroscopic()]
+
+
+def oracle_run(case, steps):
+    return oracle.Lattice(case.eps, case.k, case.kn0, **case.params).step(steps)
+
+
+def compare(lat, ref, tol=VEL_TOL):
+    rho, ux, uy = macro_np(lat)
+    r_rho, r_ux, r_uy = ref.macro()
+    err = rel_l2(np.stack([ux, uy]), np.stack([r_ux, r_uy]))
+    assert err <= tol, f"velocity rel L2 {err:.3e}"
+    assert np.max(np.abs(rho - r_rho)) < 1e-6
+    f = lat.populations().cpu().numpy()
+    fr = ref.state()
+    # deviations from the local equilibrium scale
+    scale = np.max(np.abs(fr - fr.sum(axis=0, keepdims=True) * W[:, None, None]))
+    assert np.max(np.abs(f - fr)) <= 1e-4 * scale + 1e-12
+    return err
+
+
+W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def test_channel_workload(dev):
+    """Porous-filled plates, 64x32, eps 0.5, Da 1e-3, tau 0.8, body force
+    1e-6, 10,000 steps from rest (Sec. IV.A)."""
+    case = inputs.channel(64, 32, eps=0.5, k=1.024, gx=1e-6)
+    lat = gpu_run(dev, case, 10000)
+    ref = oracle_run(case, 10000)
+    compare(lat, ref)
+    kg, kr = lat.apparent_permeability(), ref.apparent_permeability()
+    assert abs(kg / kr - 1) < 1e-5
+
+
+def test_uniform_recurrence(dev):
+    """Closed form on a uniform periodic medium with Klinkenberg on:
+    u_{n+1} = q u_n + eps G/(1 + A/2) (see the oracle pins)."""
+    eps, k, kn0, tau, G = 0.4, 0.3, 0.5, 0.8, 1e-5
+    case = inputs.Case(*(np.full((5, 70), v, np.float32) for v in (eps, k, kn0)),
+                       inputs.run_params(tau=tau, gx=G))
+    lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+    nu = (tau - 0.5) / 3
+    A = float(np.float32(eps)) * nu / (float(np.float32(k)) * oracle.fc(float(np.float32(kn0))))
+    q, b = (1 - A / 2) / (1 + A / 2), float(np.float32(eps)) * G / (1 + A / 2)
+    u = 0.5 * b
+    for n in range(40):
+        _, ux, uy = macro_np(lat)
+        assert np.allclose(ux, u, rtol=2e-6)
+        assert np.max(np.abs(uy)) < 1e-7 * u
+        lat.step(1)
+        u = q * u + b
+
+
+@pytest.mark.parametrize("bcx,bcy", [(0, 0), (0, 1), (1, 1), (1, 0), (2, 0), (2, 1)])
+def test_random_media(dev, bcx, bcy):
+    """Heterogeneous medium with free-fluid and impermeable nodes, local Kn,
+    every boundary combination; 300x37 (two full blocks and a ragged tail)."""
+    drive = dict(gx=3e-5, gy=-1e-5) if bcx != 2 else dict(rho_in=1.01, rho_out=1.0, init=1)
+    case = inputs.random_medium(300, 37, seed=100 + 3 * bcx + bcy, solid_frac=0.08,
+                                pore_frac=0.08, bc_x=bcx, bc_y=bcy, **drive)
+    lat = gpu_run(dev, case, 300)
+    ref = oracle_run(case, 300)
+    compare(lat, ref)
+
+
+def test_forchheimer(dev):
+    case = inputs.random_medium(130, 20, seed=5, bc_y=1, gx=2e-4, f_eps=0.6)
+    compare(gpu_run(dev, case, 400), oracle_run(case, 400))
+
+
+def test_global_kn(dev):
+    case = inputs.random_medium(70, 30, seed=6, kn_local=0, bc_x=2, rho_in=1.02,
+                                rho_out=1.0, init=1)
+    compare(gpu_run(dev, case, 300), oracle_run(case, 300))
+
+
+@pytest.mark.parametrize("nx,ny,bcx,bcy", [(1, 1, 0, 0), (1, 9, 0, 1), (7, 1, 0, 0),
+                                           (3, 4, 2, 1), (3, 1, 2, 0), (257, 3, 1, 1),
+                                           (64, 64, 0, 0), (513, 5, 2, 0)])
+def test_edge_sizes(dev, nx, ny, bcx, bcy):
+    drive = dict(gx=1e-4, gy=5e-5) if bcx != 2 else dict(rho_in=1.03, rho_out=1.0, init=1)
+    case = inputs.random_medium(nx, ny, seed=nx * 7 + ny, solid_frac=0.1, pore_frac=0.1,
+                                bc_x=bcx, bc_y=bcy, **drive)
+    lat = gpu_run(dev, case, 60)
+    ref = oracle_run(case, 60)
+    rho, ux, uy = macro_np(lat)
+    _, r_ux, r_uy = ref.macro()
+    un = np.linalg.norm(np.stack([r_ux, r_uy]))
+    if un > 0:
+        assert rel_l2(np.stack([ux, uy]), np.stack([r_ux, r_uy])) <= VEL_TOL
+    else:
+        assert np.max(np.abs(ux)) == 0 and np.max(np.abs(uy)) == 0
+
+
+def test_mass_conservation(dev):
+    """Periodic x, walls in y: streaming and collision conserve mass.  The
+    FP32 deviation planes round each stored value, so the FP64 total drifts
+    at the level of FP32 rounding of the deviations (not of the O(1)
+    populations): bounded here at 1e-8 relative over 2000 steps at flow
+    speeds up to ~1e-3."""
+    case = inputs.random_medium(200, 50, seed=8, solid_frac=0.1, pore_frac=0.1, bc_y=1,
+                                gx=1e-4, gy=2e-5)
+    lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+    m0, _, _ = lat.diagnostics()
+    lat.step(2000)
+    m1, _, _ = lat.diagnostics()
+    assert abs(m1 - m0) / m0 < 1e-8
+
+
+def test_apparent_permeability_pressure(dev):
+    case = inputs.channel(48, 12, eps=0.5, k=0.05, kn0=0.4, drive="pressure")
+    lat = gpu_run(dev, case, 3000)
+    ref = oracle_run(case, 3000)
+    assert abs(lat.apparent_permeability() / ref.apparent_permeability() - 1) < 1e-5
+
+
+def test_deterministic_and_resumable(dev):
+    case = inputs.random_medium(300, 40, seed=9, solid_frac=0.05, bc_x=2, rho_in=1.01,
+                                rho_out=1.0, init=1)
+    a = gpu_run(dev, case, 100)
+    b = gpu_run(dev, case, 100)
+    assert torch.equal(a.populations(), b.populations())
+    snap = a.save_state()
+    a.step(100)
+    c = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+    c.load_state(snap)
+    assert c.time == 100
+    c.step(100)
+    assert torch.equal(a.populations(), c.populations())
+    ka, kc = a.apparent_permeability(), c.apparent_permeability()
+    assert ka == kc
+
+
+def test_invalid_fields_rejected(dev):
+    from paper_1411_7051_amd._lib import LbkError
+    eps = np.full((8, 16), 0.5, np.float32)
+    k = np.full((8, 16), 1.0, np.float32)
+    bad = eps.copy()
+    bad[3, 4] = 1.5
+    with pytest.raises(LbkError):
+        Lattice(bad, k, device=dev)
+    badk = k.copy()
+    badk[0, 0] = np.nan
+    with pytest.raises(LbkError):
+        Lattice(eps, badk, device=dev)
+
+
+def test_nonfinite_detected(dev):
+    """A tau close to 1/2 with a strong force blows up; the periodic check
+    reports it instead of running on with NaNs."""
+    from paper_1411_7051_amd._lib import LbkError
+    case = inputs.random_medium(64, 16, seed=12, eps_range=(0.9, 1.0), k_range=(1e3, 1e4),
+                                tau=0.5000001, gx=0.5)
+    lat = Lattice(case.eps, case.k, case.kn0, device=dev, check_every=50, **case.params)
+    with pytest.raises(LbkError) as e:
+        lat.step(5000)
+    assert e.value.status == -4
