@@ -112,6 +112,9 @@ def main():
     ap.add_argument("--n", type=int, default=4096, help="lattice side")
     ap.add_argument("--storages", default="f32,f16,bf16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="only run 10 device-to-device copies of MIB MiB (a plain copy "
+                         "kernel of known traffic, to scale HBM byte counters) and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -128,6 +131,15 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.calib_copy:
+        n = args.calib_copy << 20
+        a = torch.ones(n, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize(dev)
+        print(json.dumps({"calib_copy_bytes": n, "copies": 10}), flush=True)
+        return
 
     t = time.perf_counter()
     case = inputs.discs(n=args.n, seed=2)

@@ -8,6 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbk.so")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 SOURCES = ["lbk_kernels.hip", "lbk_api.hip"]
 HEADERS = ["lbk_device.h", "lbk_kernels.h"]
 
@@ -28,7 +29,7 @@ def build(verbose: bool = False, extra=()) -> str:
     """Compile every source into ``liblbk.so`` (always recompiles)."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *FLAGS, *extra, "-o", tmp, *srcs]
+    cmd = [hipcc(), *FLAGS, "-I", INCLUDE, *extra, "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

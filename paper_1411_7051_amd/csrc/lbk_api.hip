@@ -1,7 +1,7 @@
 // lbk_api.hip -- host side of the C ABI declared in include/lbk.h: argument
 // validation, workspace carve-up, launch sequencing on the caller's stream,
 // FP64 diagnostics and state save/load.  No kernels live here.
-#include "../../include/lbk.h"
+#include "lbk.h"
 #include "lbk_kernels.h"
 
 #include <math.h>

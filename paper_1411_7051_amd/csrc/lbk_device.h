@@ -51,36 +51,43 @@ static_assert(opp_of(1) == 3 && opp_of(2) == 4 && opp_of(5) == 7 && opp_of(6) ==
 
 // Storage element types.  FP16 values are the deviations times a power of
 // two (scale), so that they sit in the normal FP16 range; BF16 and FP32
-// need no scale.
+// need no scale.  Every stored population is read once and written once per
+// step, so loads and stores are nontemporal: they bypass the caches' reuse
+// policy and leave L2 to the density plane, whose neighbour reads do reuse.
 template <typename T> struct Elem;
 template <> struct Elem<float> {
     static __device__ __forceinline__ float ld(const float *p, int64_t i, float)
     {
-        return p[i];
+        return __builtin_nontemporal_load(p + i);
     }
     static __device__ __forceinline__ void st(float *p, int64_t i, float v, float)
     {
-        p[i] = v;
+        __builtin_nontemporal_store(v, p + i);
     }
 };
 template <> struct Elem<__half> {
     static __device__ __forceinline__ float ld(const __half *p, int64_t i, float inv_s)
     {
-        return __half2float(p[i]) * inv_s;
+        const uint16_t u = __builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(p) + i);
+        return __half2float(__ushort_as_half(u)) * inv_s;
     }
     static __device__ __forceinline__ void st(__half *p, int64_t i, float v, float s)
     {
-        p[i] = __float2half_rn(v * s);
+        __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v * s)),
+                                    reinterpret_cast<uint16_t *>(p) + i);
     }
 };
 template <> struct Elem<__hip_bfloat16> {
     static __device__ __forceinline__ float ld(const __hip_bfloat16 *p, int64_t i, float)
     {
-        return __bfloat162float(p[i]);
+        const uint16_t u = __builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(p) + i);
+        return __uint_as_float((uint32_t)u << 16);
     }
     static __device__ __forceinline__ void st(__hip_bfloat16 *p, int64_t i, float v, float)
     {
-        p[i] = __float2bfloat16(v);
+        const __hip_bfloat16 b = __float2bfloat16(v); // round to nearest even
+        __builtin_nontemporal_store(*reinterpret_cast<const uint16_t *>(&b),
+                                    reinterpret_cast<uint16_t *>(p) + i);
     }
 };
 

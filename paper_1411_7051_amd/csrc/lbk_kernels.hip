@@ -93,7 +93,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(State<T> src, State<T> ds
     velocity(ph, rho, jx, jy, eps, m.drag[c], m.kn0[c], ux, uy, Fx, Fy);
     float hs[9];
     collide(ph, rho, dl, ux, uy, Fx, Fy, eps, hs);
-    dst.rho[c] = rho;
+    __builtin_nontemporal_store(rho, dst.rho + c);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         Elem<T>::st(dst.h + i * g.plane, c, hs[i], s);
