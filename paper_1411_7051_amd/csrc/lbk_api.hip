@@ -41,39 +41,46 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 size_t elem_size(int storage) { return storage == LBK_F32 ? 4 : 2; }
 
-// Byte offsets of every region in the workspace.
-struct Layout {
+// Byte offsets of every region in the workspace, and the strided layouts
+// the kernels use.  Each time level of the state is ny row blocks of
+// [rho FP32 | h_0 .. h_8 T], each slot `pitch` elements; the medium is ny
+// row blocks of [eps | drag | kn0] FP32.
+struct WsLayout {
     int pitch;
-    int64_t plane;       // elements per plane
-    size_t rho[2], h[2]; // two time levels
-    size_t eps, drag, kn0, uxp, uyp;
+    Layout lay;           // state row layout
+    MLayout mlay;         // medium row layout
+    size_t level_bytes;   // bytes of one time level
+    size_t level[2];      // two time levels
+    size_t med, uxp, uyp; // medium; previous velocity for the residual
     size_t partials, results;
     size_t total;
     int blocks;
 };
 
-Layout layout_of(const lbk_desc &d)
+WsLayout layout_of(const lbk_desc &d)
 {
-    Layout L{};
+    WsLayout L{};
     L.pitch = (int)align_up((size_t)d.nx, 64);
-    L.plane = (int64_t)L.pitch * d.ny;
-    const size_t f32 = (size_t)L.plane * 4, hT = (size_t)L.plane * elem_size(d.storage);
+    const size_t es = elem_size(d.storage), p = (size_t)L.pitch;
+    L.lay.row = p * (4 + 9 * es);
+    L.lay.h_off = (uint32_t)(p * 4);
+    L.lay.h_slot = (uint32_t)(p * es);
+    L.mlay.row = 3 * p * 4;
+    L.mlay.slot = (uint32_t)(p * 4);
+    L.level_bytes = L.lay.row * (size_t)d.ny;
+    const size_t f32 = p * (size_t)d.ny * 4;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
         o = align_up(o + bytes, 256);
         return at;
     };
-    for (int l = 0; l < 2; ++l) {
-        L.rho[l] = take(f32);
-        L.h[l] = take(9 * hT);
-    }
-    L.eps = take(f32);
-    L.drag = take(f32);
-    L.kn0 = take(f32);
+    L.level[0] = take(L.level_bytes);
+    L.level[1] = take(L.level_bytes);
+    L.med = take(L.mlay.row * (size_t)d.ny);
     L.uxp = take(f32);
     L.uyp = take(f32);
-    Geom g{d.nx, d.ny, L.pitch, L.plane};
+    Geom g{d.nx, d.ny, L.pitch};
     L.blocks = launch_of(g).blocks;
     L.partials = take((size_t)8 * L.blocks * sizeof(double));
     L.results = take(8 * sizeof(double));
@@ -127,10 +134,9 @@ void split(double v, float &hi, float &lo)
 
 struct lbk_lattice {
     lbk_desc d;
-    Layout L;
+    WsLayout L;
     Geom g;
     Physics ph;
-    Medium m;
     hipStream_t stream;
     char *ws;
     int cur;       // time level holding the current state
@@ -141,11 +147,8 @@ struct lbk_lattice {
     double *host;  // pinned scratch for results (8 doubles)
     int64_t since_check;
 
-    StateV state(int l) const
-    {
-        return StateV{reinterpret_cast<float *>(ws + L.rho[l]),
-                      static_cast<void *>(ws + L.h[l])};
-    }
+    char *state(int l) const { return ws + L.level[l]; }
+    char *med() const { return ws + L.med; }
     float s() const { return ldexpf(1.0f, scale_exp); }
     float inv_s() const { return ldexpf(1.0f, -scale_exp); }
     double *partials() const { return reinterpret_cast<double *>(ws + L.partials); }
@@ -169,9 +172,9 @@ lbk_status fetch(lbk_lattice *lat, int slots, unsigned max_mask)
 // the largest stored magnitude sits near 2^12 (exact power-of-two rescale).
 lbk_status check_state(lbk_lattice *lat)
 {
-    StateV s = lat->state(lat->cur);
-    HIP_TRY(launch_state_sums(lat->d.storage, s, lat->g, lat->inv_s(), lat->partials(),
-                              lat->stream));
+    char *s = lat->state(lat->cur);
+    HIP_TRY(launch_state_sums(lat->d.storage, s, lat->L.lay, lat->g, lat->inv_s(),
+                              lat->partials(), lat->stream));
     lbk_status st = fetch(lat, ST_SLOTS, 1u << ST_HMAX);
     if (st != LBK_OK)
         return st;
@@ -187,7 +190,7 @@ lbk_status check_state(lbk_lattice *lat)
             if (lat->scale_exp + k > 100)
                 k = 100 - lat->scale_exp;
             if (k != 0) {
-                HIP_TRY(launch_rescale(lat->d.storage, s, lat->g, k, lat->stream));
+                HIP_TRY(launch_rescale(lat->d.storage, s, lat->L.lay, lat->g, k, lat->stream));
                 lat->scale_exp += k;
             }
         }
@@ -239,7 +242,7 @@ lbk_status lbk_create(const lbk_desc *d, const float *eps, const float *k, const
         return fail(LBK_ERR_INVALID_ARG, "eps and k are required");
     if (!workspace || ((uintptr_t)workspace & 255u))
         return fail(LBK_ERR_INVALID_ARG, "workspace must be non-NULL and 256-byte aligned");
-    Layout L = layout_of(*d);
+    WsLayout L = layout_of(*d);
     if (ws_bytes < L.total)
         return fail(LBK_ERR_OOM, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
     int dev = -1;
@@ -254,7 +257,7 @@ lbk_status lbk_create(const lbk_desc *d, const float *eps, const float *k, const
         return fail(LBK_ERR_OOM, "host allocation failed");
     lat->d = *d;
     lat->L = L;
-    lat->g = Geom{d->nx, d->ny, L.pitch, L.plane};
+    lat->g = Geom{d->nx, d->ny, L.pitch};
     lat->stream = static_cast<hipStream_t>(stream);
     lat->ws = static_cast<char *>(workspace);
     lat->cur = 0;
@@ -287,11 +290,8 @@ lbk_status lbk_create(const lbk_desc *d, const float *eps, const float *k, const
     ph.kn_local = d->kn_local ? 1 : 0;
 
     char *ws = lat->ws;
-    float *pe = reinterpret_cast<float *>(ws + L.eps);
-    float *pd = reinterpret_cast<float *>(ws + L.drag);
-    float *pk = reinterpret_cast<float *>(ws + L.kn0);
-    lat->m = Medium{pe, pd, pk};
-    const size_t row = (size_t)d->nx * sizeof(float), prow = (size_t)L.pitch * sizeof(float);
+    char *med = lat->med();
+    const size_t row = (size_t)d->nx * sizeof(float), mrow = L.mlay.row;
     hipStream_t st = lat->stream;
     auto hip_ok = [&](hipError_t e, const char *what) {
         if (e == hipSuccess)
@@ -299,12 +299,14 @@ lbk_status lbk_create(const lbk_desc *d, const float *eps, const float *k, const
         fail(LBK_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
         return false;
     };
+    // raw fields into the medium slots (eps, k, kn0), then k -> drag
     if (!hip_ok(hipMemsetAsync(ws, 0, L.total, st), "clear workspace") ||
-        !hip_ok(hipMemcpy2DAsync(pe, prow, eps, row, row, d->ny, hipMemcpyDefault, st), "eps") ||
-        !hip_ok(hipMemcpy2DAsync(pd, prow, k, row, row, d->ny, hipMemcpyDefault, st), "k") ||
-        (kn0 && !hip_ok(hipMemcpy2DAsync(pk, prow, kn0, row, row, d->ny, hipMemcpyDefault, st),
-                        "kn0")) ||
-        !hip_ok(launch_fields(lat->g, pe, pd, pk, nu, lat->partials(), st), "fields kernel"))
+        !hip_ok(hipMemcpy2DAsync(med, mrow, eps, row, row, d->ny, hipMemcpyDefault, st), "eps") ||
+        !hip_ok(hipMemcpy2DAsync(med + L.mlay.slot, mrow, k, row, row, d->ny, hipMemcpyDefault,
+                                 st), "k") ||
+        (kn0 && !hip_ok(hipMemcpy2DAsync(med + 2 * L.mlay.slot, mrow, kn0, row, row, d->ny,
+                                         hipMemcpyDefault, st), "kn0")) ||
+        !hip_ok(launch_fields(med, L.mlay, lat->g, nu, lat->partials(), st), "fields kernel"))
         return cleanup(LBK_ERR_DEVICE);
     if ((s = fetch(lat, FLD_SLOTS, 0)) != LBK_OK)
         return cleanup(s);
@@ -321,10 +323,10 @@ lbk_status lbk_create(const lbk_desc *d, const float *eps, const float *k, const
                           hipHostMallocDefault) != hipSuccess)
             return cleanup(fail(LBK_ERR_DEVICE, "pinned host allocation failed"));
         bool ok =
-            hip_ok(hipMemcpy2DAsync(col, sizeof(float), pe, prow, sizeof(float), d->ny,
+            hip_ok(hipMemcpy2DAsync(col, sizeof(float), med, mrow, sizeof(float), d->ny,
                                     hipMemcpyDeviceToHost, st), "eps column") &&
-            hip_ok(hipMemcpy2DAsync(col + d->ny, sizeof(float), pe + d->nx - 1, prow,
-                                    sizeof(float), d->ny, hipMemcpyDeviceToHost, st),
+            hip_ok(hipMemcpy2DAsync(col + d->ny, sizeof(float), med + (d->nx - 1) * sizeof(float),
+                                    mrow, sizeof(float), d->ny, hipMemcpyDeviceToHost, st),
                    "eps column") &&
             hip_ok(hipStreamSynchronize(st), "sync");
         double sum = 0.0;
@@ -335,7 +337,7 @@ lbk_status lbk_create(const lbk_desc *d, const float *eps, const float *k, const
             return cleanup(LBK_ERR_DEVICE);
         lat->eps_b = sum / (2.0 * d->ny);
     }
-    if (!hip_ok(launch_init_state(d->storage, lat->state(0), lat->g, d->init, d->rho0,
+    if (!hip_ok(launch_init_state(d->storage, lat->state(0), L.lay, lat->g, d->init, d->rho0,
                                   d->rho_in, d->rho_out, lat->s(), st), "init kernel") ||
         !hip_ok(hipStreamSynchronize(st), "sync"))
         return cleanup(LBK_ERR_DEVICE);
@@ -362,7 +364,8 @@ lbk_status lbk_step(lbk_lattice *lat, int64_t n)
     for (int64_t i = 0; i < n; ++i) {
         const int nxt = lat->cur ^ 1;
         HIP_TRY(launch_sweep(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->state(nxt),
-                             lat->g, lat->m, lat->ph, lat->s(), lat->inv_s(), lat->stream));
+                             lat->L.lay, lat->med(), lat->L.mlay, lat->g, lat->ph, lat->s(),
+                             lat->inv_s(), lat->stream));
         lat->cur = nxt;
         ++lat->t;
         if (d.check_every > 0 && ++lat->since_check >= d.check_every) {
@@ -388,9 +391,9 @@ lbk_status lbk_read_macroscopic(lbk_lattice *lat, float *rho, float *ux, float *
     if (!lat)
         return fail(LBK_ERR_INVALID_ARG, "lattice is NULL");
     const lbk_desc &d = lat->d;
-    HIP_TRY(launch_macro(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->g, lat->m,
-                         lat->ph, lat->inv_s(), rho, ux, uy, nullptr, nullptr, lat->partials(),
-                         lat->stream));
+    HIP_TRY(launch_macro(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->L.lay,
+                         lat->med(), lat->L.mlay, lat->g, lat->ph, lat->s(), lat->inv_s(), rho, ux, uy,
+                         nullptr, nullptr, lat->partials(), lat->stream));
     return LBK_OK;
 }
 
@@ -398,8 +401,8 @@ lbk_status lbk_read_populations(lbk_lattice *lat, double *f)
 {
     if (!lat || !f)
         return fail(LBK_ERR_INVALID_ARG, "NULL argument");
-    HIP_TRY(launch_populations(lat->d.storage, lat->state(lat->cur), lat->g, lat->inv_s(), f,
-                               lat->stream));
+    HIP_TRY(launch_populations(lat->d.storage, lat->state(lat->cur), lat->L.lay, lat->g,
+                               lat->inv_s(), f, lat->stream));
     return LBK_OK;
 }
 
@@ -409,9 +412,9 @@ static lbk_status macro_sums(lbk_lattice *lat, bool residual)
     char *ws = lat->ws;
     float *uxp = residual ? reinterpret_cast<float *>(ws + lat->L.uxp) : nullptr;
     float *uyp = residual ? reinterpret_cast<float *>(ws + lat->L.uyp) : nullptr;
-    HIP_TRY(launch_macro(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->g, lat->m,
-                         lat->ph, lat->inv_s(), nullptr, nullptr, nullptr, uxp, uyp,
-                         lat->partials(), lat->stream));
+    HIP_TRY(launch_macro(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->L.lay,
+                         lat->med(), lat->L.mlay, lat->g, lat->ph, lat->s(), lat->inv_s(), nullptr, nullptr,
+                         nullptr, uxp, uyp, lat->partials(), lat->stream));
     return fetch(lat, MAC_SLOTS, 0);
 }
 
@@ -447,8 +450,8 @@ lbk_status lbk_diagnostics(lbk_lattice *lat, double *mass, double *flux_x, doubl
     if (residual)
         *residual = res;
     if (mass) {
-        HIP_TRY(launch_state_sums(lat->d.storage, lat->state(lat->cur), lat->g, lat->inv_s(),
-                                  lat->partials(), lat->stream));
+        HIP_TRY(launch_state_sums(lat->d.storage, lat->state(lat->cur), lat->L.lay, lat->g,
+                                  lat->inv_s(), lat->partials(), lat->stream));
         if ((s = fetch(lat, ST_SLOTS, 1u << ST_HMAX)) != LBK_OK)
             return s;
         *mass = lat->host[ST_MASS];
@@ -457,15 +460,14 @@ lbk_status lbk_diagnostics(lbk_lattice *lat, double *mass, double *flux_x, doubl
 }
 
 // Saved state: a 64-byte header (magic, step count, FP16 scale exponent,
-// sizes) followed by the density plane and the nine deviation planes.
+// sizes) followed by the current time level (density and deviations).
 static const uint64_t kMagic = 0x6c626b7374617465ull; // "lbkstate"
 
 lbk_status lbk_state_size(const lbk_lattice *lat, size_t *bytes)
 {
     if (!lat || !bytes)
         return fail(LBK_ERR_INVALID_ARG, "NULL argument");
-    *bytes = 64 + (lat->L.h[0] - lat->L.rho[0]) + 9 * (size_t)lat->L.plane *
-                                                     elem_size(lat->d.storage);
+    *bytes = 64 + lat->L.level_bytes;
     return LBK_OK;
 }
 
@@ -479,8 +481,8 @@ lbk_status lbk_save_state(lbk_lattice *lat, void *dst)
                       lat->d.nx,       lat->d.ny, lat->d.storage, 0};
     HIP_TRY(hipStreamSynchronize(lat->stream));
     HIP_TRY(hipMemcpy(dst, hdr, sizeof hdr, hipMemcpyDefault));
-    HIP_TRY(hipMemcpyAsync(static_cast<char *>(dst) + 64, lat->ws + lat->L.rho[lat->cur],
-                           bytes - 64, hipMemcpyDefault, lat->stream));
+    HIP_TRY(hipMemcpyAsync(static_cast<char *>(dst) + 64, lat->state(lat->cur), bytes - 64,
+                           hipMemcpyDefault, lat->stream));
     return LBK_OK;
 }
 
@@ -496,7 +498,7 @@ lbk_status lbk_load_state(lbk_lattice *lat, const void *src)
     if (hdr[0] != (int64_t)kMagic || hdr[3] != (int64_t)bytes || hdr[4] != lat->d.nx ||
         hdr[5] != lat->d.ny || hdr[6] != lat->d.storage)
         return fail(LBK_ERR_INVALID_ARG, "state does not match this lattice");
-    HIP_TRY(hipMemcpyAsync(lat->ws + lat->L.rho[lat->cur], static_cast<const char *>(src) + 64,
+    HIP_TRY(hipMemcpyAsync(lat->state(lat->cur), static_cast<const char *>(src) + 64,
                            bytes - 64, hipMemcpyDefault, lat->stream));
     lat->t = hdr[1];
     lat->scale_exp = (int)hdr[2];

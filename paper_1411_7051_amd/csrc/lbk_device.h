@@ -1,19 +1,29 @@
 // lbk_device.h -- device-side building blocks of the fused D2Q9 Klinkenberg
-// sweep for gfx950: lattice constants, storage element types, the pull
+// sweep for gfx950: lattice constants, buffer-resource element I/O, the pull
 // stream, the node velocity solve and the BGK/Guo collide, all written in
 // the density-split form used by every storage type:
 //
 //   stored per node x:  rho(x) (FP32)   and   h_i(x) = f*_i(x) - w_i rho(x)
 //
-// so that the nine planes carry only deviations from the local density.
-// The deviations are the small quantities the flow lives in (at the low
-// Mach numbers of tight media they are 1e-12 .. 1e-4), and keeping them
-// apart from the O(1) density gives every storage type its full relative
-// precision on them.  Post-stream populations are handled as
-// f_i = w_i rho_c + d_i with rho_c the node's stored density, and the
-// density update rho_new = rho_c + sum d_i is split into its FP32-rounded
-// value and an exact residual that stays in the deviations, so no mass is
-// lost to rounding of the density plane.
+// so that the nine population slots carry only deviations from the local
+// density.  The deviations are the small quantities the flow lives in (at
+// the low Mach numbers of tight media they are 1e-12 .. 1e-4), and keeping
+// them apart from the O(1) density gives every storage type its full
+// relative precision on them.  Post-stream populations are handled as
+// f_i = w_i rho_c + d_i with rho_c the node's stored density; the density
+// update rho_c + sum d_i is split into its FP32-rounded value and the exact
+// rounding residual (Fast2Sum), which stays in the deviations, so no mass is
+// lost to rounding of the density.
+//
+// FP16 stores the deviations times a power of two s (the "scaled" unit);
+// the arithmetic on deviations runs in that unit, with s folded into the
+// per-direction-class constants, so the scale costs no per-population work.
+//
+// Memory access: every kernel maps one block to 256 consecutive x of one
+// row, so each row's base is uniform.  Rows are reached through buffer
+// resources (scalar registers) with a 32-bit per-lane byte offset: no
+// per-access address arithmetic, and hardware range checking on every
+// access (an out-of-range load returns 0 instead of faulting).
 #pragma once
 
 #include <hip/hip_bf16.h>
@@ -49,47 +59,76 @@ static_assert(opp_of(1) == 3 && opp_of(2) == 4 && opp_of(5) == 7 && opp_of(6) ==
                   opp_of(7) == 5 && opp_of(8) == 6 && opp_of(3) == 1 && opp_of(4) == 2,
               "opposite directions");
 
-// Storage element types.  FP16 values are the deviations times a power of
-// two (scale), so that they sit in the normal FP16 range; BF16 and FP32
-// need no scale.  Every stored population is read once and written once per
-// step, so loads and stores are nontemporal: they bypass the caches' reuse
-// policy and leave L2 to the density plane, whose neighbour reads do reuse.
+// ---------------------------------------------------------- buffer I/O
+
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+// Raw (unstructured) buffer descriptor word 3 for the gfx9 family.
+constexpr int kRsrcWord3 = 0x00020000;
+// Cache policy of the population streams: nontemporal.  Each stored
+// population is read once and written once per step; the density and the
+// medium, whose neighbour reads reuse, keep the default policy.
+constexpr int kNT = 2;
+
+__device__ __forceinline__ Rsrc make_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             kRsrcWord3);
+}
+__device__ __forceinline__ float ld_f32(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+__device__ __forceinline__ void st_f32(Rsrc r, uint32_t voff, uint32_t soff, float v, bool nt)
+{
+    if (nt)
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, kNT);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, 0);
+}
+
+// Storage element types, loaded and stored in the storage's own unit
+// (scaled for FP16).
 template <typename T> struct Elem;
 template <> struct Elem<float> {
-    static __device__ __forceinline__ float ld(const float *p, int64_t i, float)
+    static constexpr bool kScaled = false;
+    static __device__ __forceinline__ float ld(Rsrc r, uint32_t voff, uint32_t soff)
     {
-        return __builtin_nontemporal_load(p + i);
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, kNT));
     }
-    static __device__ __forceinline__ void st(float *p, int64_t i, float v, float)
+    static __device__ __forceinline__ void st(Rsrc r, uint32_t voff, uint32_t soff, float v)
     {
-        __builtin_nontemporal_store(v, p + i);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, kNT);
     }
 };
 template <> struct Elem<__half> {
-    static __device__ __forceinline__ float ld(const __half *p, int64_t i, float inv_s)
+    static constexpr bool kScaled = true;
+    static __device__ __forceinline__ float ld(Rsrc r, uint32_t voff, uint32_t soff)
     {
-        const uint16_t u = __builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(p) + i);
-        return __half2float(__ushort_as_half(u)) * inv_s;
+        const uint16_t u = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, kNT);
+        return __half2float(__ushort_as_half(u));
     }
-    static __device__ __forceinline__ void st(__half *p, int64_t i, float v, float s)
+    static __device__ __forceinline__ void st(Rsrc r, uint32_t voff, uint32_t soff, float v)
     {
-        __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(v * s)),
-                                    reinterpret_cast<uint16_t *>(p) + i);
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, (int)voff,
+                                              (int)soff, kNT);
     }
 };
 template <> struct Elem<__hip_bfloat16> {
-    static __device__ __forceinline__ float ld(const __hip_bfloat16 *p, int64_t i, float)
+    static constexpr bool kScaled = false;
+    static __device__ __forceinline__ float ld(Rsrc r, uint32_t voff, uint32_t soff)
     {
-        const uint16_t u = __builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(p) + i);
+        const uint16_t u = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, kNT);
         return __uint_as_float((uint32_t)u << 16);
     }
-    static __device__ __forceinline__ void st(__hip_bfloat16 *p, int64_t i, float v, float)
+    static __device__ __forceinline__ void st(Rsrc r, uint32_t voff, uint32_t soff, float v)
     {
         const __hip_bfloat16 b = __float2bfloat16(v); // round to nearest even
-        __builtin_nontemporal_store(*reinterpret_cast<const uint16_t *>(&b),
-                                    reinterpret_cast<uint16_t *>(p) + i);
+        __builtin_amdgcn_raw_buffer_store_b16(*reinterpret_cast<const uint16_t *>(&b), r,
+                                              (int)voff, (int)soff, kNT);
     }
 };
+
+// -------------------------------------------------------------- layouts
 
 // Scalars of one run, precomputed on the host in FP64 and rounded once.
 struct Physics {
@@ -104,137 +143,193 @@ struct Physics {
     int kn_local;
 };
 
-// Plane geometry: nx x ny nodes, rows of `pitch` elements, `plane` = ny*pitch.
+// Lattice extent; `pitch` = elements per row slot (a multiple of 64).
 struct Geom {
     int nx, ny, pitch;
-    int64_t plane;
 };
 
-// Lattice state buffers of one time level.
-template <typename T> struct State {
-    float *rho; // [ny][pitch]
-    T *h;       // [9][ny][pitch]
+// Byte layout of one time level of the state: row block y starts at
+// y * row and holds the density (FP32) at offset 0 and h_i (T) at
+// h_off + i * h_slot.
+struct Layout {
+    uint64_t row;
+    uint32_t h_off;
+    uint32_t h_slot;
 };
 
-// Per-node medium: eps, drag = eps nu / k (0 where k = +inf), kn0.
-struct Medium {
-    const float *eps;
-    const float *drag;
-    const float *kn0;
+// Byte layout of the read-only medium: row block y starts at y * row and
+// holds eps at 0, drag = eps nu / k (0 where k = +inf) at slot, kn0 at
+// 2 slot (FP32).
+struct MLayout {
+    uint64_t row;
+    uint32_t slot;
 };
 
-// Beskok-Karniadakis/Civan factor (Eqs. 6-7, b = -1) in FP32 with the
-// hardware log2/exp2; f_c = 1 at Kn = 0.
-__device__ __forceinline__ float fc_of(float kn)
+template <typename T> __device__ __forceinline__ Rsrc state_row(const char *base, const Layout &L,
+                                                                int y)
 {
-    // Kn^-0.4348 = exp2(-0.4348 log2 Kn)
-    float p = __builtin_amdgcn_exp2f(-0.4348f * __builtin_amdgcn_logf(kn));
-    float alpha = 1.358f * __builtin_amdgcn_rcpf(1.0f + 0.170f * p);
-    float fc = (1.0f + alpha * kn) * (1.0f + 4.0f * kn * __builtin_amdgcn_rcpf(1.0f + kn));
-    return kn > 0.0f ? fc : 1.0f;
+    return make_rsrc(base + (uint64_t)y * L.row, (uint32_t)L.row);
+}
+__device__ __forceinline__ Rsrc med_row(const char *base, const MLayout &M, int y)
+{
+    return make_rsrc(base + (uint64_t)y * M.row, (uint32_t)M.row);
 }
 
-// Pull-stream of node (x, y): post-stream deviations d_i = f_i - w_i rc,
-// with rc the node's stored density.  A link that crosses a wall returns
-// the node's own opposite deviation (half-way bounce-back); periodic axes
-// wrap.  Pressure columns are never pulled for themselves (the caller pulls
-// their neighbour instead), so x - 1 and x + 1 stay inside the row there.
-template <typename T, int BCX, int BCY>
-__device__ __forceinline__ void pull(const State<T> &src, const Geom &g, float inv_s, int x,
-                                     int y, float &rc, float (&d)[9])
+// The three rows a node pulls from, and whether the row below / above lies
+// beyond a wall (then the node's own row stands in; its entries are unused).
+struct Rows {
+    Rsrc r[3];
+    bool wym, wyp;
+};
+
+template <int BCY>
+__device__ __forceinline__ Rows rows_of(const char *base, const Layout &L, const Geom &g, int y)
 {
-    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
-    bool wxm = false, wxp = false, wym = false, wyp = false;
-    if (BCX == BC_PERIODIC) {
-        xm = (x == 0) ? g.nx - 1 : xm;
-        xp = (x == g.nx - 1) ? 0 : xp;
-    } else if (BCX == BC_WALL) {
-        wxm = (x == 0);
-        wxp = (x == g.nx - 1);
-    }
+    int ym = y - 1, yp = y + 1;
+    Rows R;
     if (BCY == BC_PERIODIC) {
         ym = (y == 0) ? g.ny - 1 : ym;
         yp = (y == g.ny - 1) ? 0 : yp;
+        R.wym = R.wyp = false;
     } else {
-        wym = (y == 0);
-        wyp = (y == g.ny - 1);
+        R.wym = (y == 0);
+        R.wyp = (y == g.ny - 1);
+        ym = R.wym ? y : ym;
+        yp = R.wyp ? y : yp;
     }
-    const int c = y * g.pitch + x;
-    rc = src.rho[c];
-    d[0] = Elem<T>::ld(src.h, c, inv_s);
+    R.r[0] = make_rsrc(base + (uint64_t)ym * L.row, (uint32_t)L.row);
+    R.r[1] = make_rsrc(base + (uint64_t)y * L.row, (uint32_t)L.row);
+    R.r[2] = make_rsrc(base + (uint64_t)yp * L.row, (uint32_t)L.row);
+    return R;
+}
+
+// Pull-stream of node (x, y): post-stream deviations d_i = f_i - w_i rc in
+// the storage unit (times s for FP16), with rc the node's stored density.
+// A link that crosses a wall returns the node's own opposite deviation
+// (half-way bounce-back); periodic axes wrap.  Pressure columns are never
+// pulled for themselves (the caller pulls their neighbour instead), so
+// x - 1 and x + 1 stay inside the row there.
+template <typename T, int BCX>
+__device__ __forceinline__ void pull(const Rows &R, const Layout &L, const Geom &g, float s,
+                                     uint32_t x, float &rc, float (&d)[9])
+{
+    uint32_t xm = x - 1, xp = x + 1;
+    bool wxm = false, wxp = false;
+    if (BCX == BC_PERIODIC) {
+        xm = (x == 0) ? (uint32_t)g.nx - 1 : xm;
+        xp = (x == (uint32_t)g.nx - 1) ? 0 : xp;
+    } else if (BCX == BC_WALL) {
+        wxm = (x == 0);
+        wxp = (x == (uint32_t)g.nx - 1);
+        xm = wxm ? x : xm;
+        xp = wxp ? x : xp;
+    }
+    constexpr uint32_t es = sizeof(T);
+    rc = ld_f32(R.r[1], x * 4, 0);
+    d[0] = Elem<T>::ld(R.r[1], x * es, L.h_off);
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
         const int ex = ex_of(i), ey = ey_of(i);
-        const int sx = ex == 1 ? xm : (ex == -1 ? xp : x);
-        const int sy = ey == 1 ? ym : (ey == -1 ? yp : y);
-        const bool wall = (ex == 1 && wxm) || (ex == -1 && wxp) || (ey == 1 && wym) ||
-                          (ey == -1 && wyp);
-        // bounce-back reads the node's own opposite population; the density
-        // difference is then zero
-        const int n = wall ? c : sy * g.pitch + sx;
-        const int plane = wall ? opp_of(i) : i;
-        const float rn = src.rho[n];
-        d[i] = w_of(i) * (rn - rc) + Elem<T>::ld(src.h + plane * g.plane, n, inv_s);
+        const uint32_t sx = ex == 1 ? xm : (ex == -1 ? xp : x);
+        const bool wall_y = (ey == 1 && R.wym) || (ey == -1 && R.wyp); // uniform
+        const float ws = Elem<T>::kScaled ? w_of(i) * s : w_of(i);
+        if (wall_y) {
+            d[i] = Elem<T>::ld(R.r[1], x * es, L.h_off + opp_of(i) * L.h_slot);
+        } else {
+            const int ry = ey == 1 ? 0 : (ey == -1 ? 2 : 1);
+            const float rn = ld_f32(R.r[ry], sx * 4, 0);
+            const float h = Elem<T>::ld(R.r[ry], sx * es, L.h_off + i * L.h_slot);
+            d[i] = ws * (rn - rc) + h;
+        }
+        if (BCX == BC_WALL) {
+            const bool wall_x = (ex == 1 && wxm) || (ex == -1 && wxp); // per lane, edges only
+            if (wall_x)
+                d[i] = Elem<T>::ld(R.r[1], x * es, L.h_off + opp_of(i) * L.h_slot);
+        }
     }
 }
 
-// Split rho_c + sum d into its FP32 value and deviations relative to it:
-// delta_i = d_i - w_i (rho - rc) with rho - rc exact (Sterbenz), so that
-// w_i rho + delta_i = w_i rc + d_i holds to the rounding of the deviations.
-__device__ __forceinline__ float split_density(float rc, const float (&d)[9], float (&dl)[9])
+// Density update of a pulled node: s_phys = sum d / s; rho = FP32(rc +
+// s_phys); inc = rho - rc (exact, Sterbenz); r = s_phys - inc, the exact
+// rounding residual (Fast2Sum with |rc| >= |s_phys|).  The deviations
+// relative to rho are d_i - w_i inc; they are never formed explicitly.
+template <typename T>
+__device__ __forceinline__ float density(float rc, const float (&d)[9], float inv_s, float &inc,
+                                         float &r)
 {
-    float s = 0.0f;
+    float sum = 0.0f;
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        s += d[i];
-    const float rho = rc + s;
-    const float inc = rho - rc;
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-        dl[i] = d[i] - w_of(i) * inc;
+        sum += d[i];
+    const float sp = Elem<T>::kScaled ? sum * inv_s : sum;
+    const float rho = rc + sp;
+    inc = rho - rc;
+    r = sp - inc;
     return rho;
 }
 
-__device__ __forceinline__ void momentum(const float (&dl)[9], float &jx, float &jy)
+// sum_i e_i d_i, in the storage unit (the weights' part cancels in pairs).
+__device__ __forceinline__ void momentum(const float (&d)[9], float &jx, float &jy)
 {
-    jx = (dl[1] - dl[3]) + (dl[5] - dl[7]) + (dl[8] - dl[6]);
-    jy = (dl[2] - dl[4]) + (dl[5] - dl[7]) + (dl[6] - dl[8]);
+    jx = (d[1] - d[3]) + (d[5] - d[7]) + (d[8] - d[6]);
+    jy = (d[2] - d[4]) + (d[5] - d[7]) + (d[6] - d[8]);
 }
 
-// Velocity and force of one node from rho and j = sum f e (Eq. 16b solved as
-// Eq. 17, or the Forchheimer quadratic of Eq. 2), with k_a = k f_c(Kn) and
-// Kn = kn0 rho_ref / rho.  eps = 0: u = 0 and rho F = -2 j (the infinite
-// drag limit of Eq. 17).
+// Velocity and force of one node from rho and j = sum f e: Eq. 16b solved
+// as Eq. 17 (or the Forchheimer quadratic of Eq. 2), with the apparent
+// permeability k_a = k f_c(Kn) of Eq. 3 and Kn = kn0 rho_ref / rho.
+//
+// With t = Kn^0.4348 and a = t + 0.170, Eqs. 6-7 (b = -1) read
+//   f_c = (a + 1.358 t Kn)(1 + 5 Kn) / (a (1 + Kn)) = den / num,
+// finite and equal to 1 at Kn = 0 (t = 0).  The Darcy coefficient is
+// A = drag / f_c = drag num / den, and Eq. 17 gives u = v / (1 + A/2) with
+// v = j / rho + eps G / 2, so one reciprocal R = 1 / (2 den + drag num)
+// yields both u = 2 den R v and A u = 2 drag num R v.
+// eps = 0: u = 0 and rho F = -2 j (the infinite-drag limit of Eq. 17).
 __device__ __forceinline__ void velocity(const Physics &ph, float rho, float jx, float jy,
                                          float eps, float drag, float kn0, float &ux, float &uy,
                                          float &Fx, float &Fy)
 {
     const float rinv = __builtin_amdgcn_rcpf(rho);
-    const float kn = ph.kn_local ? kn0 * ph.rho_ref * rinv : kn0;
-    const float fc = fc_of(kn);
-    const float A = drag * __builtin_amdgcn_rcpf(fc); // eps nu / k_a
-    const float vx = jx * rinv + 0.5f * eps * ph.gx;
-    const float vy = jy * rinv + 0.5f * eps * ph.gy;
-    const float c0 = 1.0f + 0.5f * A;
-    float g, B = 0.0f;
-    if (ph.feps != 0.0f) {
-        // B = eps F_eps / sqrt(k_a), k_a = eps nu f_c / drag
-        B = eps * ph.feps * __builtin_sqrtf(drag * ph.inv_nu * __builtin_amdgcn_rcpf(eps * fc));
-        B = drag > 0.0f ? B : 0.0f;
+    const float kn = ph.kn_local ? kn0 * (ph.rho_ref * rinv) : kn0;
+    const float t = __builtin_amdgcn_exp2f(0.4348f * __builtin_amdgcn_logf(kn)); // 0 at Kn = 0
+    const float a = t + 0.170f;
+    const float num = a * (1.0f + kn);
+    const float den = (a + 1.358f * t * kn) * (1.0f + 5.0f * kn);
+    const float egx = eps * ph.gx, egy = eps * ph.gy;
+    const float vx = jx * rinv + 0.5f * egx;
+    const float vy = jy * rinv + 0.5f * egy;
+    float g, ag, B = 0.0f;
+    if (ph.feps == 0.0f) {
+        const float dn = drag * num;
+        const float R2 = 2.0f * __builtin_amdgcn_rcpf(2.0f * den + dn);
+        g = den * R2;
+        ag = dn * R2;
+    } else {
+        // Forchheimer (Eq. 2): (1 + A/2) u + (B/2) |u| u = v with
+        // B = eps F_eps / sqrt(k_a), k_a = eps nu / A; positive root of
+        // the quadratic in |u|, rationalized.
+        const float A = drag * num * __builtin_amdgcn_rcpf(den);
+        B = ph.feps * __builtin_sqrtf(eps * A * ph.inv_nu);
+        const float c0 = 1.0f + 0.5f * A;
         const float wn = __builtin_sqrtf(vx * vx + vy * vy);
         g = 2.0f / (c0 + __builtin_sqrtf(c0 * c0 + 2.0f * B * wn));
-    } else {
-        g = __builtin_amdgcn_rcpf(c0);
+        ag = A * g;
     }
     const bool solid = !(eps > 0.0f);
     ux = solid ? 0.0f : g * vx;
     uy = solid ? 0.0f : g * vy;
-    const float un = __builtin_sqrtf(ux * ux + uy * uy);
-    Fx = solid ? -2.0f * jx * rinv : -A * ux - B * un * ux + eps * ph.gx;
-    Fy = solid ? -2.0f * jy * rinv : -A * uy - B * un * uy + eps * ph.gy;
+    float fx = egx - ag * vx, fy = egy - ag * vy;
+    if (ph.feps != 0.0f) {
+        const float bu = B * __builtin_sqrtf(ux * ux + uy * uy);
+        fx -= bu * ux;
+        fy -= bu * uy;
+    }
+    Fx = solid ? -2.0f * jx * rinv : fx;
+    Fy = solid ? -2.0f * jy * rinv : fy;
 }
 
-// Equilibrium deviation of Eq. 14 from w_i rho:
+// Equilibrium deviation of Eq. 14 from w_i rho (physical unit):
 // w_i rho [3 e.u + 9/(2 eps) (e.u)^2 - 3/(2 eps) u.u]; zero at eps = 0.
 __device__ __forceinline__ void geq_dev(float rho, float ux, float uy, float eps,
                                         float (&ge)[9])
@@ -251,31 +346,46 @@ __device__ __forceinline__ void geq_dev(float rho, float ux, float uy, float eps
     }
 }
 
-// BGK relaxation with Guo forcing (Eqs. 12, 14, 15) in deviation form:
-//   h*_i = (1 - omega) dl_i + omega (w_i r + geq_i) + F_i
-// where r = sum dl (the exact density residual) and geq_i is the Eq. 14
-// deviation.  For eps = 0 the 1/eps terms vanish with u = 0.
-__device__ __forceinline__ void collide(const Physics &ph, float rho, const float (&dl)[9],
-                                        float ux, float uy, float Fx, float Fy, float eps,
-                                        float (&hs)[9])
+// BGK relaxation with Guo forcing (Eqs. 12, 14, 15) in deviation form.
+// With delta_i = d_i - w_i inc the post-stream deviations from w_i rho,
+//   h*_i = (1 - omega) delta_i + omega (w_i r + geq_i) + F_i,
+// r the density residual, geq_i the Eq. 14 deviation and F_i Eq. 15.
+// Over the pairs (i, opp i), with eu = e_i.u, eF = e_i.F, g = 1 - 1/(2 tau),
+// P = omega eu + g eF and E = eu (P + g eF):
+//   h*_i, h*_opp = (1 - omega) d_i + w_i C + w_i rho (4.5 E / eps +/- 3 P)
+//   C = omega r - (1 - omega) inc + rho/eps (-1.5 omega u.u - 3 g u.F).
+// d_i and the outputs are in the storage unit (times s for FP16).
+// For eps = 0 the 1/eps terms vanish with u = 0.
+template <typename T>
+__device__ __forceinline__ void collide(const Physics &ph, float rho, float inc, float r,
+                                        const float (&d)[9], float ux, float uy, float Fx,
+                                        float Fy, float eps, float s, float (&hs)[9])
 {
-    float r = 0.0f;
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-        r += dl[i];
     const bool solid = !(eps > 0.0f);
     const float ie = solid ? 0.0f : __builtin_amdgcn_rcpf(eps);
-    const float om = ph.omega;
-    const float base_eq = -1.5f * ie * (ux * ux + uy * uy);
-    const float base_f = -3.0f * ie * (ux * Fx + uy * Fy);
-    const float cg = ph.guo;
+    const float om = ph.omega, cg = ph.guo, keep = 1.0f - om;
+    float C = om * r - keep * inc +
+              rho * ie * (-1.5f * om * (ux * ux + uy * uy) - 3.0f * cg * (ux * Fx + uy * Fy));
+    float rs = rho;
+    if (Elem<T>::kScaled) {
+        C *= s;
+        rs *= s;
+    }
+    const float Kb = 4.5f * rs * ie, Mb = 3.0f * rs; // times w_i below
+    hs[0] = keep * d[0] + w_of(0) * C;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
+    for (int i = 1; i <= 6; ++i) {
+        if (i == 3 || i == 4)
+            continue; // pairs (1,3) (2,4) (5,7) (6,8)
+        const float w = w_of(i);
         const float eu = ex_of(i) * ux + ey_of(i) * uy;
-        const float eF = ex_of(i) * Fx + ey_of(i) * Fy;
-        const float geq = 3.0f * eu + 4.5f * ie * eu * eu + base_eq;
-        const float gf = cg * (3.0f * eF + 9.0f * ie * eu * eF + base_f);
-        hs[i] = (1.0f - om) * dl[i] + w_of(i) * (om * r + rho * (om * geq + gf));
+        const float q = cg * (ex_of(i) * Fx + ey_of(i) * Fy);
+        const float P = om * eu + q;
+        const float E = eu * (P + q);
+        const float X = (w * Kb) * E + w * C;
+        const float Y = (w * Mb) * P;
+        hs[i] = keep * d[i] + (X + Y);
+        hs[opp_of(i)] = keep * d[opp_of(i)] + (X - Y);
     }
 }
 

@@ -6,12 +6,6 @@
 
 namespace lbk {
 
-// Type-erased state of one time level (h points at T[9][ny][pitch]).
-struct StateV {
-    float *rho;
-    void *h;
-};
-
 // Threads per block of every lattice kernel: one node per thread, blocks
 // cover 256 consecutive x of one row.
 constexpr int kBlock = 256;
@@ -44,43 +38,44 @@ enum {
     FLD_SLOTS
 };
 
-hipError_t launch_sweep(int storage, int bcx, int bcy, const StateV &src, const StateV &dst,
-                        const Geom &g, const Medium &m, const Physics &ph, float s, float inv_s,
-                        hipStream_t st);
+hipError_t launch_sweep(int storage, int bcx, int bcy, const char *src, char *dst,
+                        const Layout &lay, const char *med, const MLayout &mlay, const Geom &g,
+                        const Physics &ph, float s, float inv_s, hipStream_t st);
 
-// Macroscopic read-out (any output may be null) and FP64 partials
-// [MAC_SLOTS][blocks].  If u_prev is given it is read for the residual and
-// then overwritten with the current velocity.
-hipError_t launch_macro(int storage, int bcx, int bcy, const StateV &src, const Geom &g,
-                        const Medium &m, const Physics &ph, float inv_s, float *rho_out,
-                        float *ux_out, float *uy_out, float *ux_prev, float *uy_prev,
-                        double *partials, hipStream_t st);
+// Macroscopic read-out ([ny][nx] outputs, any may be null) and FP64 partials
+// [MAC_SLOTS][blocks].  If u_prev ([ny][pitch]) is given it is read for the
+// residual and then overwritten with the current velocity.
+hipError_t launch_macro(int storage, int bcx, int bcy, const char *src, const Layout &lay,
+                        const char *med, const MLayout &mlay, const Geom &g, const Physics &ph,
+                        float s, float inv_s, float *rho_out, float *ux_out, float *uy_out,
+                        float *ux_prev, float *uy_prev, double *partials, hipStream_t st);
 
 // Mass / max|h| / non-finite partials [ST_SLOTS][blocks] of a state.
-hipError_t launch_state_sums(int storage, const StateV &src, const Geom &g, float inv_s,
-                             double *partials, hipStream_t st);
+hipError_t launch_state_sums(int storage, const char *src, const Layout &lay, const Geom &g,
+                             float inv_s, double *partials, hipStream_t st);
 
 // Reduce partials [slots][blocks] in a fixed order into out[slots]; bit k of
 // max_mask selects max instead of sum for slot k.
 hipError_t launch_finish(const double *partials, int slots, int blocks, unsigned max_mask,
                          double *out, hipStream_t st);
 
-// Field set-up: in place, turn the raw k plane into drag = eps nu / k
+// Field set-up: in place, turn the raw k slot into drag = eps nu / k
 // (0 where k = +inf or eps = 0) and count invalid values into
 // partials [FLD_SLOTS][blocks].
-hipError_t launch_fields(const Geom &g, float *eps, float *drag, float *kn0, double nu,
+hipError_t launch_fields(char *med, const MLayout &mlay, const Geom &g, double nu,
                          double *partials, hipStream_t st);
 
 // Initial state at rest: rho = rho0, or the linear ramp rho_in -> rho_out.
-hipError_t launch_init_state(int storage, const StateV &dst, const Geom &g, int ramp,
+hipError_t launch_init_state(int storage, char *dst, const Layout &lay, const Geom &g, int ramp,
                              double rho0, double rho_in, double rho_out, float s,
                              hipStream_t st);
 
 // FP64 reconstruction f*_i = w_i rho + h_i / s into out[9][ny][nx].
-hipError_t launch_populations(int storage, const StateV &src, const Geom &g, float inv_s,
-                              double *out, hipStream_t st);
+hipError_t launch_populations(int storage, const char *src, const Layout &lay, const Geom &g,
+                              float inv_s, double *out, hipStream_t st);
 
 // Multiply every stored deviation by 2^k (FP16 scale re-centring; exact).
-hipError_t launch_rescale(int storage, const StateV &st_, const Geom &g, int k, hipStream_t st);
+hipError_t launch_rescale(int storage, char *state, const Layout &lay, const Geom &g, int k,
+                          hipStream_t st);
 
 } // namespace lbk

@@ -4,17 +4,21 @@
 // read-out (Eqs. 16-17), deterministic FP64 reductions for the global
 // permeability and mass, and field / state set-up.
 //
-// Layout in HBM (per time level, two levels ping-pong):
-//   rho  FP32  [ny][pitch]          node density
-//   h    T     [9][ny][pitch]       deviations f*_i - w_i rho (T = FP32/FP16/BF16)
-// plus the read-only medium planes eps, drag = eps nu / k, kn0 (FP32).
-// pitch is a multiple of 64 elements; x is the fastest index.
+// Layout in HBM.  One time level of the state is a stack of row blocks;
+// row block y holds, for x = 0 .. pitch-1,
+//     rho   FP32      node density
+//     h_0 .. h_8  T   deviations f*_i - w_i rho   (T = FP32, FP16 or BF16)
+// so one step's reads of rows y-1, y, y+1 and writes of row y stay within a
+// few hundred KiB of each other (DRAM page locality), instead of spreading
+// over ten planes hundreds of MiB apart.  Two levels ping-pong.  The
+// read-only medium (eps, drag = eps nu / k, kn0; FP32) is row-interleaved
+// the same way.
 //
 // Work mapping: one node per thread, 256 threads = 4 wave64s per block, a
-// block covers 256 consecutive x of one row.  The 1-D grid is remapped so
-// that each of the 8 XCDs (which receive blocks round-robin) sweeps one
-// contiguous band of rows: neighbouring rows share the density plane and
-// row-edge cache lines in that XCD's L2.
+// block covers 256 consecutive x of one row, so row pointers are uniform.
+// The 1-D grid is remapped so that each of the 8 XCDs (which receive blocks
+// round-robin) sweeps one contiguous band of rows: neighbouring rows share
+// the density in that XCD's L2.
 #include "lbk_kernels.h"
 
 namespace lbk {
@@ -36,67 +40,117 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
     return j * q + (j < r ? j : r) + idx;
 }
 
-// Post-stream deviations of node (x, y) after the boundary override; returns
-// the FP32 density the deviations are taken against.
-template <typename T, int BCX, int BCY>
-__device__ __forceinline__ float post_stream(const State<T> &src, const Geom &g, const Medium &m,
-                                             const Physics &ph, float inv_s, int x, int y,
-                                             float (&dl)[9])
+// Row and column of this thread's node; y is uniform across the block.
+struct Node {
+    int y;
+    uint32_t x;
+    int L; // logical block index
+};
+__device__ __forceinline__ Node node_of(int bpr)
 {
-    if (BCX == BC_PRESSURE && (x == 0 || x == g.nx - 1)) {
+    Node n;
+    n.L = xcd_remap(blockIdx.x, gridDim.x);
+    n.y = n.L / bpr;
+    n.x = (uint32_t)(n.L - n.y * bpr) * kBlock + threadIdx.x;
+    return n;
+}
+
+// Medium of row y: eps, drag and kn0 at x.
+struct Med {
+    Rsrc r;
+    uint32_t slot;
+    __device__ __forceinline__ float eps(uint32_t x) const { return ld_f32(r, x * 4, 0); }
+    __device__ __forceinline__ float drag(uint32_t x) const { return ld_f32(r, x * 4, slot); }
+    __device__ __forceinline__ float kn0(uint32_t x) const { return ld_f32(r, x * 4, 2 * slot); }
+};
+
+// Post-stream deviations d_i (storage unit) of node (x, y) after the
+// boundary override, relative to rho - inc; returns the FP32 density rho
+// and sets inc and the density residual r (physical unit).
+template <typename T, int BCX>
+__device__ __forceinline__ float post_stream(const Rows &R, const Layout &L, const Med &md,
+                                             const Geom &g, const Physics &ph, float s,
+                                             float inv_s, uint32_t x, float (&d)[9], float &inc,
+                                             float &r)
+{
+    if (BCX == BC_PRESSURE && (x == 0 || x == (uint32_t)g.nx - 1)) {
         // non-equilibrium extrapolation from the neighbouring column:
         // f_i = f_eq_i(rho_b, u_n; eps_b) + f_i(n) - f_eq_i(rho_n, u_n; eps_n)
-        const int xn = (x == 0) ? 1 : g.nx - 2;
-        float rcn, dn[9], dln[9];
-        pull<T, BCX, BCY>(src, g, inv_s, xn, y, rcn, dn);
-        const float rhon = split_density(rcn, dn, dln);
-        float rn = 0.0f;
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            rn += dln[i];
+        const uint32_t xn = (x == 0) ? 1 : (uint32_t)g.nx - 2;
+        float rcn, dn[9], incn, rn;
+        pull<T, BCX>(R, L, g, s, xn, rcn, dn);
+        const float rhon = density<T>(rcn, dn, inv_s, incn, rn);
         float jx, jy, ux, uy, Fx, Fy;
-        momentum(dln, jx, jy);
-        const int cn = y * g.pitch + xn, cb = y * g.pitch + x;
-        velocity(ph, rhon, jx, jy, m.eps[cn], m.drag[cn], m.kn0[cn], ux, uy, Fx, Fy);
+        momentum(dn, jx, jy);
+        if (Elem<T>::kScaled) {
+            jx *= inv_s;
+            jy *= inv_s;
+        }
+        const float en = md.eps(xn);
+        velocity(ph, rhon, jx, jy, en, md.drag(xn), md.kn0(xn), ux, uy, Fx, Fy);
         const bool in = (x == 0);
         const float rb = in ? ph.rin_hi : ph.rout_hi;
         const float rbl = in ? ph.rin_lo : ph.rout_lo;
         float gb[9], gn[9];
-        geq_dev(rb, ux, uy, m.eps[cb], gb);
-        geq_dev(rhon, ux, uy, m.eps[cn], gn);
+        geq_dev(rb, ux, uy, md.eps(x), gb);
+        geq_dev(rhon, ux, uy, en, gn);
+        float sum = 0.0f;
 #pragma unroll
-        for (int i = 0; i < 9; ++i)
-            dl[i] = w_of(i) * (rbl - rn) + gb[i] + (dln[i] - gn[i]);
+        for (int i = 0; i < 9; ++i) {
+            // physical deviation of the boundary node from w_i rb
+            const float dn_phys = (Elem<T>::kScaled ? dn[i] * inv_s : dn[i]) - w_of(i) * incn;
+            const float v = w_of(i) * (rbl - rn) + gb[i] + (dn_phys - gn[i]);
+            sum += v;
+            d[i] = Elem<T>::kScaled ? v * s : v;
+        }
+        inc = 0.0f;
+        r = sum;
         return rb;
     }
-    float rc, d[9];
-    pull<T, BCX, BCY>(src, g, inv_s, x, y, rc, d);
-    return split_density(rc, d, dl);
+    float rc;
+    pull<T, BCX>(R, L, g, s, x, rc, d);
+    return density<T>(rc, d, inv_s, inc, r);
+}
+
+// One node's full update: pull, boundary override, moments, velocity,
+// collide.  Outputs the new density and deviations (storage unit).
+template <typename T, int BCX>
+__device__ __forceinline__ float update(const Rows &R, const Layout &L, const Med &md,
+                                        const Geom &g, const Physics &ph, float s, float inv_s,
+                                        uint32_t x, float (&hs)[9])
+{
+    float d[9], inc, r;
+    const float rho = post_stream<T, BCX>(R, L, md, g, ph, s, inv_s, x, d, inc, r);
+    float jx, jy, ux, uy, Fx, Fy;
+    momentum(d, jx, jy);
+    if (Elem<T>::kScaled) {
+        jx *= inv_s;
+        jy *= inv_s;
+    }
+    const float eps = md.eps(x);
+    velocity(ph, rho, jx, jy, eps, md.drag(x), md.kn0(x), ux, uy, Fx, Fy);
+    collide<T>(ph, rho, inc, r, d, ux, uy, Fx, Fy, eps, s, hs);
+    return rho;
 }
 
 template <typename T, int BCX, int BCY>
-__global__ __launch_bounds__(kBlock) void sweep_kernel(State<T> src, State<T> dst, Geom g,
-                                                        Medium m, Physics ph, float s,
-                                                        float inv_s, int bpr)
+__global__ __launch_bounds__(kBlock) void sweep_kernel(const char *src, char *dst, Layout lay,
+                                                        const char *med, MLayout mlay, Geom g,
+                                                        Physics ph, float s, float inv_s, int bpr)
 {
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int y = L / bpr;
-    const int x = (L - y * bpr) * kBlock + threadIdx.x;
-    if (x >= g.nx)
+    const Node nd = node_of(bpr);
+    if (nd.x >= (uint32_t)g.nx)
         return;
-    float dl[9];
-    const float rho = post_stream<T, BCX, BCY>(src, g, m, ph, inv_s, x, y, dl);
-    float jx, jy, ux, uy, Fx, Fy;
-    momentum(dl, jx, jy);
-    const int c = y * g.pitch + x;
-    const float eps = m.eps[c];
-    velocity(ph, rho, jx, jy, eps, m.drag[c], m.kn0[c], ux, uy, Fx, Fy);
+    const Rows R = rows_of<BCY>(src, lay, g, nd.y);
+    const Med md{med_row(med, mlay, nd.y), mlay.slot};
     float hs[9];
-    collide(ph, rho, dl, ux, uy, Fx, Fy, eps, hs);
-    __builtin_nontemporal_store(rho, dst.rho + c);
+    const float rho = update<T, BCX>(R, lay, md, g, ph, s, inv_s, nd.x, hs);
+    const Rsrc out = make_rsrc(dst + (uint64_t)nd.y * lay.row, (uint32_t)lay.row);
+    st_f32(out, nd.x * 4, 0, rho, true);
+    constexpr uint32_t es = sizeof(T);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        Elem<T>::st(dst.h + i * g.plane, c, hs[i], s);
+        Elem<T>::st(out, nd.x * es, lay.h_off + i * lay.h_slot, hs[i]);
 }
 
 // ----------------------------------------------------------- reductions
@@ -129,30 +183,30 @@ __device__ __forceinline__ double block_reduce(double v, double *sh)
 }
 
 template <typename T, int BCX, int BCY>
-__global__ __launch_bounds__(kBlock) void macro_kernel(State<T> src, Geom g, Medium m,
-                                                        Physics ph, float inv_s, int bpr,
+__global__ __launch_bounds__(kBlock) void macro_kernel(const char *src, Layout lay,
+                                                        const char *med, MLayout mlay, Geom g,
+                                                        Physics ph, float s, float inv_s, int bpr,
                                                         float *rho_out, float *ux_out,
                                                         float *uy_out, float *ux_prev,
                                                         float *uy_prev, double *partials)
 {
     __shared__ double sh[kBlock / 64];
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int y = L / bpr;
-    const int x = (L - y * bpr) * kBlock + threadIdx.x;
+    const Node nd = node_of(bpr);
     double v[MAC_SLOTS] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (x < g.nx) {
-        float dl[9];
-        const float rho = post_stream<T, BCX, BCY>(src, g, m, ph, inv_s, x, y, dl);
+    if (nd.x < (uint32_t)g.nx) {
+        const Rows R = rows_of<BCY>(src, lay, g, nd.y);
+        const Med md{med_row(med, mlay, nd.y), mlay.slot};
+        float d[9], inc, r;
+        const float rho = post_stream<T, BCX>(R, lay, md, g, ph, s, inv_s, nd.x, d, inc, r);
         float jx, jy, ux, uy, Fx, Fy;
-        momentum(dl, jx, jy);
-        const int c = y * g.pitch + x;
-        velocity(ph, rho, jx, jy, m.eps[c], m.drag[c], m.kn0[c], ux, uy, Fx, Fy);
-        float r = 0.0f;
-#pragma unroll
-        for (int i = 0; i < 9; ++i)
-            r += dl[i];
+        momentum(d, jx, jy);
+        if (Elem<T>::kScaled) {
+            jx *= inv_s;
+            jy *= inv_s;
+        }
+        velocity(ph, rho, jx, jy, md.eps(nd.x), md.drag(nd.x), md.kn0(nd.x), ux, uy, Fx, Fy);
         const double rp = (double)rho + (double)r;
-        const int o = y * g.nx + x;
+        const uint32_t o = (uint32_t)nd.y * (uint32_t)g.nx + nd.x;
         if (rho_out)
             rho_out[o] = (float)rp;
         if (ux_out)
@@ -164,6 +218,7 @@ __global__ __launch_bounds__(kBlock) void macro_kernel(State<T> src, Geom g, Med
         v[MAC_U2] = (double)ux * ux + (double)uy * uy;
         v[MAC_RHO] = rp;
         if (ux_prev) {
+            const uint32_t c = (uint32_t)nd.y * (uint32_t)g.pitch + nd.x;
             const double dx = (double)ux - ux_prev[c], dy = (double)uy - uy_prev[c];
             v[MAC_DU2] = dx * dx + dy * dy;
             ux_prev[c] = ux;
@@ -172,45 +227,44 @@ __global__ __launch_bounds__(kBlock) void macro_kernel(State<T> src, Geom g, Med
     }
 #pragma unroll
     for (int k = 0; k < MAC_SLOTS; ++k) {
-        const double r = block_reduce<SumOp>(v[k], sh);
+        const double rr = block_reduce<SumOp>(v[k], sh);
         if (threadIdx.x == 0)
-            partials[(int64_t)k * gridDim.x + L] = r;
+            partials[(int64_t)k * gridDim.x + nd.L] = rr;
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void state_sums_kernel(State<T> src, Geom g, float inv_s,
-                                                             int bpr, double *partials)
+__global__ __launch_bounds__(kBlock) void state_sums_kernel(const char *src, Layout lay, Geom g,
+                                                             float inv_s, double *partials,
+                                                             int bpr)
 {
     __shared__ double sh[kBlock / 64];
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int y = L / bpr;
-    const int x = (L - y * bpr) * kBlock + threadIdx.x;
+    const Node nd = node_of(bpr);
     double mass = 0.0, hmax = 0.0, bad = 0.0;
-    if (x < g.nx) {
-        const int c = y * g.pitch + x;
-        const float rho = src.rho[c];
-        double hs = 0.0;
+    if (nd.x < (uint32_t)g.nx) {
+        const Rsrc row = state_row<T>(src, lay, nd.y);
+        const float rho = ld_f32(row, nd.x * 4, 0);
+        double hsum = 0.0;
         bad += isfinite(rho) ? 0.0 : 1.0;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const float h = Elem<T>::ld(src.h + i * g.plane, c, inv_s);
-            hs += (double)h;
-            const double a = fabs((double)h);
+            const float v = Elem<T>::ld(row, nd.x * sizeof(T), lay.h_off + i * lay.h_slot) * inv_s;
+            hsum += (double)v;
+            const double a = fabs((double)v);
             hmax = a > hmax ? a : hmax;
-            bad += isfinite(h) ? 0.0 : 1.0;
+            bad += isfinite(v) ? 0.0 : 1.0;
         }
-        mass = (double)rho + hs;
+        mass = (double)rho + hsum;
     }
     double r = block_reduce<SumOp>(mass, sh);
     if (threadIdx.x == 0)
-        partials[(int64_t)ST_MASS * gridDim.x + L] = r;
+        partials[(int64_t)ST_MASS * gridDim.x + nd.L] = r;
     r = block_reduce<MaxOp>(hmax, sh);
     if (threadIdx.x == 0)
-        partials[(int64_t)ST_HMAX * gridDim.x + L] = r;
+        partials[(int64_t)ST_HMAX * gridDim.x + nd.L] = r;
     r = block_reduce<SumOp>(bad, sh);
     if (threadIdx.x == 0)
-        partials[(int64_t)ST_BAD * gridDim.x + L] = r;
+        partials[(int64_t)ST_BAD * gridDim.x + nd.L] = r;
 }
 
 __global__ __launch_bounds__(kBlock) void finish_kernel(const double *partials, int slots,
@@ -232,113 +286,107 @@ __global__ __launch_bounds__(kBlock) void finish_kernel(const double *partials, 
 
 // ---------------------------------------------------------------- set-up
 
-__global__ __launch_bounds__(kBlock) void fields_kernel(Geom g, float *eps, float *drag,
-                                                         float *kn0, double nu, int bpr,
-                                                         double *partials)
+__global__ __launch_bounds__(kBlock) void fields_kernel(char *med, MLayout mlay, Geom g,
+                                                         double nu, double *partials, int bpr)
 {
     __shared__ double sh[kBlock / 64];
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int y = L / bpr;
-    const int x = (L - y * bpr) * kBlock + threadIdx.x;
+    const Node nd = node_of(bpr);
     double bad = 0.0;
-    if (x < g.nx) {
-        const int c = y * g.pitch + x;
-        const float e = eps[c], k = drag[c], kn = kn0[c];
+    if (nd.x < (uint32_t)g.nx) {
+        const Rsrc row = med_row(med, mlay, nd.y);
+        const float e = ld_f32(row, nd.x * 4, 0), k = ld_f32(row, nd.x * 4, mlay.slot),
+                    kn = ld_f32(row, nd.x * 4, 2 * mlay.slot);
         const bool ok = (e >= 0.0f && e <= 1.0f) && (k > 0.0f) && (kn >= 0.0f) && isfinite(kn);
         bad = ok ? 0.0 : 1.0;
         double d = 0.0;
         if (ok && e > 0.0f && isfinite(k))
             d = (double)e * nu / (double)k;
-        drag[c] = (float)d;
+        st_f32(row, nd.x * 4, mlay.slot, (float)d, false);
     }
     const double r = block_reduce<SumOp>(bad, sh);
     if (threadIdx.x == 0)
-        partials[(int64_t)FLD_BAD * gridDim.x + L] = r;
+        partials[(int64_t)FLD_BAD * gridDim.x + nd.L] = r;
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void init_state_kernel(State<T> dst, Geom g, int ramp,
-                                                             double rho0, double rho_in,
-                                                             double rho_out, float s, int bpr)
+__global__ __launch_bounds__(kBlock) void init_state_kernel(char *dst, Layout lay, Geom g,
+                                                             int ramp, double rho0,
+                                                             double rho_in, double rho_out,
+                                                             float s, int bpr)
 {
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int y = L / bpr;
-    const int x = (L - y * bpr) * kBlock + threadIdx.x;
-    if (x >= g.nx)
+    const Node nd = node_of(bpr);
+    if (nd.x >= (uint32_t)g.nx)
         return;
     double rho = rho0;
     if (ramp)
-        rho = g.nx > 1 ? rho_in + (rho_out - rho_in) * (double)x / (double)(g.nx - 1) : rho_in;
+        rho = g.nx > 1 ? rho_in + (rho_out - rho_in) * (double)nd.x / (double)(g.nx - 1)
+                       : rho_in;
     const float hi = (float)rho;
     const float lo = (float)(rho - (double)hi);
-    const int c = y * g.pitch + x;
-    dst.rho[c] = hi;
+    const Rsrc row = state_row<T>(dst, lay, nd.y);
+    st_f32(row, nd.x * 4, 0, hi, false);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        Elem<T>::st(dst.h + i * g.plane, c, w_of(i) * lo, s);
+        Elem<T>::st(row, nd.x * sizeof(T), lay.h_off + i * lay.h_slot, w_of(i) * lo * s);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void populations_kernel(State<T> src, Geom g, float inv_s,
-                                                              int bpr, double *out)
+__global__ __launch_bounds__(kBlock) void populations_kernel(const char *src, Layout lay,
+                                                              Geom g, float inv_s, double *out,
+                                                              int bpr)
 {
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int y = L / bpr;
-    const int x = (L - y * bpr) * kBlock + threadIdx.x;
-    if (x >= g.nx)
+    const Node nd = node_of(bpr);
+    if (nd.x >= (uint32_t)g.nx)
         return;
-    const int c = y * g.pitch + x;
-    const double rho = src.rho[c];
+    const Rsrc row = state_row<T>(src, lay, nd.y);
+    const double rho = ld_f32(row, nd.x * 4, 0);
     const int64_t n = (int64_t)g.nx * g.ny;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         const double w = i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
-        out[i * n + (int64_t)y * g.nx + x] =
-            w * rho + (double)Elem<T>::ld(src.h + i * g.plane, c, inv_s);
+        const float h = Elem<T>::ld(row, nd.x * sizeof(T), lay.h_off + i * lay.h_slot) * inv_s;
+        out[i * n + (int64_t)nd.y * g.nx + nd.x] = w * rho + (double)h;
     }
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void rescale_kernel(State<T> st, Geom g, float f, int bpr)
+__global__ __launch_bounds__(kBlock) void rescale_kernel(char *st, Layout lay, Geom g, float f,
+                                                          int bpr)
 {
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int y = L / bpr;
-    const int x = (L - y * bpr) * kBlock + threadIdx.x;
-    if (x >= g.nx)
+    const Node nd = node_of(bpr);
+    if (nd.x >= (uint32_t)g.nx)
         return;
-    const int c = y * g.pitch + x;
+    const Rsrc row = state_row<T>(st, lay, nd.y);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        T *p = st.h + i * g.plane;
-        Elem<T>::st(p, c, Elem<T>::ld(p, c, 1.0f), f);
+        const uint32_t so = lay.h_off + i * lay.h_slot;
+        Elem<T>::st(row, nd.x * sizeof(T), so, Elem<T>::ld(row, nd.x * sizeof(T), so) * f);
     }
 }
 
 // ------------------------------------------------------------- launchers
 
-template <typename T> static State<T> typed(const StateV &s)
-{
-    return State<T>{s.rho, static_cast<T *>(s.h)};
-}
-
 template <typename T, int BCX, int BCY>
-static hipError_t sweep_t(const StateV &src, const StateV &dst, const Geom &g, const Medium &m,
-                          const Physics &ph, float s, float inv_s, hipStream_t st)
+static hipError_t sweep_t(const char *src, char *dst, const Layout &lay, const char *med,
+                          const MLayout &mlay, const Geom &g, const Physics &ph, float s,
+                          float inv_s, hipStream_t st)
 {
     const Launch l = launch_of(g);
-    hipLaunchKernelGGL((sweep_kernel<T, BCX, BCY>), dim3(l.blocks), dim3(kBlock), 0, st,
-                       typed<T>(src), typed<T>(dst), g, m, ph, s, inv_s, l.blocks_per_row);
+    hipLaunchKernelGGL((sweep_kernel<T, BCX, BCY>), dim3(l.blocks), dim3(kBlock), 0, st, src,
+                       dst, lay, med, mlay, g, ph, s, inv_s, l.blocks_per_row);
     return hipGetLastError();
 }
 
 template <typename T, int BCX, int BCY>
-static hipError_t macro_t(const StateV &src, const Geom &g, const Medium &m, const Physics &ph,
-                          float inv_s, float *rho_out, float *ux_out, float *uy_out,
-                          float *ux_prev, float *uy_prev, double *partials, hipStream_t st)
+static hipError_t macro_t(const char *src, const Layout &lay, const char *med,
+                          const MLayout &mlay, const Geom &g, const Physics &ph, float s,
+                          float inv_s,
+                          float *rho_out, float *ux_out, float *uy_out, float *ux_prev,
+                          float *uy_prev, double *partials, hipStream_t st)
 {
     const Launch l = launch_of(g);
-    hipLaunchKernelGGL((macro_kernel<T, BCX, BCY>), dim3(l.blocks), dim3(kBlock), 0, st,
-                       typed<T>(src), g, m, ph, inv_s, l.blocks_per_row, rho_out, ux_out,
+    hipLaunchKernelGGL((macro_kernel<T, BCX, BCY>), dim3(l.blocks), dim3(kBlock), 0, st, src,
+                       lay, med, mlay, g, ph, s, inv_s, l.blocks_per_row, rho_out, ux_out,
                        uy_out, ux_prev, uy_prev, partials);
     return hipGetLastError();
 }
@@ -363,47 +411,53 @@ static hipError_t macro_t(const StateV &src, const Geom &g, const Medium &m, con
     default: return hipErrorInvalidValue;                                                    \
     }
 
-hipError_t launch_sweep(int storage, int bcx, int bcy, const StateV &src, const StateV &dst,
-                        const Geom &g, const Medium &m, const Physics &ph, float s, float inv_s,
-                        hipStream_t st)
+// Launch KERNEL<T> for the storage type over the lattice grid; the kernel's
+// last parameter is the blocks-per-row count.
+#define LBK_LAUNCH_T(KERNEL, ...)                                                            \
+    do {                                                                                     \
+        const Launch l = launch_of(g);                                                       \
+        switch (storage) {                                                                   \
+        case 0:                                                                              \
+            hipLaunchKernelGGL(KERNEL<float>, dim3(l.blocks), dim3(kBlock), 0, st,           \
+                               __VA_ARGS__, l.blocks_per_row);                              \
+            break;                                                                           \
+        case 1:                                                                              \
+            hipLaunchKernelGGL(KERNEL<__half>, dim3(l.blocks), dim3(kBlock), 0, st,          \
+                               __VA_ARGS__, l.blocks_per_row);                              \
+            break;                                                                           \
+        case 2:                                                                              \
+            hipLaunchKernelGGL(KERNEL<__hip_bfloat16>, dim3(l.blocks), dim3(kBlock), 0, st,  \
+                               __VA_ARGS__, l.blocks_per_row);                              \
+            break;                                                                           \
+        default:                                                                             \
+            return hipErrorInvalidValue;                                                     \
+        }                                                                                    \
+    } while (0)
+
+hipError_t launch_sweep(int storage, int bcx, int bcy, const char *src, char *dst,
+                        const Layout &lay, const char *med, const MLayout &mlay, const Geom &g,
+                        const Physics &ph, float s, float inv_s, hipStream_t st)
 {
     if (bcy < 0 || bcy > 1)
         return hipErrorInvalidValue;
-    LBK_DISPATCH(sweep_t, src, dst, g, m, ph, s, inv_s, st)
+    LBK_DISPATCH(sweep_t, src, dst, lay, med, mlay, g, ph, s, inv_s, st)
 }
 
-hipError_t launch_macro(int storage, int bcx, int bcy, const StateV &src, const Geom &g,
-                        const Medium &m, const Physics &ph, float inv_s, float *rho_out,
-                        float *ux_out, float *uy_out, float *ux_prev, float *uy_prev,
-                        double *partials, hipStream_t st)
+hipError_t launch_macro(int storage, int bcx, int bcy, const char *src, const Layout &lay,
+                        const char *med, const MLayout &mlay, const Geom &g, const Physics &ph,
+                        float s, float inv_s, float *rho_out, float *ux_out, float *uy_out,
+                        float *ux_prev, float *uy_prev, double *partials, hipStream_t st)
 {
     if (bcy < 0 || bcy > 1)
         return hipErrorInvalidValue;
-    LBK_DISPATCH(macro_t, src, g, m, ph, inv_s, rho_out, ux_out, uy_out, ux_prev, uy_prev,
-                 partials, st)
+    LBK_DISPATCH(macro_t, src, lay, med, mlay, g, ph, s, inv_s, rho_out, ux_out, uy_out,
+                 ux_prev, uy_prev, partials, st)
 }
 
-hipError_t launch_state_sums(int storage, const StateV &src, const Geom &g, float inv_s,
-                             double *partials, hipStream_t st)
+hipError_t launch_state_sums(int storage, const char *src, const Layout &lay, const Geom &g,
+                             float inv_s, double *partials, hipStream_t st)
 {
-    const Launch l = launch_of(g);
-    switch (storage) {
-    case 0:
-        hipLaunchKernelGGL(state_sums_kernel<float>, dim3(l.blocks), dim3(kBlock), 0, st,
-                           typed<float>(src), g, inv_s, l.blocks_per_row, partials);
-        break;
-    case 1:
-        hipLaunchKernelGGL(state_sums_kernel<__half>, dim3(l.blocks), dim3(kBlock), 0, st,
-                           typed<__half>(src), g, inv_s, l.blocks_per_row, partials);
-        break;
-    case 2:
-        hipLaunchKernelGGL(state_sums_kernel<__hip_bfloat16>, dim3(l.blocks), dim3(kBlock), 0,
-                           st, typed<__hip_bfloat16>(src), g, inv_s, l.blocks_per_row,
-                           partials);
-        break;
-    default:
-        return hipErrorInvalidValue;
-    }
+    LBK_LAUNCH_T(state_sums_kernel, src, lay, g, inv_s, partials);
     return hipGetLastError();
 }
 
@@ -415,85 +469,35 @@ hipError_t launch_finish(const double *partials, int slots, int blocks, unsigned
     return hipGetLastError();
 }
 
-hipError_t launch_fields(const Geom &g, float *eps, float *drag, float *kn0, double nu,
+hipError_t launch_fields(char *med, const MLayout &mlay, const Geom &g, double nu,
                          double *partials, hipStream_t st)
 {
     const Launch l = launch_of(g);
-    hipLaunchKernelGGL(fields_kernel, dim3(l.blocks), dim3(kBlock), 0, st, g, eps, drag, kn0,
-                       nu, l.blocks_per_row, partials);
+    hipLaunchKernelGGL(fields_kernel, dim3(l.blocks), dim3(kBlock), 0, st, med, mlay, g, nu,
+                       partials, l.blocks_per_row);
     return hipGetLastError();
 }
 
-hipError_t launch_init_state(int storage, const StateV &dst, const Geom &g, int ramp,
+hipError_t launch_init_state(int storage, char *dst, const Layout &lay, const Geom &g, int ramp,
                              double rho0, double rho_in, double rho_out, float s,
                              hipStream_t st)
 {
-    const Launch l = launch_of(g);
-    switch (storage) {
-    case 0:
-        hipLaunchKernelGGL(init_state_kernel<float>, dim3(l.blocks), dim3(kBlock), 0, st,
-                           typed<float>(dst), g, ramp, rho0, rho_in, rho_out, s,
-                           l.blocks_per_row);
-        break;
-    case 1:
-        hipLaunchKernelGGL(init_state_kernel<__half>, dim3(l.blocks), dim3(kBlock), 0, st,
-                           typed<__half>(dst), g, ramp, rho0, rho_in, rho_out, s,
-                           l.blocks_per_row);
-        break;
-    case 2:
-        hipLaunchKernelGGL(init_state_kernel<__hip_bfloat16>, dim3(l.blocks), dim3(kBlock), 0,
-                           st, typed<__hip_bfloat16>(dst), g, ramp, rho0, rho_in, rho_out, s,
-                           l.blocks_per_row);
-        break;
-    default:
-        return hipErrorInvalidValue;
-    }
+    LBK_LAUNCH_T(init_state_kernel, dst, lay, g, ramp, rho0, rho_in, rho_out, s);
     return hipGetLastError();
 }
 
-hipError_t launch_populations(int storage, const StateV &src, const Geom &g, float inv_s,
-                              double *out, hipStream_t st)
+hipError_t launch_populations(int storage, const char *src, const Layout &lay, const Geom &g,
+                              float inv_s, double *out, hipStream_t st)
 {
-    const Launch l = launch_of(g);
-    switch (storage) {
-    case 0:
-        hipLaunchKernelGGL(populations_kernel<float>, dim3(l.blocks), dim3(kBlock), 0, st,
-                           typed<float>(src), g, inv_s, l.blocks_per_row, out);
-        break;
-    case 1:
-        hipLaunchKernelGGL(populations_kernel<__half>, dim3(l.blocks), dim3(kBlock), 0, st,
-                           typed<__half>(src), g, inv_s, l.blocks_per_row, out);
-        break;
-    case 2:
-        hipLaunchKernelGGL(populations_kernel<__hip_bfloat16>, dim3(l.blocks), dim3(kBlock), 0,
-                           st, typed<__hip_bfloat16>(src), g, inv_s, l.blocks_per_row, out);
-        break;
-    default:
-        return hipErrorInvalidValue;
-    }
+    LBK_LAUNCH_T(populations_kernel, src, lay, g, inv_s, out);
     return hipGetLastError();
 }
 
-hipError_t launch_rescale(int storage, const StateV &s_, const Geom &g, int k, hipStream_t st)
+hipError_t launch_rescale(int storage, char *state, const Layout &lay, const Geom &g, int k,
+                          hipStream_t st)
 {
-    const Launch l = launch_of(g);
     const float f = ldexpf(1.0f, k);
-    switch (storage) {
-    case 0:
-        hipLaunchKernelGGL(rescale_kernel<float>, dim3(l.blocks), dim3(kBlock), 0, st,
-                           typed<float>(s_), g, f, l.blocks_per_row);
-        break;
-    case 1:
-        hipLaunchKernelGGL(rescale_kernel<__half>, dim3(l.blocks), dim3(kBlock), 0, st,
-                           typed<__half>(s_), g, f, l.blocks_per_row);
-        break;
-    case 2:
-        hipLaunchKernelGGL(rescale_kernel<__hip_bfloat16>, dim3(l.blocks), dim3(kBlock), 0, st,
-                           typed<__hip_bfloat16>(s_), g, f, l.blocks_per_row);
-        break;
-    default:
-        return hipErrorInvalidValue;
-    }
+    LBK_LAUNCH_T(rescale_kernel, state, lay, g, f);
     return hipGetLastError();
 }
 
