@@ -17,8 +17,10 @@ host (``cpu_baseline``).
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -36,8 +38,31 @@ ALG_BYTES = {"f32": 84, "f16": 48, "bf16": 48}
 LAYOUT_BYTES = {"f32": 92, "f16": 56, "bf16": 56}
 
 
+PROFILE = os.path.join(ROOT, "profiles", "sweep_discs4096.md")
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(storage, ms_per_step, nodes):
+    """HBM traffic of one sweep launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what it
+    reads for a plain copy of known size), as GB/s over this run's measured
+    launch time.  None if the summary is missing, covers another lattice, or
+    was taken on kernel sources that have changed since."""
+    try:
+        text = open(PROFILE).read()
+        blob = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        cur = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read()
+                                      for f in blob["sources"])).hexdigest()[:16]
+        if cur != blob["source_hash"] or blob["nodes"] != nodes:
+            return None, None
+        pd = blob["per_dispatch"][storage]
+        byts = (pd["fetch_kib"] * blob["fetch_scale"] + pd["write_kib"] * blob["write_scale"]) * 1024
+        return byts / (ms_per_step * 1e-3) / 1e9, byts
+    except (OSError, KeyError, AttributeError, ValueError):
+        return None, None
 
 
 def time_storage(case, storage, steps, warmup, device):
@@ -154,13 +179,15 @@ def main():
     head = runs.get("f32") or next(iter(runs.values()))
     st = head["storage"]
     achieved = head["alg_GBps"]
+    traffic, traffic_bytes = measured_traffic(st, head["ms_per_step"], case.nodes)
     roof = {
         "bound": "hbm",
         "achieved": achieved,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": achieved / HBM_PEAK_GBS,
-        "traffic": None,
+        "traffic": traffic,
+        "traffic_bytes_per_launch": traffic_bytes,
         "kernel": f"sweep_kernel<{st}> (pressure x, periodic y)",
         "bytes_per_node": ALG_BYTES[st],
         "layout_bytes_per_node": LAYOUT_BYTES[st],
