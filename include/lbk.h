@@ -136,6 +136,51 @@ lbk_status lbk_state_size(const lbk_lattice *lat, size_t *bytes);
 lbk_status lbk_save_state(lbk_lattice *lat, void *dst);
 lbk_status lbk_load_state(lbk_lattice *lat, const void *src);
 
+/* ---------------------------------------------------------------------
+ * Gradients (reverse mode through the discrete time stepping).
+ *
+ * J is a scalar read-out of the state after n steps; the gradient is
+ * dJ / d ln k(x) for every node, with eps, kn0 and the starting state held
+ * fixed.  The reverse sweep is the exact transpose of the discrete map
+ * (pull, pressure-column override, collide of Eqs. 12, 14, 15, 17, 8, 3,
+ * 6-7 with the local Kn), evaluated along the forward trajectory, which
+ * is recomputed from checkpoints:
+ *   - lbk_adjoint_forward runs the n steps (advancing the lattice exactly
+ *     as lbk_step would) and stores the state every ckpt_every steps;
+ *   - lbk_adjoint_backward recomputes each checkpoint segment (keeping
+ *     inner checkpoints every hist_len steps when hist_len < ckpt_every),
+ *     records the per-step linearisation point (rho, j: 12 B per node and
+ *     step, hist_len steps at a time) and runs the reverse steps.
+ * Cost: backward ~ 2 forward sweeps (one-level, hist_len == ckpt_every)
+ * or ~ 3 (two-level) plus one reverse sweep per step.
+ * The Forchheimer term is not differentiated (f_eps must be 0).
+ * --------------------------------------------------------------------- */
+typedef enum lbk_objective {
+    LBK_OBJ_PERMEABILITY = 0, /* the global permeability of
+                                 lbk_apparent_permeability (Sec. IV.A) */
+    LBK_OBJ_OUTLET_FLUX = 1   /* sum over column x = nx-1 of rho u_x */
+} lbk_objective;
+
+/* Device workspace bytes for a gradient over n_steps with checkpoints every
+ * ckpt_every steps and a history of hist_len steps (1 <= hist_len <=
+ * ckpt_every; hist_len == ckpt_every is the one-level scheme). */
+lbk_status lbk_adjoint_workspace_size(const lbk_lattice *lat, int64_t n_steps,
+                                      int64_t ckpt_every, int64_t hist_len, size_t *bytes);
+
+/* Run n_steps forward from the current state, storing checkpoints in the
+ * caller's device workspace (256-byte aligned, ws_bytes >=
+ * lbk_adjoint_workspace_size), and return J (host double; synchronizes).
+ * The lattice ends at t + n_steps.  The FP16 scale is held fixed and
+ * check_every is not applied during these steps. */
+lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64_t n_steps,
+                               int64_t ckpt_every, int64_t hist_len, void *ws, size_t ws_bytes,
+                               double *J);
+
+/* Gradient of the J of the last lbk_adjoint_forward on this handle (same
+ * workspace, no lbk_step or load in between) into dJ_dlnk: a device buffer
+ * of [ny][nx] float32.  Leaves the lattice state untouched. */
+lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws_bytes, float *dJ_dlnk);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *lbk_last_error(void);
 

@@ -9,11 +9,11 @@ synthetic media.
 """
 from . import inputs  # noqa: F401
 
-__all__ = ["Lattice", "inputs", "make_desc", "workspace_bytes"]
+__all__ = ["Lattice", "ApparentPermeability", "inputs", "make_desc", "workspace_bytes"]
 
 
 def __getattr__(name):
-    if name in ("Lattice", "make_desc", "workspace_bytes"):
+    if name in ("Lattice", "ApparentPermeability", "make_desc", "workspace_bytes"):
         from . import lattice
         return getattr(lattice, name)
     raise AttributeError(name)

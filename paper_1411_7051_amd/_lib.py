@@ -21,6 +21,7 @@ STATUS = {
     -5: "LBK_ERR_UNSUPPORTED",
 }
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+OBJECTIVE = {"k_app": 0, "q_out": 1}
 
 
 class LbkError(RuntimeError):
@@ -64,6 +65,12 @@ _SIG = {
     "lbk_state_size": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "lbk_save_state": (ctypes.c_int, [_P, _P]),
     "lbk_load_state": (ctypes.c_int, [_P, _P]),
+    "lbk_adjoint_workspace_size": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64,
+                                                  ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
+    "lbk_adjoint_forward": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
+                                           ctypes.c_int64, _P, ctypes.c_size_t,
+                                           ctypes.POINTER(ctypes.c_double)]),
+    "lbk_adjoint_backward": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "lbk_last_error": (ctypes.c_char_p, []),
 }
 

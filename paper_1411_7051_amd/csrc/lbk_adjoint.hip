@@ -1,0 +1,421 @@
+// lbk_adjoint.hip -- reverse-mode (discrete adjoint) sweep of the Klinkenberg
+// lattice Boltzmann step, for gradients of a scalar read-out J of the state
+// after N steps with respect to the log-permeability field ln k(x).
+//
+// The forward step n is  f^n = B(P(S_{n-1})),  S_n = C(f^n; ln k)  with P the
+// pull (a permutation, bounce-back included), B the pressure-column override
+// and C the per-node BGK/Guo collide (Eqs. 12, 14, 15, 17, 8, 3, 6-7).
+// Given mu_n = dJ/dS_n, one reverse step computes
+//   lam_f(x) = (dC/df)(x)^T mu_n(x)          (local, 9 -> 9)
+//   grad(x) += (dC/d ln k)(x)^T mu_n(x)
+//   mu_{n-1} = P^T B^T lam_f                 (the push: each source slot of
+//                                             S_{n-1} has exactly one reader)
+// C depends on f only through rho = sum f and j = sum f e, so
+//   lam_f_k = (1 - omega) mu_k + G_rho + e_k . G_j
+// with G_rho, G_j the total derivatives of Psi = sum_i mu_i (omega f^eq_i + F_i)
+// through u(rho, j, ln k), F = -A u + eps G, A = eps nu / (k f_c(Kn)) and
+// Kn = kn0 rho_ref / rho; the linearisation point (rho, j) of every step is
+// the history written by the recomputing forward sweep.  The read-out of J
+// (global permeability or outlet flux) is the same local map with Psi the
+// node's share of J and no (1 - omega) mu term.
+//
+// Pressure columns: the boundary node's populations are a function of its
+// neighbour's (non-equilibrium extrapolation), so the thread of the
+// neighbouring column also carries the boundary node's adjoint and adds
+// B^T to its own; boundary threads only clear the adjoint slots whose
+// forward values were discarded.
+//
+// Layouts (row blocks, `pitch` elements per slot, FP32): adjoint state
+// [y][9][pitch]; history [y][3][pitch] = (rho, jx, jy); gradient FP64
+// [y][pitch].  The Forchheimer term is not differentiated (the host
+// rejects f_eps != 0).
+#include "lbk_adjoint.h"
+
+namespace lbk {
+
+namespace {
+
+__device__ __forceinline__ int xcd_remap_a(int b, int nb)
+{
+    const int q = nb >> 3, r = nb & 7;
+    const int j = b & 7, idx = b >> 3;
+    return j * q + (j < r ? j : r) + idx;
+}
+
+// Forward quantities of one node's velocity solve, as in velocity() of the
+// sweep, plus what the adjoint needs: dA/drho through the local Kn.
+struct NodeFwd {
+    float rho, rinv, jx, jy, eps, ie, A, g, ux, uy, Fx, Fy, dA_drho;
+    bool solid;
+};
+
+__device__ __forceinline__ NodeFwd node_fwd(const Physics &ph, float rho, float jx, float jy,
+                                            float eps, float drag, float kn0)
+{
+    NodeFwd n;
+    n.rho = rho;
+    n.jx = jx;
+    n.jy = jy;
+    n.eps = eps;
+    n.solid = !(eps > 0.0f);
+    n.ie = n.solid ? 0.0f : 1.0f / eps;
+    n.rinv = 1.0f / rho;
+    const float kn = ph.kn_local ? kn0 * (ph.rho_ref * n.rinv) : kn0;
+    const float t = __builtin_amdgcn_exp2f(0.4348f * __builtin_amdgcn_logf(kn)); // Kn^0.4348
+    const float a = t + 0.170f;
+    const float num = a * (1.0f + kn);
+    const float den = (a + 1.358f * t * kn) * (1.0f + 5.0f * kn); // f_c = den / num
+    const float dn = drag * num;
+    const float R2 = 2.0f / (2.0f * den + dn);
+    n.g = den * R2;     // 1 / (1 + A/2)
+    n.A = dn / den;     // drag / f_c
+    const float vx = jx * n.rinv + 0.5f * eps * ph.gx;
+    const float vy = jy * n.rinv + 0.5f * eps * ph.gy;
+    n.ux = n.solid ? 0.0f : n.g * vx;
+    n.uy = n.solid ? 0.0f : n.g * vy;
+    n.Fx = n.solid ? -2.0f * jx * n.rinv : eps * ph.gx - n.A * n.ux;
+    n.Fy = n.solid ? -2.0f * jy * n.rinv : eps * ph.gy - n.A * n.uy;
+    // f_c'(Kn) = P1' P2 + P1 P2' with P1 = 1 + alpha Kn = (a + 1.358 t Kn)/a,
+    // P2 = (1 + 5 Kn)/(1 + Kn); P1' = 1.358 t (t + 1.4348 * 0.170)/a^2,
+    // P2' = 4/(1 + Kn)^2.  dA/drho = A Kn f_c' / (f_c rho) (Kn ~ 1/rho).
+    float dA = 0.0f;
+    if (ph.kn_local && kn > 0.0f) {
+        const float P1 = (a + 1.358f * t * kn) / a, P2 = (1.0f + 5.0f * kn) / (1.0f + kn);
+        const float P1d = 1.358f * t * (t + 0.243916f) / (a * a);
+        const float P2d = 4.0f / ((1.0f + kn) * (1.0f + kn));
+        const float fc = P1 * P2;
+        dA = n.A * kn * (P1d * P2 + P1 * P2d) / (fc * rho);
+    }
+    n.dA_drho = dA;
+    return n;
+}
+
+// w-weighted moments of a 9-vector: L0 = sum w l, L1 = sum w l e,
+// L2 = sum w l e e (symmetric; xx, yy, xy).
+struct Mom {
+    float m0, m1x, m1y, mxx, myy, mxy;
+};
+__device__ __forceinline__ Mom moments(const float (&l)[9])
+{
+    Mom m{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const float wl = w_of(i) * l[i];
+        const int ex = ex_of(i), ey = ey_of(i);
+        m.m0 += wl;
+        m.m1x += ex * wl;
+        m.m1y += ey * wl;
+        m.mxx += (ex * ex) * wl;
+        m.myy += (ey * ey) * wl;
+        m.mxy += (ex * ey) * wl;
+    }
+    return m;
+}
+
+// Chain rule from the partials of a node function Psi(rho, u, F) (explicit
+// Psi_rho, vectors Psi_u, Psi_F) to its total derivatives with respect to
+// rho, j and ln k through the node's velocity solve.
+struct Grads {
+    float rho, jx, jy, lnk;
+};
+__device__ __forceinline__ Grads chain(const NodeFwd &n, float Pr, float Pux, float Puy,
+                                       float PFx, float PFy)
+{
+    Grads G;
+    if (n.solid) {
+        // u = 0, F = -2 j / rho
+        G.jx = -2.0f * n.rinv * PFx;
+        G.jy = -2.0f * n.rinv * PFy;
+        G.rho = Pr + 2.0f * n.rinv * n.rinv * (PFx * n.jx + PFy * n.jy);
+        G.lnk = 0.0f;
+        return G;
+    }
+    // u = g v, v = j / rho + eps G / 2, g = 1 / (1 + A/2), F = -A u + eps G
+    const float Tx = Pux - n.A * PFx, Ty = Puy - n.A * PFy; // dPsi/du with F(u)
+    const float GA = -0.5f * n.g * (Tx * n.ux + Ty * n.uy) - (PFx * n.ux + PFy * n.uy);
+    G.jx = n.g * n.rinv * Tx;
+    G.jy = n.g * n.rinv * Ty;
+    G.rho = Pr - (G.jx * n.jx + G.jy * n.jy) * n.rinv + GA * n.dA_drho;
+    G.lnk = -n.A * GA; // dA / d ln k = -A
+    return G;
+}
+
+// Adjoint of the collide at one node: lam_f from mu (the adjoint of the
+// post-collision populations) and the sensitivity to ln k.
+__device__ __forceinline__ Grads collide_adj(const Physics &ph, const NodeFwd &n,
+                                             const float (&mu)[9], float (&lf)[9])
+{
+    const Mom L = moments(mu);
+    const float om = ph.omega, cg = ph.guo, ie = n.ie;
+    const float ux = n.ux, uy = n.uy, Fx = n.Fx, Fy = n.Fy;
+    const float L2ux = L.mxx * ux + L.mxy * uy, L2uy = L.mxy * ux + L.myy * uy;
+    const float L2Fx = L.mxx * Fx + L.mxy * Fy, L2Fy = L.mxy * Fx + L.myy * Fy;
+    const float uu = ux * ux + uy * uy, uF = ux * Fx + uy * Fy;
+    const float L1u = L.m1x * ux + L.m1y * uy, L1F = L.m1x * Fx + L.m1y * Fy;
+    // Psi = rho { omega [L0 + 3 L1.u + 4.5/eps u.L2.u - 1.5/eps |u|^2 L0]
+    //           + g [3 L1.F + 9/eps u.L2.F - 3/eps (u.F) L0] }
+    const float Peq = L.m0 + 3.0f * L1u + 4.5f * ie * (ux * L2ux + uy * L2uy) - 1.5f * ie * uu * L.m0;
+    const float Pf = 3.0f * L1F + 9.0f * ie * (ux * L2Fx + uy * L2Fy) - 3.0f * ie * uF * L.m0;
+    const float Pr = om * Peq + cg * Pf; // Psi / rho
+    const float rho = n.rho;
+    const float Pux = rho * (om * (3.0f * L.m1x + 9.0f * ie * L2ux - 3.0f * ie * L.m0 * ux) +
+                             cg * (9.0f * ie * L2Fx - 3.0f * ie * L.m0 * Fx));
+    const float Puy = rho * (om * (3.0f * L.m1y + 9.0f * ie * L2uy - 3.0f * ie * L.m0 * uy) +
+                             cg * (9.0f * ie * L2Fy - 3.0f * ie * L.m0 * Fy));
+    const float PFx = rho * cg * (3.0f * L.m1x + 9.0f * ie * L2ux - 3.0f * ie * L.m0 * ux);
+    const float PFy = rho * cg * (3.0f * L.m1y + 9.0f * ie * L2uy - 3.0f * ie * L.m0 * uy);
+    const Grads G = chain(n, Pr, Pux, Puy, PFx, PFy);
+    const float keep = 1.0f - om;
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        lf[i] = keep * mu[i] + G.rho + ex_of(i) * G.jx + ey_of(i) * G.jy;
+    return G;
+}
+
+// Adjoint of the read-out share of J at one node, J_x = a1 rho u_x + a2 u_x.
+__device__ __forceinline__ Grads readout_adj(const NodeFwd &n, float a1, float a2,
+                                             float (&lf)[9])
+{
+    Grads G{0.0f, 0.0f, 0.0f, 0.0f};
+    if (!n.solid && (a1 != 0.0f || a2 != 0.0f))
+        G = chain(n, a1 * n.ux, a1 * n.rho + a2, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        lf[i] = G.rho + ex_of(i) * G.jx + ey_of(i) * G.jy;
+    return G;
+}
+
+// Adjoint of the pressure-column override
+//   f_i(b) = f_eq_i(rho_b, u_n; eps_b) + f_i(n) - f_eq_i(rho_n, u_n; eps_n)
+// with respect to the neighbour's post-stream populations f(n) (through
+// f(n) itself, rho_n, j_n and u_n(rho_n, j_n, ln k_n)).  Adds to lfn and
+// returns the neighbour's ln k sensitivity.
+__device__ __forceinline__ float nee_adj(const NodeFwd &n, float rho_b, float eps_b,
+                                         const float (&lb)[9], float (&lfn)[9])
+{
+    const Mom M = moments(lb);
+    const float ux = n.ux, uy = n.uy;
+    const float M2ux = M.mxx * ux + M.mxy * uy, M2uy = M.mxy * ux + M.myy * uy;
+    const float uu = ux * ux + uy * uy;
+    // Phi(rho, eps) = sum_i lb_i f_eq_i = rho [M0 + 3 M1.u + 4.5/eps u.M2.u
+    //                 - 1.5/eps |u|^2 M0]; for eps = 0 it is rho M0.
+    const bool sb = !(eps_b > 0.0f);
+    const float ieb = sb ? 0.0f : 1.0f / eps_b, ien = n.ie;
+    const float dbx = sb ? 0.0f : rho_b * (3.0f * M.m1x + 9.0f * ieb * M2ux - 3.0f * ieb * M.m0 * ux);
+    const float dby = sb ? 0.0f : rho_b * (3.0f * M.m1y + 9.0f * ieb * M2uy - 3.0f * ieb * M.m0 * uy);
+    const float dnx = n.solid ? 0.0f : n.rho * (3.0f * M.m1x + 9.0f * ien * M2ux - 3.0f * ien * M.m0 * ux);
+    const float dny = n.solid ? 0.0f : n.rho * (3.0f * M.m1y + 9.0f * ien * M2uy - 3.0f * ien * M.m0 * uy);
+    const float phin_over_rho =
+        n.solid ? M.m0
+                : M.m0 + 3.0f * (M.m1x * ux + M.m1y * uy) + 4.5f * ien * (ux * M2ux + uy * M2uy) -
+                      1.5f * ien * uu * M.m0;
+    // Psi = Phi_b(u) - Phi_n(rho_n, u): explicit d/drho_n = -Phi_n / rho_n,
+    // d/du = Hu; no direct force dependence.
+    const Grads G = chain(n, -phin_over_rho, dbx - dnx, dby - dny, 0.0f, 0.0f);
+    float gx = G.jx, gy = G.jy, gr = G.rho, gl = G.lnk;
+    if (n.solid) { // u_n = 0 does not move with f(n)
+        gx = gy = gl = 0.0f;
+        gr = -phin_over_rho;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        lfn[i] += lb[i] + gr + ex_of(i) * gx + ey_of(i) * gy;
+    return gl;
+}
+
+__device__ __forceinline__ Rsrc rsrc_row(const void *base, uint64_t row_bytes, int y)
+{
+    return make_rsrc(static_cast<const char *>(base) + (uint64_t)y * row_bytes,
+                     (uint32_t)row_bytes);
+}
+
+} // namespace
+
+// One reverse step (or, with terminal != 0, the read-out of J).
+//   mu_in  [y][9][pitch]  adjoint of S_n (ignored when terminal)
+//   mu_out [y][9][pitch]  adjoint of S_{n-1} (written by push)
+//   hist   [y][3][pitch]  (rho, jx, jy) of step n's post-stream populations
+//   grad   [y][pitch]     FP64, accumulates d J / d ln k
+// Objective: J = sum_x a1(x) rho u_x + a2 u_x with a1(x) = a1 (all nodes,
+// or only column nx-1 when outlet != 0) and a2 uniform.
+template <int BCX, int BCY>
+__global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float *mu_out,
+                                                       const float *hist, const char *med,
+                                                       MLayout mlay, double *grad, Geom g,
+                                                       Physics ph, int terminal, float a1,
+                                                       float a2, int outlet, int bpr)
+{
+    const int L = xcd_remap_a(blockIdx.x, gridDim.x);
+    const int y = L / bpr;
+    const uint32_t x = (uint32_t)(L - y * bpr) * 256 + threadIdx.x;
+    if (x >= (uint32_t)g.nx)
+        return;
+    const uint32_t nx = (uint32_t)g.nx;
+    const uint64_t lrow = 9ull * g.pitch * 4, hrow = 3ull * g.pitch * 4;
+    const uint32_t slot = (uint32_t)g.pitch * 4; // bytes per FP32 slot
+    const Rsrc hr = rsrc_row(hist, hrow, y);
+    const Rsrc mr = make_rsrc(med + (uint64_t)y * mlay.row, (uint32_t)mlay.row);
+    const Rsrc lin = rsrc_row(mu_in, lrow, y);
+    double *grow_p = grad + (uint64_t)y * g.pitch;
+
+    auto load_node = [&](uint32_t xx) {
+        const float rho = ld_f32(hr, xx * 4, 0), jx = ld_f32(hr, xx * 4, slot),
+                    jy = ld_f32(hr, xx * 4, 2 * slot);
+        return node_fwd(ph, rho, jx, jy, ld_f32(mr, xx * 4, 0), ld_f32(mr, xx * 4, mlay.slot),
+                        ld_f32(mr, xx * 4, 2 * mlay.slot));
+    };
+    auto node_adj = [&](const NodeFwd &n, uint32_t xx, float (&lf)[9]) {
+        if (terminal) {
+            const float a = (!outlet || xx == nx - 1) ? a1 : 0.0f;
+            return readout_adj(n, a, a2, lf);
+        }
+        float mu[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            mu[i] = ld_f32(lin, xx * 4, i * slot);
+        return collide_adj(ph, n, mu, lf);
+    };
+    // each gradient entry has exactly one writer per launch
+    auto add_grad = [&](uint32_t xx, float v) { grow_p[xx] += (double)v; };
+
+    // rows the push writes into: source of direction i is (x - e_ix, y - e_iy)
+    int ym = y - 1, yp = y + 1;
+    bool wym = false, wyp = false;
+    if (BCY == BC_PERIODIC) {
+        ym = (y == 0) ? g.ny - 1 : ym;
+        yp = (y == g.ny - 1) ? 0 : yp;
+    } else {
+        wym = (y == 0);
+        wyp = (y == g.ny - 1);
+        ym = wym ? y : ym;
+        yp = wyp ? y : yp;
+    }
+    const Rsrc orow[3] = {rsrc_row(mu_out, lrow, ym), rsrc_row(mu_out, lrow, y),
+                          rsrc_row(mu_out, lrow, yp)};
+
+    float lf[9];
+    const bool bnode = (BCX == BC_PRESSURE) && (x == 0 || x == nx - 1);
+    if (bnode) {
+        // forward values pulled into this node were discarded: clear the
+        // slots it would push to, and the slots whose destination lies
+        // outside the lattice
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            lf[i] = 0.0f;
+    } else {
+        const NodeFwd n = load_node(x);
+        const Grads G = node_adj(n, x, lf);
+        float gl = G.lnk;
+        if (BCX == BC_PRESSURE && (x == 1 || x == nx - 2)) {
+            // carry the boundary node next door (x = 0 or nx-1)
+            const uint32_t xb = (x == 1) ? 0 : nx - 1;
+            {
+                const NodeFwd b = load_node(xb);
+                float lb[9];
+                const Grads Gb = node_adj(b, xb, lb);
+                add_grad(xb, Gb.lnk);
+                gl += nee_adj(n, b.rho, b.eps, lb, lf);
+            }
+            if (nx == 3) {
+                // x = 1 is the neighbour of both columns: the outlet too
+                const NodeFwd b = load_node(2);
+                float lb[9];
+                const Grads Gb = node_adj(b, 2, lb);
+                add_grad(2, Gb.lnk);
+                gl += nee_adj(n, b.rho, b.eps, lb, lf);
+            }
+        }
+        add_grad(x, gl);
+    }
+
+    // push: mu_out[i](x - e_i) = lf_i, bounce-back at walls
+    uint32_t xm = x - 1, xp = x + 1;
+    bool wxm = false, wxp = false;
+    if (BCX == BC_PERIODIC) {
+        xm = (x == 0) ? nx - 1 : xm;
+        xp = (x == nx - 1) ? 0 : xp;
+    } else if (BCX == BC_WALL) {
+        wxm = (x == 0);
+        wxp = (x == nx - 1);
+    } else {
+        wxm = (x == 0); // pressure: nothing beyond the end columns
+        wxp = (x == nx - 1);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int ex = ex_of(i), ey = ey_of(i);
+        const bool wall_y = (ey == 1 && wym) || (ey == -1 && wyp); // uniform
+        const bool out_x = (ex == 1 && wxm) || (ex == -1 && wxp);  // per lane
+        const int ry = ey == 1 ? 0 : (ey == -1 ? 2 : 1);
+        const uint32_t tx = ex == 1 ? xm : (ex == -1 ? xp : x);
+        if (BCX == BC_PRESSURE) {
+            if (out_x)
+                continue; // source outside the lattice
+            if (wall_y)
+                st_f32(orow[1], x * 4, opp_of(i) * slot, lf[i], false);
+            else
+                st_f32(orow[ry], tx * 4, i * slot, lf[i], false);
+        } else {
+            if (wall_y || out_x)
+                st_f32(orow[1], x * 4, opp_of(i) * slot, lf[i], false);
+            else
+                st_f32(orow[ry], tx * 4, i * slot, lf[i], false);
+        }
+    }
+    if (BCX == BC_PRESSURE && bnode) {
+        // slots of this node whose forward destination lies outside
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const int ex = ex_of(i);
+            if ((x == 0 && ex == -1) || (x == nx - 1 && ex == 1))
+                st_f32(orow[1], x * 4, i * slot, 0.0f, false);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void grad_out_kernel(const double *grad, float *out, Geom g,
+                                                        int bpr)
+{
+    const int L = xcd_remap_a(blockIdx.x, gridDim.x);
+    const int y = L / bpr;
+    const int x = (L - y * bpr) * 256 + threadIdx.x;
+    if (x >= g.nx)
+        return;
+    out[(int64_t)y * g.nx + x] = (float)grad[(int64_t)y * g.pitch + x];
+}
+
+template <int BCX, int BCY>
+static hipError_t adj_t(const float *mu_in, float *mu_out, const float *hist, const char *med,
+                        const MLayout &mlay, double *grad, const Geom &g, const Physics &ph,
+                        int terminal, float a1, float a2, int outlet, hipStream_t st)
+{
+    const int bpr = (g.nx + 255) / 256;
+    hipLaunchKernelGGL((adjoint_kernel<BCX, BCY>), dim3(bpr * g.ny), dim3(256), 0, st, mu_in,
+                       mu_out, hist, med, mlay, grad, g, ph, terminal, a1, a2, outlet, bpr);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint(int bcx, int bcy, const float *mu_in, float *mu_out, const float *hist,
+                          const char *med, const MLayout &mlay, double *grad, const Geom &g,
+                          const Physics &ph, int terminal, float a1, float a2, int outlet,
+                          hipStream_t st)
+{
+    switch (bcx * 2 + bcy) {
+    case 0: return adj_t<BC_PERIODIC, BC_PERIODIC>(mu_in, mu_out, hist, med, mlay, grad, g, ph, terminal, a1, a2, outlet, st);
+    case 1: return adj_t<BC_PERIODIC, BC_WALL>(mu_in, mu_out, hist, med, mlay, grad, g, ph, terminal, a1, a2, outlet, st);
+    case 2: return adj_t<BC_WALL, BC_PERIODIC>(mu_in, mu_out, hist, med, mlay, grad, g, ph, terminal, a1, a2, outlet, st);
+    case 3: return adj_t<BC_WALL, BC_WALL>(mu_in, mu_out, hist, med, mlay, grad, g, ph, terminal, a1, a2, outlet, st);
+    case 4: return adj_t<BC_PRESSURE, BC_PERIODIC>(mu_in, mu_out, hist, med, mlay, grad, g, ph, terminal, a1, a2, outlet, st);
+    case 5: return adj_t<BC_PRESSURE, BC_WALL>(mu_in, mu_out, hist, med, mlay, grad, g, ph, terminal, a1, a2, outlet, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_grad_out(const double *grad, float *out, const Geom &g, hipStream_t st)
+{
+    const int bpr = (g.nx + 255) / 256;
+    hipLaunchKernelGGL(grad_out_kernel, dim3(bpr * g.ny), dim3(256), 0, st, grad, out, g, bpr);
+    return hipGetLastError();
+}
+
+} // namespace lbk

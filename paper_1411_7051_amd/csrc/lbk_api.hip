@@ -2,6 +2,7 @@
 // validation, workspace carve-up, launch sequencing on the caller's stream,
 // FP64 diagnostics and state save/load.  No kernels live here.
 #include "lbk.h"
+#include "lbk_adjoint.h"
 #include "lbk_kernels.h"
 
 #include <math.h>
@@ -9,6 +10,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 
@@ -132,6 +134,23 @@ void split(double v, float &hi, float &lo)
 
 } // namespace
 
+// Byte offsets of an adjoint workspace for (n, c1, c2): outer checkpoints
+// every c1 steps, inner checkpoints every c2 steps (two-level only), two
+// recompute levels, c2 + 1 history slots (c1 + 1 for one level), two
+// adjoint states and the FP64 gradient.
+struct AdjPlan {
+    bool valid;
+    int objective;
+    int64_t n, c1, c2, t0;
+    bool two_level;
+    int64_t k1, k2, hlen;
+    size_t outer, inner, rec, hist, lam, grad, total;
+    size_t level_bytes, hist_bytes, lam_bytes;
+    const void *ws;
+    double a1, a2;
+    int outlet;
+};
+
 struct lbk_lattice {
     lbk_desc d;
     WsLayout L;
@@ -146,6 +165,7 @@ struct lbk_lattice {
     double eps_b;  // mean porosity of the two pressure columns
     double *host;  // pinned scratch for results (8 doubles)
     int64_t since_check;
+    AdjPlan adj;
 
     char *state(int l) const { return ws + L.level[l]; }
     char *med() const { return ws + L.med; }
@@ -365,7 +385,7 @@ lbk_status lbk_step(lbk_lattice *lat, int64_t n)
         const int nxt = lat->cur ^ 1;
         HIP_TRY(launch_sweep(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->state(nxt),
                              lat->L.lay, lat->med(), lat->L.mlay, lat->g, lat->ph, lat->s(),
-                             lat->inv_s(), lat->stream));
+                             lat->inv_s(), nullptr, lat->stream));
         lat->cur = nxt;
         ++lat->t;
         if (d.check_every > 0 && ++lat->since_check >= d.check_every) {
@@ -509,3 +529,197 @@ lbk_status lbk_load_state(lbk_lattice *lat, const void *src)
 const char *lbk_last_error(void) { return g_err.c_str(); }
 
 } // extern "C"
+
+// ------------------------------------------------------------ gradients
+
+static lbk_status adj_plan(const lbk_lattice *lat, int64_t n, int64_t c1, int64_t c2,
+                           AdjPlan &P)
+{
+    if (n < 1 || c1 < 1 || c2 < 1 || c2 > c1)
+        return fail(LBK_ERR_INVALID_ARG,
+                    "need n_steps >= 1 and 1 <= hist_len <= ckpt_every (got %lld, %lld, %lld)",
+                    (long long)n, (long long)c1, (long long)c2);
+    P = AdjPlan{};
+    P.n = n;
+    P.c1 = c1;
+    P.c2 = c2;
+    P.two_level = c2 < c1 && c2 < n;
+    P.k1 = (n + c1 - 1) / c1;
+    P.k2 = P.two_level ? (c1 + c2 - 1) / c2 : 0;
+    P.hlen = P.two_level ? c2 : (c1 < n ? c1 : n);
+    const int64_t rows = lat->d.ny;
+    P.level_bytes = lat->L.level_bytes;
+    P.hist_bytes = (size_t)rows * 3 * lat->L.pitch * 4;
+    P.lam_bytes = (size_t)rows * 9 * lat->L.pitch * 4;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes, 256);
+        return at;
+    };
+    P.outer = take(P.level_bytes * (size_t)P.k1);
+    P.inner = take(P.level_bytes * (size_t)P.k2);
+    P.rec = take(2 * P.level_bytes);
+    P.hist = take(P.hist_bytes * (size_t)(P.hlen + 1));
+    P.lam = take(2 * P.lam_bytes);
+    P.grad = take((size_t)rows * lat->L.pitch * 8);
+    P.total = o;
+    return LBK_OK;
+}
+
+extern "C" lbk_status lbk_adjoint_workspace_size(const lbk_lattice *lat, int64_t n_steps,
+                                                 int64_t ckpt_every, int64_t hist_len,
+                                                 size_t *bytes)
+{
+    if (!lat || !bytes)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    AdjPlan P;
+    lbk_status s = adj_plan(lat, n_steps, ckpt_every, hist_len, P);
+    if (s != LBK_OK)
+        return s;
+    *bytes = P.total;
+    return LBK_OK;
+}
+
+extern "C" lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64_t n_steps,
+                                          int64_t ckpt_every, int64_t hist_len, void *ws,
+                                          size_t ws_bytes, double *J)
+{
+    if (!lat || !ws || !J)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    const lbk_desc &d = lat->d;
+    if (d.f_eps != 0.0)
+        return fail(LBK_ERR_UNSUPPORTED, "gradients need f_eps = 0 (Eq. 8)");
+    if (objective != LBK_OBJ_PERMEABILITY && objective != LBK_OBJ_OUTLET_FLUX)
+        return fail(LBK_ERR_INVALID_ARG, "unknown objective %d", objective);
+    if (objective == LBK_OBJ_PERMEABILITY && d.bc_x != LBK_BC_PRESSURE && d.gx == 0.0)
+        return fail(LBK_ERR_INVALID_ARG, "the global permeability needs gx != 0 or a pressure "
+                                         "drive");
+    if ((uintptr_t)ws & 255u)
+        return fail(LBK_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    AdjPlan P;
+    lbk_status s = adj_plan(lat, n_steps, ckpt_every, hist_len, P);
+    if (s != LBK_OK)
+        return s;
+    if (ws_bytes < P.total)
+        return fail(LBK_ERR_OOM, "adjoint workspace of %zu bytes < %zu needed", ws_bytes,
+                    P.total);
+    lat->adj.valid = false;
+    char *w = static_cast<char *>(ws);
+    hipStream_t st = lat->stream;
+    P.t0 = lat->t;
+    for (int64_t k = 0; k < P.k1; ++k) {
+        HIP_TRY(hipMemcpyAsync(w + P.outer + (size_t)k * P.level_bytes, lat->state(lat->cur),
+                               P.level_bytes, hipMemcpyDeviceToDevice, st));
+        const int64_t steps = std::min(P.c1, P.n - k * P.c1);
+        for (int64_t i = 0; i < steps; ++i) {
+            const int nxt = lat->cur ^ 1;
+            HIP_TRY(launch_sweep(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur),
+                                 lat->state(nxt), lat->L.lay, lat->med(), lat->L.mlay, lat->g,
+                                 lat->ph, lat->s(), lat->inv_s(), nullptr, st));
+            lat->cur = nxt;
+            ++lat->t;
+        }
+    }
+    if ((s = macro_sums(lat, false)) != LBK_OK)
+        return s;
+    const double nodes = (double)d.nx * d.ny, nu = (d.tau - 0.5) / 3.0;
+    P.objective = objective;
+    if (objective == LBK_OBJ_OUTLET_FLUX) {
+        *J = lat->host[MAC_QOUT];
+        P.a1 = 1.0;
+        P.a2 = 0.0;
+        P.outlet = 1;
+    } else if (d.bc_x == LBK_BC_PRESSURE) {
+        P.a1 = lat->eps_b * nu * (d.nx - 1) / ((1.0 / 3.0) * (d.rho_in - d.rho_out) * nodes);
+        P.a2 = 0.0;
+        P.outlet = 0;
+        *J = P.a1 * lat->host[MAC_FLUX];
+    } else {
+        P.a1 = 0.0;
+        P.a2 = nu / (d.gx * nodes);
+        P.outlet = 0;
+        *J = P.a2 * lat->host[MAC_UX];
+    }
+    P.ws = ws;
+    P.valid = true;
+    lat->adj = P;
+    return LBK_OK;
+}
+
+extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws_bytes,
+                                           float *dJ_dlnk)
+{
+    if (!lat || !ws || !dJ_dlnk)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    const AdjPlan &P = lat->adj;
+    if (!P.valid || P.ws != ws || ws_bytes < P.total)
+        return fail(LBK_ERR_INVALID_ARG, "no matching lbk_adjoint_forward for this workspace");
+    if (lat->t != P.t0 + P.n)
+        return fail(LBK_ERR_INVALID_ARG, "the lattice moved since lbk_adjoint_forward");
+    const lbk_desc &d = lat->d;
+    hipStream_t st = lat->stream;
+    char *w = static_cast<char *>(ws);
+    auto level = [&](size_t off, int64_t k) { return w + off + (size_t)k * P.level_bytes; };
+    auto histp = [&](int64_t k) {
+        return reinterpret_cast<float *>(w + P.hist + (size_t)k * P.hist_bytes);
+    };
+    float *lam[2] = {reinterpret_cast<float *>(w + P.lam),
+                     reinterpret_cast<float *>(w + P.lam + P.lam_bytes)};
+    double *grad = reinterpret_cast<double *>(w + P.grad);
+    char *rec[2] = {level(P.rec, 0), level(P.rec, 1)};
+    auto sweep = [&](const char *src, char *dst, float *hist) {
+        return launch_sweep(d.storage, d.bc_x, d.bc_y, src, dst, lat->L.lay, lat->med(),
+                            lat->L.mlay, lat->g, lat->ph, lat->s(), lat->inv_s(), hist, st);
+    };
+    const float a1 = (float)P.a1, a2 = (float)P.a2;
+
+    HIP_TRY(hipMemsetAsync(grad, 0, (size_t)d.ny * lat->L.pitch * 8, st));
+    // read-out of J at step n: linearisation point of the pull of S_n
+    HIP_TRY(sweep(lat->state(lat->cur), rec[0], histp(0)));
+    HIP_TRY(launch_adjoint(d.bc_x, d.bc_y, nullptr, lam[0], histp(0), lat->med(), lat->L.mlay,
+                           grad, lat->g, lat->ph, 1, a1, a2, P.outlet, st));
+    int cur = 0;
+    for (int64_t k = P.k1 - 1; k >= 0; --k) {
+        const int64_t a = k * P.c1, b = std::min(P.n, a + P.c1);
+        int64_t nseg = 1;
+        if (P.two_level) {
+            // rebuild the inner checkpoints of this outer segment
+            const char *src = level(P.outer, k);
+            int r = 0;
+            nseg = 0;
+            for (int64_t t = a; t < b; t += P.c2, ++nseg) {
+                HIP_TRY(hipMemcpyAsync(level(P.inner, nseg), src, P.level_bytes,
+                                       hipMemcpyDeviceToDevice, st));
+                const int64_t steps = std::min(P.c2, b - t);
+                if (t + steps >= b)
+                    break; // the last inner segment needs no further state
+                for (int64_t i = 0; i < steps; ++i) {
+                    HIP_TRY(sweep(i == 0 ? level(P.inner, nseg) : rec[r], rec[r ^ 1], nullptr));
+                    r ^= 1;
+                }
+                src = rec[r];
+            }
+            ++nseg;
+        }
+        for (int64_t j = nseg - 1; j >= 0; --j) {
+            const int64_t a2s = P.two_level ? a + j * P.c2 : a;
+            const int64_t b2s = P.two_level ? std::min(b, a2s + P.c2) : b;
+            const char *src = P.two_level ? level(P.inner, j) : level(P.outer, k);
+            // recompute the segment, recording each step's linearisation point
+            int r = 0;
+            for (int64_t t = a2s; t < b2s; ++t) {
+                HIP_TRY(sweep(t == a2s ? src : rec[r], rec[r ^ 1], histp(t - a2s + 1)));
+                r ^= 1;
+            }
+            for (int64_t t = b2s; t > a2s; --t) {
+                HIP_TRY(launch_adjoint(d.bc_x, d.bc_y, lam[cur], lam[cur ^ 1], histp(t - a2s),
+                                       lat->med(), lat->L.mlay, grad, lat->g, lat->ph, 0, a1, a2,
+                                       P.outlet, st));
+                cur ^= 1;
+            }
+        }
+    }
+    HIP_TRY(launch_grad_out(grad, dJ_dlnk, lat->g, st));
+    return LBK_OK;
+}

@@ -25,6 +25,7 @@ enum {
     MAC_DU2,      // sum |u - u_prev|^2
     MAC_U2,       // sum |u|^2
     MAC_RHO,      // sum rho
+    MAC_QOUT,     // sum over column nx-1 of rho u_x (outlet mass flux)
     MAC_SLOTS
 };
 enum {
@@ -38,9 +39,11 @@ enum {
     FLD_SLOTS
 };
 
+// One sweep src -> dst; if hist is non-null also write this step's
+// linearisation point (rho, jx, jy) as [y][3][pitch] FP32 for the adjoint.
 hipError_t launch_sweep(int storage, int bcx, int bcy, const char *src, char *dst,
                         const Layout &lay, const char *med, const MLayout &mlay, const Geom &g,
-                        const Physics &ph, float s, float inv_s, hipStream_t st);
+                        const Physics &ph, float s, float inv_s, float *hist, hipStream_t st);
 
 // Macroscopic read-out ([ny][nx] outputs, any may be null) and FP64 partials
 // [MAC_SLOTS][blocks].  If u_prev ([ny][pitch]) is given it is read for the

@@ -112,39 +112,37 @@ __device__ __forceinline__ float post_stream(const Rows &R, const Layout &L, con
     return density<T>(rc, d, inv_s, inc, r);
 }
 
-// One node's full update: pull, boundary override, moments, velocity,
-// collide.  Outputs the new density and deviations (storage unit).
-template <typename T, int BCX>
-__device__ __forceinline__ float update(const Rows &R, const Layout &L, const Med &md,
-                                        const Geom &g, const Physics &ph, float s, float inv_s,
-                                        uint32_t x, float (&hs)[9])
-{
-    float d[9], inc, r;
-    const float rho = post_stream<T, BCX>(R, L, md, g, ph, s, inv_s, x, d, inc, r);
-    float jx, jy, ux, uy, Fx, Fy;
-    momentum(d, jx, jy);
-    if (Elem<T>::kScaled) {
-        jx *= inv_s;
-        jy *= inv_s;
-    }
-    const float eps = md.eps(x);
-    velocity(ph, rho, jx, jy, eps, md.drag(x), md.kn0(x), ux, uy, Fx, Fy);
-    collide<T>(ph, rho, inc, r, d, ux, uy, Fx, Fy, eps, s, hs);
-    return rho;
-}
-
-template <typename T, int BCX, int BCY>
+template <typename T, int BCX, int BCY, bool HIST>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(const char *src, char *dst, Layout lay,
                                                         const char *med, MLayout mlay, Geom g,
-                                                        Physics ph, float s, float inv_s, int bpr)
+                                                        Physics ph, float s, float inv_s,
+                                                        float *hist, int bpr)
 {
     const Node nd = node_of(bpr);
     if (nd.x >= (uint32_t)g.nx)
         return;
     const Rows R = rows_of<BCY>(src, lay, g, nd.y);
     const Med md{med_row(med, mlay, nd.y), mlay.slot};
+    float d[9], inc, r;
+    const float rho = post_stream<T, BCX>(R, lay, md, g, ph, s, inv_s, nd.x, d, inc, r);
+    float jx, jy, ux, uy, Fx, Fy;
+    momentum(d, jx, jy);
+    if (Elem<T>::kScaled) {
+        jx *= inv_s;
+        jy *= inv_s;
+    }
+    if (HIST) {
+        // linearisation point of this step for the adjoint: (rho, jx, jy)
+        const uint32_t hrow = 3u * (uint32_t)g.pitch * 4u, hsl = (uint32_t)g.pitch * 4u;
+        const Rsrc hr = make_rsrc(reinterpret_cast<char *>(hist) + (uint64_t)nd.y * hrow, hrow);
+        st_f32(hr, nd.x * 4, 0, rho, false);
+        st_f32(hr, nd.x * 4, hsl, jx, false);
+        st_f32(hr, nd.x * 4, 2 * hsl, jy, false);
+    }
+    const float eps = md.eps(nd.x);
+    velocity(ph, rho, jx, jy, eps, md.drag(nd.x), md.kn0(nd.x), ux, uy, Fx, Fy);
     float hs[9];
-    const float rho = update<T, BCX>(R, lay, md, g, ph, s, inv_s, nd.x, hs);
+    collide<T>(ph, rho, inc, r, d, ux, uy, Fx, Fy, eps, s, hs);
     const Rsrc out = make_rsrc(dst + (uint64_t)nd.y * lay.row, (uint32_t)lay.row);
     st_f32(out, nd.x * 4, 0, rho, true);
     constexpr uint32_t es = sizeof(T);
@@ -192,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void macro_kernel(const char *src, Layout l
 {
     __shared__ double sh[kBlock / 64];
     const Node nd = node_of(bpr);
-    double v[MAC_SLOTS] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double v[MAC_SLOTS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (nd.x < (uint32_t)g.nx) {
         const Rows R = rows_of<BCY>(src, lay, g, nd.y);
         const Med md{med_row(med, mlay, nd.y), mlay.slot};
@@ -217,6 +215,7 @@ __global__ __launch_bounds__(kBlock) void macro_kernel(const char *src, Layout l
         v[MAC_UX] = ux;
         v[MAC_U2] = (double)ux * ux + (double)uy * uy;
         v[MAC_RHO] = rp;
+        v[MAC_QOUT] = (nd.x == (uint32_t)g.nx - 1) ? rp * (double)ux : 0.0;
         if (ux_prev) {
             const uint32_t c = (uint32_t)nd.y * (uint32_t)g.pitch + nd.x;
             const double dx = (double)ux - ux_prev[c], dy = (double)uy - uy_prev[c];
@@ -369,11 +368,17 @@ __global__ __launch_bounds__(kBlock) void rescale_kernel(char *st, Layout lay, G
 template <typename T, int BCX, int BCY>
 static hipError_t sweep_t(const char *src, char *dst, const Layout &lay, const char *med,
                           const MLayout &mlay, const Geom &g, const Physics &ph, float s,
-                          float inv_s, hipStream_t st)
+                          float inv_s, float *hist, hipStream_t st)
 {
     const Launch l = launch_of(g);
-    hipLaunchKernelGGL((sweep_kernel<T, BCX, BCY>), dim3(l.blocks), dim3(kBlock), 0, st, src,
-                       dst, lay, med, mlay, g, ph, s, inv_s, l.blocks_per_row);
+    if (hist)
+        hipLaunchKernelGGL((sweep_kernel<T, BCX, BCY, true>), dim3(l.blocks), dim3(kBlock), 0,
+                           st, src, dst, lay, med, mlay, g, ph, s, inv_s, hist,
+                           l.blocks_per_row);
+    else
+        hipLaunchKernelGGL((sweep_kernel<T, BCX, BCY, false>), dim3(l.blocks), dim3(kBlock), 0,
+                           st, src, dst, lay, med, mlay, g, ph, s, inv_s, hist,
+                           l.blocks_per_row);
     return hipGetLastError();
 }
 
@@ -436,11 +441,11 @@ static hipError_t macro_t(const char *src, const Layout &lay, const char *med,
 
 hipError_t launch_sweep(int storage, int bcx, int bcy, const char *src, char *dst,
                         const Layout &lay, const char *med, const MLayout &mlay, const Geom &g,
-                        const Physics &ph, float s, float inv_s, hipStream_t st)
+                        const Physics &ph, float s, float inv_s, float *hist, hipStream_t st)
 {
     if (bcy < 0 || bcy > 1)
         return hipErrorInvalidValue;
-    LBK_DISPATCH(sweep_t, src, dst, lay, med, mlay, g, ph, s, inv_s, st)
+    LBK_DISPATCH(sweep_t, src, dst, lay, med, mlay, g, ph, s, inv_s, hist, st)
 }
 
 hipError_t launch_macro(int storage, int bcx, int bcy, const char *src, const Layout &lay,

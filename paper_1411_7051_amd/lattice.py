@@ -155,6 +155,43 @@ class Lattice:
             raise ValueError("state buffer too small")
         check(_lib.load().lbk_load_state(self._handle(), src.contiguous().data_ptr()))
 
+    # -- gradients
+    def adjoint_workspace_bytes(self, steps: int, ckpt_every: int, hist_len: int) -> int:
+        n = ctypes.c_size_t()
+        check(_lib.load().lbk_adjoint_workspace_size(self._handle(), int(steps),
+                                                     int(ckpt_every), int(hist_len),
+                                                     ctypes.byref(n)))
+        return int(n.value)
+
+    def adjoint_forward(self, steps: int, objective: str = "k_app", ckpt_every: int = 500,
+                        hist_len: Optional[int] = None,
+                        workspace: Optional[torch.Tensor] = None):
+        """Run ``steps`` steps keeping checkpoints; returns (J, workspace)."""
+        ckpt_every = max(1, min(int(ckpt_every), int(steps)))
+        hist_len = ckpt_every if hist_len is None else max(1, min(int(hist_len), ckpt_every))
+        nbytes = self.adjoint_workspace_bytes(steps, ckpt_every, hist_len)
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        J = ctypes.c_double()
+        check(_lib.load().lbk_adjoint_forward(self._handle(), _lib.OBJECTIVE[objective],
+                                              int(steps), ckpt_every, hist_len,
+                                              workspace.data_ptr(), workspace.numel(),
+                                              ctypes.byref(J)))
+        return float(J.value), workspace
+
+    def adjoint_backward(self, workspace: torch.Tensor) -> torch.Tensor:
+        """dJ/d ln k of the last adjoint_forward, [ny][nx] float32."""
+        g = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+        check(_lib.load().lbk_adjoint_backward(self._handle(), workspace.data_ptr(),
+                                               workspace.numel(), g.data_ptr()))
+        return g
+
+    def gradient(self, steps: int, objective: str = "k_app", ckpt_every: int = 500,
+                 hist_len: Optional[int] = None):
+        """(J, dJ/d ln k) after ``steps`` steps from the current state."""
+        J, ws = self.adjoint_forward(steps, objective, ckpt_every, hist_len)
+        return J, self.adjoint_backward(ws)
+
     def run_to_steady(self, every: int = 100, tol: float = 1e-9, max_steps: int = 10**7,
                       patience: int = 10):
         """Step in blocks of ``every`` until the velocity residual
@@ -176,3 +213,32 @@ class Lattice:
                 if stall >= patience:
                     return steps, r, "plateau"
         return steps, r, "max_steps"
+
+
+class ApparentPermeability(torch.autograd.Function):
+    """J(ln k) after ``steps`` steps from rest, as a differentiable function
+    of the log-permeability field: forward runs the HIP sweep with
+    checkpoints, backward runs the HIP adjoint sweep.
+
+    ``ApparentPermeability.apply(log_k, eps, kn0, steps, params)`` with
+    ``params`` a dict of lattice keywords (plus optional ``objective``,
+    ``ckpt_every``, ``hist_len``); returns a float64 scalar tensor."""
+
+    @staticmethod
+    def forward(ctx, log_k, eps, kn0, steps, params):
+        params = dict(params)
+        objective = params.pop("objective", "k_app")
+        ckpt = params.pop("ckpt_every", 500)
+        hist = params.pop("hist_len", None)
+        lat = Lattice(eps, torch.exp(log_k.detach().double()).float(), kn0,
+                      device=log_k.device, **params)
+        J, ws = lat.adjoint_forward(int(steps), objective, ckpt, hist)
+        ctx.lat, ctx.ws = lat, ws
+        return torch.tensor(J, dtype=torch.float64, device=log_k.device)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        g = ctx.lat.adjoint_backward(ctx.ws)
+        ctx.lat.close()
+        ctx.lat = ctx.ws = None
+        return (grad_out.to(g.dtype) * g, None, None, None, None)
