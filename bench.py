@@ -129,6 +129,61 @@ def cpu_baseline(case, target_s=15.0):
     }
 
 
+def time_adjoint(n, steps, ckpt, hist, device):
+    """Gradient of the global permeability w.r.t. ln k on the fractured-shale
+    medium (n x n, seed 3): time of ``steps`` plain sweeps (t_fwd), of the
+    checkpointed forward, and of the backward (recompute + reverse)."""
+    import torch
+    from paper_1411_7051_amd import inputs
+    from paper_1411_7051_amd.lattice import Lattice
+
+    t = time.perf_counter()
+    case = inputs.shale(n=n, seed=3)
+    log(f"shale inputs: {case.nodes} nodes in {time.perf_counter() - t:.1f} s")
+    lat = Lattice(case.eps, case.k, case.kn0, device=device, **case.params)
+    st = lat.stream
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    ws = torch.empty(lat.adjoint_workspace_bytes(steps, ckpt, hist), dtype=torch.uint8,
+                     device=device)
+    lat.step(20)
+    torch.cuda.synchronize(device)
+    ev[0].record(st)
+    lat.step(steps)
+    ev[1].record(st)
+    ev[2].record(st)
+    J, ws = lat.adjoint_forward(steps, "k_app", ckpt, hist, ws)
+    ev[3].record(st)
+    ev[4].record(st)
+    g = lat.adjoint_backward(ws)
+    ev[5].record(st)
+    torch.cuda.synchronize(device)
+    t_fwd = ev[0].elapsed_time(ev[1])
+    t_af = ev[2].elapsed_time(ev[3])
+    t_bwd = ev[4].elapsed_time(ev[5])
+    gmax = float(g.abs().max())
+    out = {
+        "workload": f"shale{n}: {n}x{n} log-normal k (ln-sigma 1.5, corr 32, mean 1e-5), "
+                    "eps U[0.05,0.15], 24 fractures (eps 0.9, k 0.1), base Kn 0.5, "
+                    "pressure-driven x, periodic y",
+        "objective": "global permeability",
+        "steps": steps,
+        "ckpt_every": ckpt,
+        "hist_len": hist,
+        "workspace_GB": ws.numel() / 1e9,
+        "t_fwd_ms": t_fwd,
+        "t_fwd_ckpt_ms": t_af,
+        "t_grad_ms": t_bwd,
+        "grad_over_fwd": t_bwd / t_fwd,
+        "total_over_fwd": (t_af + t_bwd) / t_fwd,
+        "J": J,
+        "max_abs_grad": gmax,
+    }
+    lat.close()
+    del lat, ws, g
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,6 +192,11 @@ def main():
     ap.add_argument("--n", type=int, default=4096, help="lattice side")
     ap.add_argument("--storages", default="f32,f16,bf16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--adjoint-n", type=int, default=8192, help="shale lattice side")
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--adjoint-ckpt", type=int, default=500)
+    ap.add_argument("--adjoint-hist", type=int, default=50)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient leg")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run 10 device-to-device copies of MIB MiB (a plain copy "
                          "kernel of known traffic, to scale HBM byte counters) and exit")
@@ -192,6 +252,12 @@ def main():
         "bytes_per_node": ALG_BYTES[st],
         "layout_bytes_per_node": LAYOUT_BYTES[st],
     }
+    adj = None
+    if not args.no_adjoint:
+        adj = time_adjoint(args.adjoint_n, args.adjoint_steps, args.adjoint_ckpt,
+                           args.adjoint_hist, dev)
+        log(f"adjoint: t_grad/t_fwd = {adj['grad_over_fwd']:.2f}, "
+            f"(t_fwd + t_grad)/t_fwd = {adj['total_over_fwd']:.2f}")
     cpu = None if args.no_cpu else cpu_baseline(case)
     if cpu:
         log(f"cpu oracle: {cpu['value']:.2f} MLUPS ({cpu['sample']})")
@@ -220,7 +286,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "storage_runs": runs,
-        "adjoint": None,
+        "adjoint": adj,
     }
     print(json.dumps(out), flush=True)
 
