@@ -26,8 +26,11 @@
 // forward values were discarded.
 //
 // Layouts (row blocks, `pitch` elements per slot, FP32): adjoint state
-// [y][9][pitch]; history [y][3][pitch] = (rho, jx, jy); gradient FP64
-// [y][pitch].  The Forchheimer term is not differentiated (the host
+// [y][9][pitch]; history [y][3][pitch] = (rho, jx, jy); gradient
+// [y][pitch] accumulated in FP32 over one recomputed segment (at most a few
+// hundred steps) and folded into an FP64 total at the segment's end.  The
+// adjoint state and the history are each read once, so they stream
+// nontemporally.  The Forchheimer term is not differentiated (the host
 // rejects f_eps != 0).
 #include "lbk_adjoint.h"
 
@@ -235,13 +238,13 @@ __device__ __forceinline__ Rsrc rsrc_row(const void *base, uint64_t row_bytes, i
 //   mu_in  [y][9][pitch]  adjoint of S_n (ignored when terminal)
 //   mu_out [y][9][pitch]  adjoint of S_{n-1} (written by push)
 //   hist   [y][3][pitch]  (rho, jx, jy) of step n's post-stream populations
-//   grad   [y][pitch]     FP64, accumulates d J / d ln k
+//   grad   [y][pitch]     FP32, accumulates d J / d ln k over a segment
 // Objective: J = sum_x a1(x) rho u_x + a2 u_x with a1(x) = a1 (all nodes,
 // or only column nx-1 when outlet != 0) and a2 uniform.
 template <int BCX, int BCY>
 __global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float *mu_out,
                                                        const float *hist, const char *med,
-                                                       MLayout mlay, double *grad, Geom g,
+                                                       MLayout mlay, float *grad, Geom g,
                                                        Physics ph, int terminal, float a1,
                                                        float a2, int outlet, int bpr)
 {
@@ -256,11 +259,11 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float 
     const Rsrc hr = rsrc_row(hist, hrow, y);
     const Rsrc mr = make_rsrc(med + (uint64_t)y * mlay.row, (uint32_t)mlay.row);
     const Rsrc lin = rsrc_row(mu_in, lrow, y);
-    double *grow_p = grad + (uint64_t)y * g.pitch;
+    float *grow_p = grad + (uint64_t)y * g.pitch;
 
     auto load_node = [&](uint32_t xx) {
-        const float rho = ld_f32(hr, xx * 4, 0), jx = ld_f32(hr, xx * 4, slot),
-                    jy = ld_f32(hr, xx * 4, 2 * slot);
+        const float rho = ld_f32_nt(hr, xx * 4, 0), jx = ld_f32_nt(hr, xx * 4, slot),
+                    jy = ld_f32_nt(hr, xx * 4, 2 * slot);
         return node_fwd(ph, rho, jx, jy, ld_f32(mr, xx * 4, 0), ld_f32(mr, xx * 4, mlay.slot),
                         ld_f32(mr, xx * 4, 2 * mlay.slot));
     };
@@ -272,11 +275,11 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float 
         float mu[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            mu[i] = ld_f32(lin, xx * 4, i * slot);
+            mu[i] = ld_f32_nt(lin, xx * 4, i * slot);
         return collide_adj(ph, n, mu, lf);
     };
     // each gradient entry has exactly one writer per launch
-    auto add_grad = [&](uint32_t xx, float v) { grow_p[xx] += (double)v; };
+    auto add_grad = [&](uint32_t xx, float v) { grow_p[xx] += v; };
 
     // rows the push writes into: source of direction i is (x - e_ix, y - e_iy)
     int ym = y - 1, yp = y + 1;
@@ -352,14 +355,14 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float 
             if (out_x)
                 continue; // source outside the lattice
             if (wall_y)
-                st_f32(orow[1], x * 4, opp_of(i) * slot, lf[i], false);
+                st_f32(orow[1], x * 4, opp_of(i) * slot, lf[i], true);
             else
-                st_f32(orow[ry], tx * 4, i * slot, lf[i], false);
+                st_f32(orow[ry], tx * 4, i * slot, lf[i], true);
         } else {
             if (wall_y || out_x)
-                st_f32(orow[1], x * 4, opp_of(i) * slot, lf[i], false);
+                st_f32(orow[1], x * 4, opp_of(i) * slot, lf[i], true);
             else
-                st_f32(orow[ry], tx * 4, i * slot, lf[i], false);
+                st_f32(orow[ry], tx * 4, i * slot, lf[i], true);
         }
     }
     if (BCX == BC_PRESSURE && bnode) {
@@ -368,9 +371,23 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float 
         for (int i = 1; i < 9; ++i) {
             const int ex = ex_of(i);
             if ((x == 0 && ex == -1) || (x == nx - 1 && ex == 1))
-                st_f32(orow[1], x * 4, i * slot, 0.0f, false);
+                st_f32(orow[1], x * 4, i * slot, 0.0f, true);
         }
     }
+}
+
+// total += seg; seg = 0 (end of a recomputed segment)
+__global__ __launch_bounds__(256) void grad_fold_kernel(float *seg, double *total, Geom g,
+                                                         int bpr)
+{
+    const int L = xcd_remap_a(blockIdx.x, gridDim.x);
+    const int y = L / bpr;
+    const int x = (L - y * bpr) * 256 + threadIdx.x;
+    if (x >= g.nx)
+        return;
+    const int64_t c = (int64_t)y * g.pitch + x;
+    total[c] += (double)seg[c];
+    seg[c] = 0.0f;
 }
 
 __global__ __launch_bounds__(256) void grad_out_kernel(const double *grad, float *out, Geom g,
@@ -386,7 +403,7 @@ __global__ __launch_bounds__(256) void grad_out_kernel(const double *grad, float
 
 template <int BCX, int BCY>
 static hipError_t adj_t(const float *mu_in, float *mu_out, const float *hist, const char *med,
-                        const MLayout &mlay, double *grad, const Geom &g, const Physics &ph,
+                        const MLayout &mlay, float *grad, const Geom &g, const Physics &ph,
                         int terminal, float a1, float a2, int outlet, hipStream_t st)
 {
     const int bpr = (g.nx + 255) / 256;
@@ -396,7 +413,7 @@ static hipError_t adj_t(const float *mu_in, float *mu_out, const float *hist, co
 }
 
 hipError_t launch_adjoint(int bcx, int bcy, const float *mu_in, float *mu_out, const float *hist,
-                          const char *med, const MLayout &mlay, double *grad, const Geom &g,
+                          const char *med, const MLayout &mlay, float *grad, const Geom &g,
                           const Physics &ph, int terminal, float a1, float a2, int outlet,
                           hipStream_t st)
 {
@@ -409,6 +426,13 @@ hipError_t launch_adjoint(int bcx, int bcy, const float *mu_in, float *mu_out, c
     case 5: return adj_t<BC_PRESSURE, BC_WALL>(mu_in, mu_out, hist, med, mlay, grad, g, ph, terminal, a1, a2, outlet, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_grad_fold(float *seg, double *total, const Geom &g, hipStream_t st)
+{
+    const int bpr = (g.nx + 255) / 256;
+    hipLaunchKernelGGL(grad_fold_kernel, dim3(bpr * g.ny), dim3(256), 0, st, seg, total, g, bpr);
+    return hipGetLastError();
 }
 
 hipError_t launch_grad_out(const double *grad, float *out, const Geom &g, hipStream_t st)

@@ -137,14 +137,14 @@ void split(double v, float &hi, float &lo)
 // Byte offsets of an adjoint workspace for (n, c1, c2): outer checkpoints
 // every c1 steps, inner checkpoints every c2 steps (two-level only), two
 // recompute levels, c2 + 1 history slots (c1 + 1 for one level), two
-// adjoint states and the FP64 gradient.
+// adjoint states, the FP32 per-segment gradient and its FP64 total.
 struct AdjPlan {
     bool valid;
     int objective;
     int64_t n, c1, c2, t0;
     bool two_level;
     int64_t k1, k2, hlen;
-    size_t outer, inner, rec, hist, lam, grad, total;
+    size_t outer, inner, rec, hist, lam, grad, seg, total;
     size_t level_bytes, hist_bytes, lam_bytes;
     const void *ws;
     double a1, a2;
@@ -563,6 +563,7 @@ static lbk_status adj_plan(const lbk_lattice *lat, int64_t n, int64_t c1, int64_
     P.hist = take(P.hist_bytes * (size_t)(P.hlen + 1));
     P.lam = take(2 * P.lam_bytes);
     P.grad = take((size_t)rows * lat->L.pitch * 8);
+    P.seg = take((size_t)rows * lat->L.pitch * 4);
     P.total = o;
     return LBK_OK;
 }
@@ -667,6 +668,7 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
     float *lam[2] = {reinterpret_cast<float *>(w + P.lam),
                      reinterpret_cast<float *>(w + P.lam + P.lam_bytes)};
     double *grad = reinterpret_cast<double *>(w + P.grad);
+    float *seg = reinterpret_cast<float *>(w + P.seg);
     char *rec[2] = {level(P.rec, 0), level(P.rec, 1)};
     auto sweep = [&](const char *src, char *dst, float *hist) {
         return launch_sweep(d.storage, d.bc_x, d.bc_y, src, dst, lat->L.lay, lat->med(),
@@ -675,10 +677,11 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
     const float a1 = (float)P.a1, a2 = (float)P.a2;
 
     HIP_TRY(hipMemsetAsync(grad, 0, (size_t)d.ny * lat->L.pitch * 8, st));
+    HIP_TRY(hipMemsetAsync(seg, 0, (size_t)d.ny * lat->L.pitch * 4, st));
     // read-out of J at step n: linearisation point of the pull of S_n
     HIP_TRY(sweep(lat->state(lat->cur), rec[0], histp(0)));
     HIP_TRY(launch_adjoint(d.bc_x, d.bc_y, nullptr, lam[0], histp(0), lat->med(), lat->L.mlay,
-                           grad, lat->g, lat->ph, 1, a1, a2, P.outlet, st));
+                           seg, lat->g, lat->ph, 1, a1, a2, P.outlet, st));
     int cur = 0;
     for (int64_t k = P.k1 - 1; k >= 0; --k) {
         const int64_t a = k * P.c1, b = std::min(P.n, a + P.c1);
@@ -714,10 +717,11 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
             }
             for (int64_t t = b2s; t > a2s; --t) {
                 HIP_TRY(launch_adjoint(d.bc_x, d.bc_y, lam[cur], lam[cur ^ 1], histp(t - a2s),
-                                       lat->med(), lat->L.mlay, grad, lat->g, lat->ph, 0, a1, a2,
+                                       lat->med(), lat->L.mlay, seg, lat->g, lat->ph, 0, a1, a2,
                                        P.outlet, st));
                 cur ^= 1;
             }
+            HIP_TRY(launch_grad_fold(seg, grad, lat->g, st));
         }
     }
     HIP_TRY(launch_grad_out(grad, dJ_dlnk, lat->g, st));

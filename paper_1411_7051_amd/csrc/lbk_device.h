@@ -78,6 +78,10 @@ __device__ __forceinline__ float ld_f32(Rsrc r, uint32_t voff, uint32_t soff)
 {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
 }
+__device__ __forceinline__ float ld_f32_nt(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, kNT));
+}
 __device__ __forceinline__ void st_f32(Rsrc r, uint32_t voff, uint32_t soff, float v, bool nt)
 {
     if (nt)

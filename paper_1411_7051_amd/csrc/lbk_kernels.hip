@@ -135,9 +135,9 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const char *src, char *ds
         // linearisation point of this step for the adjoint: (rho, jx, jy)
         const uint32_t hrow = 3u * (uint32_t)g.pitch * 4u, hsl = (uint32_t)g.pitch * 4u;
         const Rsrc hr = make_rsrc(reinterpret_cast<char *>(hist) + (uint64_t)nd.y * hrow, hrow);
-        st_f32(hr, nd.x * 4, 0, rho, false);
-        st_f32(hr, nd.x * 4, hsl, jx, false);
-        st_f32(hr, nd.x * 4, 2 * hsl, jy, false);
+        st_f32(hr, nd.x * 4, 0, rho, true);
+        st_f32(hr, nd.x * 4, hsl, jx, true);
+        st_f32(hr, nd.x * 4, 2 * hsl, jy, true);
     }
     const float eps = md.eps(nd.x);
     velocity(ph, rho, jx, jy, eps, md.drag(nd.x), md.kn0(nd.x), ux, uy, Fx, Fy);
