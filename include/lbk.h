@@ -181,6 +181,70 @@ lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64_t n_steps,
  * of [ny][nx] float32.  Leaves the lattice state untouched. */
 lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws_bytes, float *dJ_dlnk);
 
+/* ---------------------------------------------------------------------
+ * Ensembles: many independent samples stepped together.
+ *
+ * A batch groups n lattices of uneven size (Sec. IV.C: heterogeneous
+ * samples, each with its own fields, tau, drive and Kn scale) so that one
+ * kernel launch advances every sample by one step.  The launch walks a list
+ * of tiles -- `tile` consecutive nodes of one row of one sample -- that
+ * covers all samples; either one workgroup per tile or a persistent grid of
+ * `grid` workgroups each taking a contiguous run of tiles.  Steps can be
+ * recorded into HIP graphs of `graph_steps` launches that are replayed.
+ * Each sample's update is the same arithmetic as lbk_step on that lattice,
+ * so results are bitwise identical to stepping the lattices one by one, for
+ * every launch configuration.
+ *
+ * The lattices stay owned by the caller (they must outlive the batch) and
+ * keep working as handles: read-outs, save/load and lbk_step may be used
+ * between batch calls.  All of them must share storage, bc_x, bc_y and
+ * the stream they were created on; the batch works on that stream.
+ * check_every is not applied by lbk_batch_step (see lbk_batch_check).
+ * --------------------------------------------------------------------- */
+typedef struct lbk_batch lbk_batch;
+
+/* Device workspace bytes for a batch over lats[0..n-1] (n >= 1). */
+lbk_status lbk_batch_workspace_size(lbk_lattice *const *lats, int32_t n, size_t *bytes);
+
+/* Create a batch over lats[0..n-1] in a caller-owned device workspace
+ * (256-byte aligned, ws_bytes >= lbk_batch_workspace_size).  The launch
+ * configuration starts at tile 256, one workgroup per tile, no graphs. */
+lbk_status lbk_batch_create(lbk_lattice *const *lats, int32_t n, void *workspace,
+                            size_t ws_bytes, lbk_batch **out);
+
+/* Release the batch (not the lattices or the workspace); NULL accepted. */
+lbk_status lbk_batch_destroy(lbk_batch *b);
+
+/* Advance every sample by n >= 0 steps (each lattice's time grows by n). */
+lbk_status lbk_batch_step(lbk_batch *b, int64_t n);
+
+/* Launch configuration: tile in {128, 256, 512} nodes (the workgroup size);
+ * grid 0 = one workgroup per tile, else a persistent grid of 1..2^20
+ * workgroups; graph_steps 0 = direct launches, else an even number of
+ * steps (2..1024) recorded per graph replay. */
+lbk_status lbk_batch_set_launch(lbk_batch *b, int32_t tile, int32_t grid,
+                                int32_t graph_steps);
+lbk_status lbk_batch_get_launch(const lbk_batch *b, int32_t *tile, int32_t *grid,
+                                int32_t *graph_steps);
+
+/* Time every tile width x grid candidate (one workgroup per tile and
+ * persistent grids of 2, 4, 8 and 16 workgroups per compute unit) over
+ * `reps` >= 1 steps each, and keep the fastest (graph_steps unchanged).
+ * The samples' states are left untouched: the timed launches re-read the
+ * current time level and overwrite only the other one.  best_us (may be
+ * NULL) receives the fastest mean time per step in microseconds.
+ * Synchronizes the stream. */
+lbk_status lbk_batch_autotune(lbk_batch *b, int32_t reps, double *best_us);
+
+/* Global permeability of every sample (as lbk_apparent_permeability of
+ * that lattice, bitwise) into host k_app[n], from one batched read-out.
+ * Synchronizes the stream. */
+lbk_status lbk_batch_apparent_permeability(lbk_batch *b, double *k_app);
+
+/* NaN/Inf check of every sample (and FP16 scale re-centring); returns
+ * LBK_ERR_NONFINITE naming the first bad sample.  Synchronizes. */
+lbk_status lbk_batch_check(lbk_batch *b);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *lbk_last_error(void);
 

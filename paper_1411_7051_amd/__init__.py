@@ -4,16 +4,20 @@ arXiv:1411.7051).
 
 The fused D2Q9 sweep and its read-outs are HIP kernels for gfx950 behind the
 C ABI of ``include/lbk.h`` (``liblbk.so``, built by ``build.py``);
-``Lattice`` is a thin ctypes binding over it.  ``inputs`` draws the seeded
+``Lattice`` and ``Batch`` (ensembles stepped together) are thin ctypes
+bindings over it.  ``inputs`` draws the seeded
 synthetic media.
 """
 from . import inputs  # noqa: F401
 
-__all__ = ["Lattice", "ApparentPermeability", "inputs", "make_desc", "workspace_bytes"]
+__all__ = ["Lattice", "Batch", "ApparentPermeability", "inputs", "make_desc", "workspace_bytes"]
 
 
 def __getattr__(name):
     if name in ("Lattice", "ApparentPermeability", "make_desc", "workspace_bytes"):
         from . import lattice
         return getattr(lattice, name)
+    if name == "Batch":
+        from .batch import Batch
+        return Batch
     raise AttributeError(name)

@@ -71,6 +71,19 @@ _SIG = {
                                            ctypes.c_int64, _P, ctypes.c_size_t,
                                            ctypes.POINTER(ctypes.c_double)]),
     "lbk_adjoint_backward": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+    "lbk_batch_workspace_size": (ctypes.c_int, [_P, ctypes.c_int32,
+                                                ctypes.POINTER(ctypes.c_size_t)]),
+    "lbk_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_size_t,
+                                        ctypes.POINTER(_P)]),
+    "lbk_batch_destroy": (ctypes.c_int, [_P]),
+    "lbk_batch_step": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "lbk_batch_set_launch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "lbk_batch_get_launch": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32)]),
+    "lbk_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "lbk_batch_apparent_permeability": (ctypes.c_int, [_P, _P]),
+    "lbk_batch_check": (ctypes.c_int, [_P]),
     "lbk_last_error": (ctypes.c_char_p, []),
 }
 

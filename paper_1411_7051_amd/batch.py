@@ -1,0 +1,133 @@
+"""Ensembles: ``Batch`` steps many ``Lattice`` samples of uneven size with one
+kernel launch per step (optionally replayed from HIP graphs), wrapping one
+``lbk_batch`` handle.  The launch configuration comes from the library's
+tuner, remembered in an optional JSON cache keyed by the batch's shape."""
+from __future__ import annotations
+
+import ctypes
+import hashlib
+import json
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+from .lattice import Lattice
+
+
+class Batch:
+    """Step ``lattices`` together.  All must share storage, boundary kinds,
+    device and stream (torch's current stream when they were created)."""
+
+    def __init__(self, lattices: Sequence[Lattice]):
+        if not lattices:
+            raise ValueError("a batch needs at least one lattice")
+        self.lattices = list(lattices)
+        self.device = self.lattices[0].device
+        lib = _lib.load()
+        n = len(self.lattices)
+        self._arr = (ctypes.c_void_p * n)(*[l._handle().value for l in self.lattices])
+        nbytes = ctypes.c_size_t()
+        check(lib.lbk_batch_workspace_size(self._arr, n, ctypes.byref(nbytes)))
+        self._ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib.lbk_batch_create(self._arr, n, self._ws.data_ptr(), self._ws.numel(),
+                                       ctypes.byref(h)))
+        self._h = h
+
+    def __len__(self) -> int:
+        return len(self.lattices)
+
+    # -- lifetime
+    def close(self) -> None:
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.load().lbk_batch_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _handle(self):
+        if self._h is None:
+            raise RuntimeError("batch is closed")
+        return self._h
+
+    # -- stepping
+    def step(self, n: int = 1) -> "Batch":
+        check(_lib.load().lbk_batch_step(self._handle(), int(n)))
+        return self
+
+    def set_launch(self, tile: int = 256, grid: int = 0, graph_steps: int = 0) -> None:
+        check(_lib.load().lbk_batch_set_launch(self._handle(), int(tile), int(grid),
+                                               int(graph_steps)))
+
+    @property
+    def launch(self):
+        """(tile, grid, graph_steps)."""
+        t, g, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(_lib.load().lbk_batch_get_launch(self._handle(), ctypes.byref(t), ctypes.byref(g),
+                                               ctypes.byref(s)))
+        return int(t.value), int(g.value), int(s.value)
+
+    def signature(self) -> str:
+        """Key of this batch's shape for the tuning cache: device, storage,
+        boundary kinds and the sorted sample sizes."""
+        l0 = self.lattices[0]
+        sizes = sorted((l.nx, l.ny) for l in self.lattices)
+        key = json.dumps([torch.cuda.get_device_name(self.device), int(l0.desc.storage),
+                          int(l0.desc.bc_x), int(l0.desc.bc_y), sizes])
+        return hashlib.sha1(key.encode()).hexdigest()[:16]
+
+    def autotune(self, reps: int = 10, cache: Optional[str] = None) -> float:
+        """Pick the fastest (tile, grid) for this batch, leaving the samples'
+        states untouched; returns the mean step time in microseconds (NaN when
+        taken from ``cache``, a JSON file of signature -> [tile, grid, us])."""
+        sig = self.signature()
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as f:
+                table = json.load(f)
+            if sig in table:
+                tile, grid, _ = table[sig]
+                self.set_launch(tile, grid, self.launch[2])
+                return float("nan")
+        us = ctypes.c_double()
+        check(_lib.load().lbk_batch_autotune(self._handle(), int(reps), ctypes.byref(us)))
+        if cache:
+            tile, grid, _ = self.launch
+            table[sig] = [tile, grid, float(us.value)]
+            tmp = cache + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(table, f, indent=1, sort_keys=True)
+            os.replace(tmp, cache)
+        return float(us.value)
+
+    # -- read-out
+    def apparent_permeability(self) -> np.ndarray:
+        """Global permeability of every sample (float64 [n])."""
+        out = np.empty(len(self), dtype=np.float64)
+        check(_lib.load().lbk_batch_apparent_permeability(
+            self._handle(), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def check(self) -> None:
+        """NaN/Inf check of every sample (and FP16 scale re-centring)."""
+        check(_lib.load().lbk_batch_check(self._handle()))
+
+
+def ensemble_lattices(cases, device=None, **overrides):
+    """One ``Lattice`` per input case (``inputs.Case``), created on the
+    current stream; keyword overrides apply to every case's parameters."""
+    out = []
+    for c in cases:
+        params = dict(c.params, **overrides)
+        out.append(Lattice(c.eps, c.k, c.kn0, device=device, **params))
+    return out

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbk.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
-SOURCES = ["lbk_kernels.hip", "lbk_adjoint.hip", "lbk_api.hip"]
+SOURCES = ["lbk_kernels.hip", "lbk_adjoint.hip", "lbk_api.hip", "lbk_batch.hip"]
 HEADERS = ["lbk_device.h", "lbk_kernels.h", "lbk_adjoint.h"]
 
 FLAGS = [
@@ -17,6 +17,10 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse a*b+c only within one source expression: the node update then
+    # rounds identically in every kernel that inlines it (single lattice,
+    # batched tile list, adjoint recompute), whatever the control flow around
+    "-ffp-contract=on",
 ]
 
 

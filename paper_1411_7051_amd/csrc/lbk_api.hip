@@ -1,9 +1,8 @@
 // lbk_api.hip -- host side of the C ABI declared in include/lbk.h: argument
 // validation, workspace carve-up, launch sequencing on the caller's stream,
 // FP64 diagnostics and state save/load.  No kernels live here.
-#include "lbk.h"
 #include "lbk_adjoint.h"
-#include "lbk_kernels.h"
+#include "lbk_host.h"
 
 #include <math.h>
 #include <stdarg.h>
@@ -17,11 +16,10 @@
 using namespace lbk;
 
 namespace {
-
 thread_local std::string g_err;
+} // namespace
 
-lbk_status fail(lbk_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
-lbk_status fail(lbk_status s, const char *fmt, ...)
+lbk_status lbk::fail(lbk_status s, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -32,32 +30,9 @@ lbk_status fail(lbk_status s, const char *fmt, ...)
     return s;
 }
 
-#define HIP_TRY(expr)                                                                        \
-    do {                                                                                     \
-        hipError_t e_ = (expr);                                                              \
-        if (e_ != hipSuccess)                                                                \
-            return fail(LBK_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));             \
-    } while (0)
-
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+namespace {
 
 size_t elem_size(int storage) { return storage == LBK_F32 ? 4 : 2; }
-
-// Byte offsets of every region in the workspace, and the strided layouts
-// the kernels use.  Each time level of the state is ny row blocks of
-// [rho FP32 | h_0 .. h_8 T], each slot `pitch` elements; the medium is ny
-// row blocks of [eps | drag | kn0] FP32.
-struct WsLayout {
-    int pitch;
-    Layout lay;           // state row layout
-    MLayout mlay;         // medium row layout
-    size_t level_bytes;   // bytes of one time level
-    size_t level[2];      // two time levels
-    size_t med, uxp, uyp; // medium; previous velocity for the residual
-    size_t partials, results;
-    size_t total;
-    int blocks;
-};
 
 WsLayout layout_of(const lbk_desc &d)
 {
@@ -134,51 +109,8 @@ void split(double v, float &hi, float &lo)
 
 } // namespace
 
-// Byte offsets of an adjoint workspace for (n, c1, c2): outer checkpoints
-// every c1 steps, inner checkpoints every c2 steps (two-level only), two
-// recompute levels, c2 + 1 history slots (c1 + 1 for one level), two
-// adjoint states, the FP32 per-segment gradient and its FP64 total.
-struct AdjPlan {
-    bool valid;
-    int objective;
-    int64_t n, c1, c2, t0;
-    bool two_level;
-    int64_t k1, k2, hlen;
-    size_t outer, inner, rec, hist, lam, grad, seg, total;
-    size_t level_bytes, hist_bytes, lam_bytes;
-    const void *ws;
-    double a1, a2;
-    int outlet;
-};
-
-struct lbk_lattice {
-    lbk_desc d;
-    WsLayout L;
-    Geom g;
-    Physics ph;
-    hipStream_t stream;
-    char *ws;
-    int cur;       // time level holding the current state
-    int64_t t;     // steps taken
-    int scale_exp; // FP16: stored = h * 2^scale_exp
-    bool have_prev;
-    double eps_b;  // mean porosity of the two pressure columns
-    double *host;  // pinned scratch for results (8 doubles)
-    int64_t since_check;
-    AdjPlan adj;
-
-    char *state(int l) const { return ws + L.level[l]; }
-    char *med() const { return ws + L.med; }
-    float s() const { return ldexpf(1.0f, scale_exp); }
-    float inv_s() const { return ldexpf(1.0f, -scale_exp); }
-    double *partials() const { return reinterpret_cast<double *>(ws + L.partials); }
-    double *results() const { return reinterpret_cast<double *>(ws + L.results); }
-};
-
-namespace {
-
 // Run a reduction's finish kernel and copy `slots` doubles to lat->host.
-lbk_status fetch(lbk_lattice *lat, int slots, unsigned max_mask)
+lbk_status lbk::fetch(lbk_lattice *lat, int slots, unsigned max_mask)
 {
     HIP_TRY(launch_finish(lat->partials(), slots, lat->L.blocks, max_mask, lat->results(),
                           lat->stream));
@@ -190,7 +122,7 @@ lbk_status fetch(lbk_lattice *lat, int slots, unsigned max_mask)
 
 // NaN/Inf check of the current state; for FP16 also re-centre the scale so
 // the largest stored magnitude sits near 2^12 (exact power-of-two rescale).
-lbk_status check_state(lbk_lattice *lat)
+lbk_status lbk::check_state(lbk_lattice *lat)
 {
     char *s = lat->state(lat->cur);
     HIP_TRY(launch_state_sums(lat->d.storage, s, lat->L.lay, lat->g, lat->inv_s(),
@@ -217,8 +149,6 @@ lbk_status check_state(lbk_lattice *lat)
     }
     return LBK_OK;
 }
-
-} // namespace
 
 extern "C" {
 
@@ -426,7 +356,19 @@ lbk_status lbk_read_populations(lbk_lattice *lat, double *f)
     return LBK_OK;
 }
 
-static lbk_status macro_sums(lbk_lattice *lat, bool residual)
+} // extern "C"
+
+double lbk::k_app_of(const lbk_lattice *lat, const double *sums)
+{
+    const lbk_desc &d = lat->d;
+    const double n = (double)d.nx * d.ny, nu = (d.tau - 0.5) / 3.0;
+    if (d.bc_x == LBK_BC_PRESSURE)
+        return lat->eps_b * nu * (d.nx - 1) * (sums[MAC_FLUX] / n) /
+               ((1.0 / 3.0) * (d.rho_in - d.rho_out));
+    return nu * (sums[MAC_UX] / n) / d.gx;
+}
+
+lbk_status lbk::macro_sums(lbk_lattice *lat, bool residual)
 {
     const lbk_desc &d = lat->d;
     char *ws = lat->ws;
@@ -438,6 +380,8 @@ static lbk_status macro_sums(lbk_lattice *lat, bool residual)
     return fetch(lat, MAC_SLOTS, 0);
 }
 
+extern "C" {
+
 lbk_status lbk_apparent_permeability(lbk_lattice *lat, double *k_app)
 {
     if (!lat || !k_app)
@@ -445,13 +389,7 @@ lbk_status lbk_apparent_permeability(lbk_lattice *lat, double *k_app)
     lbk_status s = macro_sums(lat, false);
     if (s != LBK_OK)
         return s;
-    const lbk_desc &d = lat->d;
-    const double n = (double)d.nx * d.ny, nu = (d.tau - 0.5) / 3.0;
-    if (d.bc_x == LBK_BC_PRESSURE)
-        *k_app = lat->eps_b * nu * (d.nx - 1) * (lat->host[MAC_FLUX] / n) /
-                 ((1.0 / 3.0) * (d.rho_in - d.rho_out));
-    else
-        *k_app = nu * (lat->host[MAC_UX] / n) / d.gx;
+    *k_app = k_app_of(lat, lat->host);
     return LBK_OK;
 }
 

@@ -1,0 +1,110 @@
+// lbk_host.h -- host-side internals shared by the C ABI sources (not part of
+// the public interface): the lattice handle, its workspace layout, the
+// per-thread error message and helpers that sequence launches on the
+// handle's stream.
+#pragma once
+
+#include "lbk.h"
+#include "lbk_kernels.h"
+
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lbk {
+
+// Record a formatted message as the calling thread's last error; returns s.
+lbk_status fail(lbk_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define HIP_TRY(expr)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(LBK_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));             \
+    } while (0)
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Byte offsets of every region in the workspace, and the strided layouts
+// the kernels use.  Each time level of the state is ny row blocks of
+// [rho FP32 | h_0 .. h_8 T], each slot `pitch` elements; the medium is ny
+// row blocks of [eps | drag | kn0] FP32.
+struct WsLayout {
+    int pitch;
+    Layout lay;           // state row layout
+    MLayout mlay;         // medium row layout
+    size_t level_bytes;   // bytes of one time level
+    size_t level[2];      // two time levels
+    size_t med, uxp, uyp; // medium; previous velocity for the residual
+    size_t partials, results;
+    size_t total;
+    int blocks;
+};
+
+// Byte offsets of an adjoint workspace for (n, c1, c2): outer checkpoints
+// every c1 steps, inner checkpoints every c2 steps (two-level only), two
+// recompute levels, c2 + 1 history slots (c1 + 1 for one level), two
+// adjoint states, the FP32 per-segment gradient and its FP64 total.
+struct AdjPlan {
+    bool valid;
+    int objective;
+    int64_t n, c1, c2, t0;
+    bool two_level;
+    int64_t k1, k2, hlen;
+    size_t outer, inner, rec, hist, lam, grad, seg, total;
+    size_t level_bytes, hist_bytes, lam_bytes;
+    const void *ws;
+    double a1, a2;
+    int outlet;
+};
+
+// Global permeability (Sec. IV.A, Darcy's law) from read-out sums
+// (MAC_* slots over every node).
+double k_app_of(const lbk_lattice *lat, const double *sums);
+
+} // namespace lbk
+
+struct lbk_lattice {
+    using WsLayout = lbk::WsLayout;
+    using AdjPlan = lbk::AdjPlan;
+    using Geom = lbk::Geom;
+    using Physics = lbk::Physics;
+    lbk_desc d;
+    WsLayout L;
+    Geom g;
+    Physics ph;
+    hipStream_t stream;
+    char *ws;
+    int cur;       // time level holding the current state
+    int64_t t;     // steps taken
+    int scale_exp; // FP16: stored = h * 2^scale_exp
+    bool have_prev;
+    double eps_b;  // mean porosity of the two pressure columns
+    double *host;  // pinned scratch for results (8 doubles)
+    int64_t since_check;
+    AdjPlan adj;
+
+    char *state(int l) const { return ws + L.level[l]; }
+    char *med() const { return ws + L.med; }
+    float s() const { return ldexpf(1.0f, scale_exp); }
+    float inv_s() const { return ldexpf(1.0f, -scale_exp); }
+    double *partials() const { return reinterpret_cast<double *>(ws + L.partials); }
+    double *results() const { return reinterpret_cast<double *>(ws + L.results); }
+};
+
+namespace lbk {
+
+// Finish kernel over the handle's partials, `slots` doubles into lat->host
+// (synchronizes the stream).
+lbk_status fetch(lbk_lattice *lat, int slots, unsigned max_mask);
+
+// NaN/Inf check of the current state; FP16 also re-centres the scale.
+lbk_status check_state(lbk_lattice *lat);
+
+// Read-out sums (MAC_* slots) of the current state into lat->host.
+lbk_status macro_sums(lbk_lattice *lat, bool residual);
+
+// Global permeability (Sec. IV.A, Darcy's law) from read-out sums
+// (MAC_* slots over every node).
+double k_app_of(const lbk_lattice *lat, const double *sums);
+
+} // namespace lbk

@@ -18,6 +18,20 @@ struct Launch {
 
 Launch launch_of(const Geom &g);
 
+// One sample of a batch: its two time levels, medium, layouts, scalars and
+// FP16 scale, and where its tiles sit in the batch's tile list (tile0,
+// tiles per row).
+struct SampleDesc {
+    char *state[2];
+    const char *med;
+    Layout lay;
+    MLayout mlay;
+    Geom g;
+    Physics ph;
+    float s, inv_s;
+    int tile0, tpr;
+};
+
 // Slots of the FP64 block partials written by the reduction kernels.
 enum {
     MAC_FLUX = 0, // sum rho u_x
@@ -80,5 +94,21 @@ hipError_t launch_populations(int storage, const char *src, const Layout &lay, c
 // Multiply every stored deviation by 2^k (FP16 scale re-centring; exact).
 hipError_t launch_rescale(int storage, char *state, const Layout &lay, const Geom &g, int k,
                           hipStream_t st);
+
+// One step of every sample of a batch, parity -> parity ^ 1.  tile: nodes
+// per tile (128, 256 or 512; the block size); grid > 0: persistent launch of
+// grid blocks each sweeping a contiguous tile range, 0: one block per tile.
+hipError_t launch_batch_sweep(int storage, int bcx, int bcy, const SampleDesc *samples,
+                              const int *tile_sample, int ntiles, int parity, int tile, int grid,
+                              hipStream_t st);
+
+// Read-out partials of every sample over tiles of kBlock nodes
+// ([MAC_SLOTS][ntiles]) and their per-sample fixed-order sums
+// out[nsamples][slots].
+hipError_t launch_batch_macro(int storage, int bcx, int bcy, const SampleDesc *samples,
+                              const int *tile_sample, int ntiles, int parity, double *partials,
+                              hipStream_t st);
+hipError_t launch_batch_finish(const SampleDesc *samples, int nsamples, const double *partials,
+                               int slots, int ntiles, double *out, hipStream_t st);
 
 } // namespace lbk

@@ -112,19 +112,18 @@ __device__ __forceinline__ float post_stream(const Rows &R, const Layout &L, con
     return density<T>(rc, d, inv_s, inc, r);
 }
 
+// Full update of node (x, y): pull, boundary override, moments, velocity,
+// collide, store; with HIST also the step's linearisation point.
 template <typename T, int BCX, int BCY, bool HIST>
-__global__ __launch_bounds__(kBlock) void sweep_kernel(const char *src, char *dst, Layout lay,
-                                                        const char *med, MLayout mlay, Geom g,
-                                                        Physics ph, float s, float inv_s,
-                                                        float *hist, int bpr)
+__device__ __forceinline__ void sweep_node(const char *src, char *dst, const Layout &lay,
+                                           const char *med, const MLayout &mlay, const Geom &g,
+                                           const Physics &ph, float s, float inv_s, float *hist,
+                                           int y, uint32_t x)
 {
-    const Node nd = node_of(bpr);
-    if (nd.x >= (uint32_t)g.nx)
-        return;
-    const Rows R = rows_of<BCY>(src, lay, g, nd.y);
-    const Med md{med_row(med, mlay, nd.y), mlay.slot};
+    const Rows R = rows_of<BCY>(src, lay, g, y);
+    const Med md{med_row(med, mlay, y), mlay.slot};
     float d[9], inc, r;
-    const float rho = post_stream<T, BCX>(R, lay, md, g, ph, s, inv_s, nd.x, d, inc, r);
+    const float rho = post_stream<T, BCX>(R, lay, md, g, ph, s, inv_s, x, d, inc, r);
     float jx, jy, ux, uy, Fx, Fy;
     momentum(d, jx, jy);
     if (Elem<T>::kScaled) {
@@ -134,21 +133,76 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const char *src, char *ds
     if (HIST) {
         // linearisation point of this step for the adjoint: (rho, jx, jy)
         const uint32_t hrow = 3u * (uint32_t)g.pitch * 4u, hsl = (uint32_t)g.pitch * 4u;
-        const Rsrc hr = make_rsrc(reinterpret_cast<char *>(hist) + (uint64_t)nd.y * hrow, hrow);
-        st_f32(hr, nd.x * 4, 0, rho, true);
-        st_f32(hr, nd.x * 4, hsl, jx, true);
-        st_f32(hr, nd.x * 4, 2 * hsl, jy, true);
+        const Rsrc hr = make_rsrc(reinterpret_cast<char *>(hist) + (uint64_t)y * hrow, hrow);
+        st_f32(hr, x * 4, 0, rho, true);
+        st_f32(hr, x * 4, hsl, jx, true);
+        st_f32(hr, x * 4, 2 * hsl, jy, true);
     }
-    const float eps = md.eps(nd.x);
-    velocity(ph, rho, jx, jy, eps, md.drag(nd.x), md.kn0(nd.x), ux, uy, Fx, Fy);
+    const float eps = md.eps(x);
+    velocity(ph, rho, jx, jy, eps, md.drag(x), md.kn0(x), ux, uy, Fx, Fy);
     float hs[9];
     collide<T>(ph, rho, inc, r, d, ux, uy, Fx, Fy, eps, s, hs);
-    const Rsrc out = make_rsrc(dst + (uint64_t)nd.y * lay.row, (uint32_t)lay.row);
-    st_f32(out, nd.x * 4, 0, rho, true);
+    const Rsrc out = make_rsrc(dst + (uint64_t)y * lay.row, (uint32_t)lay.row);
+    st_f32(out, x * 4, 0, rho, true);
     constexpr uint32_t es = sizeof(T);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        Elem<T>::st(out, nd.x * es, lay.h_off + i * lay.h_slot, hs[i]);
+        Elem<T>::st(out, x * es, lay.h_off + i * lay.h_slot, hs[i]);
+}
+
+template <typename T, int BCX, int BCY, bool HIST>
+__global__ __launch_bounds__(kBlock) void sweep_kernel(const char *src, char *dst, Layout lay,
+                                                        const char *med, MLayout mlay, Geom g,
+                                                        Physics ph, float s, float inv_s,
+                                                        float *hist, int bpr)
+{
+    const Node nd = node_of(bpr);
+    if (nd.x >= (uint32_t)g.nx)
+        return;
+    sweep_node<T, BCX, BCY, HIST>(src, dst, lay, med, mlay, g, ph, s, inv_s, hist, nd.y, nd.x);
+}
+
+// -------------------------------------------------------------- batches
+//
+// A batch steps many independent lattices (samples of uneven size, each
+// with its own layout, medium and scalars) in one launch per step.  The
+// work list is the concatenation of every sample's tiles -- TILE
+// consecutive x of one row -- in sample order, rows in order; tile_sample
+// maps a tile to its sample.  PERSIST = false: one block per tile, in the
+// XCD-band order of the single-lattice kernels.  PERSIST = true: a fixed
+// grid whose block b sweeps the contiguous tile range
+// [b T / G, (b + 1) T / G), so one block walks down neighbouring rows and
+// reuses their densities in its XCD's L2.
+
+template <typename T, int BCX, int BCY, int TILE>
+__device__ __forceinline__ void batch_tile(const SampleDesc *samples, const int *tile_sample,
+                                           int parity, int t)
+{
+    const int si = tile_sample[t];
+    const SampleDesc &sd = samples[si];
+    const int rel = t - sd.tile0;
+    const int y = rel / sd.tpr;
+    const uint32_t x = (uint32_t)(rel - y * sd.tpr) * TILE + threadIdx.x;
+    if (x >= (uint32_t)sd.g.nx)
+        return;
+    sweep_node<T, BCX, BCY, false>(sd.state[parity], sd.state[parity ^ 1], sd.lay, sd.med,
+                                   sd.mlay, sd.g, sd.ph, sd.s, sd.inv_s, nullptr, y, x);
+}
+
+template <typename T, int BCX, int BCY, int TILE, bool PERSIST>
+__global__ __launch_bounds__(TILE) void batch_sweep_kernel(const SampleDesc *samples,
+                                                            const int *tile_sample, int ntiles,
+                                                            int parity)
+{
+    if (PERSIST) {
+        const int G = gridDim.x, b = blockIdx.x;
+        const int t0 = (int)((int64_t)b * ntiles / G), t1 = (int)((int64_t)(b + 1) * ntiles / G);
+        for (int t = t0; t < t1; ++t)
+            batch_tile<T, BCX, BCY, TILE>(samples, tile_sample, parity, t);
+    } else {
+        batch_tile<T, BCX, BCY, TILE>(samples, tile_sample, parity,
+                                      xcd_remap(blockIdx.x, gridDim.x));
+    }
 }
 
 // ----------------------------------------------------------- reductions
@@ -264,6 +318,69 @@ __global__ __launch_bounds__(kBlock) void state_sums_kernel(const char *src, Lay
     r = block_reduce<SumOp>(bad, sh);
     if (threadIdx.x == 0)
         partials[(int64_t)ST_BAD * gridDim.x + nd.L] = r;
+}
+
+// Read-out of every sample of a batch: per-tile FP64 partials
+// [MAC_SLOTS][ntiles] (tiles of kBlock nodes), reduced per sample by
+// batch_finish_kernel in a fixed order.
+template <typename T, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) void batch_macro_kernel(const SampleDesc *samples,
+                                                              const int *tile_sample, int ntiles,
+                                                              int parity, double *partials)
+{
+    __shared__ double sh[kBlock / 64];
+    const int t = blockIdx.x;
+    const int si = tile_sample[t];
+    const SampleDesc &sd = samples[si];
+    const int rel = t - sd.tile0;
+    const int y = rel / sd.tpr;
+    const uint32_t x = (uint32_t)(rel - y * sd.tpr) * kBlock + threadIdx.x;
+    double v[MAC_SLOTS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (x < (uint32_t)sd.g.nx) {
+        const Rows R = rows_of<BCY>(sd.state[parity], sd.lay, sd.g, y);
+        const Med md{med_row(sd.med, sd.mlay, y), sd.mlay.slot};
+        float d[9], inc, r;
+        const float rho =
+            post_stream<T, BCX>(R, sd.lay, md, sd.g, sd.ph, sd.s, sd.inv_s, x, d, inc, r);
+        float jx, jy, ux, uy, Fx, Fy;
+        momentum(d, jx, jy);
+        if (Elem<T>::kScaled) {
+            jx *= sd.inv_s;
+            jy *= sd.inv_s;
+        }
+        velocity(sd.ph, rho, jx, jy, md.eps(x), md.drag(x), md.kn0(x), ux, uy, Fx, Fy);
+        const double rp = (double)rho + (double)r;
+        v[MAC_FLUX] = rp * (double)ux;
+        v[MAC_UX] = ux;
+        v[MAC_U2] = (double)ux * ux + (double)uy * uy;
+        v[MAC_RHO] = rp;
+        v[MAC_QOUT] = (x == (uint32_t)sd.g.nx - 1) ? rp * (double)ux : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < MAC_SLOTS; ++k) {
+        const double rr = block_reduce<SumOp>(v[k], sh);
+        if (threadIdx.x == 0)
+            partials[(int64_t)k * ntiles + t] = rr;
+    }
+}
+
+// out[s][k] = sum of partials[k][tile0(s) .. tile0(s) + tiles(s)) in order.
+__global__ __launch_bounds__(kBlock) void batch_finish_kernel(const SampleDesc *samples,
+                                                               const double *partials, int slots,
+                                                               int ntiles, double *out)
+{
+    __shared__ double sh[kBlock / 64];
+    const SampleDesc &sd = samples[blockIdx.x];
+    const int t0 = sd.tile0, n = sd.tpr * sd.g.ny;
+    for (int k = 0; k < slots; ++k) {
+        const double *p = partials + (int64_t)k * ntiles + t0;
+        double v = 0.0;
+        for (int j = threadIdx.x; j < n; j += kBlock)
+            v += p[j];
+        const double r = block_reduce<SumOp>(v, sh);
+        if (threadIdx.x == 0)
+            out[(int64_t)blockIdx.x * slots + k] = r;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void finish_kernel(const double *partials, int slots,
@@ -503,6 +620,65 @@ hipError_t launch_rescale(int storage, char *state, const Layout &lay, const Geo
 {
     const float f = ldexpf(1.0f, k);
     LBK_LAUNCH_T(rescale_kernel, state, lay, g, f);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------- batch launch
+
+template <typename T, int BCX, int BCY>
+static hipError_t batch_sweep_t(const SampleDesc *samples, const int *tile_sample, int ntiles,
+                                int parity, int tile, int grid, hipStream_t st)
+{
+    const bool persist = grid > 0;
+    const int nb = persist ? grid : ntiles;
+#define LBK_BS(TL, P)                                                                        \
+    hipLaunchKernelGGL((batch_sweep_kernel<T, BCX, BCY, TL, P>), dim3(nb), dim3(TL), 0, st,  \
+                       samples, tile_sample, ntiles, parity)
+    switch (tile * 2 + (persist ? 1 : 0)) {
+    case 256: LBK_BS(128, false); break;
+    case 257: LBK_BS(128, true); break;
+    case 512: LBK_BS(256, false); break;
+    case 513: LBK_BS(256, true); break;
+    case 1024: LBK_BS(512, false); break;
+    case 1025: LBK_BS(512, true); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef LBK_BS
+    return hipGetLastError();
+}
+
+template <typename T, int BCX, int BCY>
+static hipError_t batch_macro_t(const SampleDesc *samples, const int *tile_sample, int ntiles,
+                                int parity, double *partials, hipStream_t st)
+{
+    hipLaunchKernelGGL((batch_macro_kernel<T, BCX, BCY>), dim3(ntiles), dim3(kBlock), 0, st,
+                       samples, tile_sample, ntiles, parity, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sweep(int storage, int bcx, int bcy, const SampleDesc *samples,
+                              const int *tile_sample, int ntiles, int parity, int tile, int grid,
+                              hipStream_t st)
+{
+    if (bcy < 0 || bcy > 1)
+        return hipErrorInvalidValue;
+    LBK_DISPATCH(batch_sweep_t, samples, tile_sample, ntiles, parity, tile, grid, st)
+}
+
+hipError_t launch_batch_macro(int storage, int bcx, int bcy, const SampleDesc *samples,
+                              const int *tile_sample, int ntiles, int parity, double *partials,
+                              hipStream_t st)
+{
+    if (bcy < 0 || bcy > 1)
+        return hipErrorInvalidValue;
+    LBK_DISPATCH(batch_macro_t, samples, tile_sample, ntiles, parity, partials, st)
+}
+
+hipError_t launch_batch_finish(const SampleDesc *samples, int nsamples, const double *partials,
+                               int slots, int ntiles, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(batch_finish_kernel, dim3(nsamples), dim3(kBlock), 0, st, samples,
+                       partials, slots, ntiles, out);
     return hipGetLastError();
 }
 

@@ -102,3 +102,22 @@ def test_create_without_gpu_reports_device_error():
     st = lib.lbk_create(ctypes.byref(d), f.ctypes.data, f.ctypes.data, None, ws, n, None,
                         ctypes.byref(out))
     assert st == -2 and out.value is None
+
+
+def test_batch_null_arguments_rejected():
+    lib = _lib.load()
+    out = ctypes.c_void_p()
+    n = ctypes.c_size_t()
+    assert lib.lbk_batch_workspace_size(None, 1, ctypes.byref(n)) == -1
+    arr = (ctypes.c_void_p * 1)(None)
+    assert lib.lbk_batch_workspace_size(arr, 1, ctypes.byref(n)) == -1
+    assert b"lats[0] is NULL" in lib.lbk_last_error()
+    assert lib.lbk_batch_workspace_size(arr, 0, ctypes.byref(n)) == -1
+    assert lib.lbk_batch_create(arr, 1, None, 0, ctypes.byref(out)) == -1
+    assert out.value is None
+    assert lib.lbk_batch_step(None, 1) == -1
+    assert lib.lbk_batch_set_launch(None, 256, 0, 0) == -1
+    assert lib.lbk_batch_autotune(None, 1, None) == -1
+    assert lib.lbk_batch_apparent_permeability(None, None) == -1
+    assert lib.lbk_batch_check(None) == -1
+    assert lib.lbk_batch_destroy(None) == 0

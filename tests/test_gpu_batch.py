@@ -1,0 +1,186 @@
+"""Ensembles (through the C ABI): a batch of uneven samples stepped with one
+launch per step must leave every sample bitwise equal to the same lattice
+stepped alone, for every launch configuration (tile width, one workgroup per
+tile or persistent grids, graph replay), and match the FP64 oracle like the
+single-lattice path."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1411_7051_amd import inputs
+from paper_1411_7051_amd.batch import Batch, ensemble_lattices
+from paper_1411_7051_amd.lattice import Lattice
+
+pytestmark = pytest.mark.gpu
+
+VEL_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = torch.device("cuda", 0)
+    torch.cuda.set_device(d)
+    return d
+
+
+# uneven sizes: single tiles, ragged tails of every tile width, one row
+SIZES = [(37, 13), (300, 20), (129, 5), (513, 9), (256, 3), (64, 64), (1030, 2), (3, 1)]
+
+
+def cases(bcx, bcy, seed=500, sizes=SIZES):
+    out = []
+    for i, (nx, ny) in enumerate(sizes):
+        drive = (dict(rho_in=1.01 + 0.01 * i, rho_out=1.0, init=1) if bcx == inputs.PRESSURE
+                 else dict(gx=1e-5 * (1 + i), gy=-2e-6))
+        out.append(inputs.random_medium(nx, ny, seed=seed + i, solid_frac=0.05, pore_frac=0.05,
+                                        bc_x=bcx, bc_y=bcy, tau=0.6 + 0.05 * i, **drive))
+    return out
+
+
+def state_of(lat):
+    return lat.populations()
+
+
+def assert_same(batch_lats, solo_lats):
+    for i, (a, b) in enumerate(zip(batch_lats, solo_lats)):
+        assert a.time == b.time
+        fa, fb = state_of(a), state_of(b)
+        assert torch.equal(fa, fb), f"sample {i}: max |diff| {float((fa - fb).abs().max()):.3e}"
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("bcx,bcy", [(0, 0), (0, 1), (1, 1), (2, 0), (2, 1)])
+def test_batch_bitwise_equals_solo(dev, storage, bcx, bcy):
+    cs = cases(bcx, bcy)
+    if bcx == inputs.PRESSURE:
+        cs = [c for c in cs if c.eps.shape[1] >= 3]
+    lats = ensemble_lattices(cs, device=dev, storage=storage)
+    solo = ensemble_lattices(cs, device=dev, storage=storage)
+    b = Batch(lats)
+    b.step(23)
+    for l in solo:
+        l.step(23)
+    assert_same(lats, solo)
+    kb = b.apparent_permeability()
+    ks = np.array([l.apparent_permeability() for l in solo])
+    assert np.array_equal(kb, ks)
+
+
+LAUNCHES = [(t, g, s) for t in (128, 256, 512) for g in (0, 512, 4096) for s in (0, 4)]
+
+
+def test_launch_configurations_agree(dev):
+    cs = cases(2, 1, seed=600)
+    ref = ensemble_lattices(cs, device=dev)
+    for l in ref:
+        l.step(11)
+    for tile, grid, gs in LAUNCHES:
+        lats = ensemble_lattices(cs, device=dev)
+        b = Batch(lats)
+        b.set_launch(tile, grid, gs)
+        assert b.launch == (tile, grid, gs)
+        b.step(3).step(8)  # odd counts: direct steps around graph replays
+        assert_same(lats, ref)
+        b.close()
+
+
+def test_graph_replays_match_eager(dev):
+    """Repeated graph replays, with eager work and synchronisation between
+    them, give the eager trajectory at every replay."""
+    cs = cases(0, 1, seed=650)
+    lats = ensemble_lattices(cs, device=dev, storage="f16")
+    solo = ensemble_lattices(cs, device=dev, storage="f16")
+    b = Batch(lats)
+    b.set_launch(256, 1024, 6)
+    for rep in range(4):
+        b.step(6)
+        for l in solo:
+            l.step(6)
+        torch.cuda.synchronize()
+        assert_same(lats, solo)
+        _ = b.apparent_permeability()
+
+
+def test_outside_steps_and_loads_resync(dev):
+    """Lattices stepped or reloaded on their own between batch calls stay
+    consistent with the batch."""
+    cs = cases(2, 0, seed=700)
+    lats = ensemble_lattices(cs, device=dev)
+    solo = ensemble_lattices(cs, device=dev)
+    b = Batch(lats)
+    b.set_launch(128, 2048, 2)
+    b.step(5)
+    lats[2].step(1)          # one sample moves by itself
+    saved = lats[4].save_state()
+    b.step(4)
+    lats[4].load_state(saved)  # and one goes back 4 steps
+    b.step(3)
+    for i, l in enumerate(solo):
+        l.step({2: 13, 4: 8}.get(i, 12))
+    assert_same(lats, solo)
+
+
+def test_fp16_check_rescale_in_batch(dev):
+    cs = cases(2, 1, seed=750)
+    lats = ensemble_lattices(cs, device=dev, storage="f16")
+    solo = ensemble_lattices(cs, device=dev, storage="f16", check_every=10)
+    b = Batch(lats)
+    for _ in range(3):
+        b.step(10)
+        b.check()
+    for l in solo:
+        l.step(30)
+    assert_same(lats, solo)
+
+
+def test_autotune_leaves_state_untouched(dev, tmp_path):
+    cs = cases(0, 0, seed=800)
+    lats = ensemble_lattices(cs, device=dev)
+    b = Batch(lats)
+    b.step(7)
+    before = [l.save_state().clone() for l in lats]
+    us = b.autotune(reps=3, cache=str(tmp_path / "tune.json"))
+    assert us > 0
+    tile, grid, _ = b.launch
+    assert tile in (128, 256, 512) and grid >= 0
+    for l, s in zip(lats, before):
+        assert torch.equal(l.save_state(), s)
+    # the cache answers the same shape without timing
+    b2 = Batch(ensemble_lattices(cs, device=dev))
+    assert np.isnan(b2.autotune(cache=str(tmp_path / "tune.json")))
+    assert b2.launch[:2] == (tile, grid)
+
+
+def test_batch_against_oracle(dev):
+    cs = cases(2, 1, seed=850, sizes=[(300, 17), (70, 40), (513, 6)])
+    lats = ensemble_lattices(cs, device=dev)
+    b = Batch(lats)
+    b.set_launch(512, 256, 8)
+    b.step(150)
+    kb = b.apparent_permeability()
+    for c, l, k in zip(cs, lats, kb):
+        ref = oracle.Lattice(c.eps, c.k, c.kn0, **c.params).step(150)
+        _, ux, uy = (t.double().cpu().numpy() for t in l.macroscopic())
+        _, rx, ry = ref.macro()
+        err = np.linalg.norm(np.stack([ux - rx, uy - ry])) / np.linalg.norm(np.stack([rx, ry]))
+        assert err <= VEL_TOL
+        assert abs(k / ref.apparent_permeability() - 1) < 1e-5
+
+
+def test_batch_rejects_mixed(dev):
+    from paper_1411_7051_amd._lib import LbkError
+    a = Lattice(*(np.full((4, 8), v, np.float32) for v in (0.5, 0.1, 0.0)), device=dev)
+    c = Lattice(*(np.full((4, 8), v, np.float32) for v in (0.5, 0.1, 0.0)), device=dev,
+                storage="f16")
+    with pytest.raises(LbkError) as e:
+        Batch([a, c])
+    assert e.value.status == -5
+    with pytest.raises(LbkError):
+        Batch([a, a])
+    b = Batch([a])
+    for bad in [(100, 0, 0), (256, -1, 0), (256, 0, 3), (256, 0, 2048)]:
+        with pytest.raises(LbkError):
+            b.set_launch(*bad)
