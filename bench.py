@@ -11,8 +11,10 @@ is K sweeps on the lattice's stream, bracketed by HIP events.
 
 Prints ONE JSON line.  Headline value: FP32-storage MLUPS.  Also reported:
 FP16- and BF16-storage MLUPS on the same workload, the HBM roofline of the
-sweep kernel, and the FP64 CPU oracle timed on a bounded sample on the
-host (``cpu_baseline``).
+sweep kernel, the FP64 CPU oracle timed on a bounded sample on the host
+(``cpu_baseline``), the cost of the adjoint gradient relative to the
+forward sweeps on the fractured-shale medium, and a batched ensemble of
+uneven samples stepped together.
 """
 from __future__ import annotations
 
@@ -184,6 +186,69 @@ def time_adjoint(n, steps, ckpt, hist, device):
     return out
 
 
+def time_ensemble(n_samples, steps, storage, graph_steps, device):
+    """Batched ensemble of uneven samples (seed 4): per-sample lattices
+    stepped together by one launch per step, launch shape from the tuner,
+    steps replayed from HIP graphs; also the same samples stepped one launch
+    per sample per step, for comparison."""
+    import torch
+    from paper_1411_7051_amd import inputs
+    from paper_1411_7051_amd.batch import Batch, ensemble_lattices
+
+    t = time.perf_counter()
+    cases = inputs.ensemble(n_samples=n_samples, seed=4)
+    nodes = sum(c.nodes for c in cases)
+    log(f"ensemble inputs: {len(cases)} samples, {nodes} nodes in "
+        f"{time.perf_counter() - t:.1f} s")
+    lats = ensemble_lattices(cases, device=device, storage=storage)
+    b = Batch(lats)
+    st = lats[0].stream
+    tune_us = b.autotune(reps=5)
+    tile_x, rows, grid, _ = b.launch
+    b.set_launch(tile_x, rows, grid, graph_steps)
+    b.step(2 * graph_steps)  # records the graphs
+    torch.cuda.synchronize(device)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(st)
+    b.step(steps)
+    ev[1].record(st)
+    loop_steps = max(2, steps // 10)
+    ev[2].record(st)
+    for _ in range(loop_steps):
+        for l in lats:
+            l.step(1)
+    ev[3].record(st)
+    torch.cuda.synchronize(device)
+    ms = ev[0].elapsed_time(ev[1])
+    ms_loop = ev[2].elapsed_time(ev[3]) / loop_steps
+    kapp = b.apparent_permeability()
+    mlups = nodes * steps / (ms * 1e-3) / 1e6
+    out = {
+        "workload": f"ensemble{n_samples}: square sides U[256,1536], log-normal k (ln-sigma 1, "
+                    "corr 8-64, median 1e-3), eps U[0.1,0.6], base Kn U[0.01,2], "
+                    "pressure-driven x, periodic y",
+        "samples": len(cases),
+        "nodes": nodes,
+        "storage": storage,
+        "steps": steps,
+        "launch": {"tile_x": tile_x, "rows": rows, "grid": grid, "graph_steps": graph_steps},
+        "autotune_best_us": tune_us,
+        "ms_per_step": ms / steps,
+        "mlups": mlups,
+        "alg_GBps": mlups * ALG_BYTES[storage] / 1e3,
+        "alg_frac": mlups * ALG_BYTES[storage] / 1e3 / HBM_PEAK_GBS,
+        "per_sample_launch_ms_per_step": ms_loop,
+        "batched_speedup": ms_loop / (ms / steps),
+        "k_app_range": [float(kapp.min()), float(kapp.max())],
+    }
+    b.close()
+    for l in lats:
+        l.close()
+    del b, lats
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +262,11 @@ def main():
     ap.add_argument("--adjoint-ckpt", type=int, default=500)
     ap.add_argument("--adjoint-hist", type=int, default=50)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient leg")
+    ap.add_argument("--ensemble-samples", type=int, default=192)
+    ap.add_argument("--ensemble-steps", type=int, default=400)
+    ap.add_argument("--ensemble-storage", default="f16")
+    ap.add_argument("--ensemble-graph", type=int, default=20, help="steps per graph replay")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the ensemble leg")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run 10 device-to-device copies of MIB MiB (a plain copy "
                          "kernel of known traffic, to scale HBM byte counters) and exit")
@@ -258,6 +328,12 @@ def main():
                            args.adjoint_hist, dev)
         log(f"adjoint: t_grad/t_fwd = {adj['grad_over_fwd']:.2f}, "
             f"(t_fwd + t_grad)/t_fwd = {adj['total_over_fwd']:.2f}")
+    ens = None
+    if not args.no_ensemble:
+        ens = time_ensemble(args.ensemble_samples, args.ensemble_steps, args.ensemble_storage,
+                            args.ensemble_graph, dev)
+        log(f"ensemble: {ens['mlups']:.0f} MLUPS ({ens['storage']}, launch {ens['launch']}), "
+            f"{ens['batched_speedup']:.2f}x over one launch per sample")
     cpu = None if args.no_cpu else cpu_baseline(case)
     if cpu:
         log(f"cpu oracle: {cpu['value']:.2f} MLUPS ({cpu['sample']})")
@@ -287,6 +363,7 @@ def main():
         "cpu_baseline": cpu,
         "storage_runs": runs,
         "adjoint": adj,
+        "ensemble": ens,
     }
     print(json.dumps(out), flush=True)
 

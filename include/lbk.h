@@ -187,10 +187,11 @@ lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws_bytes, flo
  * A batch groups n lattices of uneven size (Sec. IV.C: heterogeneous
  * samples, each with its own fields, tau, drive and Kn scale) so that one
  * kernel launch advances every sample by one step.  The launch walks a list
- * of tiles -- `tile` consecutive nodes of one row of one sample -- that
- * covers all samples; either one workgroup per tile or a persistent grid of
- * `grid` workgroups each taking a contiguous run of tiles.  Steps can be
- * recorded into HIP graphs of `graph_steps` launches that are replayed.
+ * of tiles -- tile_x consecutive x by `rows` consecutive y of one sample --
+ * that covers all samples; either one workgroup per tile or a persistent
+ * grid of `grid` workgroups each taking a contiguous run of tiles.  Steps
+ * can be recorded into HIP graphs of `graph_steps` launches that are
+ * replayed.
  * Each sample's update is the same arithmetic as lbk_step on that lattice,
  * so results are bitwise identical to stepping the lattices one by one, for
  * every launch configuration.
@@ -208,7 +209,8 @@ lbk_status lbk_batch_workspace_size(lbk_lattice *const *lats, int32_t n, size_t 
 
 /* Create a batch over lats[0..n-1] in a caller-owned device workspace
  * (256-byte aligned, ws_bytes >= lbk_batch_workspace_size).  The launch
- * configuration starts at tile 256, one workgroup per tile, no graphs. */
+ * configuration starts at 256 x 1 tiles, one workgroup per tile, no
+ * graphs. */
 lbk_status lbk_batch_create(lbk_lattice *const *lats, int32_t n, void *workspace,
                             size_t ws_bytes, lbk_batch **out);
 
@@ -218,18 +220,20 @@ lbk_status lbk_batch_destroy(lbk_batch *b);
 /* Advance every sample by n >= 0 steps (each lattice's time grows by n). */
 lbk_status lbk_batch_step(lbk_batch *b, int64_t n);
 
-/* Launch configuration: tile in {128, 256, 512} nodes (the workgroup size);
- * grid 0 = one workgroup per tile, else a persistent grid of 1..2^20
- * workgroups; graph_steps 0 = direct launches, else an even number of
- * steps (2..1024) recorded per graph replay. */
-lbk_status lbk_batch_set_launch(lbk_batch *b, int32_t tile, int32_t grid,
+/* Launch configuration: tiles of tile_x in {64, 128, 192, 256} (the
+ * workgroup size) by rows in 1..64; grid 0 = one workgroup per tile, else a
+ * persistent grid of 1..2^20 workgroups; graph_steps 0 = direct launches,
+ * else an even number of steps (2..1024) recorded per graph replay.
+ * Changing the tiling synchronizes the stream. */
+lbk_status lbk_batch_set_launch(lbk_batch *b, int32_t tile_x, int32_t rows, int32_t grid,
                                 int32_t graph_steps);
-lbk_status lbk_batch_get_launch(const lbk_batch *b, int32_t *tile, int32_t *grid,
-                                int32_t *graph_steps);
+lbk_status lbk_batch_get_launch(const lbk_batch *b, int32_t *tile_x, int32_t *rows,
+                                int32_t *grid, int32_t *graph_steps);
 
-/* Time every tile width x grid candidate (one workgroup per tile and
- * persistent grids of 2, 4, 8 and 16 workgroups per compute unit) over
- * `reps` >= 1 steps each, and keep the fastest (graph_steps unchanged).
+/* Time every candidate -- tile_x in {64, 128, 256} x rows in {1, 4, 8, 16}
+ * x one workgroup per tile or persistent grids of 2, 4 and 8 workgroups
+ * per compute unit -- over `reps` >= 1 steps each, and keep the fastest
+ * (graph_steps unchanged).
  * The samples' states are left untouched: the timed launches re-read the
  * current time level and overwrite only the other one.  best_us (may be
  * NULL) receives the fastest mean time per step in microseconds.

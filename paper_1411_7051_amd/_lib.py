@@ -77,8 +77,10 @@ _SIG = {
                                         ctypes.POINTER(_P)]),
     "lbk_batch_destroy": (ctypes.c_int, [_P]),
     "lbk_batch_step": (ctypes.c_int, [_P, ctypes.c_int64]),
-    "lbk_batch_set_launch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "lbk_batch_set_launch": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int32]),
     "lbk_batch_get_launch": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_int32)]),
     "lbk_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),

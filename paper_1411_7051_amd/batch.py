@@ -65,17 +65,17 @@ class Batch:
         check(_lib.load().lbk_batch_step(self._handle(), int(n)))
         return self
 
-    def set_launch(self, tile: int = 256, grid: int = 0, graph_steps: int = 0) -> None:
-        check(_lib.load().lbk_batch_set_launch(self._handle(), int(tile), int(grid),
+    def set_launch(self, tile_x: int = 256, rows: int = 1, grid: int = 0,
+                   graph_steps: int = 0) -> None:
+        check(_lib.load().lbk_batch_set_launch(self._handle(), int(tile_x), int(rows), int(grid),
                                                int(graph_steps)))
 
     @property
     def launch(self):
-        """(tile, grid, graph_steps)."""
-        t, g, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        check(_lib.load().lbk_batch_get_launch(self._handle(), ctypes.byref(t), ctypes.byref(g),
-                                               ctypes.byref(s)))
-        return int(t.value), int(g.value), int(s.value)
+        """(tile_x, rows, grid, graph_steps)."""
+        v = [ctypes.c_int32() for _ in range(4)]
+        check(_lib.load().lbk_batch_get_launch(self._handle(), *[ctypes.byref(x) for x in v]))
+        return tuple(int(x.value) for x in v)
 
     def signature(self) -> str:
         """Key of this batch's shape for the tuning cache: device, storage,
@@ -87,23 +87,24 @@ class Batch:
         return hashlib.sha1(key.encode()).hexdigest()[:16]
 
     def autotune(self, reps: int = 10, cache: Optional[str] = None) -> float:
-        """Pick the fastest (tile, grid) for this batch, leaving the samples'
-        states untouched; returns the mean step time in microseconds (NaN when
-        taken from ``cache``, a JSON file of signature -> [tile, grid, us])."""
+        """Pick the fastest (tile_x, rows, grid) for this batch, leaving the
+        samples' states untouched; returns the mean step time in microseconds
+        (NaN when taken from ``cache``, a JSON file of signature ->
+        [tile_x, rows, grid, us])."""
         sig = self.signature()
         table = {}
         if cache and os.path.exists(cache):
             with open(cache) as f:
                 table = json.load(f)
             if sig in table:
-                tile, grid, _ = table[sig]
-                self.set_launch(tile, grid, self.launch[2])
+                tile_x, rows, grid, _ = table[sig]
+                self.set_launch(tile_x, rows, grid, self.launch[3])
                 return float("nan")
         us = ctypes.c_double()
         check(_lib.load().lbk_batch_autotune(self._handle(), int(reps), ctypes.byref(us)))
         if cache:
-            tile, grid, _ = self.launch
-            table[sig] = [tile, grid, float(us.value)]
+            tile_x, rows, grid, _ = self.launch
+            table[sig] = [tile_x, rows, grid, float(us.value)]
             tmp = cache + ".tmp"
             with open(tmp, "w") as f:
                 json.dump(table, f, indent=1, sort_keys=True)

@@ -14,29 +14,45 @@ using namespace lbk;
 
 namespace {
 
-constexpr int kNumTiles = 3;
-constexpr int kTiles[kNumTiles] = {128, 256, 512};
-constexpr int kMacroTile = 1; // kTiles[1] == kBlock: the read-out's tiling
 constexpr int kMaxSamples = 1 << 20;
 constexpr int kMaxGrid = 1 << 20;
 constexpr int kMaxGraphSteps = 1024;
+constexpr int kMaxRows = 64;
 
-int tile_index(int tile)
+// Tile shape: tile_x consecutive x (the workgroup size) by `rows` rows.
+struct Shape {
+    int tile_x, rows;
+};
+constexpr Shape kReadShape{kBlock, 1}; // the batched read-out's tiling
+constexpr Shape kFinest{64, 1};        // most tiles of any allowed shape
+
+bool valid_shape(int tile_x, int rows)
 {
-    for (int i = 0; i < kNumTiles; ++i)
-        if (kTiles[i] == tile)
-            return i;
-    return -1;
+    return tile_x >= 64 && tile_x <= kBatchMaxTile && (tile_x & 63) == 0 && rows >= 1 &&
+           rows <= kMaxRows;
 }
 
-int tiles_per_row(int nx, int tile) { return (nx + tile - 1) / tile; }
+int tiles_per_row(int nx, int tile_x) { return (nx + tile_x - 1) / tile_x; }
 
-// Workspace regions: per tile width a descriptor table [n] and the tile ->
-// sample map [ntiles]; read-out partials [MAC_SLOTS][ntiles(256)] and the
-// per-sample sums [n][MAC_SLOTS].
+int64_t tiles_of(const lbk_lattice *l, Shape sh)
+{
+    return (int64_t)tiles_per_row(l->d.nx, sh.tile_x) * ((l->d.ny + sh.rows - 1) / sh.rows);
+}
+
+int64_t total_tiles(lbk_lattice *const *lats, int n, Shape sh)
+{
+    int64_t t = 0;
+    for (int i = 0; i < n; ++i)
+        t += tiles_of(lats[i], sh);
+    return t;
+}
+
+// Workspace regions: descriptor table and tile -> sample map of the sweep
+// (sized for the finest allowed tiling) and of the read-out; read-out
+// partials [MAC_SLOTS][read tiles] and per-sample sums [n][MAC_SLOTS].
 struct BatchLayout {
-    size_t desc[kNumTiles], map[kNumTiles];
-    int64_t ntiles[kNumTiles];
+    size_t desc_sweep, map_sweep, desc_read, map_read;
+    int64_t max_sweep_tiles, read_tiles;
     size_t partials, results, total;
 };
 
@@ -72,15 +88,13 @@ BatchLayout batch_layout(lbk_lattice *const *lats, int n)
         o = align_up(o + bytes, 256);
         return at;
     };
-    for (int w = 0; w < kNumTiles; ++w) {
-        int64_t t = 0;
-        for (int i = 0; i < n; ++i)
-            t += (int64_t)tiles_per_row(lats[i]->d.nx, kTiles[w]) * lats[i]->d.ny;
-        B.ntiles[w] = t;
-        B.desc[w] = take((size_t)n * sizeof(SampleDesc));
-        B.map[w] = take((size_t)t * sizeof(int));
-    }
-    B.partials = take((size_t)MAC_SLOTS * (size_t)B.ntiles[kMacroTile] * sizeof(double));
+    B.max_sweep_tiles = total_tiles(lats, n, kFinest);
+    B.read_tiles = total_tiles(lats, n, kReadShape);
+    B.desc_sweep = take((size_t)n * sizeof(SampleDesc));
+    B.map_sweep = take((size_t)B.max_sweep_tiles * sizeof(int));
+    B.desc_read = take((size_t)n * sizeof(SampleDesc));
+    B.map_read = take((size_t)B.read_tiles * sizeof(int));
+    B.partials = take((size_t)MAC_SLOTS * (size_t)B.read_tiles * sizeof(double));
     B.results = take((size_t)n * MAC_SLOTS * sizeof(double));
     B.total = o;
     return B;
@@ -98,14 +112,19 @@ struct lbk_batch {
     int cus;            // compute units of the device
     int parity;         // sample i's current level is state[parity] of its descriptor
     std::vector<int> cur0, scale0;
-    SampleDesc *host_desc; // pinned staging, [kNumTiles][n]
+    Shape shape;        // sweep tiling
+    int64_t sweep_tiles;
+    std::vector<int64_t> tile0_sweep, tile0_read;
+    SampleDesc *host_desc; // pinned staging, [2][n]: sweep, read-out
     double *host_res;      // pinned, [n][MAC_SLOTS]
-    int tile, grid, graph_steps;
+    int grid, graph_steps;
     hipGraphExec_t exec[2]; // graphs starting at parity 0 / 1
     bool have_exec[2];
 
-    SampleDesc *desc(int w) const { return reinterpret_cast<SampleDesc *>(ws + B.desc[w]); }
-    int *map(int w) const { return reinterpret_cast<int *>(ws + B.map[w]); }
+    SampleDesc *desc_sweep() const { return reinterpret_cast<SampleDesc *>(ws + B.desc_sweep); }
+    SampleDesc *desc_read() const { return reinterpret_cast<SampleDesc *>(ws + B.desc_read); }
+    int *map_sweep() const { return reinterpret_cast<int *>(ws + B.map_sweep); }
+    int *map_read() const { return reinterpret_cast<int *>(ws + B.map_read); }
     double *partials() const { return reinterpret_cast<double *>(ws + B.partials); }
     double *results() const { return reinterpret_cast<double *>(ws + B.results); }
     const lbk_desc &d0() const { return lats[0]->d; }
@@ -122,6 +141,24 @@ void drop_graphs(lbk_batch *b)
         }
 }
 
+// Upload the tile -> sample map of tiling `sh` into `map`; tile0[i] gets
+// the first tile of sample i.  Synchronous.
+lbk_status upload_map(lbk_batch *b, Shape sh, int *map, std::vector<int64_t> &tile0,
+                      int64_t &ntiles)
+{
+    std::vector<int> h;
+    h.reserve((size_t)total_tiles(b->lats.data(), b->n, sh));
+    tile0.assign(b->n, 0);
+    for (int i = 0; i < b->n; ++i) {
+        tile0[i] = (int64_t)h.size();
+        h.insert(h.end(), (size_t)tiles_of(b->lats[i], sh), i);
+    }
+    ntiles = (int64_t)h.size();
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    HIP_TRY(hipMemcpy(map, h.data(), h.size() * sizeof(int), hipMemcpyHostToDevice));
+    return LBK_OK;
+}
+
 // Bring the device descriptor tables in line with the lattices: a lattice
 // stepped, loaded or rescaled outside the batch changes which of its levels
 // is current or its FP16 scale.
@@ -135,13 +172,13 @@ lbk_status sync_tables(lbk_batch *b, bool force)
     if (!stale)
         return LBK_OK;
     HIP_TRY(hipStreamSynchronize(b->stream)); // staging may still feed a copy
-    int64_t tile0[kNumTiles] = {0, 0, 0};
     for (int i = 0; i < b->n; ++i) {
         lbk_lattice *l = b->lats[i];
         b->cur0[i] = l->cur ^ b->parity;
         b->scale0[i] = l->scale_exp;
-        for (int w = 0; w < kNumTiles; ++w) {
-            SampleDesc &sd = b->host_desc[(size_t)w * b->n + i];
+        for (int k = 0; k < 2; ++k) {
+            const Shape sh = k == 0 ? b->shape : kReadShape;
+            SampleDesc &sd = b->host_desc[(size_t)k * b->n + i];
             sd.state[b->parity] = l->state(l->cur);
             sd.state[b->parity ^ 1] = l->state(l->cur ^ 1);
             sd.med = l->med();
@@ -151,25 +188,37 @@ lbk_status sync_tables(lbk_batch *b, bool force)
             sd.ph = l->ph;
             sd.s = l->s();
             sd.inv_s = l->inv_s();
-            sd.tile0 = (int)tile0[w];
-            sd.tpr = tiles_per_row(l->d.nx, kTiles[w]);
-            tile0[w] += (int64_t)sd.tpr * l->d.ny;
+            sd.tile0 = (int)(k == 0 ? b->tile0_sweep[i] : b->tile0_read[i]);
+            sd.tpr = tiles_per_row(l->d.nx, sh.tile_x);
         }
     }
-    for (int w = 0; w < kNumTiles; ++w)
-        HIP_TRY(hipMemcpyAsync(b->desc(w), b->host_desc + (size_t)w * b->n,
-                               (size_t)b->n * sizeof(SampleDesc), hipMemcpyHostToDevice,
-                               b->stream));
+    HIP_TRY(hipMemcpyAsync(b->desc_sweep(), b->host_desc, (size_t)b->n * sizeof(SampleDesc),
+                           hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->desc_read(), b->host_desc + b->n, (size_t)b->n * sizeof(SampleDesc),
+                           hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     return LBK_OK;
 }
 
-hipError_t sweep_once(lbk_batch *b, int parity, int tile, int grid, hipStream_t st)
+// Switch the sweep to tiling `sh` (map and descriptors).
+lbk_status set_shape(lbk_batch *b, Shape sh)
 {
-    const int w = tile_index(tile);
+    if (sh.tile_x == b->shape.tile_x && sh.rows == b->shape.rows && b->sweep_tiles > 0)
+        return LBK_OK;
+    drop_graphs(b);
+    b->shape = sh;
+    lbk_status s = upload_map(b, sh, b->map_sweep(), b->tile0_sweep, b->sweep_tiles);
+    if (s != LBK_OK)
+        return s;
+    return sync_tables(b, true);
+}
+
+hipError_t sweep_once(lbk_batch *b, int parity, int grid, hipStream_t st)
+{
     const lbk_desc &d = b->d0();
-    return launch_batch_sweep(d.storage, d.bc_x, d.bc_y, b->desc(w), b->map(w),
-                              (int)b->B.ntiles[w], parity, tile, grid, st);
+    return launch_batch_sweep(d.storage, d.bc_x, d.bc_y, b->desc_sweep(), b->map_sweep(),
+                              (int)b->sweep_tiles, parity, b->shape.tile_x, b->shape.rows, grid,
+                              st);
 }
 
 // Record graph_steps launches starting at `parity` on the private stream.
@@ -178,7 +227,7 @@ lbk_status record_graph(lbk_batch *b, int parity)
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int i = 0; i < b->graph_steps && e == hipSuccess; ++i)
-        e = sweep_once(b, parity ^ (i & 1), b->tile, b->grid, b->cap);
+        e = sweep_once(b, parity ^ (i & 1), b->grid, b->cap);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -236,9 +285,9 @@ lbk_status lbk_batch_create(lbk_lattice *const *lats, int32_t n, void *workspace
     const BatchLayout B = batch_layout(lats, n);
     if (ws_bytes < B.total)
         return fail(LBK_ERR_OOM, "batch workspace of %zu bytes < %zu needed", ws_bytes, B.total);
-    if (B.ntiles[0] >= ((int64_t)1 << 31))
+    if (B.max_sweep_tiles >= ((int64_t)1 << 31))
         return fail(LBK_ERR_UNSUPPORTED, "batch of %lld tiles exceeds 2^31",
-                    (long long)B.ntiles[0]);
+                    (long long)B.max_sweep_tiles);
     int dev = -1, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
@@ -256,31 +305,21 @@ lbk_status lbk_batch_create(lbk_lattice *const *lats, int32_t n, void *workspace
     b->parity = 0;
     b->cur0.assign(n, 0);
     b->scale0.assign(n, 0);
-    b->tile = 256;
+    b->shape = Shape{0, 0};
+    b->sweep_tiles = 0;
     b->grid = 0;
     b->graph_steps = 0;
+    int64_t read_tiles = 0;
     if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
-        hipHostMalloc((void **)&b->host_desc, (size_t)kNumTiles * n * sizeof(SampleDesc),
+        hipHostMalloc((void **)&b->host_desc, (size_t)2 * n * sizeof(SampleDesc),
                       hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&b->host_res, (size_t)n * MAC_SLOTS * sizeof(double),
                       hipHostMallocDefault) != hipSuccess) {
         destroy_batch(b);
         return fail(LBK_ERR_DEVICE, "stream or pinned host allocation failed");
     }
-    // tile -> sample maps (fixed for the batch's life)
-    for (int w = 0; w < kNumTiles; ++w) {
-        std::vector<int> map;
-        map.reserve((size_t)B.ntiles[w]);
-        for (int i = 0; i < n; ++i)
-            map.insert(map.end(), (size_t)tiles_per_row(lats[i]->d.nx, kTiles[w]) * lats[i]->d.ny,
-                       i);
-        if (hipMemcpy(b->map(w), map.data(), map.size() * sizeof(int), hipMemcpyHostToDevice) !=
-            hipSuccess) {
-            destroy_batch(b);
-            return fail(LBK_ERR_DEVICE, "tile map upload failed");
-        }
-    }
-    if ((s = sync_tables(b, true)) != LBK_OK) {
+    if ((s = upload_map(b, kReadShape, b->map_read(), b->tile0_read, read_tiles)) != LBK_OK ||
+        (s = set_shape(b, Shape{kBlock, 1})) != LBK_OK) {
         destroy_batch(b);
         return s;
     }
@@ -312,7 +351,7 @@ lbk_status lbk_batch_step(lbk_batch *b, int64_t n)
             HIP_TRY(hipGraphLaunch(b->exec[b->parity], b->stream));
             left -= b->graph_steps; // even: the parity is unchanged
         } else {
-            HIP_TRY(sweep_once(b, b->parity, b->tile, b->grid, b->stream));
+            HIP_TRY(sweep_once(b, b->parity, b->grid, b->stream));
             b->parity ^= 1;
             --left;
         }
@@ -325,32 +364,39 @@ lbk_status lbk_batch_step(lbk_batch *b, int64_t n)
     return LBK_OK;
 }
 
-lbk_status lbk_batch_set_launch(lbk_batch *b, int32_t tile, int32_t grid, int32_t graph_steps)
+lbk_status lbk_batch_set_launch(lbk_batch *b, int32_t tile_x, int32_t rows, int32_t grid,
+                                int32_t graph_steps)
 {
     if (!b)
         return fail(LBK_ERR_INVALID_ARG, "batch is NULL");
-    if (tile_index(tile) < 0)
-        return fail(LBK_ERR_INVALID_ARG, "tile must be 128, 256 or 512 (got %d)", tile);
+    if (!valid_shape(tile_x, rows))
+        return fail(LBK_ERR_INVALID_ARG,
+                    "tile_x must be 64, 128, 192 or 256 and rows 1..%d (got %d, %d)", kMaxRows,
+                    tile_x, rows);
     if (grid < 0 || grid > kMaxGrid)
         return fail(LBK_ERR_INVALID_ARG, "grid must be 0..%d (got %d)", kMaxGrid, grid);
     if (graph_steps < 0 || graph_steps > kMaxGraphSteps || (graph_steps & 1))
         return fail(LBK_ERR_INVALID_ARG, "graph_steps must be 0 or even in 2..%d (got %d)",
                     kMaxGraphSteps, graph_steps);
-    if (tile != b->tile || grid != b->grid || graph_steps != b->graph_steps)
+    lbk_status s = set_shape(b, Shape{tile_x, rows});
+    if (s != LBK_OK)
+        return s;
+    if (grid != b->grid || graph_steps != b->graph_steps)
         drop_graphs(b);
-    b->tile = tile;
     b->grid = grid;
     b->graph_steps = graph_steps;
     return LBK_OK;
 }
 
-lbk_status lbk_batch_get_launch(const lbk_batch *b, int32_t *tile, int32_t *grid,
-                                int32_t *graph_steps)
+lbk_status lbk_batch_get_launch(const lbk_batch *b, int32_t *tile_x, int32_t *rows,
+                                int32_t *grid, int32_t *graph_steps)
 {
     if (!b)
         return fail(LBK_ERR_INVALID_ARG, "batch is NULL");
-    if (tile)
-        *tile = b->tile;
+    if (tile_x)
+        *tile_x = b->shape.tile_x;
+    if (rows)
+        *rows = b->shape.rows;
     if (grid)
         *grid = b->grid;
     if (graph_steps)
@@ -373,38 +419,46 @@ lbk_status lbk_batch_autotune(lbk_batch *b, int32_t reps, double *best_us)
         (void)hipEventDestroy(ev[0]);
         return fail(LBK_ERR_DEVICE, "event creation failed");
     }
-    const int per_cu[5] = {0, 2, 4, 8, 16};
+    const int widths[3] = {64, 128, 256}, row_opts[4] = {1, 4, 8, 16}, per_cu[4] = {0, 2, 4, 8};
     double best = INFINITY;
-    int best_tile = b->tile, best_grid = b->grid;
+    Shape best_shape = b->shape;
+    int best_grid = b->grid;
     hipError_t e = hipSuccess;
-    for (int w = 0; w < kNumTiles && e == hipSuccess; ++w) {
-        for (int c = 0; c < 5 && e == hipSuccess; ++c) {
-            const int tile = kTiles[w], grid = per_cu[c] * b->cus;
-            // every launch reads the current level and writes the other
-            e = sweep_once(b, b->parity, tile, grid, b->stream);
-            if (e == hipSuccess)
-                e = hipEventRecord(ev[0], b->stream);
-            for (int r = 0; r < reps && e == hipSuccess; ++r)
-                e = sweep_once(b, b->parity, tile, grid, b->stream);
-            if (e == hipSuccess)
-                e = hipEventRecord(ev[1], b->stream);
-            if (e == hipSuccess)
-                e = hipEventSynchronize(ev[1]);
-            float ms = 0.0f;
-            if (e == hipSuccess)
-                e = hipEventElapsedTime(&ms, ev[0], ev[1]);
-            if (e == hipSuccess && ms / reps < best) {
-                best = ms / reps;
-                best_tile = tile;
-                best_grid = grid;
+    for (int w = 0; w < 3 && e == hipSuccess && s == LBK_OK; ++w) {
+        for (int r = 0; r < 4 && e == hipSuccess && s == LBK_OK; ++r) {
+            if ((s = set_shape(b, Shape{widths[w], row_opts[r]})) != LBK_OK)
+                break;
+            for (int c = 0; c < 4 && e == hipSuccess; ++c) {
+                const int grid = per_cu[c] * b->cus;
+                // every launch reads the current level and writes the other
+                e = sweep_once(b, b->parity, grid, b->stream);
+                if (e == hipSuccess)
+                    e = hipEventRecord(ev[0], b->stream);
+                for (int k = 0; k < reps && e == hipSuccess; ++k)
+                    e = sweep_once(b, b->parity, grid, b->stream);
+                if (e == hipSuccess)
+                    e = hipEventRecord(ev[1], b->stream);
+                if (e == hipSuccess)
+                    e = hipEventSynchronize(ev[1]);
+                float ms = 0.0f;
+                if (e == hipSuccess)
+                    e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+                if (e == hipSuccess && ms / reps < best) {
+                    best = ms / reps;
+                    best_shape = b->shape;
+                    best_grid = grid;
+                }
             }
         }
     }
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
+    if (s != LBK_OK)
+        return s;
     if (e != hipSuccess)
         return fail(LBK_ERR_DEVICE, "autotune: %s", hipGetErrorString(e));
-    if ((s = lbk_batch_set_launch(b, best_tile, best_grid, b->graph_steps)) != LBK_OK)
+    if ((s = lbk_batch_set_launch(b, best_shape.tile_x, best_shape.rows, best_grid,
+                                  b->graph_steps)) != LBK_OK)
         return s;
     if (best_us)
         *best_us = best * 1e3;
@@ -419,11 +473,11 @@ lbk_status lbk_batch_apparent_permeability(lbk_batch *b, double *k_app)
     if (s != LBK_OK)
         return s;
     const lbk_desc &d = b->d0();
-    const int w = kMacroTile;
-    HIP_TRY(launch_batch_macro(d.storage, d.bc_x, d.bc_y, b->desc(w), b->map(w),
-                               (int)b->B.ntiles[w], b->parity, b->partials(), b->stream));
-    HIP_TRY(launch_batch_finish(b->desc(w), b->n, b->partials(), MAC_SLOTS, (int)b->B.ntiles[w],
-                                b->results(), b->stream));
+    const int nt = (int)b->B.read_tiles;
+    HIP_TRY(launch_batch_macro(d.storage, d.bc_x, d.bc_y, b->desc_read(), b->map_read(), nt,
+                               b->parity, b->partials(), b->stream));
+    HIP_TRY(launch_batch_finish(b->desc_read(), b->n, b->partials(), MAC_SLOTS, nt, b->results(),
+                                b->stream));
     HIP_TRY(hipMemcpyAsync(b->host_res, b->results(), (size_t)b->n * MAC_SLOTS * sizeof(double),
                            hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));

@@ -18,9 +18,12 @@ struct Launch {
 
 Launch launch_of(const Geom &g);
 
+// Largest batch tile width (workgroup size) of the batched sweep.
+constexpr int kBatchMaxTile = 256;
+
 // One sample of a batch: its two time levels, medium, layouts, scalars and
-// FP16 scale, and where its tiles sit in the batch's tile list (tile0,
-// tiles per row).
+// FP16 scale, and where its tiles sit in the batch's tile list (tile0, and
+// tiles per tile row across x).
 struct SampleDesc {
     char *state[2];
     const char *med;
@@ -95,12 +98,14 @@ hipError_t launch_populations(int storage, const char *src, const Layout &lay, c
 hipError_t launch_rescale(int storage, char *state, const Layout &lay, const Geom &g, int k,
                           hipStream_t st);
 
-// One step of every sample of a batch, parity -> parity ^ 1.  tile: nodes
-// per tile (128, 256 or 512; the block size); grid > 0: persistent launch of
-// grid blocks each sweeping a contiguous tile range, 0: one block per tile.
+// One step of every sample of a batch, parity -> parity ^ 1, over tiles of
+// tile_x (a multiple of 64 up to kBatchMaxTile: the workgroup size) by rows
+// nodes; the descriptors' tile0/tpr must describe that tiling.  grid > 0:
+// persistent launch of grid workgroups each sweeping a contiguous tile
+// range; 0: one workgroup per tile.
 hipError_t launch_batch_sweep(int storage, int bcx, int bcy, const SampleDesc *samples,
-                              const int *tile_sample, int ntiles, int parity, int tile, int grid,
-                              hipStream_t st);
+                              const int *tile_sample, int ntiles, int parity, int tile_x,
+                              int rows, int grid, hipStream_t st);
 
 // Read-out partials of every sample over tiles of kBlock nodes
 // ([MAC_SLOTS][ntiles]) and their per-sample fixed-order sums

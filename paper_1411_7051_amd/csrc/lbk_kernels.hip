@@ -166,42 +166,49 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const char *src, char *ds
 //
 // A batch steps many independent lattices (samples of uneven size, each
 // with its own layout, medium and scalars) in one launch per step.  The
-// work list is the concatenation of every sample's tiles -- TILE
-// consecutive x of one row -- in sample order, rows in order; tile_sample
-// maps a tile to its sample.  PERSIST = false: one block per tile, in the
-// XCD-band order of the single-lattice kernels.  PERSIST = true: a fixed
-// grid whose block b sweeps the contiguous tile range
-// [b T / G, (b + 1) T / G), so one block walks down neighbouring rows and
-// reuses their densities in its XCD's L2.
+// work list is the concatenation of every sample's tiles -- blockDim.x
+// consecutive x by `rows` consecutive y of one sample -- in sample order,
+// tile rows in order; tile_sample maps a tile to its sample.  A workgroup
+// reads its tile's descriptor once and sweeps the tile row by row, so the
+// dependent descriptor loads are paid once per `rows` rows.
+// PERSIST = false: one workgroup per tile, in the XCD-band order of the
+// single-lattice kernels.  PERSIST = true: a fixed grid whose workgroup b
+// sweeps the contiguous tile range [b T / G, (b + 1) T / G).
 
-template <typename T, int BCX, int BCY, int TILE>
-__device__ __forceinline__ void batch_tile(const SampleDesc *samples, const int *tile_sample,
+template <typename T, int BCX, int BCY>
+__device__ __forceinline__ void batch_tile(const SampleDesc *__restrict__ samples,
+                                           const int *__restrict__ tile_sample, int rows,
                                            int parity, int t)
 {
-    const int si = tile_sample[t];
-    const SampleDesc &sd = samples[si];
+    // the descriptor is copied before the tile's first store, so its fields
+    // stay in scalar registers for every row
+    const SampleDesc sd = samples[tile_sample[t]];
     const int rel = t - sd.tile0;
-    const int y = rel / sd.tpr;
-    const uint32_t x = (uint32_t)(rel - y * sd.tpr) * TILE + threadIdx.x;
+    const int ty = rel / sd.tpr;
+    const uint32_t x = (uint32_t)(rel - ty * sd.tpr) * blockDim.x + threadIdx.x;
     if (x >= (uint32_t)sd.g.nx)
         return;
-    sweep_node<T, BCX, BCY, false>(sd.state[parity], sd.state[parity ^ 1], sd.lay, sd.med,
-                                   sd.mlay, sd.g, sd.ph, sd.s, sd.inv_s, nullptr, y, x);
+    const char *src = parity ? sd.state[1] : sd.state[0];
+    char *dst = parity ? sd.state[0] : sd.state[1];
+    const int y0 = ty * rows, y1 = min(y0 + rows, sd.g.ny);
+    for (int y = y0; y < y1; ++y)
+        sweep_node<T, BCX, BCY, false>(src, dst, sd.lay, sd.med, sd.mlay, sd.g, sd.ph, sd.s,
+                                       sd.inv_s, nullptr, y, x);
 }
 
-template <typename T, int BCX, int BCY, int TILE, bool PERSIST>
-__global__ __launch_bounds__(TILE) void batch_sweep_kernel(const SampleDesc *samples,
-                                                            const int *tile_sample, int ntiles,
-                                                            int parity)
+template <typename T, int BCX, int BCY, bool PERSIST>
+__global__ __launch_bounds__(kBatchMaxTile) void batch_sweep_kernel(
+    const SampleDesc *__restrict__ samples, const int *__restrict__ tile_sample, int ntiles,
+    int rows, int parity)
 {
     if (PERSIST) {
         const int G = gridDim.x, b = blockIdx.x;
         const int t0 = (int)((int64_t)b * ntiles / G), t1 = (int)((int64_t)(b + 1) * ntiles / G);
         for (int t = t0; t < t1; ++t)
-            batch_tile<T, BCX, BCY, TILE>(samples, tile_sample, parity, t);
+            batch_tile<T, BCX, BCY>(samples, tile_sample, rows, parity, t);
     } else {
-        batch_tile<T, BCX, BCY, TILE>(samples, tile_sample, parity,
-                                      xcd_remap(blockIdx.x, gridDim.x));
+        batch_tile<T, BCX, BCY>(samples, tile_sample, rows, parity,
+                                xcd_remap(blockIdx.x, gridDim.x));
     }
 }
 
@@ -627,23 +634,14 @@ hipError_t launch_rescale(int storage, char *state, const Layout &lay, const Geo
 
 template <typename T, int BCX, int BCY>
 static hipError_t batch_sweep_t(const SampleDesc *samples, const int *tile_sample, int ntiles,
-                                int parity, int tile, int grid, hipStream_t st)
+                                int parity, int tile_x, int rows, int grid, hipStream_t st)
 {
-    const bool persist = grid > 0;
-    const int nb = persist ? grid : ntiles;
-#define LBK_BS(TL, P)                                                                        \
-    hipLaunchKernelGGL((batch_sweep_kernel<T, BCX, BCY, TL, P>), dim3(nb), dim3(TL), 0, st,  \
-                       samples, tile_sample, ntiles, parity)
-    switch (tile * 2 + (persist ? 1 : 0)) {
-    case 256: LBK_BS(128, false); break;
-    case 257: LBK_BS(128, true); break;
-    case 512: LBK_BS(256, false); break;
-    case 513: LBK_BS(256, true); break;
-    case 1024: LBK_BS(512, false); break;
-    case 1025: LBK_BS(512, true); break;
-    default: return hipErrorInvalidValue;
-    }
-#undef LBK_BS
+    if (grid > 0)
+        hipLaunchKernelGGL((batch_sweep_kernel<T, BCX, BCY, true>), dim3(grid), dim3(tile_x), 0,
+                           st, samples, tile_sample, ntiles, rows, parity);
+    else
+        hipLaunchKernelGGL((batch_sweep_kernel<T, BCX, BCY, false>), dim3(ntiles), dim3(tile_x),
+                           0, st, samples, tile_sample, ntiles, rows, parity);
     return hipGetLastError();
 }
 
@@ -657,12 +655,15 @@ static hipError_t batch_macro_t(const SampleDesc *samples, const int *tile_sampl
 }
 
 hipError_t launch_batch_sweep(int storage, int bcx, int bcy, const SampleDesc *samples,
-                              const int *tile_sample, int ntiles, int parity, int tile, int grid,
-                              hipStream_t st)
+                              const int *tile_sample, int ntiles, int parity, int tile_x,
+                              int rows, int grid, hipStream_t st)
 {
-    if (bcy < 0 || bcy > 1)
+    if (bcy < 0 || bcy > 1 || tile_x < 64 || tile_x > kBatchMaxTile || (tile_x & 63) ||
+        rows < 1 || grid < 0 || ntiles < 0)
         return hipErrorInvalidValue;
-    LBK_DISPATCH(batch_sweep_t, samples, tile_sample, ntiles, parity, tile, grid, st)
+    if (ntiles == 0)
+        return hipSuccess;
+    LBK_DISPATCH(batch_sweep_t, samples, tile_sample, ntiles, parity, tile_x, rows, grid, st)
 }
 
 hipError_t launch_batch_macro(int storage, int bcx, int bcy, const SampleDesc *samples,

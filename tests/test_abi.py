@@ -116,7 +116,7 @@ def test_batch_null_arguments_rejected():
     assert lib.lbk_batch_create(arr, 1, None, 0, ctypes.byref(out)) == -1
     assert out.value is None
     assert lib.lbk_batch_step(None, 1) == -1
-    assert lib.lbk_batch_set_launch(None, 256, 0, 0) == -1
+    assert lib.lbk_batch_set_launch(None, 256, 1, 0, 0) == -1
     assert lib.lbk_batch_autotune(None, 1, None) == -1
     assert lib.lbk_batch_apparent_permeability(None, None) == -1
     assert lib.lbk_batch_check(None) == -1

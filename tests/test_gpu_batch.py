@@ -69,7 +69,8 @@ def test_batch_bitwise_equals_solo(dev, storage, bcx, bcy):
     assert np.array_equal(kb, ks)
 
 
-LAUNCHES = [(t, g, s) for t in (128, 256, 512) for g in (0, 512, 4096) for s in (0, 4)]
+LAUNCHES = [(t, r, g, s) for t in (64, 192, 256) for r in (1, 3, 64) for g in (0, 7, 2048)
+            for s in (0, 4)]
 
 
 def test_launch_configurations_agree(dev):
@@ -77,11 +78,11 @@ def test_launch_configurations_agree(dev):
     ref = ensemble_lattices(cs, device=dev)
     for l in ref:
         l.step(11)
-    for tile, grid, gs in LAUNCHES:
+    for tile, rows, grid, gs in LAUNCHES:
         lats = ensemble_lattices(cs, device=dev)
         b = Batch(lats)
-        b.set_launch(tile, grid, gs)
-        assert b.launch == (tile, grid, gs)
+        b.set_launch(tile, rows, grid, gs)
+        assert b.launch == (tile, rows, grid, gs)
         b.step(3).step(8)  # odd counts: direct steps around graph replays
         assert_same(lats, ref)
         b.close()
@@ -94,7 +95,7 @@ def test_graph_replays_match_eager(dev):
     lats = ensemble_lattices(cs, device=dev, storage="f16")
     solo = ensemble_lattices(cs, device=dev, storage="f16")
     b = Batch(lats)
-    b.set_launch(256, 1024, 6)
+    b.set_launch(128, 4, 1024, 6)
     for rep in range(4):
         b.step(6)
         for l in solo:
@@ -111,7 +112,7 @@ def test_outside_steps_and_loads_resync(dev):
     lats = ensemble_lattices(cs, device=dev)
     solo = ensemble_lattices(cs, device=dev)
     b = Batch(lats)
-    b.set_launch(128, 2048, 2)
+    b.set_launch(64, 8, 2048, 2)
     b.step(5)
     lats[2].step(1)          # one sample moves by itself
     saved = lats[4].save_state()
@@ -144,21 +145,21 @@ def test_autotune_leaves_state_untouched(dev, tmp_path):
     before = [l.save_state().clone() for l in lats]
     us = b.autotune(reps=3, cache=str(tmp_path / "tune.json"))
     assert us > 0
-    tile, grid, _ = b.launch
-    assert tile in (128, 256, 512) and grid >= 0
+    tile, rows, grid, _ = b.launch
+    assert tile in (64, 128, 256) and rows in (1, 4, 8, 16) and grid >= 0
     for l, s in zip(lats, before):
         assert torch.equal(l.save_state(), s)
     # the cache answers the same shape without timing
     b2 = Batch(ensemble_lattices(cs, device=dev))
     assert np.isnan(b2.autotune(cache=str(tmp_path / "tune.json")))
-    assert b2.launch[:2] == (tile, grid)
+    assert b2.launch[:3] == (tile, rows, grid)
 
 
 def test_batch_against_oracle(dev):
     cs = cases(2, 1, seed=850, sizes=[(300, 17), (70, 40), (513, 6)])
     lats = ensemble_lattices(cs, device=dev)
     b = Batch(lats)
-    b.set_launch(512, 256, 8)
+    b.set_launch(128, 16, 256, 8)
     b.step(150)
     kb = b.apparent_permeability()
     for c, l, k in zip(cs, lats, kb):
@@ -181,6 +182,7 @@ def test_batch_rejects_mixed(dev):
     with pytest.raises(LbkError):
         Batch([a, a])
     b = Batch([a])
-    for bad in [(100, 0, 0), (256, -1, 0), (256, 0, 3), (256, 0, 2048)]:
+    for bad in [(100, 1, 0, 0), (512, 1, 0, 0), (256, 0, 0, 0), (256, 65, 0, 0),
+                (256, 1, -1, 0), (256, 1, 0, 3), (256, 1, 0, 2048)]:
         with pytest.raises(LbkError):
             b.set_launch(*bad)
