@@ -249,6 +249,41 @@ def time_ensemble(n_samples, steps, storage, graph_steps, device):
     return out
 
 
+def kn_sweep(device, kns=(0.001, 0.01, 0.1, 1.0, 5.0)):
+    """Porous-filled plates at 1024 x 512 (eps 0.5, k 1.024, tau 0.8),
+    pressure-driven 1.01 / 1.0, local Kn, each base Kn run to steady state:
+    k_app / k next to the Brinkman-channel closed form with the Klinkenberg
+    factor f_c(Kn) (Sec. IV.A, Eqs. 6-7)."""
+    import math
+
+    from paper_1411_7051_amd import inputs
+    from paper_1411_7051_amd.lattice import Lattice
+
+    def fc(kn):  # Eqs. 6-7 with b = -1, for the closed-form column only
+        if kn <= 0:
+            return 1.0
+        alpha = 1.358 / (1.0 + 0.170 * kn ** -0.4348)
+        return (1.0 + alpha * kn) * (1.0 + 4.0 * kn / (1.0 + kn))
+
+    nx, ny, eps, k = 1024, 512, 0.5, 1.024
+    rows = []
+    t = time.perf_counter()
+    for kn in kns:
+        case = inputs.channel(nx, ny, eps=eps, k=k, kn0=kn, drive="pressure")
+        lat = Lattice(case.eps, case.k, case.kn0, device=device, **case.params)
+        steps, res, why = lat.run_to_steady(every=200, tol=1e-9, max_steps=600000)
+        a = math.sqrt(eps / (k * fc(kn)))
+        expect = fc(kn) * (1 - math.tanh(a * ny / 2) / (a * ny / 2))
+        got = lat.apparent_permeability() / k
+        rows.append({"kn": kn, "k_app_over_k": got, "closed_form": expect,
+                     "rel_diff": got / expect - 1, "steps": steps, "residual": res,
+                     "stop": why})
+        lat.close()
+    return {"workload": "channel1024x512: eps 0.5, k 1.024, tau 0.8, walls in y, "
+                        "pressure 1.01/1.0 in x, local Kn, run to residual < 1e-9 or plateau",
+            "seconds": time.perf_counter() - t, "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +302,8 @@ def main():
     ap.add_argument("--ensemble-storage", default="f16")
     ap.add_argument("--ensemble-graph", type=int, default=20, help="steps per graph replay")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the ensemble leg")
+    ap.add_argument("--no-kn-sweep", action="store_true",
+                    help="skip the Klinkenberg channel sweep")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run 10 device-to-device copies of MIB MiB (a plain copy "
                          "kernel of known traffic, to scale HBM byte counters) and exit")
@@ -306,6 +343,9 @@ def main():
         log(f"{st}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.4f} ms/step, "
             f"{r['alg_GBps']:.0f} GB/s algorithmic")
         runs[st] = r
+    if "f32" in runs:
+        for r in runs.values():
+            r["k_app_rel_vs_f32"] = r["k_app_after"] / runs["f32"]["k_app_after"] - 1
     head = runs.get("f32") or next(iter(runs.values()))
     st = head["storage"]
     achieved = head["alg_GBps"]
@@ -334,6 +374,11 @@ def main():
                             args.ensemble_graph, dev)
         log(f"ensemble: {ens['mlups']:.0f} MLUPS ({ens['storage']}, launch {ens['launch']}), "
             f"{ens['batched_speedup']:.2f}x over one launch per sample")
+    kn = None
+    if not args.no_kn_sweep:
+        kn = kn_sweep(dev)
+        log("Klinkenberg channel: " + ", ".join(
+            f"Kn {r['kn']}: {r['k_app_over_k']:.4f} ({r['rel_diff']:+.2%})" for r in kn["rows"]))
     cpu = None if args.no_cpu else cpu_baseline(case)
     if cpu:
         log(f"cpu oracle: {cpu['value']:.2f} MLUPS ({cpu['sample']})")
@@ -364,6 +409,7 @@ def main():
         "storage_runs": runs,
         "adjoint": adj,
         "ensemble": ens,
+        "klinkenberg_channel": kn,
     }
     print(json.dumps(out), flush=True)
 

@@ -165,7 +165,10 @@ class Lattice:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            _load().lbo_destroy(h)
+            try:
+                _load().lbo_destroy(h)
+            except TypeError:  # interpreter shutdown: module globals already gone
+                pass
             self._h = None
 
     def step(self, n: int = 1) -> "Lattice":

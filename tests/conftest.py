@@ -19,3 +19,11 @@ def _oracle_built():
     import oracle
     oracle.build(force=False)
     yield
+
+
+@pytest.fixture(scope="session")
+def shale8192():
+    """The fractured-shale medium at its full 8192 x 8192 size (seed 3),
+    generated once per session."""
+    from paper_1411_7051_amd import inputs
+    return inputs.shale(n=8192, seed=3)

@@ -1,0 +1,57 @@
+"""The FP64 oracle on a window of a large medium.
+
+After N steps a node depends only on nodes within N links of it (one link
+per pull; a pressure column also reads its neighbour's pulled values, one
+more link).  So the oracle runs on a window of the medium, started from the
+same state, and every node at least N + 2 links inside the window's cut
+edges equals the full-size result.  Cut edges are closed with periodic wrap
+(or, at an end column, the pressure boundary with an arbitrary density on
+the cut side); whatever they do cannot reach the kept nodes in N steps.
+Test infrastructure only."""
+import numpy as np
+
+import oracle
+from paper_1411_7051_amd import inputs
+
+W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def ramp(case, x):
+    p = case.params
+    nx = case.eps.shape[1]
+    if p.get("init", 0) != 1:
+        return np.full(len(x), p.get("rho0", 1.0))
+    return p["rho_in"] + (p["rho_out"] - p["rho_in"]) * x / (nx - 1)
+
+
+def window_oracle(case, xa, xb, ya, h, steps):
+    """FP64 oracle on columns [xa, xb) and rows ya .. ya+h-1 (wrapped in y)
+    of `case`, started from the case's initial state.  Returns the window's
+    (rho, ux, uy) and the valid sub-window as (x slice, y slice) in window
+    coordinates."""
+    ny, nx = case.eps.shape
+    rows = (ya + np.arange(h)) % ny
+    sub = lambda a: np.ascontiguousarray(a[rows][:, xa:xb])
+    p = dict(case.params)
+    xs = np.arange(xa, xb, dtype=np.float64)
+    rho0 = ramp(case, xs)
+    touches_in, touches_out = xa == 0, xb == nx
+    if p.get("bc_x") == inputs.PRESSURE and (touches_in or touches_out):
+        p["bc_x"] = inputs.PRESSURE
+        p["rho_in"] = p["rho_in"] if touches_in else float(rho0[0])
+        p["rho_out"] = p["rho_out"] if touches_out else float(rho0[-1])
+    else:
+        p["bc_x"] = inputs.PERIODIC
+    p["bc_y"] = inputs.PERIODIC
+    p["init"] = 0
+    lat = oracle.Lattice(sub(case.eps), sub(case.k), sub(case.kn0), **p)
+    f = W[:, None, None] * np.broadcast_to(rho0[None, None, :], (9, h, xb - xa))
+    lat.set_state(f)
+    lat.step(steps)
+    m = steps + 2
+    xl = 0 if touches_in and case.params.get("bc_x") == inputs.PRESSURE else m
+    xr = 0 if touches_out and case.params.get("bc_x") == inputs.PRESSURE else m
+    valid = (slice(xl, xb - xa - xr), slice(m, h - m) if h < ny else slice(0, h))
+    return lat.macro(), valid, rows
+
+

@@ -154,7 +154,7 @@ def test_gradient_rejects_forchheimer(dev):
     assert e.value.status == -5
 
 
-def test_fullsize_shale_against_gpu_fd(dev):
+def test_fullsize_shale_against_gpu_fd(dev, shale8192):
     """Fractured shale matrix at its full 8192 x 8192 size: the adjoint
     gradient of the outlet flux after 200 steps against FP32 central
     differences of the HIP path itself on 16 seeded nodes with
@@ -164,7 +164,7 @@ def test_fullsize_shale_against_gpu_fd(dev):
     sampled |g| -- the FP32 adjoint state carries a common (density
     sensitivity) part much larger than its momentum part in the stiff
     matrix, which limits per-node relative accuracy where |g| is small."""
-    case = inputs.shale(n=8192, seed=3)
+    case = shale8192
     steps = 200
     lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
     _, g = lat.gradient(steps, "q_out", ckpt_every=100, hist_len=100)

@@ -1,0 +1,178 @@
+"""Parity at the full workload sizes, in the launch configurations the
+benchmark times, on sampled outputs the FP64 oracle can compute.
+
+The oracle runs on windows of the full medium (``oracle_window``): after N
+steps every node at least N + 2 links inside a window's cut edges depends
+on nothing outside the window, so it must agree with the full-size GPU
+lattice there.
+
+Also: the reduced-precision storage bounds on the permeability (FP16, BF16
+against the oracle and against FP32), and the Klinkenberg channel at
+1024 x 512 run to steady state against the closed form."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1411_7051_amd import inputs
+from paper_1411_7051_amd.batch import Batch, ensemble_lattices
+from paper_1411_7051_amd.lattice import Lattice
+from oracle_window import window_oracle
+
+pytestmark = pytest.mark.gpu
+
+# velocity relative L2 against the FP64 oracle, per storage (FP32: the parity
+# bar; FP16 / BF16: measured errors times a margin of 3-10)
+VEL_TOL = {"f32": 1e-5, "f16": 2e-4, "bf16": 5e-3}
+# global permeability relative error bounds for reduced-precision storage
+KAPP_TOL = {"f32": 1e-6, "f16": 1e-5, "bf16": 1e-3}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = torch.device("cuda", 0)
+    torch.cuda.set_device(d)
+    return d
+
+
+def compare_window(gpu_macro, case, xa, xb, ya, h, steps, storage):
+    (r_rho, r_ux, r_uy), (vx, vy), rows = window_oracle(case, xa, xb, ya, h, steps)
+    g = [a[rows][:, xa:xb] for a in gpu_macro]
+    sel = lambda a: a[vy, vx]
+    ux, uy, rx, ry = sel(g[1]), sel(g[2]), sel(r_ux), sel(r_uy)
+    assert ux.size > 0
+    err = np.linalg.norm(np.stack([ux - rx, uy - ry])) / np.linalg.norm(np.stack([rx, ry]))
+    assert err <= VEL_TOL[storage], f"window x[{xa},{xb}) y@{ya}: velocity rel L2 {err:.3e}"
+    assert np.max(np.abs(sel(g[0]) - sel(r_rho))) < 1e-5
+    return err
+
+
+def macro_np(lat):
+    return [t.double().cpu().numpy() for t in lat.macroscopic()]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_discs4096_windows(dev, storage):
+    """Two-component disc medium at 4096 x 4096 (the benchmark workload)."""
+    case = inputs.discs(n=4096, seed=2)
+    steps = 60
+    lat = Lattice(case.eps, case.k, case.kn0, device=dev, storage=storage, **case.params)
+    lat.step(steps)
+    g = macro_np(lat)
+    lat.close()
+    rng = np.random.default_rng(11)
+    w = 2 * (steps + 2) + 48
+    for xa, xb in [(0, w), (4096 - w, 4096)] + [(int(a), int(a) + w) for a in
+                                                 rng.integers(1, 4096 - w - 1, 2)]:
+        compare_window(g, case, xa, xb, int(rng.integers(0, 4096)), w, steps, storage)
+
+
+def test_shale8192_windows(dev, shale8192):
+    """Fractured shale at 8192 x 8192 (the gradient workload), windows centred
+    on fracture nodes and at both pressure ends."""
+    case = shale8192
+    steps = 60
+    lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+    lat.step(steps)
+    g = macro_np(lat)
+    lat.close()
+    torch.cuda.empty_cache()
+    w = 2 * (steps + 2) + 40
+    frac = np.argwhere(case.eps > 0.5)
+    rng = np.random.default_rng(12)
+    picks = frac[rng.choice(len(frac), 2, replace=False)]
+    wins = [(0, w, 100), (8192 - w, 8192, 5000)]
+    for y, x in picks:
+        xa = int(min(max(x - w // 2, 1), 8192 - w - 1))
+        wins.append((xa, xa + w, int(y) - w // 2))
+    for xa, xb, ya in wins:
+        compare_window(g, case, xa, xb, ya % 8192, w, steps, "f32")
+
+
+def test_ensemble_samples(dev):
+    """The 192-sample ensemble in FP16 with the tuned launch shape and graph
+    replay: the smallest samples whole, and windows of the largest."""
+    cases = inputs.ensemble(n_samples=192, seed=4)
+    lats = ensemble_lattices(cases, device=dev, storage="f16")
+    b = Batch(lats)
+    b.autotune(reps=2)
+    tile_x, rows, grid, _ = b.launch
+    b.set_launch(tile_x, rows, grid, 20)
+    steps = 60
+    b.step(steps)
+    sizes = np.array([c.nodes for c in cases])
+    order = np.argsort(sizes)
+    for i in order[:2]:
+        c = cases[i]
+        g = macro_np(lats[i])
+        ny, nx = c.eps.shape
+        compare_window(g, c, 0, nx, 0, ny, steps, "f16")
+    i = order[-1]
+    c = cases[i]
+    g = macro_np(lats[i])
+    n = c.eps.shape[1]
+    w = 2 * (steps + 2) + 40
+    for xa, ya in [(0, 3), (n // 2, n // 3), (n - w, 7)]:
+        compare_window(g, c, xa, xa + w, ya, w, steps, "f16")
+
+
+def test_reduced_storage_permeability_vs_oracle(dev):
+    """Global permeability and velocity of FP32, FP16 and BF16 storage
+    against the FP64 oracle on a 256 x 256 copy of the disc medium (radii
+    scaled by 1/16), 2000 steps."""
+    case = inputs.discs(n=256, seed=2)
+    steps = 2000
+    ref = oracle.Lattice(case.eps, case.k, case.kn0, **case.params).step(steps)
+    kr = ref.apparent_permeability()
+    _, rx, ry = ref.macro()
+    for st in ("f32", "f16", "bf16"):
+        lat = Lattice(case.eps, case.k, case.kn0, device=dev, storage=st, **case.params)
+        lat.step(steps)
+        k = lat.apparent_permeability()
+        _, ux, uy = macro_np(lat)
+        err = np.linalg.norm(np.stack([ux - rx, uy - ry])) / np.linalg.norm(np.stack([rx, ry]))
+        assert abs(k / kr - 1) <= KAPP_TOL[st], (st, k / kr - 1)
+        assert err <= VEL_TOL[st], (st, err)
+
+
+def test_reduced_storage_permeability_fullsize(dev):
+    """FP16 and BF16 storage against FP32 storage on the 4096 x 4096 disc
+    medium after 1000 steps."""
+    case = inputs.discs(n=4096, seed=2)
+    out = {}
+    for st in ("f32", "f16", "bf16"):
+        lat = Lattice(case.eps, case.k, case.kn0, device=dev, storage=st, **case.params)
+        lat.step(1000)
+        _, ux, uy = lat.macroscopic()
+        out[st] = (lat.apparent_permeability(), torch.stack([ux, uy]).double())
+        lat.close()
+    k32, u32 = out["f32"]
+    for st in ("f16", "bf16"):
+        k, u = out[st]
+        assert abs(k / k32 - 1) <= KAPP_TOL[st], (st, k / k32 - 1)
+        err = float(torch.linalg.norm(u - u32) / torch.linalg.norm(u32))
+        assert err <= VEL_TOL[st], (st, err)
+
+
+@pytest.mark.parametrize("kn0", [0.001, 0.01, 0.1, 1.0, 5.0])
+def test_klinkenberg_channel_1024x512(dev, kn0):
+    """Porous-filled plates at 1024 x 512 (eps 0.5, k 1.024, tau 0.8),
+    pressure-driven 1.01 / 1.0, local Kn with base kn0, run to steady state:
+    k_app / k against the Brinkman channel closed form with the Klinkenberg
+    factor at the base Kn, f_c(Kn0) (1 - tanh(aH/2) / (aH/2)), a =
+    sqrt(eps / k_a) (Sec. IV.A).  Agreement to 1.5%: the density, hence Kn,
+    varies by 1% along the channel and the closed form is incompressible."""
+    nx, ny, eps, k = 1024, 512, 0.5, 1.024
+    case = inputs.channel(nx, ny, eps=eps, k=k, kn0=kn0, drive="pressure")
+    lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+    steps, res, why = lat.run_to_steady(every=200, tol=1e-9, max_steps=600000)
+    assert why in ("tol", "plateau") and res < 1e-6, (steps, res, why)
+    ka = k * oracle.fc(kn0)
+    a = math.sqrt(eps / ka)
+    expect = oracle.fc(kn0) * (1 - math.tanh(a * ny / 2) / (a * ny / 2))
+    got = lat.apparent_permeability() / k
+    assert abs(got / expect - 1) < 0.015, (got, expect)

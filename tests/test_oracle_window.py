@@ -1,0 +1,32 @@
+"""The windowed oracle used by the full-size parity tests reproduces the
+full-size oracle exactly on the nodes it keeps (CPU)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle_window import window_oracle
+from paper_1411_7051_amd import inputs
+
+
+@pytest.mark.parametrize("xa,xb,ya,h", [(0, 54, 5, 54), (186, 240, 190, 54),
+                                        (100, 154, 150, 54), (0, 240, 0, 200)])
+def test_window_matches_full_oracle(xa, xb, ya, h):
+    case = inputs.discs(n=200, seed=2, nx=240, ny=200)
+    steps = 15
+    full = oracle.Lattice(case.eps, case.k, case.kn0, **case.params).step(steps)
+    (r_rho, r_ux, r_uy), (vx, vy), rows = window_oracle(case, xa, xb, ya, h, steps)
+    assert r_ux[vy, vx].size > 0
+    for a, b in zip(full.macro(), (r_rho, r_ux, r_uy)):
+        assert np.array_equal(a[rows][:, xa:xb][vy, vx], b[vy, vx])
+
+
+def test_window_margin_is_needed():
+    """One node closer to a cut edge than the kept region and the result
+    differs: the margin is not wider than it needs to be by a whole link."""
+    case = inputs.discs(n=200, seed=2, nx=240, ny=200)
+    steps = 15
+    full = oracle.Lattice(case.eps, case.k, case.kn0, **case.params).step(steps)
+    (_, r_ux, _), (vx, vy), rows = window_oracle(case, 100, 154, 150, 54, steps)
+    g = full.macro()[1][rows][:, 100:154]
+    m = steps  # nodes steps links from the cut: reachable from the edge
+    assert not np.array_equal(g[m:54 - m, m:54 - m], r_ux[m:54 - m, m:54 - m])
