@@ -139,12 +139,14 @@ lbk_status lbk_load_state(lbk_lattice *lat, const void *src);
 /* ---------------------------------------------------------------------
  * Gradients (reverse mode through the discrete time stepping).
  *
- * J is a scalar read-out of the state after n steps; the gradient is
- * dJ / d ln k(x) for every node, with eps, kn0 and the starting state held
- * fixed.  The reverse sweep is the exact transpose of the discrete map
- * (pull, pressure-column override, collide of Eqs. 12, 14, 15, 17, 8, 3,
- * 6-7 with the local Kn), evaluated along the forward trajectory, which
- * is recomputed from checkpoints:
+ * J is a scalar read-out of the state after n steps; the gradients are
+ * dJ / d ln k(x) and, on request, dJ / d ln kn0(x) for every node, with
+ * eps and the starting state held fixed (and kn0, resp. k, held fixed: for
+ * a medium whose kn0 follows from k through Eq. 11, kn0 ~ k^-1/2, the
+ * total derivative is dJ/d ln k - 1/2 dJ/d ln kn0).  The reverse sweep is
+ * the exact transpose of the discrete map (pull, pressure-column override,
+ * collide of Eqs. 12, 14, 15, 17, 8, 3, 6-7 with the local Kn), evaluated
+ * along the forward trajectory, which is recomputed from checkpoints:
  *   - lbk_adjoint_forward runs the n steps (advancing the lattice exactly
  *     as lbk_step would) and stores the state every ckpt_every steps;
  *   - lbk_adjoint_backward recomputes each checkpoint segment (keeping
@@ -176,10 +178,12 @@ lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64_t n_steps,
                                int64_t ckpt_every, int64_t hist_len, void *ws, size_t ws_bytes,
                                double *J);
 
-/* Gradient of the J of the last lbk_adjoint_forward on this handle (same
- * workspace, no lbk_step or load in between) into dJ_dlnk: a device buffer
- * of [ny][nx] float32.  Leaves the lattice state untouched. */
-lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws_bytes, float *dJ_dlnk);
+/* Gradients of the J of the last lbk_adjoint_forward on this handle (same
+ * workspace, no lbk_step or load in between) into device buffers of
+ * [ny][nx] float32: dJ_dlnk (required) and dJ_dlnkn0 (NULL to skip it; it
+ * is 0 where kn0 = 0).  Leaves the lattice state untouched. */
+lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws_bytes, float *dJ_dlnk,
+                                float *dJ_dlnkn0);
 
 /* ---------------------------------------------------------------------
  * Ensembles: many independent samples stepped together.

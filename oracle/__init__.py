@@ -215,18 +215,22 @@ def objective(lat: Lattice, name: str) -> float:
 
 
 def fd_gradient(eps, k, kn0, steps, nodes, objective_name="k_app", h=1e-4,
-                **params) -> np.ndarray:
+                wrt="k", **params) -> np.ndarray:
     """Central finite differences of the objective after ``steps`` steps with
-    respect to ln k at each (y, x) in ``nodes``: (J(ln k + h) - J(ln k - h)) / 2h.
-    Kn0 is held fixed."""
+    respect to ln k (``wrt="k"``, kn0 held fixed) or ln kn0 (``wrt="kn0"``, k
+    held fixed) at each (y, x) in ``nodes``: (J(ln p + h) - J(ln p - h)) / 2h."""
+    if wrt not in ("k", "kn0"):
+        raise ValueError(wrt)
     out = np.zeros(len(nodes))
     k = np.asarray(k, dtype=np.float64)
+    kn0 = np.zeros_like(k) if kn0 is None else np.asarray(kn0, dtype=np.float64)
     for j, (y, x) in enumerate(nodes):
         vals = []
         for s in (+1.0, -1.0):
-            kk = k.copy()
-            kk[y, x] = k[y, x] * math.exp(s * h)
-            lat = Lattice(eps, kk, kn0, **params).step(steps)
+            kk, kn = k.copy(), kn0.copy()
+            field = kk if wrt == "k" else kn
+            field[y, x] = field[y, x] * math.exp(s * h)
+            lat = Lattice(eps, kk, kn, **params).step(steps)
             vals.append(objective(lat, objective_name))
         out[j] = (vals[0] - vals[1]) / (2.0 * h)
     return out

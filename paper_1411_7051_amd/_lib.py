@@ -70,7 +70,7 @@ _SIG = {
     "lbk_adjoint_forward": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
                                            ctypes.c_int64, _P, ctypes.c_size_t,
                                            ctypes.POINTER(ctypes.c_double)]),
-    "lbk_adjoint_backward": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+    "lbk_adjoint_backward": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, _P]),
     "lbk_batch_workspace_size": (ctypes.c_int, [_P, ctypes.c_int32,
                                                 ctypes.POINTER(ctypes.c_size_t)]),
     "lbk_batch_create": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_size_t,

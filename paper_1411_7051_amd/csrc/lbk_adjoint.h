@@ -9,11 +9,12 @@ namespace lbk {
 // read-out of J = sum_x a1 rho u_x + a2 u_x (terminal = 1; a1 only on column
 // nx-1 when outlet = 1).  mu_in / mu_out: adjoint states [y][9][pitch] FP32;
 // hist: (rho, jx, jy) [y][3][pitch] of the forward step being reversed;
-// grad: FP32 [y][pitch], accumulated over a segment.
+// grad: FP32 [y][pitch] d J / d ln k, accumulated over a segment; grad2:
+// likewise d J / d ln kn0, or NULL to skip that plane.
 hipError_t launch_adjoint(int bcx, int bcy, const float *mu_in, float *mu_out, const float *hist,
-                          const char *med, const MLayout &mlay, float *grad, const Geom &g,
-                          const Physics &ph, int terminal, float a1, float a2, int outlet,
-                          hipStream_t st);
+                          const char *med, const MLayout &mlay, float *grad, float *grad2,
+                          const Geom &g, const Physics &ph, int terminal, float a1, float a2,
+                          int outlet, hipStream_t st);
 
 // total[y][x] += seg[y][x]; seg[y][x] = 0 ([y][pitch]).
 hipError_t launch_grad_fold(float *seg, double *total, const Geom &g, hipStream_t st);

@@ -1,6 +1,7 @@
 // lbk_adjoint.hip -- reverse-mode (discrete adjoint) sweep of the Klinkenberg
 // lattice Boltzmann step, for gradients of a scalar read-out J of the state
-// after N steps with respect to the log-permeability field ln k(x).
+// after N steps with respect to the log-permeability field ln k(x) and,
+// optionally, the log base-Knudsen field ln kn0(x).
 //
 // The forward step n is  f^n = B(P(S_{n-1})),  S_n = C(f^n; ln k)  with P the
 // pull (a permutation, bounce-back included), B the pressure-column override
@@ -14,7 +15,9 @@
 //   lam_f_k = (1 - omega) mu_k + G_rho + e_k . G_j
 // with G_rho, G_j the total derivatives of Psi = sum_i mu_i (omega f^eq_i + F_i)
 // through u(rho, j, ln k), F = -A u + eps G, A = eps nu / (k f_c(Kn)) and
-// Kn = kn0 rho_ref / rho; the linearisation point (rho, j) of every step is
+// Kn = kn0 rho_ref / rho (so dA/d ln k = -A and dA/d ln kn0 =
+// -A Kn f_c'(Kn) / f_c, which varies with rho from step to step and needs a
+// gradient plane of its own); the linearisation point (rho, j) of every step is
 // the history written by the recomputing forward sweep.  The read-out of J
 // (global permeability or outlet flux) is the same local map with Psi the
 // node's share of J and no (1 - omega) mu term.
@@ -27,8 +30,9 @@
 //
 // Layouts (row blocks, `pitch` elements per slot, FP32): adjoint state
 // [y][9][pitch]; history [y][3][pitch] = (rho, jx, jy); gradient
-// [y][pitch] accumulated in FP32 over one recomputed segment (at most a few
-// hundred steps) and folded into an FP64 total at the segment's end.  The
+// [y][pitch] (one plane per parameter field) accumulated in FP32 over one
+// recomputed segment (at most a few hundred steps) and folded into an FP64
+// total at the segment's end.  The
 // adjoint state and the history are each read once, so they stream
 // nontemporally.  The Forchheimer term is not differentiated (the host
 // rejects f_eps != 0).
@@ -46,9 +50,10 @@ __device__ __forceinline__ int xcd_remap_a(int b, int nb)
 }
 
 // Forward quantities of one node's velocity solve, as in velocity() of the
-// sweep, plus what the adjoint needs: dA/drho through the local Kn.
+// sweep, plus what the adjoint needs: dA/drho through the local Kn and
+// dA/d ln kn0.
 struct NodeFwd {
-    float rho, rinv, jx, jy, eps, ie, A, g, ux, uy, Fx, Fy, dA_drho;
+    float rho, rinv, jx, jy, eps, ie, A, g, ux, uy, Fx, Fy, dA_drho, dA_dlnkn;
     bool solid;
 };
 
@@ -80,16 +85,18 @@ __device__ __forceinline__ NodeFwd node_fwd(const Physics &ph, float rho, float 
     n.Fy = n.solid ? -2.0f * jy * n.rinv : eps * ph.gy - n.A * n.uy;
     // f_c'(Kn) = P1' P2 + P1 P2' with P1 = 1 + alpha Kn = (a + 1.358 t Kn)/a,
     // P2 = (1 + 5 Kn)/(1 + Kn); P1' = 1.358 t (t + 1.4348 * 0.170)/a^2,
-    // P2' = 4/(1 + Kn)^2.  dA/drho = A Kn f_c' / (f_c rho) (Kn ~ 1/rho).
-    float dA = 0.0f;
-    if (ph.kn_local && kn > 0.0f) {
+    // P2' = 4/(1 + Kn)^2.  Kn ~ kn0: dA/d ln kn0 = -A Kn f_c' / f_c; with the
+    // local Kn ~ 1/rho also dA/drho = -(dA/d ln kn0) / rho.
+    float dAk = 0.0f;
+    if (kn > 0.0f) {
         const float P1 = (a + 1.358f * t * kn) / a, P2 = (1.0f + 5.0f * kn) / (1.0f + kn);
         const float P1d = 1.358f * t * (t + 0.243916f) / (a * a);
         const float P2d = 4.0f / ((1.0f + kn) * (1.0f + kn));
         const float fc = P1 * P2;
-        dA = n.A * kn * (P1d * P2 + P1 * P2d) / (fc * rho);
+        dAk = -n.A * kn * (P1d * P2 + P1 * P2d) / fc;
     }
-    n.dA_drho = dA;
+    n.dA_dlnkn = dAk;
+    n.dA_drho = ph.kn_local ? -dAk * n.rinv : 0.0f;
     return n;
 }
 
@@ -119,7 +126,7 @@ __device__ __forceinline__ Mom moments(const float (&l)[9])
 // Psi_rho, vectors Psi_u, Psi_F) to its total derivatives with respect to
 // rho, j and ln k through the node's velocity solve.
 struct Grads {
-    float rho, jx, jy, lnk;
+    float rho, jx, jy, lnk, lnkn;
 };
 __device__ __forceinline__ Grads chain(const NodeFwd &n, float Pr, float Pux, float Puy,
                                        float PFx, float PFy)
@@ -131,6 +138,7 @@ __device__ __forceinline__ Grads chain(const NodeFwd &n, float Pr, float Pux, fl
         G.jy = -2.0f * n.rinv * PFy;
         G.rho = Pr + 2.0f * n.rinv * n.rinv * (PFx * n.jx + PFy * n.jy);
         G.lnk = 0.0f;
+        G.lnkn = 0.0f;
         return G;
     }
     // u = g v, v = j / rho + eps G / 2, g = 1 / (1 + A/2), F = -A u + eps G
@@ -140,6 +148,7 @@ __device__ __forceinline__ Grads chain(const NodeFwd &n, float Pr, float Pux, fl
     G.jy = n.g * n.rinv * Ty;
     G.rho = Pr - (G.jx * n.jx + G.jy * n.jy) * n.rinv + GA * n.dA_drho;
     G.lnk = -n.A * GA; // dA / d ln k = -A
+    G.lnkn = n.dA_dlnkn * GA;
     return G;
 }
 
@@ -179,7 +188,7 @@ __device__ __forceinline__ Grads collide_adj(const Physics &ph, const NodeFwd &n
 __device__ __forceinline__ Grads readout_adj(const NodeFwd &n, float a1, float a2,
                                              float (&lf)[9])
 {
-    Grads G{0.0f, 0.0f, 0.0f, 0.0f};
+    Grads G{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     if (!n.solid && (a1 != 0.0f || a2 != 0.0f))
         G = chain(n, a1 * n.ux, a1 * n.rho + a2, 0.0f, 0.0f, 0.0f);
 #pragma unroll
@@ -192,8 +201,8 @@ __device__ __forceinline__ Grads readout_adj(const NodeFwd &n, float a1, float a
 //   f_i(b) = f_eq_i(rho_b, u_n; eps_b) + f_i(n) - f_eq_i(rho_n, u_n; eps_n)
 // with respect to the neighbour's post-stream populations f(n) (through
 // f(n) itself, rho_n, j_n and u_n(rho_n, j_n, ln k_n)).  Adds to lfn and
-// returns the neighbour's ln k sensitivity.
-__device__ __forceinline__ float nee_adj(const NodeFwd &n, float rho_b, float eps_b,
+// returns the neighbour's ln k and ln kn0 sensitivities.
+__device__ __forceinline__ float2 nee_adj(const NodeFwd &n, float rho_b, float eps_b,
                                          const float (&lb)[9], float (&lfn)[9])
 {
     const Mom M = moments(lb);
@@ -215,15 +224,15 @@ __device__ __forceinline__ float nee_adj(const NodeFwd &n, float rho_b, float ep
     // Psi = Phi_b(u) - Phi_n(rho_n, u): explicit d/drho_n = -Phi_n / rho_n,
     // d/du = Hu; no direct force dependence.
     const Grads G = chain(n, -phin_over_rho, dbx - dnx, dby - dny, 0.0f, 0.0f);
-    float gx = G.jx, gy = G.jy, gr = G.rho, gl = G.lnk;
+    float gx = G.jx, gy = G.jy, gr = G.rho, gl = G.lnk, gk = G.lnkn;
     if (n.solid) { // u_n = 0 does not move with f(n)
-        gx = gy = gl = 0.0f;
+        gx = gy = gl = gk = 0.0f;
         gr = -phin_over_rho;
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         lfn[i] += lb[i] + gr + ex_of(i) * gx + ey_of(i) * gy;
-    return gl;
+    return make_float2(gl, gk);
 }
 
 __device__ __forceinline__ Rsrc rsrc_row(const void *base, uint64_t row_bytes, int y)
@@ -239,14 +248,15 @@ __device__ __forceinline__ Rsrc rsrc_row(const void *base, uint64_t row_bytes, i
 //   mu_out [y][9][pitch]  adjoint of S_{n-1} (written by push)
 //   hist   [y][3][pitch]  (rho, jx, jy) of step n's post-stream populations
 //   grad   [y][pitch]     FP32, accumulates d J / d ln k over a segment
+//   grad2  [y][pitch]     FP32, d J / d ln kn0 likewise (KN only)
 // Objective: J = sum_x a1(x) rho u_x + a2 u_x with a1(x) = a1 (all nodes,
 // or only column nx-1 when outlet != 0) and a2 uniform.
-template <int BCX, int BCY>
+template <int BCX, int BCY, bool KN>
 __global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float *mu_out,
                                                        const float *hist, const char *med,
-                                                       MLayout mlay, float *grad, Geom g,
-                                                       Physics ph, int terminal, float a1,
-                                                       float a2, int outlet, int bpr)
+                                                       MLayout mlay, float *grad, float *grad2,
+                                                       Geom g, Physics ph, int terminal,
+                                                       float a1, float a2, int outlet, int bpr)
 {
     const int L = xcd_remap_a(blockIdx.x, gridDim.x);
     const int y = L / bpr;
@@ -260,6 +270,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float 
     const Rsrc mr = make_rsrc(med + (uint64_t)y * mlay.row, (uint32_t)mlay.row);
     const Rsrc lin = rsrc_row(mu_in, lrow, y);
     float *grow_p = grad + (uint64_t)y * g.pitch;
+    float *grow_k = KN ? grad2 + (uint64_t)y * g.pitch : nullptr;
 
     auto load_node = [&](uint32_t xx) {
         const float rho = ld_f32_nt(hr, xx * 4, 0), jx = ld_f32_nt(hr, xx * 4, slot),
@@ -279,7 +290,11 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float 
         return collide_adj(ph, n, mu, lf);
     };
     // each gradient entry has exactly one writer per launch
-    auto add_grad = [&](uint32_t xx, float v) { grow_p[xx] += v; };
+    auto add_grad = [&](uint32_t xx, float v, float vk) {
+        grow_p[xx] += v;
+        if (KN)
+            grow_k[xx] += vk;
+    };
 
     // rows the push writes into: source of direction i is (x - e_ix, y - e_iy)
     int ym = y - 1, yp = y + 1;
@@ -308,7 +323,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float 
     } else {
         const NodeFwd n = load_node(x);
         const Grads G = node_adj(n, x, lf);
-        float gl = G.lnk;
+        float gl = G.lnk, gk = G.lnkn;
         if (BCX == BC_PRESSURE && (x == 1 || x == nx - 2)) {
             // carry the boundary node next door (x = 0 or nx-1)
             const uint32_t xb = (x == 1) ? 0 : nx - 1;
@@ -316,19 +331,23 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float 
                 const NodeFwd b = load_node(xb);
                 float lb[9];
                 const Grads Gb = node_adj(b, xb, lb);
-                add_grad(xb, Gb.lnk);
-                gl += nee_adj(n, b.rho, b.eps, lb, lf);
+                add_grad(xb, Gb.lnk, Gb.lnkn);
+                const float2 gn = nee_adj(n, b.rho, b.eps, lb, lf);
+                gl += gn.x;
+                gk += gn.y;
             }
             if (nx == 3) {
                 // x = 1 is the neighbour of both columns: the outlet too
                 const NodeFwd b = load_node(2);
                 float lb[9];
                 const Grads Gb = node_adj(b, 2, lb);
-                add_grad(2, Gb.lnk);
-                gl += nee_adj(n, b.rho, b.eps, lb, lf);
+                add_grad(2, Gb.lnk, Gb.lnkn);
+                const float2 gn = nee_adj(n, b.rho, b.eps, lb, lf);
+                gl += gn.x;
+                gk += gn.y;
             }
         }
-        add_grad(x, gl);
+        add_grad(x, gl, gk);
     }
 
     // push: mu_out[i](x - e_i) = lf_i, bounce-back at walls
@@ -403,29 +422,39 @@ __global__ __launch_bounds__(256) void grad_out_kernel(const double *grad, float
 
 template <int BCX, int BCY>
 static hipError_t adj_t(const float *mu_in, float *mu_out, const float *hist, const char *med,
-                        const MLayout &mlay, float *grad, const Geom &g, const Physics &ph,
-                        int terminal, float a1, float a2, int outlet, hipStream_t st)
+                        const MLayout &mlay, float *grad, float *grad2, const Geom &g,
+                        const Physics &ph, int terminal, float a1, float a2, int outlet,
+                        hipStream_t st)
 {
     const int bpr = (g.nx + 255) / 256;
-    hipLaunchKernelGGL((adjoint_kernel<BCX, BCY>), dim3(bpr * g.ny), dim3(256), 0, st, mu_in,
-                       mu_out, hist, med, mlay, grad, g, ph, terminal, a1, a2, outlet, bpr);
+    if (grad2)
+        hipLaunchKernelGGL((adjoint_kernel<BCX, BCY, true>), dim3(bpr * g.ny), dim3(256), 0, st,
+                           mu_in, mu_out, hist, med, mlay, grad, grad2, g, ph, terminal, a1, a2,
+                           outlet, bpr);
+    else
+        hipLaunchKernelGGL((adjoint_kernel<BCX, BCY, false>), dim3(bpr * g.ny), dim3(256), 0,
+                           st, mu_in, mu_out, hist, med, mlay, grad, grad2, g, ph, terminal, a1,
+                           a2, outlet, bpr);
     return hipGetLastError();
 }
 
 hipError_t launch_adjoint(int bcx, int bcy, const float *mu_in, float *mu_out, const float *hist,
-                          const char *med, const MLayout &mlay, float *grad, const Geom &g,
-                          const Physics &ph, int terminal, float a1, float a2, int outlet,
-                          hipStream_t st)
+                          const char *med, const MLayout &mlay, float *grad, float *grad2,
+                          const Geom &g, const Physics &ph, int terminal, float a1, float a2,
+                          int outlet, hipStream_t st)
 {
+#define LBK_ADJ(X, Y)                                                                        \
+    adj_t<X, Y>(mu_in, mu_out, hist, med, mlay, grad, grad2, g, ph, terminal, a1, a2, outlet, st)
     switch (bcx * 2 + bcy) {
-    case 0: return adj_t<BC_PERIODIC, BC_PERIODIC>(mu_in, mu_out, hist, med, mlay, grad, g, ph, terminal, a1, a2, outlet, st);
-    case 1: return adj_t<BC_PERIODIC, BC_WALL>(mu_in, mu_out, hist, med, mlay, grad, g, ph, terminal, a1, a2, outlet, st);
-    case 2: return adj_t<BC_WALL, BC_PERIODIC>(mu_in, mu_out, hist, med, mlay, grad, g, ph, terminal, a1, a2, outlet, st);
-    case 3: return adj_t<BC_WALL, BC_WALL>(mu_in, mu_out, hist, med, mlay, grad, g, ph, terminal, a1, a2, outlet, st);
-    case 4: return adj_t<BC_PRESSURE, BC_PERIODIC>(mu_in, mu_out, hist, med, mlay, grad, g, ph, terminal, a1, a2, outlet, st);
-    case 5: return adj_t<BC_PRESSURE, BC_WALL>(mu_in, mu_out, hist, med, mlay, grad, g, ph, terminal, a1, a2, outlet, st);
+    case 0: return LBK_ADJ(BC_PERIODIC, BC_PERIODIC);
+    case 1: return LBK_ADJ(BC_PERIODIC, BC_WALL);
+    case 2: return LBK_ADJ(BC_WALL, BC_PERIODIC);
+    case 3: return LBK_ADJ(BC_WALL, BC_WALL);
+    case 4: return LBK_ADJ(BC_PRESSURE, BC_PERIODIC);
+    case 5: return LBK_ADJ(BC_PRESSURE, BC_WALL);
     default: return hipErrorInvalidValue;
     }
+#undef LBK_ADJ
 }
 
 hipError_t launch_grad_fold(float *seg, double *total, const Geom &g, hipStream_t st)

@@ -502,6 +502,8 @@ static lbk_status adj_plan(const lbk_lattice *lat, int64_t n, int64_t c1, int64_
     P.lam = take(2 * P.lam_bytes);
     P.grad = take((size_t)rows * lat->L.pitch * 8);
     P.seg = take((size_t)rows * lat->L.pitch * 4);
+    P.grad2 = take((size_t)rows * lat->L.pitch * 8);
+    P.seg2 = take((size_t)rows * lat->L.pitch * 4);
     P.total = o;
     return LBK_OK;
 }
@@ -587,7 +589,7 @@ extern "C" lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64
 }
 
 extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws_bytes,
-                                           float *dJ_dlnk)
+                                           float *dJ_dlnk, float *dJ_dlnkn0)
 {
     if (!lat || !ws || !dJ_dlnk)
         return fail(LBK_ERR_INVALID_ARG, "NULL argument");
@@ -607,6 +609,9 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
                      reinterpret_cast<float *>(w + P.lam + P.lam_bytes)};
     double *grad = reinterpret_cast<double *>(w + P.grad);
     float *seg = reinterpret_cast<float *>(w + P.seg);
+    const bool kn = dJ_dlnkn0 != nullptr;
+    double *grad2 = reinterpret_cast<double *>(w + P.grad2);
+    float *seg2 = kn ? reinterpret_cast<float *>(w + P.seg2) : nullptr;
     char *rec[2] = {level(P.rec, 0), level(P.rec, 1)};
     auto sweep = [&](const char *src, char *dst, float *hist) {
         return launch_sweep(d.storage, d.bc_x, d.bc_y, src, dst, lat->L.lay, lat->med(),
@@ -616,10 +621,14 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
 
     HIP_TRY(hipMemsetAsync(grad, 0, (size_t)d.ny * lat->L.pitch * 8, st));
     HIP_TRY(hipMemsetAsync(seg, 0, (size_t)d.ny * lat->L.pitch * 4, st));
+    if (kn) {
+        HIP_TRY(hipMemsetAsync(grad2, 0, (size_t)d.ny * lat->L.pitch * 8, st));
+        HIP_TRY(hipMemsetAsync(seg2, 0, (size_t)d.ny * lat->L.pitch * 4, st));
+    }
     // read-out of J at step n: linearisation point of the pull of S_n
     HIP_TRY(sweep(lat->state(lat->cur), rec[0], histp(0)));
     HIP_TRY(launch_adjoint(d.bc_x, d.bc_y, nullptr, lam[0], histp(0), lat->med(), lat->L.mlay,
-                           seg, lat->g, lat->ph, 1, a1, a2, P.outlet, st));
+                           seg, seg2, lat->g, lat->ph, 1, a1, a2, P.outlet, st));
     int cur = 0;
     for (int64_t k = P.k1 - 1; k >= 0; --k) {
         const int64_t a = k * P.c1, b = std::min(P.n, a + P.c1);
@@ -655,13 +664,17 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
             }
             for (int64_t t = b2s; t > a2s; --t) {
                 HIP_TRY(launch_adjoint(d.bc_x, d.bc_y, lam[cur], lam[cur ^ 1], histp(t - a2s),
-                                       lat->med(), lat->L.mlay, seg, lat->g, lat->ph, 0, a1, a2,
-                                       P.outlet, st));
+                                       lat->med(), lat->L.mlay, seg, seg2, lat->g, lat->ph, 0,
+                                       a1, a2, P.outlet, st));
                 cur ^= 1;
             }
             HIP_TRY(launch_grad_fold(seg, grad, lat->g, st));
+            if (kn)
+                HIP_TRY(launch_grad_fold(seg2, grad2, lat->g, st));
         }
     }
     HIP_TRY(launch_grad_out(grad, dJ_dlnk, lat->g, st));
+    if (kn)
+        HIP_TRY(launch_grad_out(grad2, dJ_dlnkn0, lat->g, st));
     return LBK_OK;
 }

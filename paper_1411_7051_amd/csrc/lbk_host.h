@@ -50,7 +50,7 @@ struct AdjPlan {
     int64_t n, c1, c2, t0;
     bool two_level;
     int64_t k1, k2, hlen;
-    size_t outer, inner, rec, hist, lam, grad, seg, total;
+    size_t outer, inner, rec, hist, lam, grad, seg, grad2, seg2, total;
     size_t level_bytes, hist_bytes, lam_bytes;
     const void *ws;
     double a1, a2;

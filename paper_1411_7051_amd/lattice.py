@@ -179,18 +179,23 @@ class Lattice:
                                               ctypes.byref(J)))
         return float(J.value), workspace
 
-    def adjoint_backward(self, workspace: torch.Tensor) -> torch.Tensor:
-        """dJ/d ln k of the last adjoint_forward, [ny][nx] float32."""
+    def adjoint_backward(self, workspace: torch.Tensor, wrt_kn0: bool = False):
+        """dJ/d ln k of the last adjoint_forward, [ny][nx] float32; with
+        ``wrt_kn0`` the pair (dJ/d ln k, dJ/d ln kn0)."""
         g = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+        gk = torch.empty_like(g) if wrt_kn0 else None
         check(_lib.load().lbk_adjoint_backward(self._handle(), workspace.data_ptr(),
-                                               workspace.numel(), g.data_ptr()))
-        return g
+                                               workspace.numel(), g.data_ptr(),
+                                               None if gk is None else gk.data_ptr()))
+        return (g, gk) if wrt_kn0 else g
 
     def gradient(self, steps: int, objective: str = "k_app", ckpt_every: int = 500,
-                 hist_len: Optional[int] = None):
-        """(J, dJ/d ln k) after ``steps`` steps from the current state."""
+                 hist_len: Optional[int] = None, wrt_kn0: bool = False):
+        """(J, dJ/d ln k) after ``steps`` steps from the current state; with
+        ``wrt_kn0``, (J, dJ/d ln k, dJ/d ln kn0)."""
         J, ws = self.adjoint_forward(steps, objective, ckpt_every, hist_len)
-        return J, self.adjoint_backward(ws)
+        g = self.adjoint_backward(ws, wrt_kn0)
+        return (J, *g) if wrt_kn0 else (J, g)
 
     def run_to_steady(self, every: int = 100, tol: float = 1e-9, max_steps: int = 10**7,
                       patience: int = 10):

@@ -417,6 +417,32 @@ def test_uniform_gradient_by_finite_differences():
     assert abs(g[0] * nx * ny / exact - 1) < 1e-5
 
 
+def test_uniform_kn0_gradient_by_finite_differences():
+    """d k_app / d ln kn0 at one node of a uniform periodic medium, times the
+    number of nodes, equals the derivative of the closed-form recurrence
+    u_N(A) with respect to ln kn0, A = eps nu / (k f_c(kn0)) (rho stays at
+    rho_ref, so the local Kn is kn0)."""
+    eps, k, kn0, tau, G, N = 0.5, 0.4, 0.3, 0.8, 1e-5, 25
+    nu = (tau - 0.5) / 3
+    nx, ny = 3, 2
+    fields = _uniform(nx, ny, eps, k, kn0)
+    g = oracle.fd_gradient(*fields, N, [(1, 2)], "k_app", h=1e-3, wrt="kn0", tau=tau, gx=G)
+
+    def kapp_of_lnkn(lnkn):
+        A = eps * nu / (k * oracle.fc(math.exp(lnkn)))
+        q = (1 - A / 2) / (1 + A / 2)
+        b = eps * G / (1 + A / 2)
+        u = 0.5 * b
+        for _ in range(N):
+            u = q * u + b
+        return nu * u / G
+
+    h = 1e-5
+    exact = (kapp_of_lnkn(math.log(kn0) + h) - kapp_of_lnkn(math.log(kn0) - h)) / (2 * h)
+    assert exact != 0.0
+    assert abs(g[0] * nx * ny / exact - 1) < 1e-5
+
+
 def test_finite_difference_light_cone():
     """The outlet flux after N steps cannot depend on k at nodes more than
     N + 1 links from the outlet column: the FD gradient is exactly zero
