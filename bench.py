@@ -145,6 +145,9 @@ def time_adjoint(n, steps, ckpt, hist, device):
     lat = Lattice(case.eps, case.k, case.kn0, device=device, **case.params)
     st = lat.stream
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    if hist == "auto":
+        hist = lat.adjoint_plan(steps, ckpt)
+    hist = int(hist)
     ws = torch.empty(lat.adjoint_workspace_bytes(steps, ckpt, hist), dtype=torch.uint8,
                      device=device)
     lat.step(20)
@@ -186,7 +189,7 @@ def time_adjoint(n, steps, ckpt, hist, device):
     return out
 
 
-def time_ensemble(n_samples, steps, storage, graph_steps, device):
+def time_ensemble(n_samples, steps, storage, graph_steps, device, launch=None):
     """Batched ensemble of uneven samples (seed 4): per-sample lattices
     stepped together by one launch per step, launch shape from the tuner,
     steps replayed from HIP graphs; also the same samples stepped one launch
@@ -203,8 +206,12 @@ def time_ensemble(n_samples, steps, storage, graph_steps, device):
     lats = ensemble_lattices(cases, device=device, storage=storage)
     b = Batch(lats)
     st = lats[0].stream
-    tune_us = b.autotune(reps=5)
-    tile_x, rows, grid, _ = b.launch
+    if launch is None:
+        tune_us = b.autotune(reps=5)
+        tile_x, rows, grid, _ = b.launch
+    else:
+        tune_us = None
+        tile_x, rows, grid = launch
     b.set_launch(tile_x, rows, grid, graph_steps)
     b.step(2 * graph_steps)  # records the graphs
     torch.cuda.synchronize(device)
@@ -295,12 +302,15 @@ def main():
     ap.add_argument("--adjoint-n", type=int, default=8192, help="shale lattice side")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-ckpt", type=int, default=500)
-    ap.add_argument("--adjoint-hist", type=int, default=50)
+    ap.add_argument("--adjoint-hist", default="auto",
+                    help="history steps recorded at a time, or 'auto' (longest that fits)")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient leg")
     ap.add_argument("--ensemble-samples", type=int, default=192)
     ap.add_argument("--ensemble-steps", type=int, default=400)
     ap.add_argument("--ensemble-storage", default="f16")
     ap.add_argument("--ensemble-graph", type=int, default=20, help="steps per graph replay")
+    ap.add_argument("--ensemble-launch", default=None, metavar="TX,ROWS,GRID",
+                    help="fixed batch launch shape instead of the tuner's choice")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the ensemble leg")
     ap.add_argument("--no-kn-sweep", action="store_true",
                     help="skip the Klinkenberg channel sweep")
@@ -370,8 +380,10 @@ def main():
             f"(t_fwd + t_grad)/t_fwd = {adj['total_over_fwd']:.2f}")
     ens = None
     if not args.no_ensemble:
+        fixed = (tuple(int(v) for v in args.ensemble_launch.split(","))
+                 if args.ensemble_launch else None)
         ens = time_ensemble(args.ensemble_samples, args.ensemble_steps, args.ensemble_storage,
-                            args.ensemble_graph, dev)
+                            args.ensemble_graph, dev, fixed)
         log(f"ensemble: {ens['mlups']:.0f} MLUPS ({ens['storage']}, launch {ens['launch']}), "
             f"{ens['batched_speedup']:.2f}x over one launch per sample")
     kn = None

@@ -150,11 +150,14 @@ lbk_status lbk_load_state(lbk_lattice *lat, const void *src);
  *   - lbk_adjoint_forward runs the n steps (advancing the lattice exactly
  *     as lbk_step would) and stores the state every ckpt_every steps;
  *   - lbk_adjoint_backward recomputes each checkpoint segment (keeping
- *     inner checkpoints every hist_len steps when hist_len < ckpt_every),
- *     records the per-step linearisation point (rho, j: 12 B per node and
- *     step, hist_len steps at a time) and runs the reverse steps.
- * Cost: backward ~ 2 forward sweeps (one-level, hist_len == ckpt_every)
- * or ~ 3 (two-level) plus one reverse sweep per step.
+ *     inner checkpoints every hist_len steps when hist_len < ckpt_every;
+ *     the forward pass already keeps those of the last segment), records
+ *     the per-step linearisation point (rho, j: 12 B per node and step,
+ *     hist_len steps at a time) and runs the reverse steps.
+ * Cost of the backward pass per step: one recording sweep and one reverse
+ * sweep, plus (two-level) about (1 - hist_len/ckpt_every) of a plain sweep
+ * to rebuild inner checkpoints in every segment but the last;
+ * lbk_adjoint_plan picks the longest history that fits a memory budget.
  * The Forchheimer term is not differentiated (f_eps must be 0).
  * --------------------------------------------------------------------- */
 typedef enum lbk_objective {
@@ -168,6 +171,13 @@ typedef enum lbk_objective {
  * ckpt_every; hist_len == ckpt_every is the one-level scheme). */
 lbk_status lbk_adjoint_workspace_size(const lbk_lattice *lat, int64_t n_steps,
                                       int64_t ckpt_every, int64_t hist_len, size_t *bytes);
+
+/* The longest history length (hist_len, at most ckpt_every) whose
+ * workspace for a gradient over n_steps with checkpoints every ckpt_every
+ * steps fits in budget_bytes; *bytes (may be NULL) gets that workspace
+ * size.  LBK_ERR_OOM if none fits.  Host-only, no device work. */
+lbk_status lbk_adjoint_plan(const lbk_lattice *lat, int64_t n_steps, int64_t ckpt_every,
+                            size_t budget_bytes, int64_t *hist_len, size_t *bytes);
 
 /* Run n_steps forward from the current state, storing checkpoints in the
  * caller's device workspace (256-byte aligned, ws_bytes >=

@@ -67,6 +67,9 @@ _SIG = {
     "lbk_load_state": (ctypes.c_int, [_P, _P]),
     "lbk_adjoint_workspace_size": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64,
                                                   ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)]),
+    "lbk_adjoint_plan": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64, ctypes.c_size_t,
+                                        ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_size_t)]),
     "lbk_adjoint_forward": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64, ctypes.c_int64,
                                            ctypes.c_int64, _P, ctypes.c_size_t,
                                            ctypes.POINTER(ctypes.c_double)]),

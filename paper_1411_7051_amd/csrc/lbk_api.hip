@@ -522,6 +522,37 @@ extern "C" lbk_status lbk_adjoint_workspace_size(const lbk_lattice *lat, int64_t
     return LBK_OK;
 }
 
+extern "C" lbk_status lbk_adjoint_plan(const lbk_lattice *lat, int64_t n_steps,
+                                       int64_t ckpt_every, size_t budget_bytes,
+                                       int64_t *hist_len, size_t *bytes)
+{
+    if (!lat || !hist_len)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    if (n_steps < 1 || ckpt_every < 1)
+        return fail(LBK_ERR_INVALID_ARG, "need n_steps >= 1 and ckpt_every >= 1");
+    const int64_t c1 = std::min(ckpt_every, n_steps);
+    // longest history first: fewest recomputed sweeps per reversed step
+    int64_t prev = -1;
+    for (int64_t m = 1; m <= c1; ++m) {
+        const int64_t h = (c1 + m - 1) / m;
+        if (h == prev)
+            continue;
+        prev = h;
+        AdjPlan P;
+        lbk_status s = adj_plan(lat, n_steps, c1, h, P);
+        if (s != LBK_OK)
+            return s;
+        if (P.total <= budget_bytes) {
+            *hist_len = h;
+            if (bytes)
+                *bytes = P.total;
+            return LBK_OK;
+        }
+    }
+    return fail(LBK_ERR_OOM, "no checkpoint plan for %lld steps every %lld fits in %zu bytes",
+                (long long)n_steps, (long long)c1, budget_bytes);
+}
+
 extern "C" lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64_t n_steps,
                                           int64_t ckpt_every, int64_t hist_len, void *ws,
                                           size_t ws_bytes, double *J)
@@ -553,7 +584,14 @@ extern "C" lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64
         HIP_TRY(hipMemcpyAsync(w + P.outer + (size_t)k * P.level_bytes, lat->state(lat->cur),
                                P.level_bytes, hipMemcpyDeviceToDevice, st));
         const int64_t steps = std::min(P.c1, P.n - k * P.c1);
+        // the last segment is reversed first: keep its inner checkpoints now
+        // rather than recomputing them in the backward pass
+        const bool keep_inner = P.two_level && k == P.k1 - 1;
         for (int64_t i = 0; i < steps; ++i) {
+            if (keep_inner && i % P.c2 == 0)
+                HIP_TRY(hipMemcpyAsync(w + P.inner + (size_t)(i / P.c2) * P.level_bytes,
+                                       lat->state(lat->cur), P.level_bytes,
+                                       hipMemcpyDeviceToDevice, st));
             const int nxt = lat->cur ^ 1;
             HIP_TRY(launch_sweep(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur),
                                  lat->state(nxt), lat->L.lay, lat->med(), lat->L.mlay, lat->g,
@@ -633,7 +671,9 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
     for (int64_t k = P.k1 - 1; k >= 0; --k) {
         const int64_t a = k * P.c1, b = std::min(P.n, a + P.c1);
         int64_t nseg = 1;
-        if (P.two_level) {
+        if (P.two_level && k == P.k1 - 1) {
+            nseg = (b - a + P.c2 - 1) / P.c2; // inner checkpoints kept by the forward pass
+        } else if (P.two_level) {
             // rebuild the inner checkpoints of this outer segment
             const char *src = level(P.outer, k);
             int r = 0;

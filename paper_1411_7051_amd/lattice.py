@@ -163,11 +163,26 @@ class Lattice:
                                                      ctypes.byref(n)))
         return int(n.value)
 
+    def adjoint_plan(self, steps: int, ckpt_every: int, budget: Optional[int] = None,
+                     fraction: float = 0.9) -> int:
+        """Longest history length whose gradient workspace fits ``budget``
+        bytes (default: ``fraction`` of the device's free memory)."""
+        if budget is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            budget = int(free * fraction)
+        h = ctypes.c_int64()
+        check(_lib.load().lbk_adjoint_plan(self._handle(), int(steps), int(ckpt_every),
+                                           int(budget), ctypes.byref(h), None))
+        return int(h.value)
+
     def adjoint_forward(self, steps: int, objective: str = "k_app", ckpt_every: int = 500,
-                        hist_len: Optional[int] = None,
-                        workspace: Optional[torch.Tensor] = None):
-        """Run ``steps`` steps keeping checkpoints; returns (J, workspace)."""
+                        hist_len=None, workspace: Optional[torch.Tensor] = None):
+        """Run ``steps`` steps keeping checkpoints; returns (J, workspace).
+        ``hist_len``: steps of history recorded at a time (None: ckpt_every,
+        the one-level scheme; "auto": the longest that fits in memory)."""
         ckpt_every = max(1, min(int(ckpt_every), int(steps)))
+        if hist_len == "auto":
+            hist_len = self.adjoint_plan(steps, ckpt_every)
         hist_len = ckpt_every if hist_len is None else max(1, min(int(hist_len), ckpt_every))
         nbytes = self.adjoint_workspace_bytes(steps, ckpt_every, hist_len)
         if workspace is None or workspace.numel() < nbytes:
@@ -190,7 +205,7 @@ class Lattice:
         return (g, gk) if wrt_kn0 else g
 
     def gradient(self, steps: int, objective: str = "k_app", ckpt_every: int = 500,
-                 hist_len: Optional[int] = None, wrt_kn0: bool = False):
+                 hist_len=None, wrt_kn0: bool = False):
         """(J, dJ/d ln k) after ``steps`` steps from the current state; with
         ``wrt_kn0``, (J, dJ/d ln k, dJ/d ln kn0)."""
         J, ws = self.adjoint_forward(steps, objective, ckpt_every, hist_len)

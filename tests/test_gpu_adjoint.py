@@ -143,6 +143,26 @@ def test_checkpoint_schemes_agree(dev):
         assert float((g - ref).abs().max()) <= 1e-5 * scale
 
 
+def test_adjoint_plan_fits_budget(dev):
+    """The planner returns the longest history whose workspace fits, and the
+    gradient with that plan equals the one-level gradient."""
+    from paper_1411_7051_amd._lib import LbkError
+    case = inputs.random_medium(200, 16, seed=47, bc_x=2, rho_in=1.01, rho_out=1.0, init=1)
+    lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+    full = lat.adjoint_workspace_bytes(90, 30, 30)
+    assert lat.adjoint_plan(90, 30, budget=full) == 30
+    h = lat.adjoint_plan(90, 30, budget=full - 1)
+    assert h < 30 and lat.adjoint_workspace_bytes(90, 30, h) <= full - 1
+    with pytest.raises(LbkError) as e:
+        lat.adjoint_plan(90, 30, budget=1000)
+    assert e.value.status == -3
+    J1, g1 = lat.gradient(90, "k_app", ckpt_every=30, hist_len=h)
+    lat2 = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+    J2, g2 = lat2.gradient(90, "k_app", ckpt_every=30, hist_len=30)
+    assert J1 == J2
+    assert float((g1 - g2).abs().max()) <= 1e-5 * float(g2.abs().max())
+
+
 def test_taylor_remainder(dev):
     """J(ln k + h d) - J(ln k) - h <g, d> shrinks like h^2 (GPU, FP32)."""
     case = inputs.random_medium(96, 24, seed=44, bc_x=2, bc_y=1, rho_in=1.02, rho_out=1.0,
