@@ -189,7 +189,8 @@ def time_adjoint(n, steps, ckpt, hist, device):
     return out
 
 
-def time_ensemble(n_samples, steps, storage, graph_steps, device, launch=None):
+def time_ensemble(n_samples, steps, storage, graph_steps, device, launch=None, grad_steps=0,
+                  grad_ckpt=500):
     """Batched ensemble of uneven samples (seed 4): per-sample lattices
     stepped together by one launch per step, launch shape from the tuner,
     steps replayed from HIP graphs; also the same samples stepped one launch
@@ -230,6 +231,28 @@ def time_ensemble(n_samples, steps, storage, graph_steps, device, launch=None):
     ms_loop = ev[2].elapsed_time(ev[3]) / loop_steps
     kapp = b.apparent_permeability()
     mlups = nodes * steps / (ms * 1e-3) / 1e6
+    grad = None
+    if grad_steps > 0:
+        # batched gradient of every sample's global permeability
+        ck = min(grad_ckpt, grad_steps)
+        hist = b.adjoint_plan(grad_steps, ck)
+        ws_bytes = b.adjoint_workspace_bytes(grad_steps, ck, hist)
+        ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        torch.cuda.synchronize(device)
+        ev2[0].record(st)
+        b.step(grad_steps)
+        ev2[1].record(st)
+        ev2[2].record(st)
+        J, g = b.gradient(grad_steps, "k_app", ckpt_every=ck, hist_len=hist)
+        ev2[3].record(st)
+        torch.cuda.synchronize(device)
+        t_fwd = ev2[0].elapsed_time(ev2[1])
+        t_all = ev2[2].elapsed_time(ev2[3])
+        grad = {"steps": grad_steps, "ckpt_every": ck, "hist_len": hist,
+                "workspace_GB": ws_bytes / 1e9, "t_fwd_ms": t_fwd,
+                "t_fwd_ckpt_plus_grad_ms": t_all, "total_over_fwd": t_all / t_fwd,
+                "max_abs_grad": max(float(x.abs().max()) for x in g)}
+        del g
     out = {
         "workload": f"ensemble{n_samples}: square sides U[256,1536], log-normal k (ln-sigma 1, "
                     "corr 8-64, median 1e-3), eps U[0.1,0.6], base Kn U[0.01,2], "
@@ -247,6 +270,7 @@ def time_ensemble(n_samples, steps, storage, graph_steps, device, launch=None):
         "per_sample_launch_ms_per_step": ms_loop,
         "batched_speedup": ms_loop / (ms / steps),
         "k_app_range": [float(kapp.min()), float(kapp.max())],
+        "gradient": grad,
     }
     b.close()
     for l in lats:
@@ -312,6 +336,9 @@ def main():
     ap.add_argument("--ensemble-launch", default=None, metavar="TX,ROWS,GRID",
                     help="fixed batch launch shape instead of the tuner's choice")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the ensemble leg")
+    ap.add_argument("--ensemble-grad-steps", type=int, default=1000,
+                    help="steps of the batched gradient (0: skip)")
+    ap.add_argument("--ensemble-grad-ckpt", type=int, default=500)
     ap.add_argument("--no-kn-sweep", action="store_true",
                     help="skip the Klinkenberg channel sweep")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
@@ -383,9 +410,13 @@ def main():
         fixed = (tuple(int(v) for v in args.ensemble_launch.split(","))
                  if args.ensemble_launch else None)
         ens = time_ensemble(args.ensemble_samples, args.ensemble_steps, args.ensemble_storage,
-                            args.ensemble_graph, dev, fixed)
+                            args.ensemble_graph, dev, fixed, args.ensemble_grad_steps,
+                            args.ensemble_grad_ckpt)
         log(f"ensemble: {ens['mlups']:.0f} MLUPS ({ens['storage']}, launch {ens['launch']}), "
             f"{ens['batched_speedup']:.2f}x over one launch per sample")
+        if ens["gradient"]:
+            log(f"ensemble gradient: (t_fwd + t_grad)/t_fwd = "
+                f"{ens['gradient']['total_over_fwd']:.2f} (history {ens['gradient']['hist_len']})")
     kn = None
     if not args.no_kn_sweep:
         kn = kn_sweep(dev)

@@ -263,6 +263,25 @@ lbk_status lbk_batch_apparent_permeability(lbk_batch *b, double *k_app);
  * LBK_ERR_NONFINITE naming the first bad sample.  Synchronizes. */
 lbk_status lbk_batch_check(lbk_batch *b);
 
+/* Gradients of every sample of a batch (the calls above, for all samples at
+ * once: recomputing sweeps and reverse steps walk the batch's tile list with
+ * its tiling, one workgroup per tile).  Every sample's J and gradient are
+ * bitwise those of lbk_adjoint_forward / lbk_adjoint_backward on that
+ * lattice alone with the same n_steps, ckpt_every and hist_len.  The
+ * workspace holds a per-sample slice plus a descriptor table; J: host
+ * double[n]; dJ_dlnk, dJ_dlnkn0: host arrays of n device pointers to
+ * [ny][nx] float32 planes (dJ_dlnkn0 may be NULL).  The samples must not be
+ * stepped, loaded or rescaled between forward and backward. */
+lbk_status lbk_batch_adjoint_workspace_size(lbk_batch *b, int64_t n_steps, int64_t ckpt_every,
+                                            int64_t hist_len, size_t *bytes);
+lbk_status lbk_batch_adjoint_plan(lbk_batch *b, int64_t n_steps, int64_t ckpt_every,
+                                  size_t budget_bytes, int64_t *hist_len, size_t *bytes);
+lbk_status lbk_batch_adjoint_forward(lbk_batch *b, int objective, int64_t n_steps,
+                                     int64_t ckpt_every, int64_t hist_len, void *ws,
+                                     size_t ws_bytes, double *J);
+lbk_status lbk_batch_adjoint_backward(lbk_batch *b, void *ws, size_t ws_bytes,
+                                      float *const *dJ_dlnk, float *const *dJ_dlnkn0);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *lbk_last_error(void);
 

@@ -89,6 +89,16 @@ _SIG = {
     "lbk_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "lbk_batch_apparent_permeability": (ctypes.c_int, [_P, _P]),
     "lbk_batch_check": (ctypes.c_int, [_P]),
+    "lbk_batch_adjoint_workspace_size": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64,
+                                                        ctypes.c_int64,
+                                                        ctypes.POINTER(ctypes.c_size_t)]),
+    "lbk_batch_adjoint_plan": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int64,
+                                              ctypes.c_size_t, ctypes.POINTER(ctypes.c_int64),
+                                              ctypes.POINTER(ctypes.c_size_t)]),
+    "lbk_batch_adjoint_forward": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int64,
+                                                 ctypes.c_int64, ctypes.c_int64, _P,
+                                                 ctypes.c_size_t, _P]),
+    "lbk_batch_adjoint_backward": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, _P]),
     "lbk_last_error": (ctypes.c_char_p, []),
 }
 

@@ -119,6 +119,55 @@ class Batch:
             self._handle(), out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
+    # -- gradients
+    def adjoint_plan(self, steps: int, ckpt_every: int, budget: Optional[int] = None,
+                     fraction: float = 0.9) -> int:
+        """Longest history length whose batched gradient workspace fits
+        ``budget`` bytes (default: ``fraction`` of the free device memory)."""
+        if budget is None:
+            free, _ = torch.cuda.mem_get_info(self.device)
+            budget = int(free * fraction)
+        h = ctypes.c_int64()
+        check(_lib.load().lbk_batch_adjoint_plan(self._handle(), int(steps), int(ckpt_every),
+                                                 int(budget), ctypes.byref(h), None))
+        return int(h.value)
+
+    def adjoint_workspace_bytes(self, steps: int, ckpt_every: int, hist_len: int) -> int:
+        n = ctypes.c_size_t()
+        check(_lib.load().lbk_batch_adjoint_workspace_size(self._handle(), int(steps),
+                                                           int(ckpt_every), int(hist_len),
+                                                           ctypes.byref(n)))
+        return int(n.value)
+
+    def gradient(self, steps: int, objective: str = "k_app", ckpt_every: int = 500,
+                 hist_len=None, wrt_kn0: bool = False):
+        """Per-sample J (float64 [n]) and dJ/d ln k planes (list of [ny][nx]
+        float32 tensors) after ``steps`` steps of every sample; with
+        ``wrt_kn0`` also the dJ/d ln kn0 planes.  ``hist_len``: None (one
+        level), an int, or "auto" (longest that fits in memory)."""
+        lib = _lib.load()
+        ckpt_every = max(1, min(int(ckpt_every), int(steps)))
+        if hist_len == "auto":
+            hist_len = self.adjoint_plan(steps, ckpt_every)
+        hist_len = ckpt_every if hist_len is None else max(1, min(int(hist_len), ckpt_every))
+        ws = torch.empty(self.adjoint_workspace_bytes(steps, ckpt_every, hist_len),
+                         dtype=torch.uint8, device=self.device)
+        n = len(self)
+        J = np.empty(n, dtype=np.float64)
+        check(lib.lbk_batch_adjoint_forward(self._handle(), _lib.OBJECTIVE[objective],
+                                            int(steps), ckpt_every, hist_len, ws.data_ptr(),
+                                            ws.numel(), J.ctypes.data_as(ctypes.c_void_p)))
+        g = [torch.empty((l.ny, l.nx), dtype=torch.float32, device=self.device)
+             for l in self.lattices]
+        gp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in g])
+        gk, gkp = None, None
+        if wrt_kn0:
+            gk = [torch.empty_like(t) for t in g]
+            gkp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in gk])
+        check(lib.lbk_batch_adjoint_backward(self._handle(), ws.data_ptr(), ws.numel(), gp,
+                                             gkp))
+        return (J, g, gk) if wrt_kn0 else (J, g)
+
     def check(self) -> None:
         """NaN/Inf check of every sample (and FP16 scale re-centring)."""
         check(_lib.load().lbk_batch_check(self._handle()))

@@ -37,6 +37,7 @@
 // nontemporally.  The Forchheimer term is not differentiated (the host
 // rejects f_eps != 0).
 #include "lbk_adjoint.h"
+#include "lbk_kernels.h"
 
 namespace lbk {
 
@@ -252,17 +253,12 @@ __device__ __forceinline__ Rsrc rsrc_row(const void *base, uint64_t row_bytes, i
 // Objective: J = sum_x a1(x) rho u_x + a2 u_x with a1(x) = a1 (all nodes,
 // or only column nx-1 when outlet != 0) and a2 uniform.
 template <int BCX, int BCY, bool KN>
-__global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float *mu_out,
-                                                       const float *hist, const char *med,
-                                                       MLayout mlay, float *grad, float *grad2,
-                                                       Geom g, Physics ph, int terminal,
-                                                       float a1, float a2, int outlet, int bpr)
+__device__ __forceinline__ void adjoint_node(const float *mu_in, float *mu_out, const float *hist,
+                                             const char *med, const MLayout &mlay, float *grad,
+                                             float *grad2, const Geom &g, const Physics &ph,
+                                             int terminal, float a1, float a2, int outlet, int y,
+                                             uint32_t x)
 {
-    const int L = xcd_remap_a(blockIdx.x, gridDim.x);
-    const int y = L / bpr;
-    const uint32_t x = (uint32_t)(L - y * bpr) * 256 + threadIdx.x;
-    if (x >= (uint32_t)g.nx)
-        return;
     const uint32_t nx = (uint32_t)g.nx;
     const uint64_t lrow = 9ull * g.pitch * 4, hrow = 3ull * g.pitch * 4;
     const uint32_t slot = (uint32_t)g.pitch * 4; // bytes per FP32 slot
@@ -395,6 +391,22 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float 
     }
 }
 
+template <int BCX, int BCY, bool KN>
+__global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float *mu_out,
+                                                       const float *hist, const char *med,
+                                                       MLayout mlay, float *grad, float *grad2,
+                                                       Geom g, Physics ph, int terminal,
+                                                       float a1, float a2, int outlet, int bpr)
+{
+    const int L = xcd_remap_a(blockIdx.x, gridDim.x);
+    const int y = L / bpr;
+    const uint32_t x = (uint32_t)(L - y * bpr) * 256 + threadIdx.x;
+    if (x >= (uint32_t)g.nx)
+        return;
+    adjoint_node<BCX, BCY, KN>(mu_in, mu_out, hist, med, mlay, grad, grad2, g, ph, terminal, a1,
+                               a2, outlet, y, x);
+}
+
 // total += seg; seg = 0 (end of a recomputed segment)
 __global__ __launch_bounds__(256) void grad_fold_kernel(float *seg, double *total, Geom g,
                                                          int bpr)
@@ -468,6 +480,126 @@ hipError_t launch_grad_out(const double *grad, float *out, const Geom &g, hipStr
 {
     const int bpr = (g.nx + 255) / 256;
     hipLaunchKernelGGL(grad_out_kernel, dim3(bpr * g.ny), dim3(256), 0, st, grad, out, g, bpr);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ batched gradients
+//
+// The same reverse step, fold and output over a batch's tile list (tiles of
+// blockDim.x by rows, one workgroup per tile); each sample's regions come
+// from its descriptor, copied to registers before the first store.
+
+__device__ __forceinline__ bool adj_tile(const AdjSampleDesc *__restrict__ samples,
+                                         const int *__restrict__ tile_sample, int rows,
+                                         AdjSampleDesc &sd, uint32_t &x, int &y0, int &y1)
+{
+    const int t = xcd_remap_a(blockIdx.x, gridDim.x);
+    sd = samples[tile_sample[t]];
+    const int rel = t - sd.tile0;
+    const int ty = rel / sd.tpr;
+    x = (uint32_t)(rel - ty * sd.tpr) * blockDim.x + threadIdx.x;
+    y0 = ty * rows;
+    y1 = min(y0 + rows, sd.g.ny);
+    return x < (uint32_t)sd.g.nx;
+}
+
+// lam_in < 0: the terminal read-out (writes lam[0]); else lam[lam_in] ->
+// lam[lam_in ^ 1].  hist_slot: the history of the step being reversed.
+template <int BCX, int BCY, bool KN>
+__global__ __launch_bounds__(256) void batch_adjoint_kernel(
+    const AdjSampleDesc *__restrict__ samples, const int *__restrict__ tile_sample, int rows,
+    int lam_in, int hist_slot)
+{
+    AdjSampleDesc sd;
+    uint32_t x;
+    int y0, y1;
+    if (!adj_tile(samples, tile_sample, rows, sd, x, y0, y1))
+        return;
+    const bool terminal = lam_in < 0;
+    const float *mu_in = terminal ? nullptr : (lam_in ? sd.lam[1] : sd.lam[0]);
+    float *mu_out = terminal ? sd.lam[0] : (lam_in ? sd.lam[0] : sd.lam[1]);
+    const float *hist = reinterpret_cast<const float *>(reinterpret_cast<const char *>(sd.hist) +
+                                                        (uint64_t)hist_slot * sd.hist_bytes);
+    for (int y = y0; y < y1; ++y)
+        adjoint_node<BCX, BCY, KN>(mu_in, mu_out, hist, sd.med, sd.mlay, sd.seg, sd.seg2, sd.g,
+                                   sd.ph, terminal ? 1 : 0, sd.a1, sd.a2, sd.outlet, y, x);
+}
+
+// op 0: clear the segment and total planes; 1: fold segment into total;
+// 2: write the totals to the output planes.  kn: the ln kn0 plane too.
+__global__ __launch_bounds__(256) void batch_grad_kernel(const AdjSampleDesc *__restrict__ samples,
+                                                         const int *__restrict__ tile_sample,
+                                                         int rows, int op, int kn)
+{
+    AdjSampleDesc sd;
+    uint32_t x;
+    int y0, y1;
+    if (!adj_tile(samples, tile_sample, rows, sd, x, y0, y1))
+        return;
+    for (int y = y0; y < y1; ++y) {
+        const int64_t c = (int64_t)y * sd.g.pitch + x, o = (int64_t)y * sd.g.nx + x;
+        for (int p = 0; p < (kn ? 2 : 1); ++p) {
+            float *seg = p ? sd.seg2 : sd.seg;
+            double *tot = p ? sd.grad2 : sd.grad;
+            if (op == 0) {
+                seg[c] = 0.0f;
+                tot[c] = 0.0;
+            } else if (op == 1) {
+                tot[c] += (double)seg[c];
+                seg[c] = 0.0f;
+            } else {
+                (p ? sd.out2 : sd.out)[o] = (float)tot[c];
+            }
+        }
+    }
+}
+
+template <int BCX, int BCY>
+static hipError_t batch_adj_t(const AdjSampleDesc *samples, const int *tile_sample, int ntiles,
+                              int tile_x, int rows, int lam_in, int hist_slot, int kn,
+                              hipStream_t st)
+{
+    if (kn)
+        hipLaunchKernelGGL((batch_adjoint_kernel<BCX, BCY, true>), dim3(ntiles), dim3(tile_x), 0,
+                           st, samples, tile_sample, rows, lam_in, hist_slot);
+    else
+        hipLaunchKernelGGL((batch_adjoint_kernel<BCX, BCY, false>), dim3(ntiles), dim3(tile_x),
+                           0, st, samples, tile_sample, rows, lam_in, hist_slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_adjoint(int bcx, int bcy, const AdjSampleDesc *samples,
+                                const int *tile_sample, int ntiles, int tile_x, int rows,
+                                int lam_in, int hist_slot, int kn, hipStream_t st)
+{
+    if (tile_x < 64 || tile_x > 256 || (tile_x & 63) || rows < 1 || ntiles < 0)
+        return hipErrorInvalidValue;
+    if (ntiles == 0)
+        return hipSuccess;
+#define LBK_BADJ(X, Y)                                                                       \
+    batch_adj_t<X, Y>(samples, tile_sample, ntiles, tile_x, rows, lam_in, hist_slot, kn, st)
+    switch (bcx * 2 + bcy) {
+    case 0: return LBK_BADJ(BC_PERIODIC, BC_PERIODIC);
+    case 1: return LBK_BADJ(BC_PERIODIC, BC_WALL);
+    case 2: return LBK_BADJ(BC_WALL, BC_PERIODIC);
+    case 3: return LBK_BADJ(BC_WALL, BC_WALL);
+    case 4: return LBK_BADJ(BC_PRESSURE, BC_PERIODIC);
+    case 5: return LBK_BADJ(BC_PRESSURE, BC_WALL);
+    default: return hipErrorInvalidValue;
+    }
+#undef LBK_BADJ
+}
+
+hipError_t launch_batch_grad(const AdjSampleDesc *samples, const int *tile_sample, int ntiles,
+                             int tile_x, int rows, int op, int kn, hipStream_t st)
+{
+    if (tile_x < 64 || tile_x > 256 || (tile_x & 63) || rows < 1 || ntiles < 0 || op < 0 ||
+        op > 2)
+        return hipErrorInvalidValue;
+    if (ntiles == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(batch_grad_kernel, dim3(ntiles), dim3(tile_x), 0, st, samples,
+                       tile_sample, rows, op, kn);
     return hipGetLastError();
 }
 

@@ -470,8 +470,8 @@ const char *lbk_last_error(void) { return g_err.c_str(); }
 
 // ------------------------------------------------------------ gradients
 
-static lbk_status adj_plan(const lbk_lattice *lat, int64_t n, int64_t c1, int64_t c2,
-                           AdjPlan &P)
+lbk_status lbk::adj_plan(const lbk_lattice *lat, int64_t n, int64_t c1, int64_t c2,
+                         AdjPlan &P)
 {
     if (n < 1 || c1 < 1 || c2 < 1 || c2 > c1)
         return fail(LBK_ERR_INVALID_ARG,
@@ -505,6 +505,41 @@ static lbk_status adj_plan(const lbk_lattice *lat, int64_t n, int64_t c1, int64_
     P.grad2 = take((size_t)rows * lat->L.pitch * 8);
     P.seg2 = take((size_t)rows * lat->L.pitch * 4);
     P.total = o;
+    return LBK_OK;
+}
+
+double lbk::objective_weights(const lbk_lattice *lat, int objective, const double *sums,
+                              double &a1, double &a2, int &outlet)
+{
+    const lbk_desc &d = lat->d;
+    const double nodes = (double)d.nx * d.ny, nu = (d.tau - 0.5) / 3.0;
+    if (objective == LBK_OBJ_OUTLET_FLUX) {
+        a1 = 1.0;
+        a2 = 0.0;
+        outlet = 1;
+        return sums[MAC_QOUT];
+    }
+    outlet = 0;
+    if (d.bc_x == LBK_BC_PRESSURE) {
+        a1 = lat->eps_b * nu * (d.nx - 1) / ((1.0 / 3.0) * (d.rho_in - d.rho_out) * nodes);
+        a2 = 0.0;
+        return a1 * sums[MAC_FLUX];
+    }
+    a1 = 0.0;
+    a2 = nu / (d.gx * nodes);
+    return a2 * sums[MAC_UX];
+}
+
+lbk_status lbk::check_objective(const lbk_lattice *lat, int objective)
+{
+    const lbk_desc &d = lat->d;
+    if (d.f_eps != 0.0)
+        return fail(LBK_ERR_UNSUPPORTED, "gradients need f_eps = 0 (Eq. 8)");
+    if (objective != LBK_OBJ_PERMEABILITY && objective != LBK_OBJ_OUTLET_FLUX)
+        return fail(LBK_ERR_INVALID_ARG, "unknown objective %d", objective);
+    if (objective == LBK_OBJ_PERMEABILITY && d.bc_x != LBK_BC_PRESSURE && d.gx == 0.0)
+        return fail(LBK_ERR_INVALID_ARG, "the global permeability needs gx != 0 or a pressure "
+                                         "drive");
     return LBK_OK;
 }
 
@@ -560,13 +595,9 @@ extern "C" lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64
     if (!lat || !ws || !J)
         return fail(LBK_ERR_INVALID_ARG, "NULL argument");
     const lbk_desc &d = lat->d;
-    if (d.f_eps != 0.0)
-        return fail(LBK_ERR_UNSUPPORTED, "gradients need f_eps = 0 (Eq. 8)");
-    if (objective != LBK_OBJ_PERMEABILITY && objective != LBK_OBJ_OUTLET_FLUX)
-        return fail(LBK_ERR_INVALID_ARG, "unknown objective %d", objective);
-    if (objective == LBK_OBJ_PERMEABILITY && d.bc_x != LBK_BC_PRESSURE && d.gx == 0.0)
-        return fail(LBK_ERR_INVALID_ARG, "the global permeability needs gx != 0 or a pressure "
-                                         "drive");
+    lbk_status s0 = check_objective(lat, objective);
+    if (s0 != LBK_OK)
+        return s0;
     if ((uintptr_t)ws & 255u)
         return fail(LBK_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
     AdjPlan P;
@@ -602,24 +633,8 @@ extern "C" lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64
     }
     if ((s = macro_sums(lat, false)) != LBK_OK)
         return s;
-    const double nodes = (double)d.nx * d.ny, nu = (d.tau - 0.5) / 3.0;
     P.objective = objective;
-    if (objective == LBK_OBJ_OUTLET_FLUX) {
-        *J = lat->host[MAC_QOUT];
-        P.a1 = 1.0;
-        P.a2 = 0.0;
-        P.outlet = 1;
-    } else if (d.bc_x == LBK_BC_PRESSURE) {
-        P.a1 = lat->eps_b * nu * (d.nx - 1) / ((1.0 / 3.0) * (d.rho_in - d.rho_out) * nodes);
-        P.a2 = 0.0;
-        P.outlet = 0;
-        *J = P.a1 * lat->host[MAC_FLUX];
-    } else {
-        P.a1 = 0.0;
-        P.a2 = nu / (d.gx * nodes);
-        P.outlet = 0;
-        *J = P.a2 * lat->host[MAC_UX];
-    }
+    *J = objective_weights(lat, objective, lat->host, P.a1, P.a2, P.outlet);
     P.ws = ws;
     P.valid = true;
     lat->adj = P;

@@ -2,6 +2,7 @@
 // tile list over every sample, the per-sample descriptor tables, graph
 // recording of step runs and the launch-configuration tuner.  The kernels
 // are the batched forms in lbk_kernels.hip.
+#include "lbk_adjoint.h"
 #include "lbk_host.h"
 
 #include <math.h>
@@ -100,6 +101,46 @@ BatchLayout batch_layout(lbk_lattice *const *lats, int n)
     return B;
 }
 
+// A batched gradient: the per-sample plans (same n, c1, c2 for every
+// sample), each sample's slice of the workspace, and the descriptor table at
+// the workspace's start.
+struct BatchAdj {
+    bool valid = false;
+    int objective = 0;
+    int64_t n = 0, c1 = 0, c2 = 0, k1 = 0;
+    bool two_level = false;
+    std::vector<AdjPlan> plans;
+    std::vector<size_t> base;
+    std::vector<int64_t> t0;
+    std::vector<double> a1, a2;
+    std::vector<int> outlet;
+    size_t table = 0, total = 0;
+    const void *ws = nullptr;
+};
+
+lbk_status batch_adj_layout(lbk_lattice *const *lats, int n, int64_t steps, int64_t c1,
+                            int64_t c2, BatchAdj &A)
+{
+    A.plans.assign(n, AdjPlan{});
+    A.base.assign(n, 0);
+    size_t o = align_up((size_t)n * sizeof(AdjSampleDesc), 256);
+    A.table = 0;
+    for (int i = 0; i < n; ++i) {
+        lbk_status s = adj_plan(lats[i], steps, c1, c2, A.plans[i]);
+        if (s != LBK_OK)
+            return s;
+        A.base[i] = o;
+        o = align_up(o + A.plans[i].total, 256);
+    }
+    A.total = o;
+    A.n = steps;
+    A.c1 = A.plans[0].c1;
+    A.c2 = A.plans[0].c2;
+    A.k1 = A.plans[0].k1;
+    A.two_level = A.plans[0].two_level;
+    return LBK_OK;
+}
+
 } // namespace
 
 struct lbk_batch {
@@ -120,6 +161,7 @@ struct lbk_batch {
     int grid, graph_steps;
     hipGraphExec_t exec[2]; // graphs starting at parity 0 / 1
     bool have_exec[2];
+    BatchAdj adj;           // the last batched gradient's forward pass
 
     SampleDesc *desc_sweep() const { return reinterpret_cast<SampleDesc *>(ws + B.desc_sweep); }
     SampleDesc *desc_read() const { return reinterpret_cast<SampleDesc *>(ws + B.desc_read); }
@@ -499,6 +541,266 @@ lbk_status lbk_batch_check(lbk_batch *b)
             return s;
     }
     return sync_tables(b, false);
+}
+
+} // extern "C"
+
+// ------------------------------------------------------------ gradients
+
+namespace {
+
+// Copy every sample's level `from` (ADJ_CUR: the lattice's current level)
+// to level `to` of its adjoint workspace slice.
+lbk_status copy_levels(lbk_batch *b, char *w, LevelSel from, LevelSel to)
+{
+    const BatchAdj &A = b->adj;
+    for (int i = 0; i < b->n; ++i) {
+        lbk_lattice *l = b->lats[i];
+        const AdjPlan &P = A.plans[i];
+        char *base = w + A.base[i];
+        auto at = [&](LevelSel s) -> char * {
+            if (s.region == ADJ_CUR)
+                return l->state(l->cur);
+            const size_t off = s.region == ADJ_OUTER ? P.outer
+                               : s.region == ADJ_INNER ? P.inner : P.rec;
+            return base + off + (size_t)s.index * P.level_bytes;
+        };
+        HIP_TRY(hipMemcpyAsync(at(to), at(from), P.level_bytes, hipMemcpyDeviceToDevice,
+                               b->stream));
+    }
+    return LBK_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+lbk_status lbk_batch_adjoint_workspace_size(lbk_batch *b, int64_t n_steps, int64_t ckpt_every,
+                                            int64_t hist_len, size_t *bytes)
+{
+    if (!b || !bytes)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    BatchAdj A;
+    lbk_status s = batch_adj_layout(b->lats.data(), b->n, n_steps, ckpt_every, hist_len, A);
+    if (s != LBK_OK)
+        return s;
+    *bytes = A.total;
+    return LBK_OK;
+}
+
+lbk_status lbk_batch_adjoint_plan(lbk_batch *b, int64_t n_steps, int64_t ckpt_every,
+                                  size_t budget_bytes, int64_t *hist_len, size_t *bytes)
+{
+    if (!b || !hist_len)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    if (n_steps < 1 || ckpt_every < 1)
+        return fail(LBK_ERR_INVALID_ARG, "need n_steps >= 1 and ckpt_every >= 1");
+    const int64_t c1 = ckpt_every < n_steps ? ckpt_every : n_steps;
+    int64_t prev = -1;
+    for (int64_t m = 1; m <= c1; ++m) {
+        const int64_t h = (c1 + m - 1) / m;
+        if (h == prev)
+            continue;
+        prev = h;
+        BatchAdj A;
+        lbk_status s = batch_adj_layout(b->lats.data(), b->n, n_steps, c1, h, A);
+        if (s != LBK_OK)
+            return s;
+        if (A.total <= budget_bytes) {
+            *hist_len = h;
+            if (bytes)
+                *bytes = A.total;
+            return LBK_OK;
+        }
+    }
+    return fail(LBK_ERR_OOM, "no batched checkpoint plan fits in %zu bytes", budget_bytes);
+}
+
+lbk_status lbk_batch_adjoint_forward(lbk_batch *b, int objective, int64_t n_steps,
+                                     int64_t ckpt_every, int64_t hist_len, void *ws,
+                                     size_t ws_bytes, double *J)
+{
+    if (!b || !ws || !J)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    if ((uintptr_t)ws & 255u)
+        return fail(LBK_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    for (int i = 0; i < b->n; ++i) {
+        lbk_status s = check_objective(b->lats[i], objective);
+        if (s != LBK_OK)
+            return fail(s, "sample %d: %s", i, lbk_last_error());
+    }
+    BatchAdj &A = b->adj;
+    A.valid = false;
+    lbk_status s = batch_adj_layout(b->lats.data(), b->n, n_steps, ckpt_every, hist_len, A);
+    if (s != LBK_OK)
+        return s;
+    if (ws_bytes < A.total)
+        return fail(LBK_ERR_OOM, "batched adjoint workspace of %zu bytes < %zu needed", ws_bytes,
+                    A.total);
+    if ((s = sync_tables(b, false)) != LBK_OK)
+        return s;
+    char *w = static_cast<char *>(ws);
+    A.t0.assign(b->n, 0);
+    for (int i = 0; i < b->n; ++i)
+        A.t0[i] = b->lats[i]->t;
+    for (int64_t k = 0; k < A.k1; ++k) {
+        if ((s = copy_levels(b, w, LevelSel{ADJ_CUR, 0}, LevelSel{ADJ_OUTER, (int)k})) != LBK_OK)
+            return s;
+        const int64_t steps = std::min(A.c1, A.n - k * A.c1);
+        if (A.two_level && k == A.k1 - 1) {
+            // the last segment is reversed first: keep its inner checkpoints
+            for (int64_t i = 0; i < steps; i += A.c2) {
+                if ((s = copy_levels(b, w, LevelSel{ADJ_CUR, 0},
+                                     LevelSel{ADJ_INNER, (int)(i / A.c2)})) != LBK_OK ||
+                    (s = lbk_batch_step(b, std::min(A.c2, steps - i))) != LBK_OK)
+                    return s;
+            }
+        } else if ((s = lbk_batch_step(b, steps)) != LBK_OK) {
+            return s;
+        }
+    }
+    // J of every sample from one batched read-out
+    const lbk_desc &d = b->d0();
+    const int nt = (int)b->B.read_tiles;
+    HIP_TRY(launch_batch_macro(d.storage, d.bc_x, d.bc_y, b->desc_read(), b->map_read(), nt,
+                               b->parity, b->partials(), b->stream));
+    HIP_TRY(launch_batch_finish(b->desc_read(), b->n, b->partials(), MAC_SLOTS, nt, b->results(),
+                                b->stream));
+    HIP_TRY(hipMemcpyAsync(b->host_res, b->results(), (size_t)b->n * MAC_SLOTS * sizeof(double),
+                           hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    A.a1.assign(b->n, 0.0);
+    A.a2.assign(b->n, 0.0);
+    A.outlet.assign(b->n, 0);
+    for (int i = 0; i < b->n; ++i)
+        J[i] = objective_weights(b->lats[i], objective, b->host_res + (size_t)i * MAC_SLOTS,
+                                 A.a1[i], A.a2[i], A.outlet[i]);
+    A.objective = objective;
+    A.ws = ws;
+    A.valid = true;
+    return LBK_OK;
+}
+
+lbk_status lbk_batch_adjoint_backward(lbk_batch *b, void *ws, size_t ws_bytes,
+                                      float *const *dJ_dlnk, float *const *dJ_dlnkn0)
+{
+    if (!b || !ws || !dJ_dlnk)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    BatchAdj &A = b->adj;
+    if (!A.valid || A.ws != ws || ws_bytes < A.total)
+        return fail(LBK_ERR_INVALID_ARG,
+                    "no matching lbk_batch_adjoint_forward for this workspace");
+    const bool kn = dJ_dlnkn0 != nullptr;
+    for (int i = 0; i < b->n; ++i) {
+        if (b->lats[i]->t != A.t0[i] + A.n)
+            return fail(LBK_ERR_INVALID_ARG, "sample %d moved since the forward pass", i);
+        if (!dJ_dlnk[i] || (kn && !dJ_dlnkn0[i]))
+            return fail(LBK_ERR_INVALID_ARG, "output plane of sample %d is NULL", i);
+    }
+    char *w = static_cast<char *>(ws);
+    hipStream_t st = b->stream;
+    // descriptor table of this pass (the sweep's tiling, one workgroup per tile)
+    std::vector<AdjSampleDesc> h(b->n);
+    for (int i = 0; i < b->n; ++i) {
+        lbk_lattice *l = b->lats[i];
+        const AdjPlan &P = A.plans[i];
+        char *base = w + A.base[i];
+        AdjSampleDesc &sd = h[i];
+        sd.region[ADJ_CUR] = l->state(l->cur);
+        sd.region[ADJ_OUTER] = base + P.outer;
+        sd.region[ADJ_INNER] = base + P.inner;
+        sd.region[ADJ_REC] = base + P.rec;
+        sd.level_bytes = P.level_bytes;
+        sd.hist = reinterpret_cast<float *>(base + P.hist);
+        sd.hist_bytes = P.hist_bytes;
+        sd.lam[0] = reinterpret_cast<float *>(base + P.lam);
+        sd.lam[1] = reinterpret_cast<float *>(base + P.lam + P.lam_bytes);
+        sd.seg = reinterpret_cast<float *>(base + P.seg);
+        sd.seg2 = reinterpret_cast<float *>(base + P.seg2);
+        sd.grad = reinterpret_cast<double *>(base + P.grad);
+        sd.grad2 = reinterpret_cast<double *>(base + P.grad2);
+        sd.out = dJ_dlnk[i];
+        sd.out2 = kn ? dJ_dlnkn0[i] : nullptr;
+        sd.med = l->med();
+        sd.lay = l->L.lay;
+        sd.mlay = l->L.mlay;
+        sd.g = l->g;
+        sd.ph = l->ph;
+        sd.s = l->s();
+        sd.inv_s = l->inv_s();
+        sd.a1 = (float)A.a1[i];
+        sd.a2 = (float)A.a2[i];
+        sd.outlet = A.outlet[i];
+        sd.tile0 = (int)b->tile0_sweep[i];
+        sd.tpr = tiles_per_row(l->d.nx, b->shape.tile_x);
+    }
+    AdjSampleDesc *table = reinterpret_cast<AdjSampleDesc *>(w + A.table);
+    HIP_TRY(hipMemcpyAsync(table, h.data(), h.size() * sizeof(AdjSampleDesc),
+                           hipMemcpyHostToDevice, st));
+    const lbk_desc &d = b->d0();
+    const int *map = b->map_sweep();
+    const int nt = (int)b->sweep_tiles, tx = b->shape.tile_x, rows = b->shape.rows, knf = kn;
+    auto rec = [&](LevelSel src, LevelSel dst, int slot) {
+        return launch_batch_rec_sweep(d.storage, d.bc_x, d.bc_y, table, map, nt, tx, rows, src,
+                                      dst, slot, st);
+    };
+    auto reverse = [&](int lam_in, int slot) {
+        return launch_batch_adjoint(d.bc_x, d.bc_y, table, map, nt, tx, rows, lam_in, slot, knf,
+                                    st);
+    };
+    HIP_TRY(launch_batch_grad(table, map, nt, tx, rows, 0, knf, st));
+    // read-out of J at step n: linearisation point of the pull of S_n
+    HIP_TRY(rec(LevelSel{ADJ_CUR, 0}, LevelSel{ADJ_REC, 0}, 0));
+    HIP_TRY(reverse(-1, 0));
+    int cur = 0;
+    for (int64_t k = A.k1 - 1; k >= 0; --k) {
+        const int64_t a = k * A.c1, e = std::min(A.n, a + A.c1);
+        int64_t nseg = 1;
+        if (A.two_level && k == A.k1 - 1) {
+            nseg = (e - a + A.c2 - 1) / A.c2; // kept by the forward pass
+        } else if (A.two_level) {
+            // rebuild the inner checkpoints of this outer segment
+            LevelSel src{ADJ_OUTER, (int)k};
+            int r = 0;
+            nseg = 0;
+            for (int64_t t = a; t < e; t += A.c2, ++nseg) {
+                lbk_status s = copy_levels(b, w, src, LevelSel{ADJ_INNER, (int)nseg});
+                if (s != LBK_OK)
+                    return s;
+                const int64_t steps = std::min(A.c2, e - t);
+                if (t + steps >= e)
+                    break;
+                for (int64_t i = 0; i < steps; ++i) {
+                    HIP_TRY(rec(i == 0 ? LevelSel{ADJ_INNER, (int)nseg} : LevelSel{ADJ_REC, r},
+                                LevelSel{ADJ_REC, r ^ 1}, -1));
+                    r ^= 1;
+                }
+                src = LevelSel{ADJ_REC, r};
+            }
+            ++nseg;
+        }
+        for (int64_t j = nseg - 1; j >= 0; --j) {
+            const int64_t a2s = A.two_level ? a + j * A.c2 : a;
+            const int64_t b2s = A.two_level ? std::min(e, a2s + A.c2) : e;
+            const LevelSel src = A.two_level ? LevelSel{ADJ_INNER, (int)j}
+                                             : LevelSel{ADJ_OUTER, (int)k};
+            int r = 0;
+            for (int64_t t = a2s; t < b2s; ++t) {
+                HIP_TRY(rec(t == a2s ? src : LevelSel{ADJ_REC, r}, LevelSel{ADJ_REC, r ^ 1},
+                            (int)(t - a2s + 1)));
+                r ^= 1;
+            }
+            for (int64_t t = b2s; t > a2s; --t) {
+                HIP_TRY(reverse(cur, (int)(t - a2s)));
+                cur ^= 1;
+            }
+            HIP_TRY(launch_batch_grad(table, map, nt, tx, rows, 1, knf, st));
+        }
+    }
+    HIP_TRY(launch_batch_grad(table, map, nt, tx, rows, 2, knf, st));
+    // the host copy of the table must outlive the upload
+    HIP_TRY(hipStreamSynchronize(st));
+    return LBK_OK;
 }
 
 } // extern "C"

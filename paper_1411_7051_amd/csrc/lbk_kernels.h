@@ -98,6 +98,43 @@ hipError_t launch_populations(int storage, const char *src, const Layout &lay, c
 hipError_t launch_rescale(int storage, char *state, const Layout &lay, const Geom &g, int k,
                           hipStream_t st);
 
+// One sample of a batched gradient: its levels (the lattice's current level
+// and, in its adjoint workspace, the outer / inner checkpoint and recompute
+// level arrays, level_bytes apart), history slots, adjoint states, FP32
+// segment and FP64 total gradient planes (the second plane is ln kn0), the
+// read-out weights of J, the output planes, and its tiles in the batch's
+// tile list.
+enum { ADJ_CUR = 0, ADJ_OUTER = 1, ADJ_INNER = 2, ADJ_REC = 3 };
+struct AdjSampleDesc {
+    char *region[4];
+    uint64_t level_bytes;
+    float *hist;
+    uint64_t hist_bytes;
+    float *lam[2];
+    float *seg, *seg2;
+    double *grad, *grad2;
+    float *out, *out2;
+    const char *med;
+    Layout lay;
+    MLayout mlay;
+    Geom g;
+    Physics ph;
+    float s, inv_s, a1, a2;
+    int outlet, tile0, tpr;
+};
+
+// A level of a batched gradient's sample: region ADJ_* and index.
+struct LevelSel {
+    int region, index;
+};
+
+// One recomputing step of every sample of a batched gradient: level src ->
+// level dst, recording the history into slot hist_slot (< 0: none).  Tiles
+// of tile_x by rows, one workgroup per tile.
+hipError_t launch_batch_rec_sweep(int storage, int bcx, int bcy, const AdjSampleDesc *samples,
+                                  const int *tile_sample, int ntiles, int tile_x, int rows,
+                                  LevelSel src, LevelSel dst, int hist_slot, hipStream_t st);
+
 // One step of every sample of a batch, parity -> parity ^ 1, over tiles of
 // tile_x (a multiple of 64 up to kBatchMaxTile: the workgroup size) by rows
 // nodes; the descriptors' tile0/tpr must describe that tiling.  grid > 0:

@@ -212,6 +212,37 @@ __global__ __launch_bounds__(kBatchMaxTile) void batch_sweep_kernel(
     }
 }
 
+// Recomputing sweep of a batched gradient: the same node update between two
+// levels chosen per launch, optionally recording the history.
+template <typename T, int BCX, int BCY, bool HIST>
+__global__ __launch_bounds__(kBatchMaxTile) void batch_rec_sweep_kernel(
+    const AdjSampleDesc *__restrict__ samples, const int *__restrict__ tile_sample, int ntiles,
+    int rows, LevelSel src_sel, LevelSel dst_sel, int hist_slot)
+{
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const AdjSampleDesc sd = samples[tile_sample[t]];
+    const int rel = t - sd.tile0;
+    const int ty = rel / sd.tpr;
+    const uint32_t x = (uint32_t)(rel - ty * sd.tpr) * blockDim.x + threadIdx.x;
+    if (x >= (uint32_t)sd.g.nx)
+        return;
+    // selects, not an indexed read: the descriptor stays in registers
+    auto region = [&](int r) {
+        return r == ADJ_CUR ? sd.region[0]
+                            : (r == ADJ_OUTER ? sd.region[1]
+                                              : (r == ADJ_INNER ? sd.region[2] : sd.region[3]));
+    };
+    const char *src = region(src_sel.region) + (uint64_t)src_sel.index * sd.level_bytes;
+    char *dst = region(dst_sel.region) + (uint64_t)dst_sel.index * sd.level_bytes;
+    float *hist = HIST ? reinterpret_cast<float *>(reinterpret_cast<char *>(sd.hist) +
+                                                   (uint64_t)hist_slot * sd.hist_bytes)
+                       : nullptr;
+    const int y0 = ty * rows, y1 = min(y0 + rows, sd.g.ny);
+    for (int y = y0; y < y1; ++y)
+        sweep_node<T, BCX, BCY, HIST>(src, dst, sd.lay, sd.med, sd.mlay, sd.g, sd.ph, sd.s,
+                                      sd.inv_s, hist, y, x);
+}
+
 // ----------------------------------------------------------- reductions
 
 struct SumOp {
@@ -681,6 +712,35 @@ hipError_t launch_batch_finish(const SampleDesc *samples, int nsamples, const do
     hipLaunchKernelGGL(batch_finish_kernel, dim3(nsamples), dim3(kBlock), 0, st, samples,
                        partials, slots, ntiles, out);
     return hipGetLastError();
+}
+
+template <typename T, int BCX, int BCY>
+static hipError_t batch_rec_t(const AdjSampleDesc *samples, const int *tile_sample, int ntiles,
+                              int tile_x, int rows, LevelSel src, LevelSel dst, int hist_slot,
+                              hipStream_t st)
+{
+    if (hist_slot >= 0)
+        hipLaunchKernelGGL((batch_rec_sweep_kernel<T, BCX, BCY, true>), dim3(ntiles),
+                           dim3(tile_x), 0, st, samples, tile_sample, ntiles, rows, src, dst,
+                           hist_slot);
+    else
+        hipLaunchKernelGGL((batch_rec_sweep_kernel<T, BCX, BCY, false>), dim3(ntiles),
+                           dim3(tile_x), 0, st, samples, tile_sample, ntiles, rows, src, dst,
+                           hist_slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_rec_sweep(int storage, int bcx, int bcy, const AdjSampleDesc *samples,
+                                  const int *tile_sample, int ntiles, int tile_x, int rows,
+                                  LevelSel src, LevelSel dst, int hist_slot, hipStream_t st)
+{
+    if (bcy < 0 || bcy > 1 || tile_x < 64 || tile_x > kBatchMaxTile || (tile_x & 63) ||
+        rows < 1 || ntiles < 0 || src.region < 0 || src.region > 3 || dst.region < 0 ||
+        dst.region > 3)
+        return hipErrorInvalidValue;
+    if (ntiles == 0)
+        return hipSuccess;
+    LBK_DISPATCH(batch_rec_t, samples, tile_sample, ntiles, tile_x, rows, src, dst, hist_slot, st)
 }
 
 } // namespace lbk

@@ -121,3 +121,15 @@ def test_batch_null_arguments_rejected():
     assert lib.lbk_batch_apparent_permeability(None, None) == -1
     assert lib.lbk_batch_check(None) == -1
     assert lib.lbk_batch_destroy(None) == 0
+
+
+def test_batch_gradient_null_arguments_rejected():
+    lib = _lib.load()
+    n = ctypes.c_size_t()
+    h = ctypes.c_int64()
+    assert lib.lbk_batch_adjoint_workspace_size(None, 10, 5, 5, ctypes.byref(n)) == -1
+    assert lib.lbk_batch_adjoint_plan(None, 10, 5, 1 << 30, ctypes.byref(h), None) == -1
+    J = ctypes.c_double()
+    assert lib.lbk_batch_adjoint_forward(None, 0, 10, 5, 5, None, 0, ctypes.byref(J)) == -1
+    assert lib.lbk_batch_adjoint_backward(None, None, 0, None, None) == -1
+    assert lib.lbk_adjoint_plan(None, 10, 5, 1 << 30, ctypes.byref(h), None) == -1

@@ -186,3 +186,41 @@ def test_batch_rejects_mixed(dev):
                 (256, 1, -1, 0), (256, 1, 0, 3), (256, 1, 0, 2048)]:
         with pytest.raises(LbkError):
             b.set_launch(*bad)
+
+
+@pytest.mark.parametrize("storage,bcx,bcy,obj,ck,hl", [
+    ("f32", 2, 1, "k_app", 10, 4), ("f16", 2, 0, "q_out", 12, 12), ("f32", 0, 1, "k_app", 30, 30),
+    ("bf16", 1, 1, "k_app", 9, 3)])
+def test_batch_gradient_bitwise_equals_solo(dev, storage, bcx, bcy, obj, ck, hl):
+    """Batched J and gradients (both planes) equal each lattice's own, bit
+    for bit, for one- and two-level checkpointing."""
+    cs = cases(bcx, bcy, seed=900)
+    if bcx == inputs.PRESSURE:
+        cs = [c for c in cs if c.eps.shape[1] >= 3]
+    steps = 25
+    lats = ensemble_lattices(cs, device=dev, storage=storage)
+    b = Batch(lats)
+    b.set_launch(64, 3, 0, 4)
+    b.step(5)
+    J, g, gk = b.gradient(steps, obj, ckpt_every=ck, hist_len=hl, wrt_kn0=True)
+    for i, c in enumerate(cs):
+        solo = Lattice(c.eps, c.k, c.kn0, device=dev, storage=storage, **c.params).step(5)
+        Js, gs, gks = solo.gradient(steps, obj, ckpt_every=ck, hist_len=hl, wrt_kn0=True)
+        assert J[i] == Js, i
+        assert torch.equal(g[i], gs), (i, float((g[i] - gs).abs().max()))
+        assert torch.equal(gk[i], gks), i
+        assert lats[i].time == solo.time == 5 + steps
+
+
+def test_batch_gradient_launch_shapes_agree(dev):
+    cs = cases(2, 1, seed=950)
+    out = []
+    for shape in [(256, 1), (64, 16), (192, 5)]:
+        b = Batch(ensemble_lattices(cs, device=dev))
+        b.set_launch(*shape, 0, 0)
+        J, g = b.gradient(20, "k_app", ckpt_every=7, hist_len=3)
+        out.append((J, g))
+    for J, g in out[1:]:
+        assert np.array_equal(J, out[0][0])
+        for a, c in zip(g, out[0][1]):
+            assert torch.equal(a, c)
