@@ -244,6 +244,12 @@ lbk_status lbk_batch_set_launch(lbk_batch *b, int32_t tile_x, int32_t rows, int3
 lbk_status lbk_batch_get_launch(const lbk_batch *b, int32_t *tile_x, int32_t *rows,
                                 int32_t *grid, int32_t *graph_steps);
 
+/* on != 0: every graph replay ends with the per-sample read-out reductions
+ * (the FP64 sums behind lbk_batch_apparent_permeability), so that after
+ * steps that end in a replay the permeabilities need only a copy of the
+ * sums.  Off by default. */
+lbk_status lbk_batch_set_graph_readout(lbk_batch *b, int32_t on);
+
 /* Time every candidate -- tile_x in {64, 128, 256} x rows in {1, 4, 8, 16}
  * x one workgroup per tile or persistent grids of 2, 4 and 8 workgroups
  * per compute unit -- over `reps` >= 1 steps each, and keep the fastest

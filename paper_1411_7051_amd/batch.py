@@ -70,6 +70,10 @@ class Batch:
         check(_lib.load().lbk_batch_set_launch(self._handle(), int(tile_x), int(rows), int(grid),
                                                int(graph_steps)))
 
+    def set_graph_readout(self, on: bool = True) -> None:
+        """Make every graph replay end with the per-sample read-out sums."""
+        check(_lib.load().lbk_batch_set_graph_readout(self._handle(), int(bool(on))))
+
     @property
     def launch(self):
         """(tile_x, rows, grid, graph_steps)."""

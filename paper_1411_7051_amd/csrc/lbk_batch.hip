@@ -161,6 +161,8 @@ struct lbk_batch {
     int grid, graph_steps;
     hipGraphExec_t exec[2]; // graphs starting at parity 0 / 1
     bool have_exec[2];
+    bool graph_readout;     // graphs end with the per-sample read-out sums
+    bool sums_fresh;        // results() holds the sums of the current state
     BatchAdj adj;           // the last batched gradient's forward pass
 
     SampleDesc *desc_sweep() const { return reinterpret_cast<SampleDesc *>(ws + B.desc_sweep); }
@@ -213,6 +215,7 @@ lbk_status sync_tables(lbk_batch *b, bool force)
     }
     if (!stale)
         return LBK_OK;
+    b->sums_fresh = false;
     HIP_TRY(hipStreamSynchronize(b->stream)); // staging may still feed a copy
     for (int i = 0; i < b->n; ++i) {
         lbk_lattice *l = b->lats[i];
@@ -263,13 +266,29 @@ hipError_t sweep_once(lbk_batch *b, int parity, int grid, hipStream_t st)
                               st);
 }
 
-// Record graph_steps launches starting at `parity` on the private stream.
+// Per-sample read-out sums of the state at `parity` into results().
+hipError_t readout(lbk_batch *b, int parity, hipStream_t st)
+{
+    const lbk_desc &d = b->d0();
+    const int nt = (int)b->B.read_tiles;
+    hipError_t e = launch_batch_macro(d.storage, d.bc_x, d.bc_y, b->desc_read(), b->map_read(),
+                                      nt, parity, b->partials(), st);
+    if (e == hipSuccess)
+        e = launch_batch_finish(b->desc_read(), b->n, b->partials(), MAC_SLOTS, nt,
+                                b->results(), st);
+    return e;
+}
+
+// Record graph_steps launches starting at `parity` on the private stream
+// (and, with graph_readout, the read-out of the state they end in).
 lbk_status record_graph(lbk_batch *b, int parity)
 {
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     for (int i = 0; i < b->graph_steps && e == hipSuccess; ++i)
         e = sweep_once(b, parity ^ (i & 1), b->grid, b->cap);
+    if (e == hipSuccess && b->graph_readout)
+        e = readout(b, parity, b->cap); // graph_steps is even
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -351,6 +370,8 @@ lbk_status lbk_batch_create(lbk_lattice *const *lats, int32_t n, void *workspace
     b->sweep_tiles = 0;
     b->grid = 0;
     b->graph_steps = 0;
+    b->graph_readout = false;
+    b->sums_fresh = false;
     int64_t read_tiles = 0;
     if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
         hipHostMalloc((void **)&b->host_desc, (size_t)2 * n * sizeof(SampleDesc),
@@ -392,10 +413,12 @@ lbk_status lbk_batch_step(lbk_batch *b, int64_t n)
                 return s;
             HIP_TRY(hipGraphLaunch(b->exec[b->parity], b->stream));
             left -= b->graph_steps; // even: the parity is unchanged
+            b->sums_fresh = b->graph_readout;
         } else {
             HIP_TRY(sweep_once(b, b->parity, b->grid, b->stream));
             b->parity ^= 1;
             --left;
+            b->sums_fresh = false;
         }
     }
     for (int i = 0; i < b->n; ++i) {
@@ -443,6 +466,16 @@ lbk_status lbk_batch_get_launch(const lbk_batch *b, int32_t *tile_x, int32_t *ro
         *grid = b->grid;
     if (graph_steps)
         *graph_steps = b->graph_steps;
+    return LBK_OK;
+}
+
+lbk_status lbk_batch_set_graph_readout(lbk_batch *b, int32_t on)
+{
+    if (!b)
+        return fail(LBK_ERR_INVALID_ARG, "batch is NULL");
+    if ((on != 0) != b->graph_readout)
+        drop_graphs(b);
+    b->graph_readout = on != 0;
     return LBK_OK;
 }
 
@@ -514,12 +547,8 @@ lbk_status lbk_batch_apparent_permeability(lbk_batch *b, double *k_app)
     lbk_status s = sync_tables(b, false);
     if (s != LBK_OK)
         return s;
-    const lbk_desc &d = b->d0();
-    const int nt = (int)b->B.read_tiles;
-    HIP_TRY(launch_batch_macro(d.storage, d.bc_x, d.bc_y, b->desc_read(), b->map_read(), nt,
-                               b->parity, b->partials(), b->stream));
-    HIP_TRY(launch_batch_finish(b->desc_read(), b->n, b->partials(), MAC_SLOTS, nt, b->results(),
-                                b->stream));
+    if (!b->sums_fresh) // else the last graph replay already reduced this state
+        HIP_TRY(readout(b, b->parity, b->stream));
     HIP_TRY(hipMemcpyAsync(b->host_res, b->results(), (size_t)b->n * MAC_SLOTS * sizeof(double),
                            hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
@@ -660,12 +689,8 @@ lbk_status lbk_batch_adjoint_forward(lbk_batch *b, int objective, int64_t n_step
         }
     }
     // J of every sample from one batched read-out
-    const lbk_desc &d = b->d0();
-    const int nt = (int)b->B.read_tiles;
-    HIP_TRY(launch_batch_macro(d.storage, d.bc_x, d.bc_y, b->desc_read(), b->map_read(), nt,
-                               b->parity, b->partials(), b->stream));
-    HIP_TRY(launch_batch_finish(b->desc_read(), b->n, b->partials(), MAC_SLOTS, nt, b->results(),
-                                b->stream));
+    if (!b->sums_fresh)
+        HIP_TRY(readout(b, b->parity, b->stream));
     HIP_TRY(hipMemcpyAsync(b->host_res, b->results(), (size_t)b->n * MAC_SLOTS * sizeof(double),
                            hipMemcpyDeviceToHost, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
