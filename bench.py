@@ -189,12 +189,14 @@ def time_adjoint(n, steps, ckpt, hist, device):
     return out
 
 
-def time_ensemble(n_samples, steps, storage, graph_steps, device, launch=None, grad_steps=0,
+def time_ensemble(n_samples, steps, storages, graph_steps, device, launch=None, grad_steps=0,
                   grad_ckpt=500):
     """Batched ensemble of uneven samples (seed 4): per-sample lattices
     stepped together by one launch per step, launch shape from the tuner,
-    steps replayed from HIP graphs; also the same samples stepped one launch
-    per sample per step, for comparison."""
+    steps replayed from HIP graphs, for each storage type in ``storages``
+    (the first is the headline); for the first also the same samples stepped
+    one launch per sample per step, and the batched gradient."""
+    import numpy as np
     import torch
     from paper_1411_7051_amd import inputs
     from paper_1411_7051_amd.batch import Batch, ensemble_lattices
@@ -204,79 +206,84 @@ def time_ensemble(n_samples, steps, storage, graph_steps, device, launch=None, g
     nodes = sum(c.nodes for c in cases)
     log(f"ensemble inputs: {len(cases)} samples, {nodes} nodes in "
         f"{time.perf_counter() - t:.1f} s")
-    lats = ensemble_lattices(cases, device=device, storage=storage)
-    b = Batch(lats)
-    st = lats[0].stream
-    if launch is None:
-        tune_us = b.autotune(reps=5)
-        tile_x, rows, grid, _ = b.launch
-    else:
-        tune_us = None
-        tile_x, rows, grid = launch
-    b.set_launch(tile_x, rows, grid, graph_steps)
-    b.step(2 * graph_steps)  # records the graphs
-    torch.cuda.synchronize(device)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    ev[0].record(st)
-    b.step(steps)
-    ev[1].record(st)
-    loop_steps = max(2, steps // 10)
-    ev[2].record(st)
-    for _ in range(loop_steps):
+    runs, kapps, out = {}, {}, None
+    for si, storage in enumerate(storages):
+        lats = ensemble_lattices(cases, device=device, storage=storage)
+        b = Batch(lats)
+        st = lats[0].stream
+        if launch is None:
+            tune_us = b.autotune(reps=5)
+            tile_x, rows, grid, _ = b.launch
+        else:
+            tune_us = None
+            tile_x, rows, grid = launch
+        b.set_launch(tile_x, rows, grid, graph_steps)
+        b.step(2 * graph_steps)  # records the graphs
+        torch.cuda.synchronize(device)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(st)
+        b.step(steps)
+        ev[1].record(st)
+        torch.cuda.synchronize(device)
+        ms = ev[0].elapsed_time(ev[1])
+        kapps[storage] = b.apparent_permeability()
+        mlups = nodes * steps / (ms * 1e-3) / 1e6
+        runs[storage] = {
+            "launch": {"tile_x": tile_x, "rows": rows, "grid": grid, "graph_steps": graph_steps},
+            "autotune_best_us": tune_us, "ms_per_step": ms / steps, "mlups": mlups,
+            "alg_GBps": mlups * ALG_BYTES[storage] / 1e3,
+            "alg_frac": mlups * ALG_BYTES[storage] / 1e3 / HBM_PEAK_GBS}
+        if si == 0:
+            loop_steps = max(2, steps // 10)
+            ev[2].record(st)
+            for _ in range(loop_steps):
+                for l in lats:
+                    l.step(1)
+            ev[3].record(st)
+            torch.cuda.synchronize(device)
+            ms_loop = ev[2].elapsed_time(ev[3]) / loop_steps
+            grad = None
+            if grad_steps > 0:
+                # batched gradient of every sample's global permeability
+                ck = min(grad_ckpt, grad_steps)
+                hist = b.adjoint_plan(grad_steps, ck)
+                ws_bytes = b.adjoint_workspace_bytes(grad_steps, ck, hist)
+                ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+                torch.cuda.synchronize(device)
+                ev2[0].record(st)
+                b.step(grad_steps)
+                ev2[1].record(st)
+                ev2[2].record(st)
+                J, g = b.gradient(grad_steps, "k_app", ckpt_every=ck, hist_len=hist)
+                ev2[3].record(st)
+                torch.cuda.synchronize(device)
+                t_fwd = ev2[0].elapsed_time(ev2[1])
+                t_all = ev2[2].elapsed_time(ev2[3])
+                grad = {"steps": grad_steps, "ckpt_every": ck, "hist_len": hist,
+                        "workspace_GB": ws_bytes / 1e9, "t_fwd_ms": t_fwd,
+                        "t_fwd_ckpt_plus_grad_ms": t_all, "total_over_fwd": t_all / t_fwd,
+                        "max_abs_grad": max(float(x.abs().max()) for x in g)}
+                del g
+            out = {
+                "workload": f"ensemble{n_samples}: square sides U[256,1536], log-normal k "
+                            "(ln-sigma 1, corr 8-64, median 1e-3), eps U[0.1,0.6], base Kn "
+                            "U[0.01,2], pressure-driven x, periodic y",
+                "samples": len(cases), "nodes": nodes, "storage": storage, "steps": steps,
+                **runs[storage],
+                "per_sample_launch_ms_per_step": ms_loop,
+                "batched_speedup": ms_loop / (ms / steps),
+                "k_app_range": [float(kapps[storage].min()), float(kapps[storage].max())],
+                "gradient": grad,
+            }
+        b.close()
         for l in lats:
-            l.step(1)
-    ev[3].record(st)
-    torch.cuda.synchronize(device)
-    ms = ev[0].elapsed_time(ev[1])
-    ms_loop = ev[2].elapsed_time(ev[3]) / loop_steps
-    kapp = b.apparent_permeability()
-    mlups = nodes * steps / (ms * 1e-3) / 1e6
-    grad = None
-    if grad_steps > 0:
-        # batched gradient of every sample's global permeability
-        ck = min(grad_ckpt, grad_steps)
-        hist = b.adjoint_plan(grad_steps, ck)
-        ws_bytes = b.adjoint_workspace_bytes(grad_steps, ck, hist)
-        ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        torch.cuda.synchronize(device)
-        ev2[0].record(st)
-        b.step(grad_steps)
-        ev2[1].record(st)
-        ev2[2].record(st)
-        J, g = b.gradient(grad_steps, "k_app", ckpt_every=ck, hist_len=hist)
-        ev2[3].record(st)
-        torch.cuda.synchronize(device)
-        t_fwd = ev2[0].elapsed_time(ev2[1])
-        t_all = ev2[2].elapsed_time(ev2[3])
-        grad = {"steps": grad_steps, "ckpt_every": ck, "hist_len": hist,
-                "workspace_GB": ws_bytes / 1e9, "t_fwd_ms": t_fwd,
-                "t_fwd_ckpt_plus_grad_ms": t_all, "total_over_fwd": t_all / t_fwd,
-                "max_abs_grad": max(float(x.abs().max()) for x in g)}
-        del g
-    out = {
-        "workload": f"ensemble{n_samples}: square sides U[256,1536], log-normal k (ln-sigma 1, "
-                    "corr 8-64, median 1e-3), eps U[0.1,0.6], base Kn U[0.01,2], "
-                    "pressure-driven x, periodic y",
-        "samples": len(cases),
-        "nodes": nodes,
-        "storage": storage,
-        "steps": steps,
-        "launch": {"tile_x": tile_x, "rows": rows, "grid": grid, "graph_steps": graph_steps},
-        "autotune_best_us": tune_us,
-        "ms_per_step": ms / steps,
-        "mlups": mlups,
-        "alg_GBps": mlups * ALG_BYTES[storage] / 1e3,
-        "alg_frac": mlups * ALG_BYTES[storage] / 1e3 / HBM_PEAK_GBS,
-        "per_sample_launch_ms_per_step": ms_loop,
-        "batched_speedup": ms_loop / (ms / steps),
-        "k_app_range": [float(kapp.min()), float(kapp.max())],
-        "gradient": grad,
-    }
-    b.close()
-    for l in lats:
-        l.close()
-    del b, lats
-    torch.cuda.empty_cache()
+            l.close()
+        del b, lats
+        torch.cuda.empty_cache()
+    out["storage_runs"] = runs
+    if "f32" in kapps:
+        out["k_app_max_rel_vs_f32"] = {
+            s: float(np.max(np.abs(k / kapps["f32"] - 1))) for s, k in kapps.items()}
     return out
 
 
@@ -331,7 +338,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the gradient leg")
     ap.add_argument("--ensemble-samples", type=int, default=192)
     ap.add_argument("--ensemble-steps", type=int, default=400)
-    ap.add_argument("--ensemble-storage", default="f16")
+    ap.add_argument("--ensemble-storage", default="f16,f32",
+                    help="storage types of the ensemble leg (the first is the headline)")
     ap.add_argument("--ensemble-graph", type=int, default=20, help="steps per graph replay")
     ap.add_argument("--ensemble-launch", default=None, metavar="TX,ROWS,GRID",
                     help="fixed batch launch shape instead of the tuner's choice")
@@ -409,11 +417,15 @@ def main():
     if not args.no_ensemble:
         fixed = (tuple(int(v) for v in args.ensemble_launch.split(","))
                  if args.ensemble_launch else None)
-        ens = time_ensemble(args.ensemble_samples, args.ensemble_steps, args.ensemble_storage,
+        ens = time_ensemble(args.ensemble_samples, args.ensemble_steps,
+                            args.ensemble_storage.split(","),
                             args.ensemble_graph, dev, fixed, args.ensemble_grad_steps,
                             args.ensemble_grad_ckpt)
         log(f"ensemble: {ens['mlups']:.0f} MLUPS ({ens['storage']}, launch {ens['launch']}), "
             f"{ens['batched_speedup']:.2f}x over one launch per sample")
+        for sname, r in ens["storage_runs"].items():
+            log(f"  ensemble {sname}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.3f} ms/step, "
+                f"k_app vs f32 {ens.get('k_app_max_rel_vs_f32', {}).get(sname, float('nan')):.2e}")
         if ens["gradient"]:
             log(f"ensemble gradient: (t_fwd + t_grad)/t_fwd = "
                 f"{ens['gradient']['total_over_fwd']:.2f} (history {ens['gradient']['hist_len']})")
