@@ -55,6 +55,7 @@ class _Params(ctypes.Structure):
         ("rho0", ctypes.c_double), ("rho_ref", ctypes.c_double),
         ("kn_local", ctypes.c_int), ("init", ctypes.c_int),
         ("eq15_printed", ctypes.c_int),
+        ("correlation", ctypes.c_int), ("slip_b", ctypes.c_double),
     ]
 
 
@@ -70,6 +71,8 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         lib.lbo_fc.restype = ctypes.c_double
         lib.lbo_fc.argtypes = [ctypes.c_double]
+        lib.lbo_fc_with.restype = ctypes.c_double
+        lib.lbo_fc_with.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
         lib.lbo_feq.argtypes = [ctypes.c_double] * 4 + [_D]
         lib.lbo_guo.argtypes = [ctypes.c_double] * 7 + [ctypes.c_int, _D]
         lib.lbo_node_macro.argtypes = [ctypes.POINTER(_Params), _D] + [ctypes.c_double] * 3 + [_D] * 5
@@ -97,16 +100,20 @@ def _ptr(a: np.ndarray):
 
 def _params(nx, ny, tau=0.8, gx=0.0, gy=0.0, f_eps=0.0, bc_x=PERIODIC,
             bc_y=PERIODIC, rho_in=1.0, rho_out=1.0, rho0=1.0, rho_ref=1.0,
-            kn_local=1, init=0, eq15_printed=0) -> _Params:
+            kn_local=1, init=0, eq15_printed=0, correlation=0, slip_b=-1.0) -> _Params:
     return _Params(int(nx), int(ny), float(tau), float(gx), float(gy),
                    float(f_eps), int(bc_x), int(bc_y), float(rho_in),
                    float(rho_out), float(rho0), float(rho_ref), int(kn_local),
-                   int(init), int(eq15_printed))
+                   int(init), int(eq15_printed), int(correlation), float(slip_b))
 
 
-def fc(kn: float) -> float:
-    """Eqs. 6-7 (b = -1), f_c(0) = 1."""
-    return _load().lbo_fc(float(kn))
+def fc(kn: float, correlation: int = 0, slip_b: float = -1.0) -> float:
+    """Correction factor f_c(Kn): Eqs. 6-7 with slip coefficient b
+    (correlation 0; b = -1 by default), Eqs. 4-5 (1: 1 + 4 Kn) or none (2);
+    f_c(0) = 1."""
+    if correlation == 0 and slip_b == -1.0:
+        return _load().lbo_fc(float(kn))
+    return _load().lbo_fc_with(int(correlation), float(slip_b), float(kn))
 
 
 def feq(rho, ux, uy, eps) -> np.ndarray:

@@ -74,14 +74,17 @@ static double viscosity(const lbo_params *p)
 
 /* Eqs. 6-7: f_c = (1 + alpha Kn) [1 + 4 Kn / (1 - b Kn)], b = -1,
  * alpha = 1.358 / (1 + 0.170 Kn^-0.4348). */
-double lbo_fc(double kn)
+double lbo_fc_with(int correlation, double b, double kn)
 {
-    if (!(kn > 0.0))
-        return 1.0; /* R3 */
-    const double b = -1.0; /* R4 */
-    double alpha = 1.358 / (1.0 + 0.170 * pow(kn, -0.4348));
-    return (1.0 + alpha * kn) * (1.0 + 4.0 * kn / (1.0 - b * kn));
+    if (!(kn > 0.0) || correlation == 2)
+        return 1.0; /* R3; or no slip correction */
+    if (correlation == 1)
+        return 1.0 + 4.0 * kn; /* Eqs. 4-5, c = 1 */
+    double alpha = 1.358 / (1.0 + 0.170 * pow(kn, -0.4348)); /* Eq. 7 */
+    return (1.0 + alpha * kn) * (1.0 + 4.0 * kn / (1.0 - b * kn)); /* Eq. 6 */
 }
+
+double lbo_fc(double kn) { return lbo_fc_with(0, -1.0 /* R4 */, kn); }
 
 /* Eq. 14 with c = 1. */
 void lbo_feq(double rho, double ux, double uy, double eps, double out[9])
@@ -138,7 +141,7 @@ void lbo_node_macro(const lbo_params *p, const double f[9], double eps,
     } else {
         double nu = viscosity(p);
         double kn = p->kn_local ? kn0 * p->rho_ref / rho : kn0;
-        double ka = k * lbo_fc(kn);                       /* Eq. 3 */
+        double ka = k * lbo_fc_with(p->correlation, p->slip_b, kn); /* Eq. 3 */
         double A = isinf(ka) ? 0.0 : eps * nu / ka;      /* Darcy, Eq. 8 */
         double B = (isinf(ka) || p->f_eps == 0.0)
                        ? 0.0
@@ -262,6 +265,8 @@ lbo_lattice *lbo_create(const lbo_params *p, const double *eps,
         (p->nx < 3 || !(p->rho_in > 0.0) || !(p->rho_out > 0.0)))
         return NULL;
     if (p->init == 0 && !(p->rho0 > 0.0))
+        return NULL;
+    if (p->correlation < 0 || p->correlation > 2 || !(p->slip_b <= 0.0) || !isfinite(p->slip_b))
         return NULL;
     if (p->init == 1 && (!(p->rho_in > 0.0) || !(p->rho_out > 0.0)))
         return NULL;

@@ -54,12 +54,18 @@ typedef struct lbo_params {
     int kn_local;        /* 1: Kn = kn0 * rho_ref / rho;  0: Kn = kn0 */
     int init;            /* 0: rest at rho0;  1: rest on a linear rho ramp */
     int eq15_printed;    /* test-only: Eq. 15 exactly as printed */
+    int correlation;     /* 0: Eqs. 6-7 (second order); 1: Eqs. 4-5 (first
+                            order, f_c = 1 + 4 Kn); 2: none (f_c = 1) */
+    double slip_b;       /* slip coefficient b of Eq. 6 (R4: -1), <= 0 */
 } lbo_params;
 
 typedef struct lbo_lattice lbo_lattice;
 
 /* Eqs. 6-7 with b = -1: the Beskok-Karniadakis/Civan correction factor. */
 double lbo_fc(double kn);
+
+/* The correction factor of the selected correlation (see lbo_params). */
+double lbo_fc_with(int correlation, double b, double kn);
 
 /* Eq. 14 for one node; out[9]. */
 void lbo_feq(double rho, double ux, double uy, double eps, double out[9]);

@@ -54,12 +54,15 @@ class Case:
 
 def run_params(tau=0.8, gx=0.0, gy=0.0, f_eps=0.0, bc_x=PERIODIC, bc_y=PERIODIC,
                rho_in=1.0, rho_out=1.0, rho0=1.0, rho_ref=1.0, kn_local=1,
-               init=0) -> Dict[str, float]:
-    """Run description shared by the oracle and the HIP path (lattice units)."""
+               init=0, correlation=0, slip_b=-1.0) -> Dict[str, float]:
+    """Run description shared by the oracle and the HIP path (lattice units).
+    correlation: 0 second order (Eqs. 6-7, slip coefficient slip_b), 1 first
+    order (Eqs. 4-5), 2 none."""
     return dict(tau=float(tau), gx=float(gx), gy=float(gy), f_eps=float(f_eps),
                 bc_x=int(bc_x), bc_y=int(bc_y), rho_in=float(rho_in),
                 rho_out=float(rho_out), rho0=float(rho0),
-                rho_ref=float(rho_ref), kn_local=int(kn_local), init=int(init))
+                rho_ref=float(rho_ref), kn_local=int(kn_local), init=int(init),
+                correlation=int(correlation), slip_b=float(slip_b))
 
 
 def _f32(a) -> np.ndarray:

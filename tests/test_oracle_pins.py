@@ -376,6 +376,40 @@ def test_klinkenberg_darcy_column(kn0):
     assert np.allclose(flux, flux.mean(), rtol=1e-6)
 
 
+def test_first_order_klinkenberg_column():
+    """Correlation 1 (Eqs. 4-5, f_c = 1 + 4 Kn with Kn = kn0 rho_ref / rho):
+    the compressible Darcy column integrates Klinkenberg's linear law in
+    1/p to k_app / k = 1 + 4 kn0 ln(rho_in / rho_out) / (rho_in - rho_out);
+    with no correction (correlation 2) it is exactly Darcy's k."""
+    ny, nx, k, kn0 = 1, 48, 0.01, 0.3
+    out = {}
+    for corr in (1, 2):
+        lat = oracle.Lattice(*_uniform(nx, ny, 0.5, k, kn0), tau=0.8,
+                             bc_x=oracle.PRESSURE, rho_in=2.0, rho_out=1.0, init=1,
+                             correlation=corr).step(30000)
+        out[corr] = lat.apparent_permeability() / k
+    assert abs(out[1] / (1 + 4 * kn0 * math.log(2.0)) - 1) < 2e-3
+    assert abs(out[2] - 1) < 2e-3
+
+
+def test_first_order_is_the_small_kn_limit():
+    """Klinkenberg's first-order factor is the leading term of the
+    second-order correlation (Sec. II.B): their excesses over 1 agree as
+    Kn -> 0, and differ at Kn = 1."""
+    r = [(oracle.fc(x) - 1) / (oracle.fc(x, correlation=1) - 1) for x in (1e-6, 1e-8)]
+    assert abs(r[-1] - 1) < 1e-3 and abs(r[0] - 1) > abs(r[1] - 1)
+    assert abs(oracle.fc(1.0) / oracle.fc(1.0, correlation=1) - 1) > 0.2
+
+
+def test_slip_coefficient():
+    """Eq. 6 with slip coefficient b: b = -1 is the default reading; with
+    b = 0 the bracket no longer saturates, so f_c / Kn^2 -> 4 * 1.358 as
+    Kn -> oo (against 5 * 1.358 Kn for b = -1)."""
+    assert oracle.fc(0.7, slip_b=-1.0) == oracle.fc(0.7)
+    assert abs(oracle.fc(1e8, slip_b=0.0) / 1e16 - 4 * 1.358) < 1e-3
+    assert oracle.fc(2.0, slip_b=-0.5) > oracle.fc(2.0)
+
+
 def test_pressure_channel_matches_body_force_channel():
     """G = dp/(L rho) (Sec. IV.A): a pressure-driven porous channel and the
     body-force channel with the equivalent G = cs^2 (rho_in - rho_out)/
