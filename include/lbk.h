@@ -58,6 +58,14 @@ typedef enum lbk_storage {
     LBK_BF16 = 2
 } lbk_storage;
 
+/* Slip correction f_c of the apparent permeability k_a = k f_c (Eq. 3). */
+typedef enum lbk_correlation {
+    LBK_FC_BKC = 0,         /* second-order Beskok-Karniadakis/Civan, Eqs. 6-7,
+                               with slip coefficient slip_b (default -1) */
+    LBK_FC_KLINKENBERG = 1, /* first-order Klinkenberg, Eqs. 4-5: 1 + 4 Kn */
+    LBK_FC_NONE = 2         /* no slip correction: k_a = k */
+} lbk_correlation;
+
 /* Run description (Sec. IV: plates, heterogeneous media, fractured shale). */
 typedef struct lbk_desc {
     int32_t nx, ny;      /* lattice size; nx >= 3 with pressure boundaries */
@@ -75,11 +83,15 @@ typedef struct lbk_desc {
     double rho_in, rho_out; /* pressure-boundary densities */
     double rho0;         /* initial density for a start at rest */
     double rho_ref;      /* density at which kn0 is quoted */
+    double slip_b;       /* slip coefficient b of Eq. 6, <= 0 (default -1) */
+    int32_t correlation; /* lbk_correlation */
+    int32_t reserved;    /* must be 0 */
 } lbk_desc;
 
 typedef struct lbk_lattice lbk_lattice;
 
-/* Fill *d with defaults: periodic, FP32, tau 0.8, rho 1, no force. */
+/* Fill *d with defaults: periodic, FP32, tau 0.8, rho 1, no force, local Kn,
+ * the second-order correlation with b = -1. */
 lbk_status lbk_desc_default(lbk_desc *d);
 
 /* Bytes of device workspace lbk_create needs for this description. */

@@ -22,6 +22,7 @@ STATUS = {
 }
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 OBJECTIVE = {"k_app": 0, "q_out": 1}
+CORRELATION = {"bkc": 0, "klinkenberg": 1, "none": 2}
 
 
 class LbkError(RuntimeError):
@@ -43,6 +44,8 @@ class Desc(ctypes.Structure):
         ("f_eps", ctypes.c_double),
         ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
         ("rho0", ctypes.c_double), ("rho_ref", ctypes.c_double),
+        ("slip_b", ctypes.c_double),
+        ("correlation", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

@@ -70,10 +70,8 @@ __device__ __forceinline__ NodeFwd node_fwd(const Physics &ph, float rho, float 
     n.ie = n.solid ? 0.0f : 1.0f / eps;
     n.rinv = 1.0f / rho;
     const float kn = ph.kn_local ? kn0 * (ph.rho_ref * n.rinv) : kn0;
-    const float t = __builtin_amdgcn_exp2f(0.4348f * __builtin_amdgcn_logf(kn)); // Kn^0.4348
-    const float a = t + 0.170f;
-    const float num = a * (1.0f + kn);
-    const float den = (a + 1.358f * t * kn) * (1.0f + 5.0f * kn); // f_c = den / num
+    float num, den; // f_c = den / num, as in the sweep
+    fc_parts(ph, kn, num, den);
     const float dn = drag * num;
     const float R2 = 2.0f / (2.0f * den + dn);
     n.g = den * R2;     // 1 / (1 + A/2)
@@ -84,17 +82,23 @@ __device__ __forceinline__ NodeFwd node_fwd(const Physics &ph, float rho, float 
     n.uy = n.solid ? 0.0f : n.g * vy;
     n.Fx = n.solid ? -2.0f * jx * n.rinv : eps * ph.gx - n.A * n.ux;
     n.Fy = n.solid ? -2.0f * jy * n.rinv : eps * ph.gy - n.A * n.uy;
-    // f_c'(Kn) = P1' P2 + P1 P2' with P1 = 1 + alpha Kn = (a + 1.358 t Kn)/a,
-    // P2 = (1 + 5 Kn)/(1 + Kn); P1' = 1.358 t (t + 1.4348 * 0.170)/a^2,
-    // P2' = 4/(1 + Kn)^2.  Kn ~ kn0: dA/d ln kn0 = -A Kn f_c' / f_c; with the
-    // local Kn ~ 1/rho also dA/drho = -(dA/d ln kn0) / rho.
+    // Kn ~ kn0: dA/d ln kn0 = -A Kn f_c'(Kn) / f_c; with the local Kn ~ 1/rho
+    // also dA/drho = -(dA/d ln kn0) / rho.  For Eqs. 6-7, f_c = P1 P2 with
+    // P1 = 1 + alpha Kn = (a + 1.358 t Kn)/a, P2 = (1 + (4 - b) Kn)/(1 - b Kn):
+    // P1' = 1.358 t (t + 1.4348 * 0.170)/a^2, P2' = 4/(1 - b Kn)^2.  For
+    // Eqs. 4-5, Kn f_c'/f_c = 4 Kn / (1 + 4 Kn).
     float dAk = 0.0f;
-    if (kn > 0.0f) {
-        const float P1 = (a + 1.358f * t * kn) / a, P2 = (1.0f + 5.0f * kn) / (1.0f + kn);
+    if (kn > 0.0f && ph.corr == CORR_BKC) {
+        const float t = __builtin_amdgcn_exp2f(0.4348f * __builtin_amdgcn_logf(kn));
+        const float a = t + 0.170f;
+        const float q = 1.0f + ph.slip_nb * kn;
+        const float P1 = (a + 1.358f * t * kn) / a, P2 = (1.0f + ph.slip_c * kn) / q;
         const float P1d = 1.358f * t * (t + 0.243916f) / (a * a);
-        const float P2d = 4.0f / ((1.0f + kn) * (1.0f + kn));
+        const float P2d = 4.0f / (q * q);
         const float fc = P1 * P2;
         dAk = -n.A * kn * (P1d * P2 + P1 * P2d) / fc;
+    } else if (kn > 0.0f && ph.corr == CORR_KLINKENBERG) {
+        dAk = -n.A * 4.0f * kn / (1.0f + 4.0f * kn);
     }
     n.dA_dlnkn = dAk;
     n.dA_drho = ph.kn_local ? -dAk * n.rinv : 0.0f;

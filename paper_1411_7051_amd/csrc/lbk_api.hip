@@ -97,6 +97,12 @@ lbk_status check_desc(const lbk_desc *d)
         return fail(LBK_ERR_INVALID_ARG, "rho_ref must be positive and finite");
     if (d->check_every < 0)
         return fail(LBK_ERR_INVALID_ARG, "check_every must be >= 0");
+    if (d->correlation < 0 || d->correlation > 2)
+        return fail(LBK_ERR_INVALID_ARG, "correlation must be 0..2 (got %d)", d->correlation);
+    if (!(d->slip_b <= 0.0) || !isfinite(d->slip_b))
+        return fail(LBK_ERR_INVALID_ARG, "slip_b must be finite and <= 0 (got %g)", d->slip_b);
+    if (d->reserved != 0)
+        return fail(LBK_ERR_INVALID_ARG, "reserved must be 0");
     return LBK_OK;
 }
 
@@ -165,6 +171,8 @@ lbk_status lbk_desc_default(lbk_desc *d)
     d->check_every = 0;
     d->tau = 0.8;
     d->rho_in = d->rho_out = d->rho0 = d->rho_ref = 1.0;
+    d->slip_b = -1.0;
+    d->correlation = LBK_FC_BKC;
     return LBK_OK;
 }
 
@@ -238,6 +246,9 @@ lbk_status lbk_create(const lbk_desc *d, const float *eps, const float *k, const
     split(d->rho_in, ph.rin_hi, ph.rin_lo);
     split(d->rho_out, ph.rout_hi, ph.rout_lo);
     ph.kn_local = d->kn_local ? 1 : 0;
+    ph.corr = d->correlation;
+    ph.slip_nb = (float)(-d->slip_b);
+    ph.slip_c = (float)(4.0 - d->slip_b);
 
     char *ws = lat->ws;
     char *med = lat->med();

@@ -145,7 +145,35 @@ struct Physics {
     float rin_hi, rin_lo;   // rho_in = hi + lo exactly (FP64 -> 2 x FP32)
     float rout_hi, rout_lo; // rho_out likewise
     int kn_local;
+    int corr;        // slip correlation: CORR_BKC, CORR_KLINKENBERG, CORR_NONE
+    float slip_nb;   // -b, b the slip coefficient of Eq. 6
+    float slip_c;    // 4 - b
 };
+
+enum { CORR_BKC = 0, CORR_KLINKENBERG = 1, CORR_NONE = 2 };
+
+// Correction factor of the selected correlation as a ratio f_c = den / num
+// (one reciprocal serves f_c and the velocity solve):
+//   CORR_BKC (Eqs. 6-7): with t = Kn^0.4348 and a = t + 0.170,
+//     1 + alpha Kn = (a + 1.358 t Kn) / a and
+//     1 + 4 Kn / (1 - b Kn) = (1 + (4 - b) Kn) / (1 - b Kn);
+//   CORR_KLINKENBERG (Eqs. 4-5): 1 + 4 Kn;  CORR_NONE: 1.
+// t = exp2(0.4348 log2 Kn) is 0 at Kn = 0, so f_c(0) = 1.
+__device__ __forceinline__ void fc_parts(const Physics &ph, float kn, float &num, float &den)
+{
+    if (ph.corr == CORR_BKC) {
+        const float t = __builtin_amdgcn_exp2f(0.4348f * __builtin_amdgcn_logf(kn));
+        const float a = t + 0.170f;
+        num = a * (1.0f + ph.slip_nb * kn);
+        den = (a + 1.358f * t * kn) * (1.0f + ph.slip_c * kn);
+    } else if (ph.corr == CORR_KLINKENBERG) {
+        num = 1.0f;
+        den = 1.0f + 4.0f * kn;
+    } else {
+        num = 1.0f;
+        den = 1.0f;
+    }
+}
 
 // Lattice extent; `pitch` = elements per row slot (a multiple of 64).
 struct Geom {
@@ -296,10 +324,8 @@ __device__ __forceinline__ void velocity(const Physics &ph, float rho, float jx,
 {
     const float rinv = __builtin_amdgcn_rcpf(rho);
     const float kn = ph.kn_local ? kn0 * (ph.rho_ref * rinv) : kn0;
-    const float t = __builtin_amdgcn_exp2f(0.4348f * __builtin_amdgcn_logf(kn)); // 0 at Kn = 0
-    const float a = t + 0.170f;
-    const float num = a * (1.0f + kn);
-    const float den = (a + 1.358f * t * kn) * (1.0f + 5.0f * kn);
+    float num, den;
+    fc_parts(ph, kn, num, den);
     const float egx = eps * ph.gx, egy = eps * ph.gy;
     const float vx = jx * rinv + 0.5f * egx;
     const float vy = jy * rinv + 0.5f * egy;

@@ -20,7 +20,8 @@ PERIODIC, WALL, PRESSURE = 0, 1, 2
 
 def make_desc(nx, ny, tau=0.8, gx=0.0, gy=0.0, f_eps=0.0, bc_x=PERIODIC,
               bc_y=PERIODIC, rho_in=1.0, rho_out=1.0, rho0=1.0, rho_ref=1.0,
-              kn_local=1, init=0, storage="f32", check_every=0) -> Desc:
+              kn_local=1, init=0, storage="f32", check_every=0, correlation=0,
+              slip_b=-1.0) -> Desc:
     lib = _lib.load()
     d = Desc()
     check(lib.lbk_desc_default(ctypes.byref(d)))
@@ -31,6 +32,9 @@ def make_desc(nx, ny, tau=0.8, gx=0.0, gy=0.0, f_eps=0.0, bc_x=PERIODIC,
     d.rho_ref, d.kn_local, d.init = float(rho_ref), int(kn_local), int(init)
     d.storage = _lib.STORAGE[storage] if isinstance(storage, str) else int(storage)
     d.check_every = int(check_every)
+    d.correlation = (_lib.CORRELATION[correlation] if isinstance(correlation, str)
+                     else int(correlation))
+    d.slip_b = float(slip_b)
     return d
 
 
@@ -54,7 +58,7 @@ class Lattice:
     ``eps``, ``k``, ``kn0``: [ny][nx] arrays (numpy or torch); ``k`` may be
     +inf.  Keyword parameters are those of ``lbk_desc`` (tau, gx, gy, f_eps,
     bc_x, bc_y, rho_in, rho_out, rho0, rho_ref, kn_local, init, storage,
-    check_every)."""
+    check_every, correlation, slip_b)."""
 
     def __init__(self, eps, k, kn0=None, device: Optional[torch.device] = None,
                  **params):

@@ -29,8 +29,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_desc_struct_layout():
-    # 8 int32 then 8 doubles: 32 + 64 bytes, no padding
-    assert ctypes.sizeof(_lib.Desc) == 96
+    # 8 int32, 9 doubles, 2 int32: 32 + 72 + 8 bytes, no padding
+    assert ctypes.sizeof(_lib.Desc) == 112
+    assert _lib.Desc.slip_b.offset == 96 and _lib.Desc.correlation.offset == 104
 
 
 def test_workspace_size_scales_with_lattice():
@@ -54,6 +55,8 @@ def test_workspace_size_scales_with_lattice():
     (dict(rho_ref=0.0), "rho_ref"),
     (dict(check_every=-1), "check_every"),
     (dict(f_eps=-1.0), "f_eps"),
+    (dict(correlation=3), "correlation"),
+    (dict(slip_b=0.5), "slip_b"),
 ])
 def test_invalid_descriptions_rejected(kw, msg):
     d = make_desc(16, 8, **kw)

@@ -97,6 +97,32 @@ def test_kn0_gradient_matches_oracle_fd(dev, bcx, bcy, obj, kn_local):
     assert err <= GRAD_TOL * scale, f"max |adjoint - fd| = {err:.3e}, scale {scale:.3e}"
 
 
+@pytest.mark.parametrize("corr,slip_b", [(1, -1.0), (0, -0.3), (2, -1.0)])
+def test_gradient_correlations(dev, corr, slip_b):
+    """Both gradient planes with the first-order correlation, a different
+    slip coefficient and no correction, against oracle finite differences
+    (no correction: the ln kn0 plane is exactly zero)."""
+    nx, ny, N = 36, 10, 20
+    case = inputs.random_medium(nx, ny, seed=360 + corr, solid_frac=0.05, pore_frac=0.05,
+                                kn_range=(0.05, 3.0), bc_x=2, bc_y=1, rho_in=1.02,
+                                rho_out=1.0, init=1, correlation=corr, slip_b=slip_b)
+    lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+    _, gk, gn = lat.gradient(N, "k_app", ckpt_every=8, hist_len=3, wrt_kn0=True)
+    for g, wrt in ((gk, "k"), (gn, "kn0")):
+        g = g.double().cpu().numpy()
+        if corr == 2 and wrt == "kn0":
+            assert np.all(g == 0.0)
+            continue
+        order = np.argsort(-np.abs(g).ravel())
+        cand = [divmod(int(i), nx) for i in order[:5]]
+        fd = oracle.fd_gradient(case.eps, case.k, case.kn0, N, cand, "k_app", h=1e-4, wrt=wrt,
+                                **case.params)
+        scale = np.max(np.abs(g))
+        assert scale > 0
+        err = np.max(np.abs(np.array([g[c] for c in cand]) - fd))
+        assert err <= GRAD_TOL * scale, (wrt, err, scale)
+
+
 def test_whole_field_small(dev):
     """Every node of a 10x6 pressure-driven lattice against oracle FD."""
     nx, ny, N = 10, 6, 12

@@ -113,6 +113,22 @@ def test_global_kn(dev):
     compare(gpu_run(dev, case, 300), oracle_run(case, 300))
 
 
+@pytest.mark.parametrize("corr,slip_b,kn_local", [(1, -1.0, 1), (2, -1.0, 1), (0, -0.4, 1),
+                                                 (0, 0.0, 0), (1, -1.0, 0)])
+def test_correlations(dev, corr, slip_b, kn_local):
+    """Selectable slip correlation (Eqs. 6-7 with slip coefficient b, Eqs.
+    4-5, none) against the oracle on a pressure-driven heterogeneous
+    medium with Kn up to 3."""
+    case = inputs.random_medium(130, 21, seed=60 + corr, solid_frac=0.05, pore_frac=0.05,
+                                kn_range=(0.0, 3.0), bc_x=2, bc_y=1, rho_in=1.02,
+                                rho_out=1.0, init=1, correlation=corr, slip_b=slip_b,
+                                kn_local=kn_local)
+    lat = gpu_run(dev, case, 300)
+    ref = oracle_run(case, 300)
+    compare(lat, ref)
+    assert abs(lat.apparent_permeability() / ref.apparent_permeability() - 1) < 1e-5
+
+
 @pytest.mark.parametrize("nx,ny,bcx,bcy", [(1, 1, 0, 0), (1, 9, 0, 1), (7, 1, 0, 0),
                                            (3, 4, 2, 1), (3, 1, 2, 0), (257, 3, 1, 1),
                                            (64, 64, 0, 0), (513, 5, 2, 0)])
