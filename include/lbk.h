@@ -300,6 +300,13 @@ lbk_status lbk_batch_adjoint_forward(lbk_batch *b, int objective, int64_t n_step
 lbk_status lbk_batch_adjoint_backward(lbk_batch *b, void *ws, size_t ws_bytes,
                                       float *const *dJ_dlnk, float *const *dJ_dlnkn0);
 
+/* Host-side correction factor f_c(Kn) of a correlation in FP64 (Eq. 3's
+ * k_a / k; Eqs. 6-7 with slip coefficient slip_b, Eqs. 4-5, or 1), for
+ * n >= 0 Knudsen numbers in host memory (finite, >= 0); f_c(0) = 1.  For
+ * front ends that map physical conditions to lattice inputs. */
+lbk_status lbk_correction_factor(int32_t correlation, double slip_b, const double *kn,
+                                 double *fc, size_t n);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *lbk_last_error(void);
 

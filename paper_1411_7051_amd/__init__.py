@@ -5,12 +5,14 @@ arXiv:1411.7051).
 The fused D2Q9 sweep and its read-outs are HIP kernels for gfx950 behind the
 C ABI of ``include/lbk.h`` (``liblbk.so``, built by ``build.py``);
 ``Lattice`` and ``Batch`` (ensembles stepped together) are thin ctypes
-bindings over it.  ``inputs`` draws the seeded
+bindings over it; ``units`` maps physical conditions (Eqs. 9-11) to lattice
+inputs.  ``inputs`` draws the seeded
 synthetic media.
 """
 from . import inputs  # noqa: F401
 
-__all__ = ["Lattice", "Batch", "ApparentPermeability", "inputs", "make_desc", "workspace_bytes"]
+__all__ = ["Lattice", "Batch", "ApparentPermeability", "inputs", "units", "make_desc",
+           "workspace_bytes"]
 
 
 def __getattr__(name):
@@ -20,4 +22,7 @@ def __getattr__(name):
     if name == "Batch":
         from .batch import Batch
         return Batch
+    if name == "units":
+        from . import units
+        return units
     raise AttributeError(name)

@@ -103,6 +103,8 @@ _SIG = {
                                                  ctypes.c_int64, ctypes.c_int64, _P,
                                                  ctypes.c_size_t, _P]),
     "lbk_batch_adjoint_backward": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, _P]),
+    "lbk_correction_factor": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, _P, _P,
+                                             ctypes.c_size_t]),
     "lbk_last_error": (ctypes.c_char_p, []),
 }
 

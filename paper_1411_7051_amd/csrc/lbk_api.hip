@@ -475,6 +475,31 @@ lbk_status lbk_load_state(lbk_lattice *lat, const void *src)
     return LBK_OK;
 }
 
+lbk_status lbk_correction_factor(int32_t correlation, double slip_b, const double *kn,
+                                 double *fc, size_t n)
+{
+    if ((n && (!kn || !fc)))
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    if (correlation < 0 || correlation > 2)
+        return fail(LBK_ERR_INVALID_ARG, "correlation must be 0..2 (got %d)", correlation);
+    if (!(slip_b <= 0.0) || !isfinite(slip_b))
+        return fail(LBK_ERR_INVALID_ARG, "slip_b must be finite and <= 0");
+    for (size_t i = 0; i < n; ++i) {
+        const double k = kn[i];
+        if (!(k >= 0.0) || !isfinite(k))
+            return fail(LBK_ERR_INVALID_ARG, "Kn[%zu] = %g is not finite and >= 0", i, k);
+        double f = 1.0;
+        if (k > 0.0 && correlation == LBK_FC_KLINKENBERG) {
+            f = 1.0 + 4.0 * k;
+        } else if (k > 0.0 && correlation == LBK_FC_BKC) {
+            const double alpha = 1.358 / (1.0 + 0.170 * pow(k, -0.4348));
+            f = (1.0 + alpha * k) * (1.0 + 4.0 * k / (1.0 - slip_b * k));
+        }
+        fc[i] = f;
+    }
+    return LBK_OK;
+}
+
 const char *lbk_last_error(void) { return g_err.c_str(); }
 
 } // extern "C"
