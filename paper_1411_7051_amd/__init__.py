@@ -23,6 +23,6 @@ def __getattr__(name):
         from .batch import Batch
         return Batch
     if name == "units":
-        from . import units
-        return units
+        import importlib
+        return importlib.import_module(".units", __name__)
     raise AttributeError(name)
