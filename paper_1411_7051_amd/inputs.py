@@ -17,6 +17,10 @@ available, so these are statistical stand-ins with the stated shapes):
 * ``shale``     -- log-normal permeability matrix with straight fractures
                    (Sec. IV.C).
 * ``ensemble``  -- independent heterogeneous samples of uneven size.
+* ``trimodal``  -- pores, impermeable and permeable solids (Sec. IV.B, Fig. 4)
+                   from overlapping tolerance circles and QSGS growth.
+* ``fractured_matrix`` -- nonorganic matrix with organic matter and a
+                   tree-like fracture system (Sec. IV.C, Fig. 8).
 
 Kn fields follow the pore-radius scaling of Eq. 11 (r ~ sqrt(k/eps)): a node
 with permeability k and porosity eps gets
@@ -251,3 +255,176 @@ def random_medium(nx, ny, seed, eps_range=(0.2, 0.9), k_range=(1e-2, 1.0),
     kn0 = np.where(pore | solid, 0.0, kn0)
     return Case(_f32(eps), _f32(k), _f32(kn0), run_params(**params),
                 f"random{nx}x{ny}s{seed}")
+
+
+# ------------------------------------------------------------------ geometry
+#
+# Stand-ins for the generators the paper names without specifying them: the
+# overlapping tolerance circle method (impermeable solids, Sec. IV.B), the
+# quartet structure generation set (permeable solids, Sec. IV.B) and the
+# tree-like fracture generator (Sec. IV.C).  Each returns a boolean mask.
+
+
+def tolerance_circles(shape, frac, r_range, tol, rng, periodic_y=True,
+                      max_tries=200000, centres: Optional[list] = None) -> np.ndarray:
+    """Overlapping tolerance circles: centres uniform, radii uniform in
+    ``r_range``; a candidate is kept when its centre is at least
+    (1 - tol)(r_i + r_j) from every kept centre (tol = 0: no overlap, 1: any
+    overlap); circles are added until they cover ``frac`` of the domain.
+    Wrapped in y when ``periodic_y``; the kept (x, y, r) are appended to
+    ``centres`` when given."""
+    ny, nx = shape
+    mask = np.zeros(shape, dtype=bool)
+    cs = np.zeros((0, 3))
+    target = frac * nx * ny
+    xs = np.arange(nx) + 0.5
+    tries = 0
+    while mask.sum() < target and tries < max_tries:
+        tries += 1
+        cx, cy = rng.uniform(0, nx), rng.uniform(0, ny)
+        r = rng.uniform(r_range[0], r_range[1])
+        if len(cs):
+            dy = np.abs(cs[:, 1] - cy)
+            if periodic_y:
+                dy = np.minimum(dy, ny - dy)
+            d = np.hypot(cs[:, 0] - cx, dy)
+            if np.any(d < (1.0 - tol) * (cs[:, 2] + r)):
+                continue
+        cs = np.vstack([cs, [cx, cy, r]])
+        x0, x1 = max(int(cx - r) - 1, 0), min(int(cx + r) + 2, nx)
+        for yy in range(int(math.floor(cy - r)) - 1, int(math.ceil(cy + r)) + 2):
+            if not periodic_y and not 0 <= yy < ny:
+                continue
+            dyy = (yy + 0.5) - cy
+            if abs(dyy) > r:
+                continue
+            dx = xs[x0:x1] - cx
+            mask[yy % ny, x0:x1] |= dx * dx + dyy * dyy <= r * r
+    if centres is not None:
+        centres.extend(map(tuple, cs))
+    return mask
+
+
+_QSGS_DIRS = [(1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+
+
+def qsgs(shape, frac, rng, core=0.005, grow_axis=0.02, grow_diag=0.005,
+         allowed=None) -> np.ndarray:
+    """Quartet structure generation set: cells become growth cores with
+    probability ``core``; every grown cell then grows into each of its eight
+    neighbours with probability ``grow_axis`` (axis directions) or
+    ``grow_diag`` (diagonals), periodically, until exactly ``frac`` of all
+    cells are grown (the last growth step is thinned at random).  Only cells
+    in ``allowed`` (default: all) can grow."""
+    ny, nx = shape
+    allowed = np.ones(shape, dtype=bool) if allowed is None else np.asarray(allowed, bool)
+    target = int(round(frac * nx * ny))
+    if target > allowed.sum():
+        raise ValueError("target fraction exceeds the allowed cells")
+    grown = np.zeros(shape, dtype=bool)
+
+    def add(cand):
+        idx = np.flatnonzero(cand & allowed & ~grown)
+        need = target - int(grown.sum())
+        if len(idx) > need:
+            idx = rng.choice(idx, need, replace=False)
+        grown.flat[idx] = True
+
+    add(rng.random(shape) < core)
+    while grown.sum() < target:
+        new = np.zeros(shape, dtype=bool)
+        for i, (ex, ey) in enumerate(_QSGS_DIRS):
+            p = grow_axis if i < 4 else grow_diag
+            new |= np.roll(grown, (ey, ex), axis=(0, 1)) & (rng.random(shape) < p)
+        if not (new & allowed & ~grown).any():
+            new = rng.random(shape) < core  # growth stalled: seed new cores
+        add(new)
+    return grown
+
+
+def _segment(mask, x0, y0, x1, y1, width):
+    """Mark the cells within width/2 of the segment (x0, y0)-(x1, y1)."""
+    ny, nx = mask.shape
+    h = 0.5 * width
+    xa, xb = int(max(math.floor(min(x0, x1) - h), 0)), int(min(math.ceil(max(x0, x1) + h) + 1, nx))
+    ya, yb = int(max(math.floor(min(y0, y1) - h), 0)), int(min(math.ceil(max(y0, y1) + h) + 1, ny))
+    if xa >= xb or ya >= yb:
+        return
+    X, Y = np.meshgrid(np.arange(xa, xb) + 0.5, np.arange(ya, yb) + 0.5)
+    dx, dy = x1 - x0, y1 - y0
+    L2 = dx * dx + dy * dy
+    t = np.clip(((X - x0) * dx + (Y - y0) * dy) / L2, 0.0, 1.0) if L2 > 0 else 0.0
+    d2 = (X - (x0 + t * dx)) ** 2 + (Y - (y0 + t * dy)) ** 2
+    mask[ya:yb, xa:xb] |= d2 <= h * h
+
+
+def tree_fractures(shape, rng, aperture=10.0, n_first=10, n_second=3,
+                   angle=(20.0, 60.0)) -> np.ndarray:
+    """Tree-like fracture system: a trunk of width ``aperture`` crossing the
+    domain along x through its middle (wandering gently), ``n_first`` first
+    branches leaving it at angles in ``angle`` (degrees) with 0.6 times the
+    width, and ``n_second`` second branches on each first branch with 0.4
+    times the width."""
+    ny, nx = shape
+    mask = np.zeros(shape, dtype=bool)
+    nseg = 8
+    xs = np.linspace(0.0, nx, nseg + 1)
+    ys = ny / 2 + np.cumsum(rng.normal(0.0, 0.02 * ny, nseg + 1))
+    ys = np.clip(ys, 0.25 * ny, 0.75 * ny)
+    for j in range(nseg):
+        _segment(mask, xs[j], ys[j], xs[j + 1], ys[j + 1], aperture)
+    for _ in range(n_first):
+        j = int(rng.integers(0, nseg))
+        s = rng.uniform(0.0, 1.0)
+        bx, by = xs[j] + s * (xs[j + 1] - xs[j]), ys[j] + s * (ys[j + 1] - ys[j])
+        a = math.radians(rng.uniform(*angle)) * (1 if rng.random() < 0.5 else -1)
+        a += 0.0 if rng.random() < 0.5 else math.pi
+        L = rng.uniform(0.3, 0.5) * ny / max(abs(math.sin(a)), 0.3)
+        ex, ey = bx + L * math.cos(a), by + L * math.sin(a)
+        _segment(mask, bx, by, ex, ey, 0.6 * aperture)
+        for _ in range(n_second):
+            s2 = rng.uniform(0.3, 0.9)
+            cx, cy = bx + s2 * (ex - bx), by + s2 * (ey - by)
+            a2 = a + math.radians(rng.uniform(*angle)) * (1 if rng.random() < 0.5 else -1)
+            L2 = 0.5 * L * rng.uniform(0.5, 1.0)
+            _segment(mask, cx, cy, cx + L2 * math.cos(a2), cy + L2 * math.sin(a2), 0.4 * aperture)
+    return mask
+
+
+def trimodal(nx=410, ny=200, seed=5, imp_frac=0.4, perm_frac=0.3, r_range=(6.0, 20.0),
+             tol=0.2, eps_ps=0.5, k_ps=0.05, kn_ps=0.5, rho_in=1.01, rho_out=1.0,
+             tau=0.8, **params) -> Case:
+    """Three-component medium of Sec. IV.B (Fig. 4): impermeable solid
+    (eps = 0) from overlapping tolerance circles covering ``imp_frac``,
+    permeable solid (eps_ps, k_ps, kn_ps in lattice units) grown by QSGS in
+    the remaining space to ``perm_frac``, and pores (eps = 1, k = +inf)
+    elsewhere; pressure-driven in x, periodic in y."""
+    rng = np.random.default_rng(seed)
+    imp = tolerance_circles((ny, nx), imp_frac, r_range, tol, rng)
+    perm = qsgs((ny, nx), perm_frac, rng, allowed=~imp)
+    eps = np.where(imp, 0.0, np.where(perm, eps_ps, 1.0))
+    k = np.where(perm, k_ps, np.where(imp, 1.0, np.inf))
+    kn0 = np.where(perm, kn_ps, 0.0)
+    p = run_params(tau=tau, bc_x=PRESSURE, bc_y=PERIODIC, rho_in=rho_in, rho_out=rho_out,
+                   init=1, **params)
+    return Case(_f32(eps), _f32(k), _f32(kn0), p, f"trimodal{nx}x{ny}s{seed}")
+
+
+def fractured_matrix(nx=1164, ny=536, seed=6, organic_frac=0.106, aperture=10.0,
+                     eps_in=0.05, k_in=1e-4, kn_in=2.0, eps_org=0.2, k_org=1e-3,
+                     kn_org=1.0, eps_frac=1.0, k_frac=np.inf, rho_in=1.01, rho_out=1.0,
+                     tau=0.8, **params) -> Case:
+    """Fractured shale matrix of Sec. IV.C (Fig. 8): a permeable nonorganic
+    matrix (eps_in, k_in, kn_in) holding QSGS-grown organic matter
+    (``organic_frac``; eps_org, k_org, kn_org) and a tree-like fracture
+    system of width ``aperture`` nodes (free fluid by default); pressure
+    driven in x, periodic in y."""
+    rng = np.random.default_rng(seed)
+    org = qsgs((ny, nx), organic_frac, rng)
+    frac = tree_fractures((ny, nx), rng, aperture=aperture)
+    eps = np.where(frac, eps_frac, np.where(org, eps_org, eps_in))
+    k = np.where(frac, k_frac, np.where(org, k_org, k_in))
+    kn0 = np.where(frac, 0.0 if np.isinf(k_frac) else kn_in, np.where(org, kn_org, kn_in))
+    p = run_params(tau=tau, bc_x=PRESSURE, bc_y=PERIODIC, rho_in=rho_in, rho_out=rho_out,
+                   init=1, **params)
+    return Case(_f32(eps), _f32(k), _f32(kn0), p, f"fractured{nx}x{ny}s{seed}")
