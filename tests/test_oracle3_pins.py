@@ -1,0 +1,144 @@
+"""Pins for the D3Q19 form of the FP64 oracle, against what the paper's
+model and the lattice fix rather than the oracle's own formulas: the
+isotropy conditions that define the D3Q19 set, the moment conditions of
+Eqs. 14-15 with three-component vectors, the uniform-medium recurrence
+(Darcy limit) for a force along an arbitrary direction, mass conservation,
+the Brinkman channel of Eq. 20 and the compressible Klinkenberg-Darcy
+column (CPU)."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+
+import oracle
+
+CS2 = 1.0 / 3.0
+
+
+def _fields(nz, ny, nx, eps, k, kn0=0.0):
+    s = (nz, ny, nx)
+    return np.full(s, eps), np.full(s, k), np.full(s, kn0)
+
+
+def test_d3q19_set_and_isotropy():
+    ex, ey, ez, w = oracle.tables3()
+    E = np.stack([ex, ey, ez], axis=1).astype(float)
+    n2 = (E ** 2).sum(1)
+    # rest, six axis links, twelve face diagonals; no cube corners
+    assert sorted(n2) == [0] + [1] * 6 + [2] * 12
+    assert len({tuple(e) for e in E.astype(int)}) == 19
+    assert math.isclose(w.sum(), 1.0, rel_tol=1e-15)
+    d = np.eye(3)
+    # odd moments vanish, second moment cs^2 delta, fourth moment cs^4 (dd + dd + dd)
+    assert np.allclose(np.einsum("i,ia->a", w, E), 0, atol=1e-16)
+    assert np.allclose(np.einsum("i,ia,ib->ab", w, E, E), CS2 * d, atol=1e-15)
+    assert np.allclose(np.einsum("i,ia,ib,ic->abc", w, E, E, E), 0, atol=1e-16)
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", w, E, E, E, E)
+    iso = CS2 ** 2 * (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d) +
+                      np.einsum("ad,bc->abcd", d, d))
+    assert np.allclose(m4, iso, atol=1e-15)
+
+
+@pytest.mark.parametrize("eps", [1.0, 0.6, 0.15])
+def test_equilibrium_and_forcing_moments(eps):
+    """Eq. 14: density, momentum, momentum flux cs^2 rho I + rho u u / eps;
+    Eq. 15 (Guo): 0, (1 - 1/2tau) rho F, (1 - 1/2tau) rho (uF + Fu)/eps."""
+    ex, ey, ez, _ = oracle.tables3()
+    E = np.stack([ex, ey, ez], axis=1).astype(float)
+    rng = np.random.default_rng(1)
+    for _ in range(10):
+        rho, tau = rng.uniform(0.5, 1.5), rng.uniform(0.55, 2.0)
+        u = rng.uniform(-0.05, 0.05, 3)
+        F = rng.uniform(-1e-3, 1e-3, 3)
+        f = oracle.feq3(rho, u, eps)
+        assert math.isclose(f.sum(), rho, rel_tol=1e-14)
+        assert np.allclose(E.T @ f, rho * u, atol=1e-15)
+        assert np.allclose(np.einsum("ia,ib,i->ab", E, E, f),
+                           CS2 * rho * np.eye(3) + rho * np.outer(u, u) / eps, atol=1e-14)
+        Fi = oracle.guo3(rho, u, F, eps, tau)
+        c = 1 - 1 / (2 * tau)
+        assert abs(Fi.sum()) < 1e-18
+        assert np.allclose(E.T @ Fi, c * rho * F, atol=1e-18)
+        assert np.allclose(np.einsum("ia,ib,i->ab", E, E, Fi),
+                           c * rho * (np.outer(u, F) + np.outer(F, u)) / eps, atol=1e-18)
+
+
+@pytest.mark.parametrize("eps,k,kn0", [(0.5, 1.0, 0.0), (0.3, 0.2, 0.4)])
+def test_uniform_recurrence_and_darcy_limit(eps, k, kn0):
+    """Uniform periodic medium: j_{n+1} = j_n + rho F_n exactly, so
+    u_{n+1} = q u_n + eps G / (1 + A/2), q = (1 - A/2)/(1 + A/2), with the
+    fixed point k_a G / nu (Darcy), for G along an arbitrary direction."""
+    tau, nu = 0.8, 0.1
+    G = np.array([1e-5, -4e-6, 7e-6])
+    lat = oracle.Lattice3(*_fields(3, 4, 5, eps, k, kn0), tau=tau, gx=G[0], gy=G[1], gz=G[2])
+    A = eps * nu / (k * oracle.fc(kn0))
+    q, b = (1 - A / 2) / (1 + A / 2), eps / (1 + A / 2)
+    u = 0.5 * b * G
+    for _ in range(60):
+        _, ux, uy, uz = lat.macro()
+        assert np.allclose([ux.mean(), uy.mean(), uz.mean()], u, rtol=1e-10, atol=0)
+        assert np.ptp(ux) < 1e-18
+        lat.step(1)
+        u = q * u + b * G
+    ustar = k * oracle.fc(kn0) * G / nu
+    assert np.allclose(b * G / (1 - q), ustar, rtol=1e-12)
+
+
+def test_mass_conservation_with_walls():
+    """Streaming, bounce-back and collision conserve mass: the FP64 total
+    moves only by the round-off of the sums (about 1e-13 after 300 steps
+    here, the same with and without walls)."""
+    rng = np.random.default_rng(2)
+    s = (6, 7, 9)
+    eps = rng.uniform(0.2, 1.0, s)
+    k = np.exp(rng.uniform(np.log(0.05), 0.0, s))
+    kn0 = rng.uniform(0, 1, s)
+    lat = oracle.Lattice3(eps, k, kn0, gx=1e-4, gy=2e-5, gz=-3e-5, bc_y=oracle.WALL,
+                          bc_z=oracle.WALL)
+    m0 = lat.mass()
+    lat.step(300)
+    assert abs(lat.mass() - m0) / m0 < 1e-12
+
+
+def _brinkman(y, H, G, K, eps, nu):
+    a = math.sqrt(eps / K)
+    return G * K / nu * (1 - np.cosh(a * (y - H / 2)) / np.cosh(a * H / 2))
+
+
+def test_brinkman_channel():
+    """Plates normal to y (walls), periodic in x and z: the steady profile is
+    Eq. 20, uniform in x and z; the channel permeability k (1 - tanh(aH/2)/
+    (aH/2))."""
+    H, eps, k, G, nu = 32, 0.5, 1.024, 1e-6, 0.1
+    lat = oracle.Lattice3(*_fields(2, H, 3, eps, k), tau=0.8, gx=G, bc_y=oracle.WALL)
+    lat.step(10000)
+    _, ux, uy, uz = lat.macro()
+    ua = _brinkman(np.arange(H) + 0.5, H, G, k, eps, nu)
+    prof = ux[0, :, 0]
+    assert abs(0.5 * (prof[15] + prof[16]) / _brinkman(np.array([H / 2]), H, G, k, eps, nu)[0]
+               - 1) < 1e-4
+    assert np.linalg.norm(prof - ua) / np.linalg.norm(ua) < 1e-2
+    assert np.all(ux == ux[:1, :, :1])
+    assert max(np.abs(uy).max(), np.abs(uz).max()) < 1e-9 * np.abs(ux).max()
+    a = math.sqrt(eps / k)
+    kg = k * (1 - math.tanh(a * H / 2) / (a * H / 2))
+    assert abs(lat.apparent_permeability() / kg - 1) < 5e-3
+
+
+def test_klinkenberg_darcy_column():
+    """Pressure planes with a 2:1 density ratio in a uniform medium with local
+    Kn: k_app = k / (rho_in - rho_out) int f_c(kn0 / rho) d rho."""
+    k, kn0 = 0.01, 0.5
+    lat = oracle.Lattice3(*_fields(2, 1, 40, 0.5, k, kn0), tau=0.8, bc_x=oracle.PRESSURE,
+                          rho_in=2.0, rho_out=1.0, init=1).step(25000)
+    integral = quad(lambda r: oracle.fc(kn0 / r), 1.0, 2.0, epsabs=1e-13)[0]
+    assert abs(lat.apparent_permeability() / k / integral - 1) < 2e-3
+
+
+def test_rejects_invalid():
+    with pytest.raises(ValueError):
+        oracle.Lattice3(*_fields(2, 2, 2, 1.5, 1.0))
+    with pytest.raises(ValueError):
+        oracle.Lattice3(*_fields(2, 2, 2, 0.5, 1.0), bc_z=2)
