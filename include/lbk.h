@@ -307,6 +307,57 @@ lbk_status lbk_batch_adjoint_backward(lbk_batch *b, void *ws, size_t ws_bytes,
 lbk_status lbk_correction_factor(int32_t correlation, double slip_b, const double *kn,
                                  double *fc, size_t n);
 
+/* ---------------------------------------------------------------------
+ * Three dimensions: the same model on a D3Q19 lattice.
+ *
+ * The sweep of lbk_step with nineteen velocities (rest, six axis links with
+ * weight 1/18, twelve face diagonals with weight 1/36; cs^2 = 1/3): pull
+ * with wrap or half-way bounce-back on each axis, pressure planes at x = 0
+ * and x = nx-1 (non-equilibrium extrapolation from the neighbouring plane),
+ * Eqs. 14-17 with three-component vectors, the local Kn and the selected
+ * slip correlation.  Fields are [nz][ny][nx] float32 (x fastest).  Storage,
+ * ownership, streams and errors follow the D2Q9 calls; gradients and
+ * batches are D2Q9 only.
+ * --------------------------------------------------------------------- */
+typedef struct lbk_desc3 {
+    int32_t nx, ny, nz;
+    int32_t bc_x, bc_y, bc_z; /* lbk_bc; only bc_x may be LBK_BC_PRESSURE */
+    int32_t storage;          /* lbk_storage */
+    int32_t kn_local;         /* 1: Kn = kn0 * rho_ref / rho; 0: Kn = kn0 */
+    int32_t init;             /* 0: rest at rho0; 1: ramp rho_in -> rho_out in x */
+    int32_t check_every;      /* NaN check (and FP16 re-scaling) interval; 0 = never */
+    int32_t correlation;      /* lbk_correlation */
+    int32_t reserved;         /* must be 0 */
+    double tau;
+    double gx, gy, gz;        /* external acceleration G */
+    double f_eps;             /* Forchheimer function of Eq. 2; 0 = Eq. 8 */
+    double rho_in, rho_out, rho0, rho_ref;
+    double slip_b;            /* slip coefficient of Eq. 6, <= 0 (default -1) */
+} lbk_desc3;
+
+typedef struct lbk_lattice3 lbk_lattice3;
+
+/* Defaults: periodic, FP32, tau 0.8, rho 1, no force, local Kn, Eqs. 6-7. */
+lbk_status lbk3_desc_default(lbk_desc3 *d);
+lbk_status lbk3_workspace_size(const lbk_desc3 *d, size_t *bytes);
+/* As lbk_create, with fields [nz][ny][nx]. */
+lbk_status lbk3_create(const lbk_desc3 *d, const float *eps, const float *k, const float *kn0,
+                       void *workspace, size_t ws_bytes, void *stream, lbk_lattice3 **out);
+lbk_status lbk3_destroy(lbk_lattice3 *lat);
+lbk_status lbk3_step(lbk_lattice3 *lat, int64_t n);
+lbk_status lbk3_time(const lbk_lattice3 *lat, int64_t *t);
+/* rho and the three velocity components as [nz][ny][nx] float32 device
+ * buffers (any may be NULL). */
+lbk_status lbk3_read_macroscopic(lbk_lattice3 *lat, float *rho, float *ux, float *uy,
+                                 float *uz);
+/* Post-collision populations in FP64, [19][nz][ny][nx], into a device buffer. */
+lbk_status lbk3_read_populations(lbk_lattice3 *lat, double *f);
+/* Global permeability as lbk_apparent_permeability (means over every node;
+ * eps_b over the two pressure planes).  Synchronizes. */
+lbk_status lbk3_apparent_permeability(lbk_lattice3 *lat, double *k_app);
+/* FP64 total mass and x mass flux (either may be NULL).  Synchronizes. */
+lbk_status lbk3_diagnostics(lbk_lattice3 *lat, double *mass, double *flux_x);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *lbk_last_error(void);
 

@@ -49,6 +49,24 @@ class Desc(ctypes.Structure):
     ]
 
 
+class Desc3(ctypes.Structure):
+    """``lbk_desc3``."""
+
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32), ("bc_z", ctypes.c_int32),
+        ("storage", ctypes.c_int32), ("kn_local", ctypes.c_int32),
+        ("init", ctypes.c_int32), ("check_every", ctypes.c_int32),
+        ("correlation", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("tau", ctypes.c_double),
+        ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("gz", ctypes.c_double),
+        ("f_eps", ctypes.c_double),
+        ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
+        ("rho0", ctypes.c_double), ("rho_ref", ctypes.c_double),
+        ("slip_b", ctypes.c_double),
+    ]
+
+
 # Every symbol include/lbk.h declares, with (restype, argtypes).
 _P = ctypes.c_void_p
 _SIG = {
@@ -105,6 +123,19 @@ _SIG = {
     "lbk_batch_adjoint_backward": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, _P]),
     "lbk_correction_factor": (ctypes.c_int, [ctypes.c_int32, ctypes.c_double, _P, _P,
                                              ctypes.c_size_t]),
+    "lbk3_desc_default": (ctypes.c_int, [ctypes.POINTER(Desc3)]),
+    "lbk3_workspace_size": (ctypes.c_int, [ctypes.POINTER(Desc3),
+                                           ctypes.POINTER(ctypes.c_size_t)]),
+    "lbk3_create": (ctypes.c_int, [ctypes.POINTER(Desc3), _P, _P, _P, _P, ctypes.c_size_t, _P,
+                                   ctypes.POINTER(_P)]),
+    "lbk3_destroy": (ctypes.c_int, [_P]),
+    "lbk3_step": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "lbk3_time": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "lbk3_read_macroscopic": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "lbk3_read_populations": (ctypes.c_int, [_P, _P]),
+    "lbk3_apparent_permeability": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "lbk3_diagnostics": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]),
     "lbk_last_error": (ctypes.c_char_p, []),
 }
 

@@ -428,3 +428,73 @@ def fractured_matrix(nx=1164, ny=536, seed=6, organic_frac=0.106, aperture=10.0,
     p = run_params(tau=tau, bc_x=PRESSURE, bc_y=PERIODIC, rho_in=rho_in, rho_out=rho_out,
                    init=1, **params)
     return Case(_f32(eps), _f32(k), _f32(kn0), p, f"fractured{nx}x{ny}s{seed}")
+
+
+# ------------------------------------------------------------ three dims
+
+
+def run_params3(tau=0.8, gx=0.0, gy=0.0, gz=0.0, f_eps=0.0, bc_x=PERIODIC, bc_y=PERIODIC,
+                bc_z=PERIODIC, rho_in=1.0, rho_out=1.0, rho0=1.0, rho_ref=1.0, kn_local=1,
+                init=0, correlation=0, slip_b=-1.0) -> Dict[str, float]:
+    """Run description of a D3Q19 lattice shared by the oracle and the HIP
+    path (lattice units)."""
+    return dict(tau=float(tau), gx=float(gx), gy=float(gy), gz=float(gz), f_eps=float(f_eps),
+                bc_x=int(bc_x), bc_y=int(bc_y), bc_z=int(bc_z), rho_in=float(rho_in),
+                rho_out=float(rho_out), rho0=float(rho0), rho_ref=float(rho_ref),
+                kn_local=int(kn_local), init=int(init), correlation=int(correlation),
+                slip_b=float(slip_b))
+
+
+def random_medium3(nx, ny, nz, seed, eps_range=(0.2, 0.9), k_range=(1e-2, 1.0),
+                   kn_range=(0.0, 1.0), solid_frac=0.0, pore_frac=0.0, **params) -> Case:
+    """Small i.i.d. heterogeneous 3-D medium ([nz][ny][nx]) with optional
+    impermeable (eps = 0) and free-fluid (eps = 1, k = inf) nodes."""
+    rng = np.random.default_rng(seed)
+    s = (nz, ny, nx)
+    eps = rng.uniform(eps_range[0], eps_range[1], s)
+    k = np.exp(rng.uniform(math.log(k_range[0]), math.log(k_range[1]), s))
+    kn0 = rng.uniform(kn_range[0], kn_range[1], s)
+    u = rng.uniform(0, 1, s)
+    solid = u < solid_frac
+    pore = (u >= solid_frac) & (u < solid_frac + pore_frac)
+    eps = np.where(solid, 0.0, np.where(pore, 1.0, eps))
+    k = np.where(pore, np.inf, k)
+    kn0 = np.where(pore | solid, 0.0, kn0)
+    return Case(_f32(eps), _f32(k), _f32(kn0), run_params3(**params),
+                f"random3_{nx}x{ny}x{nz}s{seed}")
+
+
+def channel3(nx, ny, nz, eps=0.5, k=1.024, kn0=0.0, gx=1e-6, tau=0.8) -> Case:
+    """Porous-filled plates normal to y (walls), periodic in x and z,
+    driven by a body force along x (Sec. IV.A in three dimensions)."""
+    s = (nz, ny, nx)
+    return Case(_f32(np.full(s, eps)), _f32(np.full(s, k)), _f32(np.full(s, kn0)),
+                run_params3(tau=tau, gx=gx, bc_y=WALL), f"channel3_{nx}x{ny}x{nz}")
+
+
+def spheres(n=256, seed=7, n_spheres=96, r_min=8.0, r_max=40.0, eps_inc=0.2, k_inc=1e-4,
+            eps_matrix=0.5, k_matrix=1e-2, kn_base=0.05, rho_in=1.01, rho_out=1.0,
+            tau=0.8) -> Case:
+    """Two-component 3-D medium, the disc medium of Sec. IV.B in three
+    dimensions: overlapping spherical inclusions (radius uniform in [r_min,
+    r_max] scaled by n/256, centres uniform, wrapped in y and z) of a
+    low-permeability solid in a permeable matrix; Kn by the pore-radius
+    scaling of Eq. 11; pressure-driven in x, periodic in y and z."""
+    rng = np.random.default_rng(seed)
+    scale = n / 256.0
+    inside = np.zeros((n, n, n), dtype=bool)
+    g = np.arange(n) + 0.5
+    for _ in range(n_spheres):
+        c = rng.uniform(0, n, 3)
+        r = rng.uniform(r_min, r_max) * scale
+        dz = np.minimum(np.abs(g - c[2]), n - np.abs(g - c[2]))
+        dy = np.minimum(np.abs(g - c[1]), n - np.abs(g - c[1]))
+        dx = np.abs(g - c[0])
+        inside |= (dz[:, None, None] ** 2 + dy[None, :, None] ** 2 + dx[None, None, :] ** 2) <= r * r
+    eps = np.where(inside, eps_inc, eps_matrix)
+    k = np.where(inside, k_inc, k_matrix)
+    eps32, k32 = _f32(eps), _f32(k)
+    kn0 = kn_from_pore_scaling(k32, eps32, kn_base, k_matrix, eps_matrix)
+    return Case(eps32, k32, _f32(kn0),
+                run_params3(tau=tau, bc_x=PRESSURE, rho_in=rho_in, rho_out=rho_out, init=1),
+                f"spheres{n}")

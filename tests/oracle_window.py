@@ -55,3 +55,42 @@ def window_oracle(case, xa, xb, ya, h, steps):
     return lat.macro(), valid, rows
 
 
+
+
+def window3_oracle(case, xa, xb, ya, h, za, d, steps):
+    """D3Q19 form: the oracle on columns [xa, xb), rows ya .. ya+h-1 and
+    planes za .. za+d-1 (wrapped in y and z) of `case`, from its initial
+    state.  Returns the window's (rho, ux, uy, uz), the kept sub-window as
+    (z slice, y slice, x slice) and the (rows, planes) index arrays."""
+    nz, ny, nx = case.eps.shape
+    rows = (ya + np.arange(h)) % ny
+    planes = (za + np.arange(d)) % nz
+    sub = lambda a: np.ascontiguousarray(a[planes][:, rows][:, :, xa:xb])
+    p = dict(case.params)
+    xs = np.arange(xa, xb, dtype=np.float64)
+    rho0 = ramp(case, xs)
+    touches_in, touches_out = xa == 0, xb == nx
+    pressure = case.params.get("bc_x") == inputs.PRESSURE
+    if pressure and (touches_in or touches_out):
+        p["rho_in"] = p["rho_in"] if touches_in else float(rho0[0])
+        p["rho_out"] = p["rho_out"] if touches_out else float(rho0[-1])
+    else:
+        p["bc_x"] = inputs.PERIODIC
+    if h < ny:
+        p["bc_y"] = inputs.PERIODIC
+    if d < nz:
+        p["bc_z"] = inputs.PERIODIC
+    p["init"] = 0
+    lat = oracle.Lattice3(sub(case.eps), sub(case.k), sub(case.kn0), **p)
+    _, _, _, w = oracle.tables3()
+    f = w[:, None, None, None] * np.broadcast_to(rho0[None, None, None, :],
+                                                  (19, d, h, xb - xa))
+    lat.set_state(f)
+    lat.step(steps)
+    m = steps + 2
+    xl = 0 if touches_in and pressure else m
+    xr = 0 if touches_out and pressure else m
+    keep = (slice(m, d - m) if d < nz else slice(0, d),
+            slice(m, h - m) if h < ny else slice(0, h),
+            slice(xl, xb - xa - xr))
+    return lat.macro(), keep, rows, planes

@@ -15,7 +15,7 @@ HEADER = os.path.join(os.path.dirname(__file__), "..", "include", "lbk.h")
 def declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbk_[a-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(lbk3?_[a-z_0-9]+)\s*\(", text)))
 
 
 def test_header_and_binding_agree():

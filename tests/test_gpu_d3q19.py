@@ -1,0 +1,183 @@
+"""The D3Q19 sweep (through the C ABI) against the D3Q19 FP64 oracle: every
+boundary combination on heterogeneous media with free-fluid and impermeable
+nodes, the Brinkman channel, the uniform recurrence, mass, the slip
+correlations and Forchheimer term, reduced-precision storage, edge sizes,
+and windows of the 256^3 sphere medium the benchmark times."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle_window import window3_oracle
+from paper_1411_7051_amd import inputs
+from paper_1411_7051_amd.lattice3 import Lattice3
+
+pytestmark = pytest.mark.gpu
+
+VEL_TOL = {"f32": 1e-5, "f16": 2e-4, "bf16": 5e-3}
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    d = torch.device("cuda", 0)
+    torch.cuda.set_device(d)
+    return d
+
+
+def np3(lat):
+    return [t.double().cpu().numpy() for t in lat.macroscopic()]
+
+
+def rel_vel(g, r):
+    du = np.stack([g[1] - r[1], g[2] - r[2], g[3] - r[3]])
+    return np.linalg.norm(du) / np.linalg.norm(np.stack(r[1:]))
+
+
+def run_both(dev, case, steps, storage="f32"):
+    lat = Lattice3(case.eps, case.k, case.kn0, device=dev, storage=storage, **case.params)
+    lat.step(steps)
+    ref = oracle.Lattice3(case.eps, case.k, case.kn0, **case.params).step(steps)
+    return lat, ref
+
+
+def drive(bcx):
+    return (dict(rho_in=1.02, rho_out=1.0, init=1) if bcx == inputs.PRESSURE
+            else dict(gx=2e-5, gy=-1e-5, gz=5e-6))
+
+
+@pytest.mark.parametrize("bcx,bcy,bcz", [(x, y, z) for x in (0, 1, 2) for y in (0, 1)
+                                         for z in (0, 1)])
+def test_random_media(dev, bcx, bcy, bcz):
+    nx = 300 if (bcy, bcz) == (1, 1) else 37
+    case = inputs.random_medium3(nx, 9, 6, seed=700 + 4 * bcx + 2 * bcy + bcz, solid_frac=0.06,
+                                 pore_frac=0.06, bc_x=bcx, bc_y=bcy, bc_z=bcz, **drive(bcx))
+    lat, ref = run_both(dev, case, 120)
+    g, r = np3(lat), ref.macro()
+    assert rel_vel(g, r) <= VEL_TOL["f32"]
+    assert np.max(np.abs(g[0] - r[0])) < 1e-6
+    f = lat.populations().cpu().numpy()
+    fr = ref.state()
+    _, _, _, w = oracle.tables3()
+    scale = np.max(np.abs(fr - fr.sum(axis=0, keepdims=True) * w[:, None, None, None]))
+    # f_i = w_i rho + h_i rebuilt from an FP32 density: up to w_0 ulp(rho)/2
+    # per population (the rounding residual is carried by the h_i jointly)
+    quantum = (1.0 / 3.0) * np.max(fr.sum(axis=0)) * 2.0 ** -24
+    assert np.max(np.abs(f - fr)) <= 1e-4 * scale + 2 * quantum
+
+
+def test_brinkman_channel(dev):
+    case = inputs.channel3(4, 32, 3)
+    lat, ref = run_both(dev, case, 10000)
+    g, r = np3(lat), ref.macro()
+    assert rel_vel(g, r) <= VEL_TOL["f32"]
+    assert abs(lat.apparent_permeability() / ref.apparent_permeability() - 1) < 1e-5
+
+
+def test_uniform_recurrence(dev):
+    eps, k, kn0, tau = 0.4, 0.3, 0.5, 0.8
+    G = np.array([1e-5, -4e-6, 7e-6])
+    s = (3, 4, 70)
+    lat = Lattice3(np.full(s, eps, np.float32), np.full(s, k, np.float32),
+                   np.full(s, kn0, np.float32), device=dev, tau=tau, gx=G[0], gy=G[1], gz=G[2])
+    nu = (tau - 0.5) / 3
+    e32, k32, kn32 = (float(np.float32(v)) for v in (eps, k, kn0))
+    A = e32 * nu / (k32 * oracle.fc(kn32))
+    q, b = (1 - A / 2) / (1 + A / 2), e32 / (1 + A / 2)
+    u = 0.5 * b * G
+    for _ in range(30):
+        _, ux, uy, uz = np3(lat)
+        assert np.allclose([ux.mean(), uy.mean(), uz.mean()], u, rtol=2e-6)
+        lat.step(1)
+        u = q * u + b * G
+
+
+def test_mass_conservation(dev):
+    case = inputs.random_medium3(40, 12, 10, seed=720, solid_frac=0.1, pore_frac=0.1,
+                                 bc_y=1, bc_z=1, gx=1e-4, gy=2e-5, gz=-1e-5)
+    lat = Lattice3(case.eps, case.k, case.kn0, device=dev, **case.params)
+    m0, _ = lat.diagnostics()
+    lat.step(1000)
+    m1, _ = lat.diagnostics()
+    assert abs(m1 - m0) / m0 < 1e-8
+
+
+@pytest.mark.parametrize("extra", [dict(correlation=1), dict(correlation=2),
+                                   dict(kn_local=0, slip_b=-0.4), dict(f_eps=0.6)])
+def test_model_options(dev, extra):
+    bcx = 0 if "f_eps" in extra else 2
+    d = dict(gx=2e-4, gz=5e-5) if bcx == 0 else drive(2)
+    case = inputs.random_medium3(50, 8, 7, seed=730, solid_frac=0.05, pore_frac=0.05,
+                                 kn_range=(0.0, 3.0), bc_x=bcx, bc_y=1, **d, **extra)
+    lat, ref = run_both(dev, case, 150)
+    assert rel_vel(np3(lat), ref.macro()) <= VEL_TOL["f32"]
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_reduced_storage(dev, storage):
+    case = inputs.random_medium3(64, 16, 12, seed=740, solid_frac=0.05, pore_frac=0.05, bc_x=2,
+                                 bc_y=1, rho_in=1.01, rho_out=1.0, init=1)
+    lat, ref = run_both(dev, case, 300, storage)
+    assert rel_vel(np3(lat), ref.macro()) <= VEL_TOL[storage]
+
+
+@pytest.mark.parametrize("n,bc", [((1, 1, 1), (0, 0, 0)), ((3, 1, 1), (2, 0, 0)),
+                                  ((5, 1, 7), (0, 0, 1)), ((257, 2, 3), (1, 1, 0))])
+def test_edge_sizes(dev, n, bc):
+    nx, ny, nz = n
+    case = inputs.random_medium3(nx, ny, nz, seed=750 + nx, solid_frac=0.1, pore_frac=0.1,
+                                 bc_x=bc[0], bc_y=bc[1], bc_z=bc[2], **drive(bc[0]))
+    lat, ref = run_both(dev, case, 40)
+    g, r = np3(lat), ref.macro()
+    un = np.linalg.norm(np.stack(r[1:]))
+    if un > 0:
+        assert rel_vel(g, r) <= VEL_TOL["f32"]
+    else:
+        assert max(np.abs(a).max() for a in g[1:]) == 0
+
+
+def test_invalid_and_nonfinite(dev):
+    from paper_1411_7051_amd._lib import LbkError
+    s = (2, 3, 4)
+    ok = np.full(s, 0.5, np.float32)
+    bad = ok.copy()
+    bad[1, 2, 3] = 1.5
+    with pytest.raises(LbkError):
+        Lattice3(bad, ok, device=dev)
+    with pytest.raises(LbkError):
+        Lattice3(ok, ok, device=dev, bc_z=2)
+    with pytest.raises(LbkError):
+        Lattice3(ok, ok, device=dev, gx=float("nan"))
+    # a tau close to 1/2 with a strong force blows up; the check reports it
+    case = inputs.random_medium3(32, 8, 8, seed=760, eps_range=(0.9, 1.0), k_range=(1e3, 1e4),
+                                 tau=0.5000001, gx=0.5)
+    lat = Lattice3(case.eps, case.k, case.kn0, device=dev, check_every=50, **case.params)
+    with pytest.raises(LbkError) as e:
+        lat.step(5000)
+    assert e.value.status == -4
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_spheres256_windows(dev, storage):
+    """The 256^3 sphere medium of the benchmark: windows against the
+    windowed D3Q19 oracle after 16 steps."""
+    case = inputs.spheres(n=256, seed=7)
+    steps = 16
+    lat = Lattice3(case.eps, case.k, case.kn0, device=dev, storage=storage, **case.params)
+    lat.step(steps)
+    g = np3(lat)
+    lat.close()
+    w = 2 * (steps + 2) + 10
+    rng = np.random.default_rng(13)
+    for xa in (0, 256 - w, int(rng.integers(1, 256 - w - 1))):
+        ya, za = (int(v) for v in rng.integers(0, 256, 2))
+        (r_rho, rx, ry, rz), (kz, ky, kx), rows, planes = window3_oracle(
+            case, xa, xa + w, ya, w, za, w, steps)
+        sel = lambda a: a[planes][:, rows][:, :, xa:xa + w][kz, ky, kx]
+        gw = [sel(a) for a in g]
+        rw = [r_rho[kz, ky, kx], rx[kz, ky, kx], ry[kz, ky, kx], rz[kz, ky, kx]]
+        assert gw[1].size > 0
+        assert rel_vel(gw, rw) <= VEL_TOL[storage], (xa, ya, za)

@@ -30,3 +30,18 @@ def test_window_margin_is_needed():
     g = full.macro()[1][rows][:, 100:154]
     m = steps  # nodes steps links from the cut: reachable from the edge
     assert not np.array_equal(g[m:54 - m, m:54 - m], r_ux[m:54 - m, m:54 - m])
+
+
+def test_window3_matches_full_oracle():
+    from oracle_window import window3_oracle
+    case = inputs.spheres(n=32, seed=7)
+    steps = 5
+    full = oracle.Lattice3(case.eps, case.k, case.kn0, **case.params).step(steps)
+    g = full.macro()
+    for xa, xb, ya, za in [(0, 20, 3, 30), (12, 32, 28, 5), (6, 26, 10, 10)]:
+        (wr, wx, wy, wz), (kz, ky, kx), rows, planes = window3_oracle(
+            case, xa, xb, ya, 20, za, 20, steps)
+        for a, b in zip(g, (wr, wx, wy, wz)):
+            sel = a[planes][:, rows][:, :, xa:xb][kz, ky, kx]
+            assert sel.size > 0
+            assert np.array_equal(sel, b[kz, ky, kx])
