@@ -287,6 +287,47 @@ def time_ensemble(n_samples, steps, storages, graph_steps, device, launch=None, 
     return out
 
 
+ALG_BYTES3 = {"f32": 164, "f16": 88, "bf16": 88}   # 19 populations in + out, 3 fields
+LAYOUT_BYTES3 = {"f32": 172, "f16": 96, "bf16": 96}
+
+
+def time_d3q19(n, steps, warmup, storages, device):
+    """D3Q19 sweep on the n^3 sphere medium (the disc medium of Sec. IV.B in
+    three dimensions), per storage type."""
+    import torch
+    from paper_1411_7051_amd import inputs
+    from paper_1411_7051_amd.lattice3 import Lattice3
+
+    t = time.perf_counter()
+    case = inputs.spheres(n=n, seed=7)
+    log(f"spheres{n} inputs: {case.nodes} nodes in {time.perf_counter() - t:.1f} s")
+    runs = {}
+    for st in storages:
+        lat = Lattice3(case.eps, case.k, case.kn0, device=device, storage=st, **case.params)
+        lat.step(warmup)
+        torch.cuda.synchronize(device)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(lat.stream)
+        lat.step(steps)
+        e1.record(lat.stream)
+        torch.cuda.synchronize(device)
+        ms = e0.elapsed_time(e1)
+        mlups = case.nodes * steps / (ms * 1e-3) / 1e6
+        runs[st] = {"ms_per_step": ms / steps, "mlups": mlups,
+                    "alg_GBps": mlups * ALG_BYTES3[st] / 1e3,
+                    "alg_frac": mlups * ALG_BYTES3[st] / 1e3 / HBM_PEAK_GBS,
+                    "layout_GBps": mlups * LAYOUT_BYTES3[st] / 1e3,
+                    "k_app_after": lat.apparent_permeability()}
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    return {"workload": f"spheres{n}: {n}^3 two-component medium, 96 seeded spheres "
+                        "(r 8-40 scaled, eps 0.2, k 1e-4) in a matrix (eps 0.5, k 1e-2), local "
+                        "Kn base 0.05, pressure-driven x (1.01/1.0), periodic y and z, tau 0.8",
+            "nodes": case.nodes, "steps": steps, "bytes_per_node": ALG_BYTES3,
+            "storage_runs": runs}
+
+
 def kn_sweep(device, kns=(0.001, 0.01, 0.1, 1.0, 5.0)):
     """Porous-filled plates at 1024 x 512 (eps 0.5, k 1.024, tau 0.8),
     pressure-driven 1.01 / 1.0, local Kn, each base Kn run to steady state:
@@ -349,6 +390,10 @@ def main():
     ap.add_argument("--ensemble-grad-ckpt", type=int, default=500)
     ap.add_argument("--no-kn-sweep", action="store_true",
                     help="skip the Klinkenberg channel sweep")
+    ap.add_argument("--d3q19-n", type=int, default=256, help="side of the D3Q19 sphere medium")
+    ap.add_argument("--d3q19-steps", type=int, default=300)
+    ap.add_argument("--d3q19-storages", default="f32,f16")
+    ap.add_argument("--no-d3q19", action="store_true", help="skip the D3Q19 leg")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run 10 device-to-device copies of MIB MiB (a plain copy "
                          "kernel of known traffic, to scale HBM byte counters) and exit")
@@ -429,6 +474,12 @@ def main():
         if ens["gradient"]:
             log(f"ensemble gradient: (t_fwd + t_grad)/t_fwd = "
                 f"{ens['gradient']['total_over_fwd']:.2f} (history {ens['gradient']['hist_len']})")
+    d3 = None
+    if not args.no_d3q19:
+        d3 = time_d3q19(args.d3q19_n, args.d3q19_steps, 20, args.d3q19_storages.split(","), dev)
+        for sname, r in d3["storage_runs"].items():
+            log(f"d3q19 {sname}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.4f} ms/step, "
+                f"{r['alg_GBps']:.0f} GB/s algorithmic")
     kn = None
     if not args.no_kn_sweep:
         kn = kn_sweep(dev)
@@ -465,6 +516,7 @@ def main():
         "adjoint": adj,
         "ensemble": ens,
         "klinkenberg_channel": kn,
+        "d3q19": d3,
     }
     print(json.dumps(out), flush=True)
 
