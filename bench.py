@@ -392,7 +392,7 @@ def main():
                     help="skip the Klinkenberg channel sweep")
     ap.add_argument("--d3q19-n", type=int, default=256, help="side of the D3Q19 sphere medium")
     ap.add_argument("--d3q19-steps", type=int, default=300)
-    ap.add_argument("--d3q19-storages", default="f32,f16")
+    ap.add_argument("--d3q19-storages", default="f32,f16,bf16")
     ap.add_argument("--no-d3q19", action="store_true", help="skip the D3Q19 leg")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run 10 device-to-device copies of MIB MiB (a plain copy "

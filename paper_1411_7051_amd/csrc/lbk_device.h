@@ -66,7 +66,9 @@ typedef __amdgpu_buffer_rsrc_t Rsrc;
 constexpr int kRsrcWord3 = 0x00020000;
 // Cache policy of the population streams: nontemporal.  Each stored
 // population is read once and written once per step; the density and the
-// medium, whose neighbour reads reuse, keep the default policy.
+// medium, whose neighbour reads reuse, keep the default policy.  Population
+// loads take the policy as a template argument (a sweep whose density
+// reuse spans more rows than stay cached passes the default policy).
 constexpr int kNT = 2;
 
 __device__ __forceinline__ Rsrc make_rsrc(const void *base, uint32_t bytes)
@@ -95,9 +97,10 @@ __device__ __forceinline__ void st_f32(Rsrc r, uint32_t voff, uint32_t soff, flo
 template <typename T> struct Elem;
 template <> struct Elem<float> {
     static constexpr bool kScaled = false;
+    template <int AUX = kNT>
     static __device__ __forceinline__ float ld(Rsrc r, uint32_t voff, uint32_t soff)
     {
-        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, kNT));
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, AUX));
     }
     static __device__ __forceinline__ void st(Rsrc r, uint32_t voff, uint32_t soff, float v)
     {
@@ -106,9 +109,10 @@ template <> struct Elem<float> {
 };
 template <> struct Elem<__half> {
     static constexpr bool kScaled = true;
+    template <int AUX = kNT>
     static __device__ __forceinline__ float ld(Rsrc r, uint32_t voff, uint32_t soff)
     {
-        const uint16_t u = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, kNT);
+        const uint16_t u = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, AUX);
         return __half2float(__ushort_as_half(u));
     }
     static __device__ __forceinline__ void st(Rsrc r, uint32_t voff, uint32_t soff, float v)
@@ -119,9 +123,10 @@ template <> struct Elem<__half> {
 };
 template <> struct Elem<__hip_bfloat16> {
     static constexpr bool kScaled = false;
+    template <int AUX = kNT>
     static __device__ __forceinline__ float ld(Rsrc r, uint32_t voff, uint32_t soff)
     {
-        const uint16_t u = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, kNT);
+        const uint16_t u = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, AUX);
         return __uint_as_float((uint32_t)u << 16);
     }
     static __device__ __forceinline__ void st(Rsrc r, uint32_t voff, uint32_t soff, float v)
