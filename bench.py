@@ -100,6 +100,31 @@ def time_storage(case, storage, steps, warmup, device):
     }
 
 
+def copy_bandwidth(device, mib=1024, reps=20):
+    """Device-to-device copy rate (bytes read + written per second) of a
+    plain 1 GiB copy on the same GPU: what this part's HBM delivers to a
+    simple stream, as context for the roofline fraction."""
+    import torch
+
+    n = mib << 20
+    a = torch.ones(n, dtype=torch.uint8, device=device)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    stream = torch.cuda.current_stream(device)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(reps):
+        b.copy_(a)
+    t1.record(stream)
+    torch.cuda.synchronize(device)
+    ms = t0.elapsed_time(t1)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * n * reps / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(case, target_s=15.0):
     """The FP64 oracle, single-threaded, on a 384 x 384 window of the same
     medium (same fields and boundary conditions), as many steps as fit in
@@ -451,7 +476,9 @@ def main():
         "kernel": f"sweep_kernel<{st}> (pressure x, periodic y)",
         "bytes_per_node": ALG_BYTES[st],
         "layout_bytes_per_node": LAYOUT_BYTES[st],
+        "copy_GBps": copy_bandwidth(dev),
     }
+    log(f"plain 1 GiB device copy: {roof['copy_GBps']:.0f} GB/s (read + write)")
     adj = None
     if not args.no_adjoint:
         adj = time_adjoint(args.adjoint_n, args.adjoint_steps, args.adjoint_ckpt,
