@@ -67,15 +67,16 @@ __device__ __forceinline__ NodeFwd node_fwd(const Physics &ph, float rho, float 
     n.jy = jy;
     n.eps = eps;
     n.solid = !(eps > 0.0f);
-    n.ie = n.solid ? 0.0f : 1.0f / eps;
-    n.rinv = 1.0f / rho;
+    // hardware reciprocals, as in the sweep's velocity solve
+    n.ie = n.solid ? 0.0f : __builtin_amdgcn_rcpf(eps);
+    n.rinv = __builtin_amdgcn_rcpf(rho);
     const float kn = ph.kn_local ? kn0 * (ph.rho_ref * n.rinv) : kn0;
     float num, den; // f_c = den / num, as in the sweep
     fc_parts(ph, kn, num, den);
     const float dn = drag * num;
-    const float R2 = 2.0f / (2.0f * den + dn);
-    n.g = den * R2;     // 1 / (1 + A/2)
-    n.A = dn / den;     // drag / f_c
+    const float R2 = 2.0f * __builtin_amdgcn_rcpf(2.0f * den + dn);
+    n.g = den * R2;                          // 1 / (1 + A/2)
+    n.A = dn * __builtin_amdgcn_rcpf(den);   // drag / f_c
     const float vx = jx * n.rinv + 0.5f * eps * ph.gx;
     const float vy = jy * n.rinv + 0.5f * eps * ph.gy;
     n.ux = n.solid ? 0.0f : n.g * vx;
@@ -84,21 +85,22 @@ __device__ __forceinline__ NodeFwd node_fwd(const Physics &ph, float rho, float 
     n.Fy = n.solid ? -2.0f * jy * n.rinv : eps * ph.gy - n.A * n.uy;
     // Kn ~ kn0: dA/d ln kn0 = -A Kn f_c'(Kn) / f_c; with the local Kn ~ 1/rho
     // also dA/drho = -(dA/d ln kn0) / rho.  For Eqs. 6-7, f_c = P1 P2 with
-    // P1 = 1 + alpha Kn = (a + 1.358 t Kn)/a, P2 = (1 + (4 - b) Kn)/(1 - b Kn):
-    // P1' = 1.358 t (t + 1.4348 * 0.170)/a^2, P2' = 4/(1 - b Kn)^2.  For
-    // Eqs. 4-5, Kn f_c'/f_c = 4 Kn / (1 + 4 Kn).
+    // P1 = 1 + alpha Kn = p1/a, p1 = a + 1.358 t Kn, and P2 = p2/q,
+    // p2 = 1 + (4 - b) Kn, q = 1 - b Kn: P1' = 1.358 t (t + 1.4348 * 0.170)/a^2
+    // and P2' = 4/q^2, so f_c'/f_c = P1'/P1 + P2'/P2
+    // = 1.358 t (t + 0.243916)/(a p1) + 4/(q p2).  For Eqs. 4-5,
+    // Kn f_c'/f_c = 4 Kn / (1 + 4 Kn).
     float dAk = 0.0f;
     if (kn > 0.0f && ph.corr == CORR_BKC) {
         const float t = __builtin_amdgcn_exp2f(0.4348f * __builtin_amdgcn_logf(kn));
         const float a = t + 0.170f;
         const float q = 1.0f + ph.slip_nb * kn;
-        const float P1 = (a + 1.358f * t * kn) / a, P2 = (1.0f + ph.slip_c * kn) / q;
-        const float P1d = 1.358f * t * (t + 0.243916f) / (a * a);
-        const float P2d = 4.0f / (q * q);
-        const float fc = P1 * P2;
-        dAk = -n.A * kn * (P1d * P2 + P1 * P2d) / fc;
+        const float p1 = a + 1.358f * t * kn, p2 = 1.0f + ph.slip_c * kn;
+        const float l1 = 1.358f * t * (t + 0.243916f) * __builtin_amdgcn_rcpf(a * p1);
+        const float l2 = 4.0f * __builtin_amdgcn_rcpf(q * p2);
+        dAk = -n.A * kn * (l1 + l2);
     } else if (kn > 0.0f && ph.corr == CORR_KLINKENBERG) {
-        dAk = -n.A * 4.0f * kn / (1.0f + 4.0f * kn);
+        dAk = -n.A * 4.0f * kn * __builtin_amdgcn_rcpf(1.0f + 4.0f * kn);
     }
     n.dA_dlnkn = dAk;
     n.dA_drho = ph.kn_local ? -dAk * n.rinv : 0.0f;
@@ -217,7 +219,7 @@ __device__ __forceinline__ float2 nee_adj(const NodeFwd &n, float rho_b, float e
     // Phi(rho, eps) = sum_i lb_i f_eq_i = rho [M0 + 3 M1.u + 4.5/eps u.M2.u
     //                 - 1.5/eps |u|^2 M0]; for eps = 0 it is rho M0.
     const bool sb = !(eps_b > 0.0f);
-    const float ieb = sb ? 0.0f : 1.0f / eps_b, ien = n.ie;
+    const float ieb = sb ? 0.0f : __builtin_amdgcn_rcpf(eps_b), ien = n.ie;
     const float dbx = sb ? 0.0f : rho_b * (3.0f * M.m1x + 9.0f * ieb * M2ux - 3.0f * ieb * M.m0 * ux);
     const float dby = sb ? 0.0f : rho_b * (3.0f * M.m1y + 9.0f * ieb * M2uy - 3.0f * ieb * M.m0 * uy);
     const float dnx = n.solid ? 0.0f : n.rho * (3.0f * M.m1x + 9.0f * ien * M2ux - 3.0f * ien * M.m0 * ux);

@@ -76,6 +76,28 @@ def test_too_large_rejected():
     assert e.value.status == -5
 
 
+def test_size_limit_is_exact():
+    """2^30 padded nodes is the largest lattice: 32768 x 32768 (and any nx
+    whose pitch is 32768) is accepted, one more row is not; FP32 needs
+    about 108 GB of workspace there."""
+    n = workspace_bytes(make_desc(32768, 32768))
+    assert 100e9 < n < 112e9
+    workspace_bytes(make_desc(32705, 32768))  # pitch 32768
+    for nx, ny in [(32768, 32769), (32769, 32768)]:
+        with pytest.raises(_lib.LbkError) as e:
+            workspace_bytes(make_desc(nx, ny))
+        assert e.value.status == -5
+
+
+def test_size_limit_3d():
+    from paper_1411_7051_amd.lattice3 import make_desc3, workspace_bytes3
+    workspace_bytes3(make_desc3(1024, 1024, 1024))  # 2^30 nodes
+    for n in [(1024, 1024, 1025), (64, 4096, 4097)]:
+        with pytest.raises(_lib.LbkError) as e:
+            workspace_bytes3(make_desc3(*n))
+        assert e.value.status == -5
+
+
 def test_null_arguments_rejected():
     lib = _lib.load()
     assert lib.lbk_step(None, 1) == -1

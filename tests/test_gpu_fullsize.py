@@ -71,6 +71,38 @@ def test_discs4096_windows(dev, storage):
         compare_window(g, case, xa, xb, int(rng.integers(0, 4096)), w, steps, storage)
 
 
+def test_largest_lattice_windows(dev):
+    """The largest lattice the library accepts, 32768 x 32768 = 2^30 nodes
+    (FP32: 108 GB of workspace, byte offsets far beyond 2^32): the
+    4096 x 4096 disc medium tiled 8 x 8, against the windowed oracle at
+    the inlet, at the outlet across the last rows, and in the interior
+    wrapping from the last rows to the first."""
+    base = inputs.discs(n=4096, seed=2)
+    tile = lambda a: np.tile(a, (8, 8))
+    case = inputs.Case(tile(base.eps), tile(base.k), tile(base.kn0), dict(base.params))
+    del base
+    n, steps = 32768, 12
+    assert case.eps.shape == (n, n)
+    lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+    lat.step(steps)
+    macro = lat.macroscopic()
+    w = 2 * (steps + 2) + 40
+    for xa, ya in [(0, 5), (n - w, n - w // 2), (n // 2 + 1234, n - 7)]:
+        (r_rho, r_ux, r_uy), (vx, vy), rows = window_oracle(case, xa, xa + w, ya, w, steps)
+        idx = torch.as_tensor(rows, device=dev)
+        g = [t.index_select(0, idx)[:, xa:xa + w].double().cpu().numpy()[vy, vx]
+             for t in macro]
+        rx, ry = r_ux[vy, vx], r_uy[vy, vx]
+        assert g[1].size > 0
+        err = np.linalg.norm(np.stack([g[1] - rx, g[2] - ry])) / np.linalg.norm(np.stack([rx, ry]))
+        assert err <= VEL_TOL["f32"], (xa, ya, err)
+        assert np.max(np.abs(g[0] - r_rho[vy, vx])) < 1e-5
+    del macro
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+
+
 def test_shale8192_windows(dev, shale8192):
     """Fractured shale at 8192 x 8192 (the gradient workload), windows centred
     on fracture nodes and at both pressure ends."""
