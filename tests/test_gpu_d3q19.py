@@ -181,3 +181,34 @@ def test_spheres256_windows(dev, storage):
         rw = [r_rho[kz, ky, kx], rx[kz, ky, kx], ry[kz, ky, kx], rz[kz, ky, kx]]
         assert gw[1].size > 0
         assert rel_vel(gw, rw) <= VEL_TOL[storage], (xa, ya, za)
+
+
+def test_largest_lattice3_windows(dev):
+    """The largest D3Q19 lattice the library accepts, 1024^3 = 2^30 nodes
+    (FP32: about 186 GB of workspace): the 256^3 sphere medium tiled
+    4 x 4 x 4, against the windowed oracle at the inlet and at the outlet
+    across the wrap of the last rows and planes."""
+    base = inputs.spheres(n=256, seed=7)
+    tile = lambda a: np.tile(a, (4, 4, 4))
+    case = inputs.Case(tile(base.eps), tile(base.k), tile(base.kn0), dict(base.params))
+    del base
+    n, steps = 1024, 8
+    assert case.eps.shape == (n, n, n)
+    torch.cuda.empty_cache()
+    lat = Lattice3(case.eps, case.k, case.kn0, device=dev, **case.params)
+    lat.step(steps)
+    macro = lat.macroscopic()
+    w = 2 * (steps + 2) + 10
+    for xa, ya, za in [(0, 3, 500), (n - w, n - 9, n - 5)]:
+        r, (kz, ky, kx), rows, planes = window3_oracle(case, xa, xa + w, ya, w, za, w, steps)
+        pi = torch.as_tensor(planes, device=dev)
+        ri = torch.as_tensor(rows, device=dev)
+        g = [t.index_select(0, pi).index_select(1, ri)[:, :, xa:xa + w].double().cpu().numpy()
+             [kz, ky, kx] for t in macro]
+        rw = [a[kz, ky, kx] for a in r]
+        assert g[1].size > 0
+        assert rel_vel(g, rw) <= VEL_TOL["f32"], (xa, ya, za)
+    del macro
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
