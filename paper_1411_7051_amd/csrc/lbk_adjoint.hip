@@ -352,7 +352,11 @@ __device__ __forceinline__ void adjoint_node(const float *mu_in, float *mu_out, 
         add_grad(x, gl, gk);
     }
 
-    // push: mu_out[i](x - e_i) = lf_i, bounce-back at walls
+    // push: mu_out[i](x - e_i) = lf_i, bounce-back at walls.  The pushed
+    // stores keep the default cache policy: a wave's shifted store covers
+    // parts of two cache lines whose other parts the neighbouring wave
+    // writes, and L2 merges them (3% less gradient time than streaming
+    // stores on the 8192^2 shale)
     uint32_t xm = x - 1, xp = x + 1;
     bool wxm = false, wxp = false;
     if (BCX == BC_PERIODIC) {
@@ -376,14 +380,14 @@ __device__ __forceinline__ void adjoint_node(const float *mu_in, float *mu_out, 
             if (out_x)
                 continue; // source outside the lattice
             if (wall_y)
-                st_f32(orow[1], x * 4, opp_of(i) * slot, lf[i], true);
+                st_f32(orow[1], x * 4, opp_of(i) * slot, lf[i], false);
             else
-                st_f32(orow[ry], tx * 4, i * slot, lf[i], true);
+                st_f32(orow[ry], tx * 4, i * slot, lf[i], false);
         } else {
             if (wall_y || out_x)
-                st_f32(orow[1], x * 4, opp_of(i) * slot, lf[i], true);
+                st_f32(orow[1], x * 4, opp_of(i) * slot, lf[i], false);
             else
-                st_f32(orow[ry], tx * 4, i * slot, lf[i], true);
+                st_f32(orow[ry], tx * 4, i * slot, lf[i], false);
         }
     }
     if (BCX == BC_PRESSURE && bnode) {
@@ -392,7 +396,7 @@ __device__ __forceinline__ void adjoint_node(const float *mu_in, float *mu_out, 
         for (int i = 1; i < 9; ++i) {
             const int ex = ex_of(i);
             if ((x == 0 && ex == -1) || (x == nx - 1 && ex == 1))
-                st_f32(orow[1], x * 4, i * slot, 0.0f, true);
+                st_f32(orow[1], x * 4, i * slot, 0.0f, false);
         }
     }
 }
