@@ -171,11 +171,12 @@ def time_adjoint(n, steps, ckpt, hist, device):
     lat = Lattice(case.eps, case.k, case.kn0, device=device, **case.params)
     st = lat.stream
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    planned = 0
     if hist == "auto":
-        hist = lat.adjoint_plan(steps, ckpt)
+        hist, planned = lat.adjoint_plan(steps, ckpt, with_bytes=True)
     hist = int(hist)
-    ws = torch.empty(lat.adjoint_workspace_bytes(steps, ckpt, hist), dtype=torch.uint8,
-                     device=device)
+    ws = torch.empty(max(planned, lat.adjoint_workspace_bytes(steps, ckpt, hist)),
+                     dtype=torch.uint8, device=device)
     lat.step(20)
     torch.cuda.synchronize(device)
     ev[0].record(st)

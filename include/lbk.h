@@ -161,15 +161,20 @@ lbk_status lbk_load_state(lbk_lattice *lat, const void *src);
  * along the forward trajectory, which is recomputed from checkpoints:
  *   - lbk_adjoint_forward runs the n steps (advancing the lattice exactly
  *     as lbk_step would) and stores the state every ckpt_every steps;
- *   - lbk_adjoint_backward recomputes each checkpoint segment (keeping
- *     inner checkpoints every hist_len steps when hist_len < ckpt_every;
- *     the forward pass already keeps those of the last segment), records
+ *   - lbk_adjoint_backward recomputes each checkpoint segment (from inner
+ *     checkpoints every hist_len steps when hist_len < ckpt_every), records
  *     the per-step linearisation point (rho, j: 12 B per node and step,
  *     hist_len steps at a time) and runs the reverse steps.
+ * With hist_len < ckpt_every the forward pass also keeps the inner
+ * checkpoints of the last segments, as many as the workspace holds (at
+ * least the last one; each further segment takes ceil(ckpt_every /
+ * hist_len) state levels beyond lbk_adjoint_workspace_size); the backward
+ * pass rebuilds those of the other segments.
  * Cost of the backward pass per step: one recording sweep and one reverse
  * sweep, plus (two-level) about (1 - hist_len/ckpt_every) of a plain sweep
- * to rebuild inner checkpoints in every segment but the last;
- * lbk_adjoint_plan picks the longest history that fits a memory budget.
+ * in every segment whose inner checkpoints were not kept;
+ * lbk_adjoint_plan picks the plan that rebuilds least within a memory
+ * budget.
  * The Forchheimer term is not differentiated (f_eps must be 0).
  * --------------------------------------------------------------------- */
 typedef enum lbk_objective {
@@ -184,16 +189,20 @@ typedef enum lbk_objective {
 lbk_status lbk_adjoint_workspace_size(const lbk_lattice *lat, int64_t n_steps,
                                       int64_t ckpt_every, int64_t hist_len, size_t *bytes);
 
-/* The longest history length (hist_len, at most ckpt_every) whose
- * workspace for a gradient over n_steps with checkpoints every ckpt_every
- * steps fits in budget_bytes; *bytes (may be NULL) gets that workspace
- * size.  LBK_ERR_OOM if none fits.  Host-only, no device work. */
+/* The checkpoint plan for a gradient over n_steps with checkpoints every
+ * ckpt_every steps that fits in budget_bytes and spends the fewest plain
+ * sweeps rebuilding inner checkpoints (among equals, the longest history):
+ * *hist_len (at most ckpt_every) and, in *bytes (may be NULL), the
+ * workspace to pass to lbk_adjoint_forward, which includes the kept inner
+ * checkpoints of as many segments as fit.  LBK_ERR_OOM if none fits.
+ * Host-only, no device work. */
 lbk_status lbk_adjoint_plan(const lbk_lattice *lat, int64_t n_steps, int64_t ckpt_every,
                             size_t budget_bytes, int64_t *hist_len, size_t *bytes);
 
 /* Run n_steps forward from the current state, storing checkpoints in the
  * caller's device workspace (256-byte aligned, ws_bytes >=
- * lbk_adjoint_workspace_size), and return J (host double; synchronizes).
+ * lbk_adjoint_workspace_size; a larger workspace keeps inner checkpoints
+ * of more segments), and return J (host double; synchronizes).
  * The lattice ends at t + n_steps.  The FP16 scale is held fixed and
  * check_every is not applied during these steps. */
 lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64_t n_steps,

@@ -532,7 +532,6 @@ lbk_status lbk::adj_plan(const lbk_lattice *lat, int64_t n, int64_t c1, int64_t 
         return at;
     };
     P.outer = take(P.level_bytes * (size_t)P.k1);
-    P.inner = take(P.level_bytes * (size_t)P.k2);
     P.rec = take(2 * P.level_bytes);
     P.hist = take(P.hist_bytes * (size_t)(P.hlen + 1));
     P.lam = take(2 * P.lam_bytes);
@@ -540,8 +539,32 @@ lbk_status lbk::adj_plan(const lbk_lattice *lat, int64_t n, int64_t c1, int64_t 
     P.seg = take((size_t)rows * lat->L.pitch * 4);
     P.grad2 = take((size_t)rows * lat->L.pitch * 8);
     P.seg2 = take((size_t)rows * lat->L.pitch * 4);
+    P.inner_seg = P.level_bytes * (size_t)P.k2;
+    P.inner = take(P.inner_seg);
+    P.keep = P.two_level ? 1 : 0;
     P.total = o;
     return LBK_OK;
+}
+
+void lbk::adj_keep(AdjPlan &P, size_t ws_bytes)
+{
+    if (!P.two_level || ws_bytes < P.total)
+        return;
+    const size_t extra = (ws_bytes - P.total) / P.inner_seg;
+    P.keep = std::min<int64_t>(P.k1, 1 + (int64_t)std::min<size_t>(extra, (size_t)P.k1));
+    P.total += (size_t)(P.keep - 1) * P.inner_seg;
+}
+
+int64_t lbk::adj_rebuild_steps(const AdjPlan &P)
+{
+    if (!P.two_level)
+        return 0;
+    int64_t steps = 0;
+    for (int64_t k = 0; k < P.k1 - P.keep; ++k) {
+        const int64_t len = std::min(P.c1, P.n - k * P.c1);
+        steps += ((len + P.c2 - 1) / P.c2 - 1) * P.c2; // sweep to the last inner start
+    }
+    return steps;
 }
 
 double lbk::objective_weights(const lbk_lattice *lat, int objective, const double *sums,
@@ -602,8 +625,10 @@ extern "C" lbk_status lbk_adjoint_plan(const lbk_lattice *lat, int64_t n_steps,
     if (n_steps < 1 || ckpt_every < 1)
         return fail(LBK_ERR_INVALID_ARG, "need n_steps >= 1 and ckpt_every >= 1");
     const int64_t c1 = std::min(ckpt_every, n_steps);
-    // longest history first: fewest recomputed sweeps per reversed step
-    int64_t prev = -1;
+    // fewest sweeps spent rebuilding inner checkpoints; among equals, the
+    // longest history (fewest segments)
+    int64_t prev = -1, best_h = -1, best_cost = -1;
+    size_t best_bytes = 0;
     for (int64_t m = 1; m <= c1; ++m) {
         const int64_t h = (c1 + m - 1) / m;
         if (h == prev)
@@ -613,15 +638,25 @@ extern "C" lbk_status lbk_adjoint_plan(const lbk_lattice *lat, int64_t n_steps,
         lbk_status s = adj_plan(lat, n_steps, c1, h, P);
         if (s != LBK_OK)
             return s;
-        if (P.total <= budget_bytes) {
-            *hist_len = h;
-            if (bytes)
-                *bytes = P.total;
-            return LBK_OK;
+        if (P.total > budget_bytes)
+            continue;
+        adj_keep(P, budget_bytes);
+        const int64_t cost = adj_rebuild_steps(P);
+        if (best_h < 0 || cost < best_cost) {
+            best_h = h;
+            best_cost = cost;
+            best_bytes = P.total;
         }
+        if (cost == 0)
+            break;
     }
-    return fail(LBK_ERR_OOM, "no checkpoint plan for %lld steps every %lld fits in %zu bytes",
-                (long long)n_steps, (long long)c1, budget_bytes);
+    if (best_h < 0)
+        return fail(LBK_ERR_OOM, "no checkpoint plan for %lld steps every %lld fits in %zu bytes",
+                    (long long)n_steps, (long long)c1, budget_bytes);
+    *hist_len = best_h;
+    if (bytes)
+        *bytes = best_bytes;
+    return LBK_OK;
 }
 
 extern "C" lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64_t n_steps,
@@ -643,6 +678,7 @@ extern "C" lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64
     if (ws_bytes < P.total)
         return fail(LBK_ERR_OOM, "adjoint workspace of %zu bytes < %zu needed", ws_bytes,
                     P.total);
+    adj_keep(P, ws_bytes);
     lat->adj.valid = false;
     char *w = static_cast<char *>(ws);
     hipStream_t st = lat->stream;
@@ -651,12 +687,14 @@ extern "C" lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64
         HIP_TRY(hipMemcpyAsync(w + P.outer + (size_t)k * P.level_bytes, lat->state(lat->cur),
                                P.level_bytes, hipMemcpyDeviceToDevice, st));
         const int64_t steps = std::min(P.c1, P.n - k * P.c1);
-        // the last segment is reversed first: keep its inner checkpoints now
-        // rather than recomputing them in the backward pass
-        const bool keep_inner = P.two_level && k == P.k1 - 1;
+        // the last `keep` segments are reversed first: keep their inner
+        // checkpoints now rather than recomputing them in the backward pass
+        const int64_t kept = k - (P.k1 - P.keep);
+        const bool keep_inner = P.two_level && kept >= 0;
         for (int64_t i = 0; i < steps; ++i) {
             if (keep_inner && i % P.c2 == 0)
-                HIP_TRY(hipMemcpyAsync(w + P.inner + (size_t)(i / P.c2) * P.level_bytes,
+                HIP_TRY(hipMemcpyAsync(w + P.inner + (size_t)kept * P.inner_seg +
+                                           (size_t)(i / P.c2) * P.level_bytes,
                                        lat->state(lat->cur), P.level_bytes,
                                        hipMemcpyDeviceToDevice, st));
             const int nxt = lat->cur ^ 1;
@@ -722,21 +760,26 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
     for (int64_t k = P.k1 - 1; k >= 0; --k) {
         const int64_t a = k * P.c1, b = std::min(P.n, a + P.c1);
         int64_t nseg = 1;
-        if (P.two_level && k == P.k1 - 1) {
-            nseg = (b - a + P.c2 - 1) / P.c2; // inner checkpoints kept by the forward pass
+        // inner checkpoints of this segment: kept by the forward pass, or
+        // rebuilt into the first kept segment's slots (free by now, since
+        // the kept segments are the last ones and reversed first)
+        const int64_t kept = k - (P.k1 - P.keep);
+        const size_t inner = P.inner + (size_t)(kept > 0 ? kept : 0) * P.inner_seg;
+        if (P.two_level && kept >= 0) {
+            nseg = (b - a + P.c2 - 1) / P.c2;
         } else if (P.two_level) {
             // rebuild the inner checkpoints of this outer segment
             const char *src = level(P.outer, k);
             int r = 0;
             nseg = 0;
             for (int64_t t = a; t < b; t += P.c2, ++nseg) {
-                HIP_TRY(hipMemcpyAsync(level(P.inner, nseg), src, P.level_bytes,
+                HIP_TRY(hipMemcpyAsync(level(inner, nseg), src, P.level_bytes,
                                        hipMemcpyDeviceToDevice, st));
                 const int64_t steps = std::min(P.c2, b - t);
                 if (t + steps >= b)
                     break; // the last inner segment needs no further state
                 for (int64_t i = 0; i < steps; ++i) {
-                    HIP_TRY(sweep(i == 0 ? level(P.inner, nseg) : rec[r], rec[r ^ 1], nullptr));
+                    HIP_TRY(sweep(i == 0 ? level(inner, nseg) : rec[r], rec[r ^ 1], nullptr));
                     r ^= 1;
                 }
                 src = rec[r];
@@ -746,7 +789,7 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
         for (int64_t j = nseg - 1; j >= 0; --j) {
             const int64_t a2s = P.two_level ? a + j * P.c2 : a;
             const int64_t b2s = P.two_level ? std::min(b, a2s + P.c2) : b;
-            const char *src = P.two_level ? level(P.inner, j) : level(P.outer, k);
+            const char *src = P.two_level ? level(inner, j) : level(P.outer, k);
             // recompute the segment, recording each step's linearisation point
             int r = 0;
             for (int64_t t = a2s; t < b2s; ++t) {

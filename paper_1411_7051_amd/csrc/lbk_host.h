@@ -50,7 +50,9 @@ struct AdjPlan {
     int64_t n, c1, c2, t0;
     bool two_level;
     int64_t k1, k2, hlen;
+    int64_t keep; // trailing outer segments whose inner checkpoints the forward keeps
     size_t outer, inner, rec, hist, lam, grad, seg, grad2, seg2, total;
+    size_t inner_seg; // bytes of one segment's inner checkpoints (k2 levels)
     size_t level_bytes, hist_bytes, lam_bytes;
     const void *ws;
     double a1, a2;
@@ -62,8 +64,14 @@ struct AdjPlan {
 double k_app_of(const lbk_lattice *lat, const double *sums);
 
 // Workspace offsets of a gradient over n steps, checkpoints every c1,
-// history c2 at a time (1 <= c2 <= c1).
+// history c2 at a time (1 <= c2 <= c1).  The inner checkpoints come last:
+// the minimum (total) holds those of one segment; with ws_bytes >= total,
+// adj_keep sets how many trailing segments' inner checkpoints fit (keep)
+// and the bytes they use.
 lbk_status adj_plan(const lbk_lattice *lat, int64_t n, int64_t c1, int64_t c2, AdjPlan &P);
+void adj_keep(AdjPlan &P, size_t ws_bytes);
+// Plain sweeps the backward pass spends rebuilding inner checkpoints.
+int64_t adj_rebuild_steps(const AdjPlan &P);
 
 // Gradients need f_eps = 0 and a drive the objective can be normalised by.
 lbk_status check_objective(const lbk_lattice *lat, int objective);
@@ -120,8 +128,14 @@ lbk_status macro_sums(lbk_lattice *lat, bool residual);
 double k_app_of(const lbk_lattice *lat, const double *sums);
 
 // Workspace offsets of a gradient over n steps, checkpoints every c1,
-// history c2 at a time (1 <= c2 <= c1).
+// history c2 at a time (1 <= c2 <= c1).  The inner checkpoints come last:
+// the minimum (total) holds those of one segment; with ws_bytes >= total,
+// adj_keep sets how many trailing segments' inner checkpoints fit (keep)
+// and the bytes they use.
 lbk_status adj_plan(const lbk_lattice *lat, int64_t n, int64_t c1, int64_t c2, AdjPlan &P);
+void adj_keep(AdjPlan &P, size_t ws_bytes);
+// Plain sweeps the backward pass spends rebuilding inner checkpoints.
+int64_t adj_rebuild_steps(const AdjPlan &P);
 
 // Gradients need f_eps = 0 and a drive the objective can be normalised by.
 lbk_status check_objective(const lbk_lattice *lat, int objective);

@@ -168,16 +168,18 @@ class Lattice:
         return int(n.value)
 
     def adjoint_plan(self, steps: int, ckpt_every: int, budget: Optional[int] = None,
-                     fraction: float = 0.9) -> int:
-        """Longest history length whose gradient workspace fits ``budget``
-        bytes (default: ``fraction`` of the device's free memory)."""
+                     fraction: float = 0.9, with_bytes: bool = False):
+        """History length of the checkpoint plan that recomputes least within
+        ``budget`` bytes (default: ``fraction`` of the device's free memory);
+        with ``with_bytes`` also the workspace bytes that plan uses (more than
+        the minimum when inner checkpoints of more segments fit)."""
         if budget is None:
             free, _ = torch.cuda.mem_get_info(self.device)
             budget = int(free * fraction)
-        h = ctypes.c_int64()
+        h, n = ctypes.c_int64(), ctypes.c_size_t()
         check(_lib.load().lbk_adjoint_plan(self._handle(), int(steps), int(ckpt_every),
-                                           int(budget), ctypes.byref(h), None))
-        return int(h.value)
+                                           int(budget), ctypes.byref(h), ctypes.byref(n)))
+        return (int(h.value), int(n.value)) if with_bytes else int(h.value)
 
     def adjoint_forward(self, steps: int, objective: str = "k_app", ckpt_every: int = 500,
                         hist_len=None, workspace: Optional[torch.Tensor] = None):
@@ -185,10 +187,11 @@ class Lattice:
         ``hist_len``: steps of history recorded at a time (None: ckpt_every,
         the one-level scheme; "auto": the longest that fits in memory)."""
         ckpt_every = max(1, min(int(ckpt_every), int(steps)))
+        planned = 0
         if hist_len == "auto":
-            hist_len = self.adjoint_plan(steps, ckpt_every)
+            hist_len, planned = self.adjoint_plan(steps, ckpt_every, with_bytes=True)
         hist_len = ckpt_every if hist_len is None else max(1, min(int(hist_len), ckpt_every))
-        nbytes = self.adjoint_workspace_bytes(steps, ckpt_every, hist_len)
+        nbytes = max(planned, self.adjoint_workspace_bytes(steps, ckpt_every, hist_len))
         if workspace is None or workspace.numel() < nbytes:
             workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         J = ctypes.c_double()

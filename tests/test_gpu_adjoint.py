@@ -189,6 +189,43 @@ def test_adjoint_plan_fits_budget(dev):
     assert float((g1 - g2).abs().max()) <= 1e-5 * float(g2.abs().max())
 
 
+def test_kept_inner_checkpoints(dev):
+    """A workspace larger than the minimum keeps the inner checkpoints of
+    more trailing segments (none rebuilt when all fit): the gradient is
+    bitwise the same, since the kept states are those the backward pass
+    would recompute.  The planner spends extra budget on kept segments."""
+    case = inputs.random_medium(150, 12, seed=49, solid_frac=0.05, bc_x=2, rho_in=1.01,
+                                rho_out=1.0, init=1)
+    steps, ck, hl = 100, 25, 6
+    out = []
+    for extra_segments in (0, 1, 3, 10):
+        lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+        base = lat.adjoint_workspace_bytes(steps, ck, hl)
+        seg = lat.state_bytes() * -(-ck // hl)
+        ws = torch.empty(base + extra_segments * seg, dtype=torch.uint8, device=dev)
+        J, ws = lat.adjoint_forward(steps, "k_app", ck, hl, ws)
+        g = lat.adjoint_backward(ws)
+        out.append((J, g))
+    for J, g in out[1:]:
+        assert J == out[0][0]
+        assert torch.equal(g, out[0][1])
+    # one-level (history of 50 steps) does not fit, two-level with every
+    # segment's inner checkpoints kept does: the planner finds the latter
+    lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+    budget = lat.adjoint_workspace_bytes(100, 50, 10) + 5 * lat.state_bytes()
+    assert lat.adjoint_workspace_bytes(100, 50, 50) > budget
+    h, nbytes = lat.adjoint_plan(100, 50, budget=budget, with_bytes=True)
+    assert h < 50 and nbytes <= budget
+    assert nbytes >= lat.adjoint_workspace_bytes(100, 50, h) + lat.state_bytes() * (-(-50 // h)) - 256
+    J1, ws = lat.adjoint_forward(100, "k_app", 50, h, torch.empty(nbytes, dtype=torch.uint8,
+                                                                  device=dev))
+    g1 = lat.adjoint_backward(ws)
+    lat2 = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+    J2, g2 = lat2.gradient(100, "k_app", ckpt_every=50, hist_len=50)
+    assert J1 == J2
+    assert float((g1 - g2).abs().max()) <= 1e-5 * float(g2.abs().max())
+
+
 def test_taylor_remainder(dev):
     """J(ln k + h d) - J(ln k) - h <g, d> shrinks like h^2 (GPU, FP32)."""
     case = inputs.random_medium(96, 24, seed=44, bc_x=2, bc_y=1, rho_in=1.02, rho_out=1.0,
