@@ -273,15 +273,15 @@ def time_ensemble(n_samples, steps, storages, graph_steps, device, launch=None, 
             if grad_steps > 0:
                 # batched gradient of every sample's global permeability
                 ck = min(grad_ckpt, grad_steps)
-                hist = b.adjoint_plan(grad_steps, ck)
-                ws_bytes = b.adjoint_workspace_bytes(grad_steps, ck, hist)
+                hist, ws_bytes = b.adjoint_plan(grad_steps, ck, with_bytes=True)
                 ev2 = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
                 torch.cuda.synchronize(device)
                 ev2[0].record(st)
                 b.step(grad_steps)
                 ev2[1].record(st)
                 ev2[2].record(st)
-                J, g = b.gradient(grad_steps, "k_app", ckpt_every=ck, hist_len=hist)
+                J, g = b.gradient(grad_steps, "k_app", ckpt_every=ck, hist_len=hist,
+                                  workspace_bytes=ws_bytes)
                 ev2[3].record(st)
                 torch.cuda.synchronize(device)
                 t_fwd = ev2[0].elapsed_time(ev2[1])

@@ -125,16 +125,18 @@ class Batch:
 
     # -- gradients
     def adjoint_plan(self, steps: int, ckpt_every: int, budget: Optional[int] = None,
-                     fraction: float = 0.9) -> int:
-        """Longest history length whose batched gradient workspace fits
-        ``budget`` bytes (default: ``fraction`` of the free device memory)."""
+                     fraction: float = 0.9, with_bytes: bool = False):
+        """History length of the batched checkpoint plan that recomputes
+        least within ``budget`` bytes (default: ``fraction`` of the free
+        device memory); with ``with_bytes`` also the workspace bytes it uses
+        (more than the minimum when more segments' inner checkpoints fit)."""
         if budget is None:
             free, _ = torch.cuda.mem_get_info(self.device)
             budget = int(free * fraction)
-        h = ctypes.c_int64()
+        h, nb = ctypes.c_int64(), ctypes.c_size_t()
         check(_lib.load().lbk_batch_adjoint_plan(self._handle(), int(steps), int(ckpt_every),
-                                                 int(budget), ctypes.byref(h), None))
-        return int(h.value)
+                                                 int(budget), ctypes.byref(h), ctypes.byref(nb)))
+        return (int(h.value), int(nb.value)) if with_bytes else int(h.value)
 
     def adjoint_workspace_bytes(self, steps: int, ckpt_every: int, hist_len: int) -> int:
         n = ctypes.c_size_t()
@@ -144,17 +146,21 @@ class Batch:
         return int(n.value)
 
     def gradient(self, steps: int, objective: str = "k_app", ckpt_every: int = 500,
-                 hist_len=None, wrt_kn0: bool = False):
+                 hist_len=None, wrt_kn0: bool = False, workspace_bytes: int = 0):
         """Per-sample J (float64 [n]) and dJ/d ln k planes (list of [ny][nx]
         float32 tensors) after ``steps`` steps of every sample; with
         ``wrt_kn0`` also the dJ/d ln kn0 planes.  ``hist_len``: None (one
-        level), an int, or "auto" (longest that fits in memory)."""
+        level), an int, or "auto" (the plan that recomputes least within the
+        free memory).  ``workspace_bytes`` beyond the minimum keeps inner
+        checkpoints of more segments."""
         lib = _lib.load()
         ckpt_every = max(1, min(int(ckpt_every), int(steps)))
         if hist_len == "auto":
-            hist_len = self.adjoint_plan(steps, ckpt_every)
+            hist_len, planned = self.adjoint_plan(steps, ckpt_every, with_bytes=True)
+            workspace_bytes = max(int(workspace_bytes), planned)
         hist_len = ckpt_every if hist_len is None else max(1, min(int(hist_len), ckpt_every))
-        ws = torch.empty(self.adjoint_workspace_bytes(steps, ckpt_every, hist_len),
+        ws = torch.empty(max(int(workspace_bytes),
+                             self.adjoint_workspace_bytes(steps, ckpt_every, hist_len)),
                          dtype=torch.uint8, device=self.device)
         n = len(self)
         J = np.empty(n, dtype=np.float64)

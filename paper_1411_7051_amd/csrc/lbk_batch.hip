@@ -107,7 +107,8 @@ BatchLayout batch_layout(lbk_lattice *const *lats, int n)
 struct BatchAdj {
     bool valid = false;
     int objective = 0;
-    int64_t n = 0, c1 = 0, c2 = 0, k1 = 0;
+    int64_t n = 0, c1 = 0, c2 = 0, k1 = 0, k2 = 0;
+    int64_t keep = 0; // trailing segments whose inner checkpoints the forward keeps
     bool two_level = false;
     std::vector<AdjPlan> plans;
     std::vector<size_t> base;
@@ -118,26 +119,51 @@ struct BatchAdj {
     const void *ws = nullptr;
 };
 
+// Sample slices for `keep` kept segments (every sample keeps the same
+// ones); returns the workspace total.
+size_t batch_adj_place(BatchAdj &A, int64_t keep)
+{
+    const int n = (int)A.plans.size();
+    size_t o = align_up((size_t)n * sizeof(AdjSampleDesc), 256);
+    for (int i = 0; i < n; ++i) {
+        AdjPlan &P = A.plans[i];
+        P.total = P.inner + (size_t)(keep > 1 ? keep : 1) * P.inner_seg;
+        P.keep = P.two_level ? keep : 0;
+        A.base[i] = o;
+        o = align_up(o + P.total, 256);
+    }
+    A.keep = A.two_level ? keep : 0;
+    A.total = o;
+    return o;
+}
+
+// Layout of a batched gradient; with ws_bytes beyond the minimum, the
+// inner checkpoints of as many trailing segments as fit are kept.
 lbk_status batch_adj_layout(lbk_lattice *const *lats, int n, int64_t steps, int64_t c1,
-                            int64_t c2, BatchAdj &A)
+                            int64_t c2, BatchAdj &A, size_t ws_bytes = 0)
 {
     A.plans.assign(n, AdjPlan{});
     A.base.assign(n, 0);
-    size_t o = align_up((size_t)n * sizeof(AdjSampleDesc), 256);
     A.table = 0;
     for (int i = 0; i < n; ++i) {
         lbk_status s = adj_plan(lats[i], steps, c1, c2, A.plans[i]);
         if (s != LBK_OK)
             return s;
-        A.base[i] = o;
-        o = align_up(o + A.plans[i].total, 256);
     }
-    A.total = o;
     A.n = steps;
     A.c1 = A.plans[0].c1;
     A.c2 = A.plans[0].c2;
     A.k1 = A.plans[0].k1;
+    A.k2 = A.plans[0].k2;
     A.two_level = A.plans[0].two_level;
+    int64_t keep = 1;
+    if (A.two_level)
+        for (int64_t K = A.k1; K > 1; --K)
+            if (batch_adj_place(A, K) <= ws_bytes) {
+                keep = K;
+                break;
+            }
+    batch_adj_place(A, keep);
     return LBK_OK;
 }
 
@@ -625,7 +651,10 @@ lbk_status lbk_batch_adjoint_plan(lbk_batch *b, int64_t n_steps, int64_t ckpt_ev
     if (n_steps < 1 || ckpt_every < 1)
         return fail(LBK_ERR_INVALID_ARG, "need n_steps >= 1 and ckpt_every >= 1");
     const int64_t c1 = ckpt_every < n_steps ? ckpt_every : n_steps;
-    int64_t prev = -1;
+    // fewest sweeps rebuilding inner checkpoints; among equals, the longest
+    // history
+    int64_t prev = -1, best_h = -1, best_cost = -1;
+    size_t best_bytes = 0;
     for (int64_t m = 1; m <= c1; ++m) {
         const int64_t h = (c1 + m - 1) / m;
         if (h == prev)
@@ -635,14 +664,26 @@ lbk_status lbk_batch_adjoint_plan(lbk_batch *b, int64_t n_steps, int64_t ckpt_ev
         lbk_status s = batch_adj_layout(b->lats.data(), b->n, n_steps, c1, h, A);
         if (s != LBK_OK)
             return s;
-        if (A.total <= budget_bytes) {
-            *hist_len = h;
-            if (bytes)
-                *bytes = A.total;
-            return LBK_OK;
+        if (A.total > budget_bytes)
+            continue;
+        if ((s = batch_adj_layout(b->lats.data(), b->n, n_steps, c1, h, A, budget_bytes)) !=
+            LBK_OK)
+            return s;
+        const int64_t cost = adj_rebuild_steps(A.plans[0]);
+        if (best_h < 0 || cost < best_cost) {
+            best_h = h;
+            best_cost = cost;
+            best_bytes = A.total;
         }
+        if (cost == 0)
+            break;
     }
-    return fail(LBK_ERR_OOM, "no batched checkpoint plan fits in %zu bytes", budget_bytes);
+    if (best_h < 0)
+        return fail(LBK_ERR_OOM, "no batched checkpoint plan fits in %zu bytes", budget_bytes);
+    *hist_len = best_h;
+    if (bytes)
+        *bytes = best_bytes;
+    return LBK_OK;
 }
 
 lbk_status lbk_batch_adjoint_forward(lbk_batch *b, int objective, int64_t n_steps,
@@ -666,6 +707,9 @@ lbk_status lbk_batch_adjoint_forward(lbk_batch *b, int objective, int64_t n_step
     if (ws_bytes < A.total)
         return fail(LBK_ERR_OOM, "batched adjoint workspace of %zu bytes < %zu needed", ws_bytes,
                     A.total);
+    if ((s = batch_adj_layout(b->lats.data(), b->n, n_steps, ckpt_every, hist_len, A,
+                              ws_bytes)) != LBK_OK)
+        return s;
     if ((s = sync_tables(b, false)) != LBK_OK)
         return s;
     char *w = static_cast<char *>(ws);
@@ -676,11 +720,14 @@ lbk_status lbk_batch_adjoint_forward(lbk_batch *b, int objective, int64_t n_step
         if ((s = copy_levels(b, w, LevelSel{ADJ_CUR, 0}, LevelSel{ADJ_OUTER, (int)k})) != LBK_OK)
             return s;
         const int64_t steps = std::min(A.c1, A.n - k * A.c1);
-        if (A.two_level && k == A.k1 - 1) {
-            // the last segment is reversed first: keep its inner checkpoints
+        const int64_t kept = k - (A.k1 - A.keep);
+        if (A.two_level && kept >= 0) {
+            // the last `keep` segments are reversed first: keep their inner
+            // checkpoints
             for (int64_t i = 0; i < steps; i += A.c2) {
                 if ((s = copy_levels(b, w, LevelSel{ADJ_CUR, 0},
-                                     LevelSel{ADJ_INNER, (int)(i / A.c2)})) != LBK_OK ||
+                                     LevelSel{ADJ_INNER, (int)(kept * A.k2 + i / A.c2)})) !=
+                        LBK_OK ||
                     (s = lbk_batch_step(b, std::min(A.c2, steps - i))) != LBK_OK)
                     return s;
             }
@@ -781,8 +828,12 @@ lbk_status lbk_batch_adjoint_backward(lbk_batch *b, void *ws, size_t ws_bytes,
     for (int64_t k = A.k1 - 1; k >= 0; --k) {
         const int64_t a = k * A.c1, e = std::min(A.n, a + A.c1);
         int64_t nseg = 1;
-        if (A.two_level && k == A.k1 - 1) {
-            nseg = (e - a + A.c2 - 1) / A.c2; // kept by the forward pass
+        // inner checkpoints kept by the forward pass, or rebuilt into the
+        // first kept segment's slots (free by now)
+        const int64_t kept = k - (A.k1 - A.keep);
+        const int i0 = (int)((kept > 0 ? kept : 0) * A.k2);
+        if (A.two_level && kept >= 0) {
+            nseg = (e - a + A.c2 - 1) / A.c2;
         } else if (A.two_level) {
             // rebuild the inner checkpoints of this outer segment
             LevelSel src{ADJ_OUTER, (int)k};
@@ -807,7 +858,7 @@ lbk_status lbk_batch_adjoint_backward(lbk_batch *b, void *ws, size_t ws_bytes,
         for (int64_t j = nseg - 1; j >= 0; --j) {
             const int64_t a2s = A.two_level ? a + j * A.c2 : a;
             const int64_t b2s = A.two_level ? std::min(e, a2s + A.c2) : e;
-            const LevelSel src = A.two_level ? LevelSel{ADJ_INNER, (int)j}
+            const LevelSel src = A.two_level ? LevelSel{ADJ_INNER, i0 + (int)j}
                                              : LevelSel{ADJ_OUTER, (int)k};
             int r = 0;
             for (int64_t t = a2s; t < b2s; ++t) {

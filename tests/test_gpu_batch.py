@@ -228,6 +228,22 @@ def test_batch_gradient_bitwise_equals_solo(dev, storage, bcx, bcy, obj, ck, hl)
         assert lats[i].time == solo.time == 5 + steps
 
 
+def test_batch_gradient_kept_segments(dev):
+    """A batched gradient workspace beyond the minimum keeps the inner
+    checkpoints of more trailing segments; J and the gradients stay bitwise
+    the same as with the minimum (where all but the last are rebuilt)."""
+    cs = cases(2, 1, seed=960)
+    out = []
+    for extra in (0, 1):
+        b = Batch(ensemble_lattices(cs, device=dev))
+        lo = b.adjoint_workspace_bytes(30, 10, 4)
+        J, g = b.gradient(30, "k_app", ckpt_every=10, hist_len=4, workspace_bytes=lo * (1 + 3 * extra))
+        out.append((J, g))
+    assert np.array_equal(out[0][0], out[1][0])
+    for a, c in zip(out[0][1], out[1][1]):
+        assert torch.equal(a, c)
+
+
 def test_batch_gradient_launch_shapes_agree(dev):
     cs = cases(2, 1, seed=950)
     out = []
