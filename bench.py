@@ -399,7 +399,8 @@ def main():
     ap.add_argument("--storages", default="f32,f16,bf16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--adjoint-n", type=int, default=8192, help="shale lattice side")
-    ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--adjoint-steps", type=int, default=20000,
+                    help="steps of the gradient (the configuration's 20,000)")
     ap.add_argument("--adjoint-ckpt", type=int, default=500)
     ap.add_argument("--adjoint-hist", default="auto",
                     help="history steps recorded at a time, or 'auto' (longest that fits)")
