@@ -295,7 +295,11 @@ lbk_status lbk_batch_check(lbk_batch *b);
  * its tiling, one workgroup per tile).  Every sample's J and gradient are
  * bitwise those of lbk_adjoint_forward / lbk_adjoint_backward on that
  * lattice alone with the same n_steps, ckpt_every and hist_len.  The
- * workspace holds a per-sample slice plus a descriptor table; J: host
+ * workspace holds a per-sample slice plus a descriptor table; as for one
+ * lattice, a workspace beyond lbk_batch_adjoint_workspace_size keeps the
+ * inner checkpoints of more trailing segments (the same number for every
+ * sample), and lbk_batch_adjoint_plan returns the hist_len and workspace
+ * size that rebuild least within a budget.  J: host
  * double[n]; dJ_dlnk, dJ_dlnkn0: host arrays of n device pointers to
  * [ny][nx] float32 planes (dJ_dlnkn0 may be NULL).  The samples must not be
  * stepped, loaded or rescaled between forward and backward. */
