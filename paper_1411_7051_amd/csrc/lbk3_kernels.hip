@@ -307,7 +307,10 @@ struct Med3 {
 };
 
 // Post-stream deviations of node x (pressure planes: non-equilibrium
-// extrapolation from the neighbouring plane, as in the D2Q9 sweep).
+// extrapolation from the neighbouring plane, as in the D2Q9 sweep).  A
+// pressure-plane node pulls at its neighbour xn with the same code as every
+// other lane, so that only the extrapolation itself diverges: with 256-wide
+// rows, half the waves hold a boundary lane.
 template <typename T, int BCX>
 __device__ __forceinline__ float post_stream3(const Rows3 &R, const Layout &L, const Med3 &md,
                                               const Geom3 &g, const Physics3 &p3, float s,
@@ -315,31 +318,34 @@ __device__ __forceinline__ float post_stream3(const Rows3 &R, const Layout &L, c
                                               float &inc, float &r)
 {
     const Physics &ph = p3.ph;
-    if (BCX == BC_PRESSURE && (x == 0 || x == (uint32_t)g.nx - 1)) {
-        const uint32_t xn = (x == 0) ? 1 : (uint32_t)g.nx - 2;
-        float rcn, dn[19], incn, rn;
-        pull3<T, BCX>(R, L, g, s, xn, rcn, dn);
-        const float rhon = density3<T>(rcn, dn, inv_s, incn, rn);
+    const bool bnode = BCX == BC_PRESSURE && (x == 0 || x == (uint32_t)g.nx - 1);
+    const uint32_t xs = !bnode ? x : (x == 0 ? 1u : (uint32_t)g.nx - 2);
+    float rc;
+    pull3<T, BCX>(R, L, g, s, xs, rc, d);
+    const float rho = density3<T>(rc, d, inv_s, inc, r);
+    if (BCX == BC_PRESSURE && bnode) {
+        // d, rho, inc, r are the neighbour's: f_i = f_eq_i(rho_b, u_n; eps_b)
+        // + f_i(n) - f_eq_i(rho_n, u_n; eps_n)
         float j[3], u[3], F[3];
-        momentum3(dn, j);
+        momentum3(d, j);
         if (Elem<T>::kScaled) {
 #pragma unroll
             for (int a = 0; a < 3; ++a)
                 j[a] *= inv_s;
         }
-        const float en = md.eps(xn);
-        velocity3(p3, rhon, j, en, md.drag(xn), md.kn0(xn), u, F);
+        const float en = md.eps(xs);
+        velocity3(p3, rho, j, en, md.drag(xs), md.kn0(xs), u, F);
         const bool in = (x == 0);
         const float rb = in ? ph.rin_hi : ph.rout_hi;
         const float rbl = in ? ph.rin_lo : ph.rout_lo;
         float gb[19], gn[19];
         geq_dev3(rb, u, md.eps(x), gb);
-        geq_dev3(rhon, u, en, gn);
+        geq_dev3(rho, u, en, gn);
         float sum = 0.0f;
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
-            const float dn_phys = (Elem<T>::kScaled ? dn[i] * inv_s : dn[i]) - w3(i) * incn;
-            const float v = w3(i) * (rbl - rn) + gb[i] + (dn_phys - gn[i]);
+            const float dn_phys = (Elem<T>::kScaled ? d[i] * inv_s : d[i]) - w3(i) * inc;
+            const float v = w3(i) * (rbl - r) + gb[i] + (dn_phys - gn[i]);
             sum += v;
             d[i] = Elem<T>::kScaled ? v * s : v;
         }
@@ -347,9 +353,7 @@ __device__ __forceinline__ float post_stream3(const Rows3 &R, const Layout &L, c
         r = sum;
         return rb;
     }
-    float rc;
-    pull3<T, BCX>(R, L, g, s, x, rc, d);
-    return density3<T>(rc, d, inv_s, inc, r);
+    return rho;
 }
 
 template <typename T, int BCX, int BCY, int BCZ>

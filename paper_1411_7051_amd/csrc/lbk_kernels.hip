@@ -66,40 +66,45 @@ struct Med {
 
 // Post-stream deviations d_i (storage unit) of node (x, y) after the
 // boundary override, relative to rho - inc; returns the FP32 density rho
-// and sets inc and the density residual r (physical unit).
+// and sets inc and the density residual r (physical unit).  A pressure-
+// column node pulls at its neighbour xn with the same code as every other
+// lane, so that only the extrapolation itself diverges (narrow samples of
+// a batch have boundary lanes in a large share of their waves).
 template <typename T, int BCX>
 __device__ __forceinline__ float post_stream(const Rows &R, const Layout &L, const Med &md,
                                              const Geom &g, const Physics &ph, float s,
                                              float inv_s, uint32_t x, float (&d)[9], float &inc,
                                              float &r)
 {
-    if (BCX == BC_PRESSURE && (x == 0 || x == (uint32_t)g.nx - 1)) {
-        // non-equilibrium extrapolation from the neighbouring column:
+    const bool bnode = BCX == BC_PRESSURE && (x == 0 || x == (uint32_t)g.nx - 1);
+    const uint32_t xs = !bnode ? x : (x == 0 ? 1u : (uint32_t)g.nx - 2);
+    float rc;
+    pull<T, BCX>(R, L, g, s, xs, rc, d);
+    const float rho = density<T>(rc, d, inv_s, inc, r);
+    if (BCX == BC_PRESSURE && bnode) {
+        // non-equilibrium extrapolation from the neighbouring column (d,
+        // rho, inc, r are the neighbour's):
         // f_i = f_eq_i(rho_b, u_n; eps_b) + f_i(n) - f_eq_i(rho_n, u_n; eps_n)
-        const uint32_t xn = (x == 0) ? 1 : (uint32_t)g.nx - 2;
-        float rcn, dn[9], incn, rn;
-        pull<T, BCX>(R, L, g, s, xn, rcn, dn);
-        const float rhon = density<T>(rcn, dn, inv_s, incn, rn);
         float jx, jy, ux, uy, Fx, Fy;
-        momentum(dn, jx, jy);
+        momentum(d, jx, jy);
         if (Elem<T>::kScaled) {
             jx *= inv_s;
             jy *= inv_s;
         }
-        const float en = md.eps(xn);
-        velocity(ph, rhon, jx, jy, en, md.drag(xn), md.kn0(xn), ux, uy, Fx, Fy);
+        const float en = md.eps(xs);
+        velocity(ph, rho, jx, jy, en, md.drag(xs), md.kn0(xs), ux, uy, Fx, Fy);
         const bool in = (x == 0);
         const float rb = in ? ph.rin_hi : ph.rout_hi;
         const float rbl = in ? ph.rin_lo : ph.rout_lo;
         float gb[9], gn[9];
         geq_dev(rb, ux, uy, md.eps(x), gb);
-        geq_dev(rhon, ux, uy, en, gn);
+        geq_dev(rho, ux, uy, en, gn);
         float sum = 0.0f;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             // physical deviation of the boundary node from w_i rb
-            const float dn_phys = (Elem<T>::kScaled ? dn[i] * inv_s : dn[i]) - w_of(i) * incn;
-            const float v = w_of(i) * (rbl - rn) + gb[i] + (dn_phys - gn[i]);
+            const float dn_phys = (Elem<T>::kScaled ? d[i] * inv_s : d[i]) - w_of(i) * inc;
+            const float v = w_of(i) * (rbl - r) + gb[i] + (dn_phys - gn[i]);
             sum += v;
             d[i] = Elem<T>::kScaled ? v * s : v;
         }
@@ -107,9 +112,7 @@ __device__ __forceinline__ float post_stream(const Rows &R, const Layout &L, con
         r = sum;
         return rb;
     }
-    float rc;
-    pull<T, BCX>(R, L, g, s, x, rc, d);
-    return density<T>(rc, d, inv_s, inc, r);
+    return rho;
 }
 
 // Full update of node (x, y): pull, boundary override, moments, velocity,
