@@ -160,7 +160,7 @@ def test_invalid_and_nonfinite(dev):
     assert e.value.status == -4
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 def test_spheres256_windows(dev, storage):
     """The 256^3 sphere medium of the benchmark: windows against the
     windowed D3Q19 oracle after 16 steps."""

@@ -55,7 +55,7 @@ def macro_np(lat):
     return [t.double().cpu().numpy() for t in lat.macroscopic()]
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
 def test_discs4096_windows(dev, storage):
     """Two-component disc medium at 4096 x 4096 (the benchmark workload)."""
     case = inputs.discs(n=4096, seed=2)
