@@ -65,6 +65,21 @@ def test_invalid_descriptions_rejected(kw, msg):
     assert e.value.status == -1 and msg in str(e.value)
 
 
+@pytest.mark.parametrize("nx,ny", [(0, 8), (8, 0), (0, 0), (-3, 4)])
+def test_empty_lattice_rejected(nx, ny):
+    with pytest.raises(_lib.LbkError) as e:
+        workspace_bytes(make_desc(nx, ny))
+    assert e.value.status == -1 and "nx, ny" in str(e.value)
+
+
+def test_empty_lattice3_rejected():
+    from paper_1411_7051_amd.lattice3 import make_desc3, workspace_bytes3
+    for n in [(0, 4, 4), (4, 0, 4), (4, 4, 0)]:
+        with pytest.raises(_lib.LbkError) as e:
+            workspace_bytes3(make_desc3(*n))
+        assert e.value.status == -1
+
+
 def test_pressure_needs_three_columns():
     with pytest.raises(_lib.LbkError):
         workspace_bytes(make_desc(2, 8, bc_x=2))

@@ -210,3 +210,18 @@ def test_nonfinite_detected(dev):
     with pytest.raises(LbkError) as e:
         lat.step(5000)
     assert e.value.status == -4
+
+
+def test_zero_and_negative_steps(dev):
+    """step(0) leaves the state and the clock untouched; a negative count is
+    rejected before any device work."""
+    from paper_1411_7051_amd._lib import LbkError
+    case = inputs.random_medium(40, 9, seed=13, bc_x=2, rho_in=1.01, rho_out=1.0, init=1)
+    lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+    lat.step(3)
+    before = lat.populations().clone()
+    lat.step(0)
+    assert lat.time == 3 and torch.equal(lat.populations(), before)
+    with pytest.raises(LbkError) as e:
+        lat.step(-1)
+    assert e.value.status == -1 and lat.time == 3
