@@ -305,3 +305,38 @@ def test_fullsize_shale_against_gpu_fd(dev, shale8192):
     for y, x in pick:
         fd = (4.0 * central(y, x, 0.05) - central(y, x, 0.1)) / 3.0
         assert abs(fd - g[y, x]) <= bar, (y, x, g[y, x], fd)
+
+
+def test_fullsize_shale_20000_steps_directional(dev, shale8192):
+    """The gradient run of the benchmark configuration: global permeability
+    of the 8192 x 8192 shale after 20,000 steps, checkpoints every 500, the
+    planner's history length and kept segments.  The whole gradient field is
+    checked at once through a directional derivative: <g, d> for a smooth
+    random direction d (Gaussian field, correlation length 64, scaled to
+    max |d| = 1) against a central difference of the HIP forward pass along
+    d (ln k +- h d, h = 0.01; truncation O(h^2) ~ 1e-4 relative).  Bar: 1e-3
+    relative."""
+    case = shale8192
+    steps, ck, h = 20000, 500, 0.01
+    lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+    J0, g = lat.gradient(steps, "k_app", ckpt_every=ck, hist_len="auto")
+    g = g.double().cpu().numpy()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    ny, nx = case.k.shape
+    d = inputs.gaussian_field(ny, nx, 64.0, np.random.default_rng(20000))
+    d /= np.abs(d).max()
+    vals = []
+    for sgn in (1.0, -1.0):
+        kk = (case.k.astype(np.float64) * np.exp(sgn * h * d)).astype(np.float32)
+        l2 = Lattice(case.eps, kk, case.kn0, device=dev, **case.params).step(steps)
+        vals.append(l2.apparent_permeability())
+        l2.close()
+        del l2
+        torch.cuda.empty_cache()
+    fd = (vals[0] - vals[1]) / (2 * h)
+    dot = float((g * d).sum())
+    print(f"20000-step gradient: <g, d> = {dot:.6e}, central difference = {fd:.6e}, "
+          f"relative difference {abs(fd - dot) / abs(dot):.2e}", flush=True)
+    assert abs(fd - dot) <= 1e-3 * abs(dot), (fd, dot, J0)
