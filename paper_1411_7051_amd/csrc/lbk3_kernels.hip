@@ -115,8 +115,10 @@ __device__ __forceinline__ Rows3 rows3_of(const char *base, const Layout &L, con
         ys[0] = y == 0 ? g.ny - 1 : ys[0];
         ys[2] = y == g.ny - 1 ? 0 : ys[2];
     } else {
-        R.wym = y == 0;
-        R.wyp = y == g.ny - 1;
+        // the row is the workgroup's: scalar wall flags keep the selects
+        // of buffer resources scalar
+        R.wym = __builtin_amdgcn_readfirstlane(y == 0 ? 1 : 0) != 0;
+        R.wyp = __builtin_amdgcn_readfirstlane(y == g.ny - 1 ? 1 : 0) != 0;
         ys[0] = R.wym ? y : ys[0];
         ys[2] = R.wyp ? y : ys[2];
     }
@@ -124,8 +126,8 @@ __device__ __forceinline__ Rows3 rows3_of(const char *base, const Layout &L, con
         zs[0] = z == 0 ? g.nz - 1 : zs[0];
         zs[2] = z == g.nz - 1 ? 0 : zs[2];
     } else {
-        R.wzm = z == 0;
-        R.wzp = z == g.nz - 1;
+        R.wzm = __builtin_amdgcn_readfirstlane(z == 0 ? 1 : 0) != 0;
+        R.wzp = __builtin_amdgcn_readfirstlane(z == g.nz - 1 ? 1 : 0) != 0;
         zs[0] = R.wzm ? z : zs[0];
         zs[2] = R.wzp ? z : zs[2];
     }
@@ -300,10 +302,10 @@ __device__ __forceinline__ void collide3(const Physics &ph, float rho, float inc
 
 struct Med3 {
     Rsrc row;
-    uint32_t slot;
+    uint32_t slot, slot2; // byte offsets of the drag and kn0 slots
     __device__ float eps(uint32_t x) const { return ld_f32(row, x * 4, 0); }
     __device__ float drag(uint32_t x) const { return ld_f32(row, x * 4, slot); }
-    __device__ float kn0(uint32_t x) const { return ld_f32(row, x * 4, 2 * slot); }
+    __device__ float kn0(uint32_t x) const { return ld_f32(row, x * 4, slot2); }
 };
 
 // Post-stream deviations of node x (pressure planes: non-equilibrium
@@ -363,7 +365,8 @@ __device__ __forceinline__ float macro_node3(const char *src, const Layout &lay,
                                              int z, uint32_t x, float (&u)[3], float &r)
 {
     const Rows3 R = rows3_of<BCY, BCZ>(src, lay, g, y, z);
-    const Med3 md{make_rsrc(med + row3(g, y, z) * mlay.row, (uint32_t)mlay.row), mlay.slot};
+    const Med3 md{make_rsrc(med + row3(g, y, z) * mlay.row, (uint32_t)mlay.row), mlay.slot,
+                  2 * mlay.slot};
     float d[19], inc;
     const float rho = post_stream3<T, BCX>(R, lay, md, g, p3, s, inv_s, x, d, inc, r);
     float j[3], F[3];
@@ -388,7 +391,8 @@ __global__ __launch_bounds__(kBlock3) void sweep3_kernel(const char *src, char *
         return;
     const Rows3 R = rows3_of<BCY, BCZ>(src, lay, g, nd.y, nd.z);
     const uint64_t row = row3(g, nd.y, nd.z);
-    const Med3 md{make_rsrc(med + row * mlay.row, (uint32_t)mlay.row), mlay.slot};
+    const Med3 md{make_rsrc(med + row * mlay.row, (uint32_t)mlay.row), mlay.slot,
+                  2 * mlay.slot};
     float d[19], inc, r;
     const float rho = post_stream3<T, BCX>(R, lay, md, g, p3, s, inv_s, nd.x, d, inc, r);
     float j[3], u[3], F[3];

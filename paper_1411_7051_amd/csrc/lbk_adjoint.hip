@@ -305,8 +305,10 @@ __device__ __forceinline__ void adjoint_node(const float *mu_in, float *mu_out, 
         ym = (y == 0) ? g.ny - 1 : ym;
         yp = (y == g.ny - 1) ? 0 : yp;
     } else {
-        wym = (y == 0);
-        wyp = (y == g.ny - 1);
+        // scalar wall flags (the row is the workgroup's): keeps the selects
+        // of the pushed rows' buffer resources scalar
+        wym = __builtin_amdgcn_readfirstlane(y == 0 ? 1 : 0) != 0;
+        wyp = __builtin_amdgcn_readfirstlane(y == g.ny - 1 ? 1 : 0) != 0;
         ym = wym ? y : ym;
         yp = wyp ? y : yp;
     }

@@ -229,8 +229,11 @@ __device__ __forceinline__ Rows rows_of(const char *base, const Layout &L, const
         yp = (y == g.ny - 1) ? 0 : yp;
         R.wym = R.wyp = false;
     } else {
-        R.wym = (y == 0);
-        R.wyp = (y == g.ny - 1);
+        // the row is the same for the whole workgroup: read the wall flags
+        // through a scalar register, so that selects on them stay scalar
+        // (a lane-mask select of a buffer resource becomes a waterfall loop)
+        R.wym = __builtin_amdgcn_readfirstlane(y == 0 ? 1 : 0) != 0;
+        R.wyp = __builtin_amdgcn_readfirstlane(y == g.ny - 1 ? 1 : 0) != 0;
         ym = R.wym ? y : ym;
         yp = R.wyp ? y : yp;
     }
@@ -270,14 +273,16 @@ __device__ __forceinline__ void pull(const Rows &R, const Layout &L, const Geom 
         const uint32_t sx = ex == 1 ? xm : (ex == -1 ? xp : x);
         const bool wall_y = (ey == 1 && R.wym) || (ey == -1 && R.wyp); // uniform
         const float ws = Elem<T>::kScaled ? w_of(i) * s : w_of(i);
-        if (wall_y) {
-            d[i] = Elem<T>::ld(R.r[1], x * es, L.h_off + opp_of(i) * L.h_slot);
-        } else {
-            const int ry = ey == 1 ? 0 : (ey == -1 ? 2 : 1);
-            const float rn = ld_f32(R.r[ry], sx * 4, 0);
-            const float h = Elem<T>::ld(R.r[ry], sx * es, L.h_off + i * L.h_slot);
-            d[i] = ws * (rn - rc) + h;
-        }
+        // a wall link reads the node's own opposite slot; its density term
+        // is then rho(x) - rc = 0 exactly, so one expression serves both
+        // (uniform selects of the row and slot, no divergent load)
+        const int ry = ey == 1 ? 0 : (ey == -1 ? 2 : 1);
+        const Rsrc src = wall_y ? R.r[1] : R.r[ry];
+        const uint32_t vx = wall_y ? x : sx;
+        const uint32_t so = L.h_off + (uint32_t)(wall_y ? opp_of(i) : i) * L.h_slot;
+        const float rn = ld_f32(src, vx * 4, 0);
+        const float h = Elem<T>::ld(src, vx * es, so);
+        d[i] = ws * (rn - rc) + h;
         if (BCX == BC_WALL) {
             const bool wall_x = (ex == 1 && wxm) || (ex == -1 && wxp); // per lane, edges only
             if (wall_x)

@@ -58,10 +58,10 @@ __device__ __forceinline__ Node node_of(int bpr)
 // Medium of row y: eps, drag and kn0 at x.
 struct Med {
     Rsrc r;
-    uint32_t slot;
+    uint32_t slot, slot2; // byte offsets of the drag and kn0 slots
     __device__ __forceinline__ float eps(uint32_t x) const { return ld_f32(r, x * 4, 0); }
     __device__ __forceinline__ float drag(uint32_t x) const { return ld_f32(r, x * 4, slot); }
-    __device__ __forceinline__ float kn0(uint32_t x) const { return ld_f32(r, x * 4, 2 * slot); }
+    __device__ __forceinline__ float kn0(uint32_t x) const { return ld_f32(r, x * 4, slot2); }
 };
 
 // Post-stream deviations d_i (storage unit) of node (x, y) after the
@@ -124,7 +124,7 @@ __device__ __forceinline__ void sweep_node(const char *src, char *dst, const Lay
                                            int y, uint32_t x)
 {
     const Rows R = rows_of<BCY>(src, lay, g, y);
-    const Med md{med_row(med, mlay, y), mlay.slot};
+    const Med md{med_row(med, mlay, y), mlay.slot, 2 * mlay.slot};
     float d[9], inc, r;
     const float rho = post_stream<T, BCX>(R, lay, md, g, ph, s, inv_s, x, d, inc, r);
     float jx, jy, ux, uy, Fx, Fy;
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void macro_kernel(const char *src, Layout l
     double v[MAC_SLOTS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (nd.x < (uint32_t)g.nx) {
         const Rows R = rows_of<BCY>(src, lay, g, nd.y);
-        const Med md{med_row(med, mlay, nd.y), mlay.slot};
+        const Med md{med_row(med, mlay, nd.y), mlay.slot, 2 * mlay.slot};
         float d[9], inc, r;
         const float rho = post_stream<T, BCX>(R, lay, md, g, ph, s, inv_s, nd.x, d, inc, r);
         float jx, jy, ux, uy, Fx, Fy;
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void batch_macro_kernel(const SampleDesc *s
     double v[MAC_SLOTS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (x < (uint32_t)sd.g.nx) {
         const Rows R = rows_of<BCY>(sd.state[parity], sd.lay, sd.g, y);
-        const Med md{med_row(sd.med, sd.mlay, y), sd.mlay.slot};
+        const Med md{med_row(sd.med, sd.mlay, y), sd.mlay.slot, 2 * sd.mlay.slot};
         float d[9], inc, r;
         const float rho =
             post_stream<T, BCX>(R, sd.lay, md, sd.g, sd.ph, sd.s, sd.inv_s, x, d, inc, r);
