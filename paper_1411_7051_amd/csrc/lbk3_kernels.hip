@@ -249,21 +249,6 @@ __device__ __forceinline__ void velocity3(const Physics3 &p3, float rho, const f
         F[a] = solid ? -2.0f * j[a] * rinv : eps * G[a] - ag * v[a] - bu * u[a];
 }
 
-// Eq. 14 deviation from w_i rho: w_i rho [3 e.u + 9/(2 eps)(e.u)^2 - 3/(2 eps) u.u].
-__device__ __forceinline__ void geq_dev3(float rho, const float (&u0)[3], float eps,
-                                         float (&ge)[19])
-{
-    const bool solid = !(eps > 0.0f);
-    const float ie = solid ? 0.0f : __builtin_amdgcn_rcpf(eps);
-    const float ux = solid ? 0.0f : u0[0], uy = solid ? 0.0f : u0[1], uz = solid ? 0.0f : u0[2];
-    const float base = -1.5f * ie * (ux * ux + uy * uy + uz * uz);
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        const float eu = ex3(i) * ux + ey3(i) * uy + ez3(i) * uz;
-        ge[i] = w3(i) * rho * (3.0f * eu + 4.5f * ie * eu * eu + base);
-    }
-}
-
 // BGK + Guo in deviation form over the opposite pairs (see the D2Q9
 // collide): h*_i, h*_opp = (1 - omega) d_i + w_i C + w_i rho (4.5 E / eps +/- 3 P).
 template <typename T>
@@ -335,21 +320,35 @@ __device__ __forceinline__ float post_stream3(const Rows3 &R, const Layout &L, c
             for (int a = 0; a < 3; ++a)
                 j[a] *= inv_s;
         }
-        const float en = md.eps(xs);
+        const float en = md.eps(xs), eb = md.eps(x);
         velocity3(p3, rho, j, en, md.drag(xs), md.kn0(xs), u, F);
         const bool in = (x == 0);
         const float rb = in ? ph.rin_hi : ph.rout_hi;
         const float rbl = in ? ph.rin_lo : ph.rout_lo;
-        float gb[19], gn[19];
-        geq_dev3(rb, u, md.eps(x), gb);
-        geq_dev3(rho, u, en, gn);
-        float sum = 0.0f;
+        // f_eq_i(rho_b, u; eps_b) - f_eq_i(rho_n, u; eps_n) of Eq. 14 as
+        // w_i [a e.u + b (4.5 (e.u)^2 - 1.5 u.u)], each equilibrium's
+        // deviation from w_i rho vanishing at eps = 0; the pairs (i, i + 1)
+        // are opposite, so e.u is formed once per pair
+        const bool sb = !(eb > 0.0f), sn = !(en > 0.0f);
+        const float a = 3.0f * ((sb ? 0.0f : rb) - (sn ? 0.0f : rho));
+        const float b = (sb ? 0.0f : rb * __builtin_amdgcn_rcpf(eb)) -
+                        (sn ? 0.0f : rho * __builtin_amdgcn_rcpf(en));
+        const float uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+        const float c = (rbl - r) - inc; // w_i (rbl - r) - w_i inc, over w_i
+        auto phys = [&](float v) { return Elem<T>::kScaled ? v * inv_s : v; };
+        float v0 = w3(0) * (c - 1.5f * b * uu) + phys(d[0]);
+        float sum = v0;
+        d[0] = Elem<T>::kScaled ? v0 * s : v0;
 #pragma unroll
-        for (int i = 0; i < 19; ++i) {
-            const float dn_phys = (Elem<T>::kScaled ? d[i] * inv_s : d[i]) - w3(i) * inc;
-            const float v = w3(i) * (rbl - r) + gb[i] + (dn_phys - gn[i]);
-            sum += v;
-            d[i] = Elem<T>::kScaled ? v * s : v;
+        for (int i = 1; i < 19; i += 2) {
+            const float eu = ex3(i) * u[0] + ey3(i) * u[1] + ez3(i) * u[2];
+            const float q = c + b * (4.5f * eu * eu - 1.5f * uu), t = a * eu;
+            const float v1 = w3(i) * (q + t) + phys(d[i]);
+            const float v2 = w3(i) * (q - t) + phys(d[i + 1]);
+            sum += v1;
+            sum += v2;
+            d[i] = Elem<T>::kScaled ? v1 * s : v1;
+            d[i + 1] = Elem<T>::kScaled ? v2 * s : v2;
         }
         inc = 0.0f;
         r = sum;

@@ -369,23 +369,6 @@ __device__ __forceinline__ void velocity(const Physics &ph, float rho, float jx,
     Fy = solid ? -2.0f * jy * rinv : fy;
 }
 
-// Equilibrium deviation of Eq. 14 from w_i rho (physical unit):
-// w_i rho [3 e.u + 9/(2 eps) (e.u)^2 - 3/(2 eps) u.u]; zero at eps = 0.
-__device__ __forceinline__ void geq_dev(float rho, float ux, float uy, float eps,
-                                        float (&ge)[9])
-{
-    const bool solid = !(eps > 0.0f);
-    const float ie = solid ? 0.0f : __builtin_amdgcn_rcpf(eps);
-    ux = solid ? 0.0f : ux;
-    uy = solid ? 0.0f : uy;
-    const float base = -1.5f * ie * (ux * ux + uy * uy);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const float eu = ex_of(i) * ux + ey_of(i) * uy;
-        ge[i] = w_of(i) * rho * (3.0f * eu + 4.5f * ie * eu * eu + base);
-    }
-}
-
 // BGK relaxation with Guo forcing (Eqs. 12, 14, 15) in deviation form.
 // With delta_i = d_i - w_i inc the post-stream deviations from w_i rho,
 //   h*_i = (1 - omega) delta_i + omega (w_i r + geq_i) + F_i,

@@ -91,20 +91,27 @@ __device__ __forceinline__ float post_stream(const Rows &R, const Layout &L, con
             jx *= inv_s;
             jy *= inv_s;
         }
-        const float en = md.eps(xs);
+        const float en = md.eps(xs), eb = md.eps(x);
         velocity(ph, rho, jx, jy, en, md.drag(xs), md.kn0(xs), ux, uy, Fx, Fy);
         const bool in = (x == 0);
         const float rb = in ? ph.rin_hi : ph.rout_hi;
         const float rbl = in ? ph.rin_lo : ph.rout_lo;
-        float gb[9], gn[9];
-        geq_dev(rb, ux, uy, md.eps(x), gb);
-        geq_dev(rho, ux, uy, en, gn);
+        // f_eq_i(rho_b, u; eps_b) - f_eq_i(rho_n, u; eps_n) of Eq. 14 as
+        // w_i [a e.u + b (4.5 (e.u)^2 - 1.5 u.u)], each equilibrium's
+        // deviation from w_i rho vanishing at eps = 0
+        const bool sb = !(eb > 0.0f), sn = !(en > 0.0f);
+        const float a = 3.0f * ((sb ? 0.0f : rb) - (sn ? 0.0f : rho));
+        const float b = (sb ? 0.0f : rb * __builtin_amdgcn_rcpf(eb)) -
+                        (sn ? 0.0f : rho * __builtin_amdgcn_rcpf(en));
+        const float uu = ux * ux + uy * uy;
+        const float c = (rbl - r) - inc; // w_i (rbl - r) - w_i inc, over w_i
         float sum = 0.0f;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             // physical deviation of the boundary node from w_i rb
-            const float dn_phys = (Elem<T>::kScaled ? d[i] * inv_s : d[i]) - w_of(i) * inc;
-            const float v = w_of(i) * (rbl - r) + gb[i] + (dn_phys - gn[i]);
+            const float eu = ex_of(i) * ux + ey_of(i) * uy;
+            const float q = c + b * (4.5f * eu * eu - 1.5f * uu) + a * eu;
+            const float v = w_of(i) * q + (Elem<T>::kScaled ? d[i] * inv_s : d[i]);
             sum += v;
             d[i] = Elem<T>::kScaled ? v * s : v;
         }
