@@ -148,12 +148,21 @@ def cpu_baseline(case, target_s=15.0):
     t = time.perf_counter()
     lat.step(steps)
     dt = time.perf_counter() - t
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")),
+                         "")
+    except OSError:
+        pass
     return {
         "value": n * n * steps / dt / 1e6,
         "unit": "MLUPS",
         "cores": 1,
         "kind": "oracle",
         "sample": f"{n}x{n} window of the same medium, {steps} FP64 steps in {dt:.1f} s",
+        "host_cpu": model,
+        "host_cpus_visible": len(os.sched_getaffinity(0)),
     }
 
 
