@@ -175,7 +175,8 @@ lbk_status lbk_load_state(lbk_lattice *lat, const void *src);
  * in every segment whose inner checkpoints were not kept;
  * lbk_adjoint_plan picks the plan that rebuilds least within a memory
  * budget.
- * The Forchheimer term is not differentiated (f_eps must be 0).
+ * With the Forchheimer term (f_eps > 0) the reverse sweep differentiates
+ * the quadratic velocity solve of Eq. 2 as well.
  * --------------------------------------------------------------------- */
 typedef enum lbk_objective {
     LBK_OBJ_PERMEABILITY = 0, /* the global permeability of

@@ -54,7 +54,7 @@ __device__ __forceinline__ int xcd_remap_a(int b, int nb)
 // sweep, plus what the adjoint needs: dA/drho through the local Kn and
 // dA/d ln kn0.
 struct NodeFwd {
-    float rho, rinv, jx, jy, eps, ie, A, g, ux, uy, Fx, Fy, dA_drho, dA_dlnkn;
+    float rho, rinv, jx, jy, eps, ie, A, B, c0, g, ux, uy, un, Fx, Fy, dA_drho, dA_dlnkn;
     bool solid;
 };
 
@@ -74,15 +74,26 @@ __device__ __forceinline__ NodeFwd node_fwd(const Physics &ph, float rho, float 
     float num, den; // f_c = den / num, as in the sweep
     fc_parts(ph, kn, num, den);
     const float dn = drag * num;
-    const float R2 = 2.0f * __builtin_amdgcn_rcpf(2.0f * den + dn);
-    n.g = den * R2;                          // 1 / (1 + A/2)
     n.A = dn * __builtin_amdgcn_rcpf(den);   // drag / f_c
+    n.c0 = 1.0f + 0.5f * n.A;
     const float vx = jx * n.rinv + 0.5f * eps * ph.gx;
     const float vy = jy * n.rinv + 0.5f * eps * ph.gy;
+    n.B = 0.0f;
+    if (ph.feps == 0.0f) {
+        const float R2 = 2.0f * __builtin_amdgcn_rcpf(2.0f * den + dn);
+        n.g = den * R2; // 1 / (1 + A/2)
+    } else {
+        // Forchheimer (Eq. 2): c0 u + (B/2) |u| u = v, B = eps F_eps / sqrt(k_a),
+        // the positive root as in the forward velocity solve
+        n.B = ph.feps * __builtin_sqrtf(eps * n.A * ph.inv_nu);
+        const float wn = __builtin_sqrtf(vx * vx + vy * vy);
+        n.g = 2.0f / (n.c0 + __builtin_sqrtf(n.c0 * n.c0 + 2.0f * n.B * wn));
+    }
     n.ux = n.solid ? 0.0f : n.g * vx;
     n.uy = n.solid ? 0.0f : n.g * vy;
-    n.Fx = n.solid ? -2.0f * jx * n.rinv : eps * ph.gx - n.A * n.ux;
-    n.Fy = n.solid ? -2.0f * jy * n.rinv : eps * ph.gy - n.A * n.uy;
+    n.un = __builtin_sqrtf(n.ux * n.ux + n.uy * n.uy);
+    n.Fx = n.solid ? -2.0f * jx * n.rinv : eps * ph.gx - n.A * n.ux - n.B * n.un * n.ux;
+    n.Fy = n.solid ? -2.0f * jy * n.rinv : eps * ph.gy - n.A * n.uy - n.B * n.un * n.uy;
     // Kn ~ kn0: dA/d ln kn0 = -A Kn f_c'(Kn) / f_c; with the local Kn ~ 1/rho
     // also dA/drho = -(dA/d ln kn0) / rho.  For Eqs. 6-7, f_c = P1 P2 with
     // P1 = 1 + alpha Kn = p1/a, p1 = a + 1.358 t Kn, and P2 = p2/q,
@@ -148,11 +159,35 @@ __device__ __forceinline__ Grads chain(const NodeFwd &n, float Pr, float Pux, fl
         G.lnkn = 0.0f;
         return G;
     }
-    // u = g v, v = j / rho + eps G / 2, g = 1 / (1 + A/2), F = -A u + eps G
-    const float Tx = Pux - n.A * PFx, Ty = Puy - n.A * PFy; // dPsi/du with F(u)
-    const float GA = -0.5f * n.g * (Tx * n.ux + Ty * n.uy) - (PFx * n.ux + PFy * n.uy);
-    G.jx = n.g * n.rinv * Tx;
-    G.jy = n.g * n.rinv * Ty;
+    // The velocity solves M(u) = c0 u + (B/2) |u| u = v, v = j / rho + eps G / 2,
+    // c0 = 1 + A/2, and F = eps G - A u - B |u| u.  With T = dPsi/du through
+    // u and F(u) at fixed A, B, and K = dM/du = a I + (B/2) u u^T / |u|,
+    // a = c0 + B |u| / 2: dPsi/dv = S = K^-1 T, dPsi/dj = S / rho, and
+    // dPsi/dA = -(S.u / 2 + Psi_F.u) = GA, dPsi/dB = |u| GA.  B ~ sqrt(A), so
+    // the B path adds GA |u| B / (2 A) per unit of dA.  Darcy (B = 0): S = T / c0.
+    const float PFu = PFx * n.ux + PFy * n.uy;
+    float Tx = Pux - n.A * PFx, Ty = Puy - n.A * PFy;
+    float Sx, Sy, fac = 1.0f;
+    if (n.B == 0.0f) {
+        Sx = n.g * Tx;
+        Sy = n.g * Ty;
+    } else {
+        const float un = n.un, hb = 0.5f * n.B * un;
+        const float q = un > 0.0f ? PFu * __builtin_amdgcn_rcpf(un) : 0.0f; // u.Psi_F / |u|
+        Tx -= n.B * (un * PFx + q * n.ux);
+        Ty -= n.B * (un * PFy + q * n.uy);
+        const float a = n.c0 + hb;
+        // K^-1 = (I - b/(a + b) u u^T / |u|^2) / a with b = B |u| / 2
+        const float kap =
+            un > 0.0f ? 0.5f * n.B * __builtin_amdgcn_rcpf((a + hb) * un) : 0.0f;
+        const float uT = n.ux * Tx + n.uy * Ty, ia = __builtin_amdgcn_rcpf(a);
+        Sx = ia * (Tx - kap * uT * n.ux);
+        Sy = ia * (Ty - kap * uT * n.uy);
+        fac = n.A > 0.0f ? 1.0f + un * n.B * __builtin_amdgcn_rcpf(2.0f * n.A) : 1.0f;
+    }
+    const float GA = (-0.5f * (Sx * n.ux + Sy * n.uy) - PFu) * fac;
+    G.jx = n.rinv * Sx;
+    G.jy = n.rinv * Sy;
     G.rho = Pr - (G.jx * n.jx + G.jy * n.jy) * n.rinv + GA * n.dA_drho;
     G.lnk = -n.A * GA; // dA / d ln k = -A
     G.lnkn = n.dA_dlnkn * GA;

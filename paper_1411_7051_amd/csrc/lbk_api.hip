@@ -592,8 +592,6 @@ double lbk::objective_weights(const lbk_lattice *lat, int objective, const doubl
 lbk_status lbk::check_objective(const lbk_lattice *lat, int objective)
 {
     const lbk_desc &d = lat->d;
-    if (d.f_eps != 0.0)
-        return fail(LBK_ERR_UNSUPPORTED, "gradients need f_eps = 0 (Eq. 8)");
     if (objective != LBK_OBJ_PERMEABILITY && objective != LBK_OBJ_OUTLET_FLUX)
         return fail(LBK_ERR_INVALID_ARG, "unknown objective %d", objective);
     if (objective == LBK_OBJ_PERMEABILITY && d.bc_x != LBK_BC_PRESSURE && d.gx == 0.0)
