@@ -91,7 +91,7 @@ __device__ __forceinline__ NodeFwd node_fwd(const Physics &ph, float rho, float 
     }
     n.ux = n.solid ? 0.0f : n.g * vx;
     n.uy = n.solid ? 0.0f : n.g * vy;
-    n.un = __builtin_sqrtf(n.ux * n.ux + n.uy * n.uy);
+    n.un = ph.feps == 0.0f ? 0.0f : __builtin_sqrtf(n.ux * n.ux + n.uy * n.uy); // |u|, Eq. 2 only
     n.Fx = n.solid ? -2.0f * jx * n.rinv : eps * ph.gx - n.A * n.ux - n.B * n.un * n.ux;
     n.Fy = n.solid ? -2.0f * jy * n.rinv : eps * ph.gy - n.A * n.uy - n.B * n.un * n.uy;
     // Kn ~ kn0: dA/d ln kn0 = -A Kn f_c'(Kn) / f_c; with the local Kn ~ 1/rho
