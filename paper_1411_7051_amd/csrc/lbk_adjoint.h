@@ -26,10 +26,11 @@ hipError_t launch_grad_out(const double *grad, float *out, const Geom &g, hipStr
 // Batched gradients over a batch's tile list (tiles of tile_x by rows, one
 // workgroup per tile).  Reverse step: lam_in < 0 is the terminal read-out
 // (into lam[0]), else lam[lam_in] -> lam[lam_in ^ 1] with the history in
-// hist_slot; kn: also the ln kn0 plane.
+// hist_slot; kn: also the ln kn0 plane; fc: some sample has the
+// Forchheimer term on.
 hipError_t launch_batch_adjoint(int bcx, int bcy, const AdjSampleDesc *samples,
                                 const int *tile_sample, int ntiles, int tile_x, int rows,
-                                int lam_in, int hist_slot, int kn, hipStream_t st);
+                                int lam_in, int hist_slot, int kn, int fc, hipStream_t st);
 
 // Gradient planes of every sample: op 0 clears segments and totals, op 1
 // folds segments into totals (and clears them), op 2 writes the totals to

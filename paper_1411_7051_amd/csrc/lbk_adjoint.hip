@@ -58,6 +58,9 @@ struct NodeFwd {
     bool solid;
 };
 
+// FC: the Forchheimer term may be on (else it is known to be off, and the
+// Darcy path alone is compiled: fewer registers for the common case).
+template <bool FC>
 __device__ __forceinline__ NodeFwd node_fwd(const Physics &ph, float rho, float jx, float jy,
                                             float eps, float drag, float kn0)
 {
@@ -79,7 +82,7 @@ __device__ __forceinline__ NodeFwd node_fwd(const Physics &ph, float rho, float 
     const float vx = jx * n.rinv + 0.5f * eps * ph.gx;
     const float vy = jy * n.rinv + 0.5f * eps * ph.gy;
     n.B = 0.0f;
-    if (ph.feps == 0.0f) {
+    if (!FC || ph.feps == 0.0f) {
         const float R2 = 2.0f * __builtin_amdgcn_rcpf(2.0f * den + dn);
         n.g = den * R2; // 1 / (1 + A/2)
     } else {
@@ -91,7 +94,7 @@ __device__ __forceinline__ NodeFwd node_fwd(const Physics &ph, float rho, float 
     }
     n.ux = n.solid ? 0.0f : n.g * vx;
     n.uy = n.solid ? 0.0f : n.g * vy;
-    n.un = ph.feps == 0.0f ? 0.0f : __builtin_sqrtf(n.ux * n.ux + n.uy * n.uy); // |u|, Eq. 2 only
+    n.un = (!FC || ph.feps == 0.0f) ? 0.0f : __builtin_sqrtf(n.ux * n.ux + n.uy * n.uy);
     n.Fx = n.solid ? -2.0f * jx * n.rinv : eps * ph.gx - n.A * n.ux - n.B * n.un * n.ux;
     n.Fy = n.solid ? -2.0f * jy * n.rinv : eps * ph.gy - n.A * n.uy - n.B * n.un * n.uy;
     // Kn ~ kn0: dA/d ln kn0 = -A Kn f_c'(Kn) / f_c; with the local Kn ~ 1/rho
@@ -293,7 +296,7 @@ __device__ __forceinline__ Rsrc rsrc_row(const void *base, uint64_t row_bytes, i
 //   grad2  [y][pitch]     FP32, d J / d ln kn0 likewise (KN only)
 // Objective: J = sum_x a1(x) rho u_x + a2 u_x with a1(x) = a1 (all nodes,
 // or only column nx-1 when outlet != 0) and a2 uniform.
-template <int BCX, int BCY, bool KN>
+template <int BCX, int BCY, bool KN, bool FC>
 __device__ __forceinline__ void adjoint_node(const float *mu_in, float *mu_out, const float *hist,
                                              const char *med, const MLayout &mlay, float *grad,
                                              float *grad2, const Geom &g, const Physics &ph,
@@ -312,7 +315,7 @@ __device__ __forceinline__ void adjoint_node(const float *mu_in, float *mu_out, 
     auto load_node = [&](uint32_t xx) {
         const float rho = ld_f32_nt(hr, xx * 4, 0), jx = ld_f32_nt(hr, xx * 4, slot),
                     jy = ld_f32_nt(hr, xx * 4, 2 * slot);
-        return node_fwd(ph, rho, jx, jy, ld_f32(mr, xx * 4, 0), ld_f32(mr, xx * 4, mlay.slot),
+        return node_fwd<FC>(ph, rho, jx, jy, ld_f32(mr, xx * 4, 0), ld_f32(mr, xx * 4, mlay.slot),
                         ld_f32(mr, xx * 4, 2 * mlay.slot));
     };
     auto node_adj = [&](const NodeFwd &n, uint32_t xx, float (&lf)[9]) {
@@ -438,7 +441,7 @@ __device__ __forceinline__ void adjoint_node(const float *mu_in, float *mu_out, 
     }
 }
 
-template <int BCX, int BCY, bool KN>
+template <int BCX, int BCY, bool KN, bool FC>
 __global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float *mu_out,
                                                        const float *hist, const char *med,
                                                        MLayout mlay, float *grad, float *grad2,
@@ -450,7 +453,7 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float 
     const uint32_t x = (uint32_t)(L - y * bpr) * 256 + threadIdx.x;
     if (x >= (uint32_t)g.nx)
         return;
-    adjoint_node<BCX, BCY, KN>(mu_in, mu_out, hist, med, mlay, grad, grad2, g, ph, terminal, a1,
+    adjoint_node<BCX, BCY, KN, FC>(mu_in, mu_out, hist, med, mlay, grad, grad2, g, ph, terminal, a1,
                                a2, outlet, y, x);
 }
 
@@ -486,14 +489,20 @@ static hipError_t adj_t(const float *mu_in, float *mu_out, const float *hist, co
                         hipStream_t st)
 {
     const int bpr = (g.nx + 255) / 256;
-    if (grad2)
-        hipLaunchKernelGGL((adjoint_kernel<BCX, BCY, true>), dim3(bpr * g.ny), dim3(256), 0, st,
-                           mu_in, mu_out, hist, med, mlay, grad, grad2, g, ph, terminal, a1, a2,
-                           outlet, bpr);
+#define LBK_ADJK(KN, FC)                                                                     \
+    hipLaunchKernelGGL((adjoint_kernel<BCX, BCY, KN, FC>), dim3(bpr * g.ny), dim3(256), 0, st, \
+                       mu_in, mu_out, hist, med, mlay, grad, grad2, g, ph, terminal, a1, a2,   \
+                       outlet, bpr)
+    const bool fc = ph.feps != 0.0f;
+    if (grad2 && fc)
+        LBK_ADJK(true, true);
+    else if (grad2)
+        LBK_ADJK(true, false);
+    else if (fc)
+        LBK_ADJK(false, true);
     else
-        hipLaunchKernelGGL((adjoint_kernel<BCX, BCY, false>), dim3(bpr * g.ny), dim3(256), 0,
-                           st, mu_in, mu_out, hist, med, mlay, grad, grad2, g, ph, terminal, a1,
-                           a2, outlet, bpr);
+        LBK_ADJK(false, false);
+#undef LBK_ADJK
     return hipGetLastError();
 }
 
@@ -552,7 +561,7 @@ __device__ __forceinline__ bool adj_tile(const AdjSampleDesc *__restrict__ sampl
 
 // lam_in < 0: the terminal read-out (writes lam[0]); else lam[lam_in] ->
 // lam[lam_in ^ 1].  hist_slot: the history of the step being reversed.
-template <int BCX, int BCY, bool KN>
+template <int BCX, int BCY, bool KN, bool FC>
 __global__ __launch_bounds__(256) void batch_adjoint_kernel(
     const AdjSampleDesc *__restrict__ samples, const int *__restrict__ tile_sample, int rows,
     int lam_in, int hist_slot)
@@ -568,7 +577,7 @@ __global__ __launch_bounds__(256) void batch_adjoint_kernel(
     const float *hist = reinterpret_cast<const float *>(reinterpret_cast<const char *>(sd.hist) +
                                                         (uint64_t)hist_slot * sd.hist_bytes);
     for (int y = y0; y < y1; ++y)
-        adjoint_node<BCX, BCY, KN>(mu_in, mu_out, hist, sd.med, sd.mlay, sd.seg, sd.seg2, sd.g,
+        adjoint_node<BCX, BCY, KN, FC>(mu_in, mu_out, hist, sd.med, sd.mlay, sd.seg, sd.seg2, sd.g,
                                    sd.ph, terminal ? 1 : 0, sd.a1, sd.a2, sd.outlet, y, x);
 }
 
@@ -603,28 +612,34 @@ __global__ __launch_bounds__(256) void batch_grad_kernel(const AdjSampleDesc *__
 
 template <int BCX, int BCY>
 static hipError_t batch_adj_t(const AdjSampleDesc *samples, const int *tile_sample, int ntiles,
-                              int tile_x, int rows, int lam_in, int hist_slot, int kn,
+                              int tile_x, int rows, int lam_in, int hist_slot, int kn, int fc,
                               hipStream_t st)
 {
-    if (kn)
-        hipLaunchKernelGGL((batch_adjoint_kernel<BCX, BCY, true>), dim3(ntiles), dim3(tile_x), 0,
-                           st, samples, tile_sample, rows, lam_in, hist_slot);
+#define LBK_BADJK(KN, FC)                                                                    \
+    hipLaunchKernelGGL((batch_adjoint_kernel<BCX, BCY, KN, FC>), dim3(ntiles), dim3(tile_x), 0, \
+                       st, samples, tile_sample, rows, lam_in, hist_slot)
+    if (kn && fc)
+        LBK_BADJK(true, true);
+    else if (kn)
+        LBK_BADJK(true, false);
+    else if (fc)
+        LBK_BADJK(false, true);
     else
-        hipLaunchKernelGGL((batch_adjoint_kernel<BCX, BCY, false>), dim3(ntiles), dim3(tile_x),
-                           0, st, samples, tile_sample, rows, lam_in, hist_slot);
+        LBK_BADJK(false, false);
+#undef LBK_BADJK
     return hipGetLastError();
 }
 
 hipError_t launch_batch_adjoint(int bcx, int bcy, const AdjSampleDesc *samples,
                                 const int *tile_sample, int ntiles, int tile_x, int rows,
-                                int lam_in, int hist_slot, int kn, hipStream_t st)
+                                int lam_in, int hist_slot, int kn, int fc, hipStream_t st)
 {
     if (tile_x < 64 || tile_x > 256 || (tile_x & 63) || rows < 1 || ntiles < 0)
         return hipErrorInvalidValue;
     if (ntiles == 0)
         return hipSuccess;
 #define LBK_BADJ(X, Y)                                                                       \
-    batch_adj_t<X, Y>(samples, tile_sample, ntiles, tile_x, rows, lam_in, hist_slot, kn, st)
+    batch_adj_t<X, Y>(samples, tile_sample, ntiles, tile_x, rows, lam_in, hist_slot, kn, fc, st)
     switch (bcx * 2 + bcy) {
     case 0: return LBK_BADJ(BC_PERIODIC, BC_PERIODIC);
     case 1: return LBK_BADJ(BC_PERIODIC, BC_WALL);

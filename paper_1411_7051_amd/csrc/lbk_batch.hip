@@ -816,9 +816,12 @@ lbk_status lbk_batch_adjoint_backward(lbk_batch *b, void *ws, size_t ws_bytes,
         return launch_batch_rec_sweep(d.storage, d.bc_x, d.bc_y, table, map, nt, tx, rows, src,
                                       dst, slot, st);
     };
+    int fc = 0;
+    for (int i = 0; i < b->n; ++i)
+        fc |= b->lats[i]->d.f_eps != 0.0;
     auto reverse = [&](int lam_in, int slot) {
         return launch_batch_adjoint(d.bc_x, d.bc_y, table, map, nt, tx, rows, lam_in, slot, knf,
-                                    st);
+                                    fc, st);
     };
     HIP_TRY(launch_batch_grad(table, map, nt, tx, rows, 0, knf, st));
     // read-out of J at step n: linearisation point of the pull of S_n
