@@ -228,6 +228,25 @@ def test_batch_gradient_bitwise_equals_solo(dev, storage, bcx, bcy, obj, ck, hl)
         assert lats[i].time == solo.time == 5 + steps
 
 
+def test_batch_gradient_mixed_forchheimer(dev):
+    """A batch where some samples have the Forchheimer term on runs the
+    reverse step that can differentiate it for every sample; the Darcy
+    samples still get bitwise the gradients of their own lattices."""
+    cs = cases(2, 1, seed=970)
+    cs = [c for c in cs if c.eps.shape[1] >= 3]
+    for i, c in enumerate(cs):
+        c.params["f_eps"] = 0.7 if i % 2 else 0.0
+    steps = 20
+    b = Batch(ensemble_lattices(cs, device=dev))
+    J, g, gk = b.gradient(steps, "k_app", ckpt_every=8, hist_len=3, wrt_kn0=True)
+    for i, c in enumerate(cs):
+        solo = Lattice(c.eps, c.k, c.kn0, device=dev, **c.params)
+        Js, gs, gks = solo.gradient(steps, "k_app", ckpt_every=8, hist_len=3, wrt_kn0=True)
+        assert J[i] == Js, i
+        assert torch.equal(g[i], gs), (i, float((g[i] - gs).abs().max()))
+        assert torch.equal(gk[i], gks), i
+
+
 def test_batch_gradient_kept_segments(dev):
     """A batched gradient workspace beyond the minimum keeps the inner
     checkpoints of more trailing segments; J and the gradients stay bitwise
