@@ -225,3 +225,18 @@ def test_zero_and_negative_steps(dev):
     with pytest.raises(LbkError) as e:
         lat.step(-1)
     assert e.value.status == -1 and lat.time == 3
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-7), ("f16", 2e-6)])
+def test_pressure_columns_hold_their_density(dev, storage, tol):
+    """As in the oracle: after every step the end columns hold rho_in and
+    rho_out (their populations sum to the boundary density; FP32 density
+    plane plus rounded deviations)."""
+    case = inputs.random_medium(70, 11, seed=17, solid_frac=0.05, bc_x=2, bc_y=1,
+                                rho_in=1.03, rho_out=0.99, init=1, kn_range=(0.0, 2.0))
+    lat = Lattice(case.eps, case.k, case.kn0, device=dev, storage=storage, **case.params)
+    for _ in range(3):
+        lat.step(9)
+        rho = lat.populations().sum(dim=0).cpu().numpy()
+        assert np.allclose(rho[:, 0], 1.03, rtol=tol, atol=0)
+        assert np.allclose(rho[:, -1], 0.99, rtol=tol, atol=0)

@@ -142,3 +142,29 @@ def test_rejects_invalid():
         oracle.Lattice3(*_fields(2, 2, 2, 1.5, 1.0))
     with pytest.raises(ValueError):
         oracle.Lattice3(*_fields(2, 2, 2, 0.5, 1.0), bc_z=2)
+
+
+@pytest.mark.parametrize("bc_y,bc_z", [(oracle.PERIODIC, oracle.PERIODIC),
+                                       (oracle.WALL, oracle.WALL)])
+def test_axis_permutation_symmetry(bc_y, bc_z):
+    """The D3Q19 set is closed under swapping the y and z axes, and so is the
+    model: a heterogeneous medium with its y and z axes swapped, and the
+    force components swapped with them, gives the swapped flow.  A velocity
+    or opposite-direction table inconsistent in one direction breaks this."""
+    rng = np.random.default_rng(31)
+    s = (5, 7, 9)  # nz, ny, nx
+    eps = rng.uniform(0.3, 1.0, s)
+    k = np.exp(rng.uniform(np.log(0.05), np.log(2.0), s))
+    kn0 = rng.uniform(0.0, 1.0, s)
+    eps[2, 3, 4], k[2, 3, 4] = 0.0, 1.0      # an impermeable node
+    eps[1, 5, 2], k[1, 5, 2] = 1.0, np.inf   # a free-fluid node
+    kw = dict(gx=2e-4, gy=5e-5, gz=-3e-5, bc_y=bc_y, bc_z=bc_z)
+    a = oracle.Lattice3(eps, k, kn0, **kw).step(40)
+    sw = lambda f: np.ascontiguousarray(np.swapaxes(f, 0, 1))
+    kw2 = dict(gx=2e-4, gy=-3e-5, gz=5e-5, bc_y=bc_z, bc_z=bc_y)
+    b = oracle.Lattice3(sw(eps), sw(k), sw(kn0), **kw2).step(40)
+    ra, uxa, uya, uza = a.macro()
+    rb, uxb, uyb, uzb = b.macro()
+    scale = np.max(np.abs(uxa))
+    for p, q in [(ra, rb), (uxa, uxb), (uya, uzb), (uza, uyb)]:
+        assert np.max(np.abs(sw(p) - q)) <= 1e-12 * max(scale, 1.0)

@@ -522,3 +522,26 @@ def test_pressure_start_agrees_with_boundary_densities():
     rho, ux, _ = lat.macro()
     assert np.allclose(rho[:, 0], 1.04, rtol=1e-15)
     assert np.allclose(rho[:, -1], 1.0, rtol=1e-15)
+
+
+def test_pressure_columns_hold_their_density():
+    """The non-equilibrium extrapolation sets the end columns' populations
+    to f_eq(rho_b, u_n) + f(n) - f_eq(rho_n, u_n): their sum is rho_b
+    whatever the neighbour's state (the non-equilibrium part has zero mass),
+    and the collision conserves it, so after every step the stored density
+    of column 0 is rho_in and of column nx-1 is rho_out (Sec. IV.A pressure
+    difference), on a heterogeneous medium with walls."""
+    rng = np.random.default_rng(41)
+    ny, nx = 9, 17
+    eps = rng.uniform(0.3, 1.0, (ny, nx))
+    k = np.exp(rng.uniform(np.log(0.01), np.log(1.0), (ny, nx)))
+    kn0 = rng.uniform(0.0, 2.0, (ny, nx))
+    lat = oracle.Lattice(eps, k, kn0, bc_x=oracle.PRESSURE, bc_y=oracle.WALL, rho_in=1.03,
+                         rho_out=0.99, init=1)
+    for _ in range(3):
+        lat.step(7)
+        f = lat.state()
+        rho = f.sum(axis=0)
+        assert np.allclose(rho[:, 0], 1.03, rtol=1e-14, atol=0)
+        assert np.allclose(rho[:, -1], 0.99, rtol=1e-14, atol=0)
+        assert np.max(np.abs(rho[:, 1:-1] - 1.0)) > 1e-4  # the interior moves
