@@ -23,7 +23,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.environ.get("LBO_SRC", os.path.join(_HERE, "lbo.c"))
-_SRC3 = os.path.join(_HERE, "lbo3.c")
+_SRC3 = os.environ.get("LBO_SRC3", os.path.join(_HERE, "lbo3.c"))
 _LIB = os.environ.get("LBO_LIB", os.path.join(_HERE, "liblbo.so"))
 
 PERIODIC, WALL, PRESSURE = 0, 1, 2

@@ -168,3 +168,23 @@ def test_axis_permutation_symmetry(bc_y, bc_z):
     scale = np.max(np.abs(uxa))
     for p, q in [(ra, rb), (uxa, uxb), (uya, uzb), (uza, uyb)]:
         assert np.max(np.abs(sw(p) - q)) <= 1e-12 * max(scale, 1.0)
+
+
+def test_impermeable_node_is_infinite_drag_limit():
+    """eps = 0 nodes behave as the limit k -> 0 of a permeable node (Sec.
+    III: infinite drag; R7), whatever that node's porosity: a block of
+    impermeable nodes and the same block with k = 1e-13 give the same
+    populations."""
+    rng = np.random.default_rng(8)
+    s = (6, 7, 9)
+    eps = rng.uniform(0.3, 1.0, s)
+    k = np.exp(rng.uniform(np.log(0.05), np.log(2.0), s))
+    kn0 = rng.uniform(0.0, 1.0, s)
+    e0, k0 = eps.copy(), k.copy()
+    e0[2:4, 2:5, 3:6] = 0.0
+    k1 = k.copy()
+    k1[2:4, 2:5, 3:6] = 1e-13
+    kw = dict(gx=1e-4, gy=3e-5, gz=-2e-5, bc_y=oracle.WALL)
+    a = oracle.Lattice3(e0, k0, kn0, **kw).step(200).state()
+    b = oracle.Lattice3(eps, k1, kn0, **kw).step(200).state()
+    assert np.max(np.abs(a - b)) < 1e-12
