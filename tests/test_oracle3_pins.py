@@ -188,3 +188,36 @@ def test_impermeable_node_is_infinite_drag_limit():
     a = oracle.Lattice3(e0, k0, kn0, **kw).step(200).state()
     b = oracle.Lattice3(eps, k1, kn0, **kw).step(200).state()
     assert np.max(np.abs(a - b)) < 1e-12
+
+
+def test_pressure_plane_next_to_equilibrium_is_own_equilibrium():
+    """The inlet/outlet scheme in three dimensions: a pressure plane takes its
+    own equilibrium at the imposed density and the neighbour's velocity plus
+    the neighbour's non-equilibrium part, so next to a neighbour whose pulled
+    populations are an equilibrium, in free fluid without a body force, it
+    holds exactly its own equilibrium after the step: density rho_b,
+    momentum rho_b u and momentum flux cs^2 rho_b I + rho_b u u / eps_b with
+    the plane's own porosity (moment conditions of Eq. 14)."""
+    ex, ey, ez, _ = oracle.tables3()
+    E = np.stack([ex, ey, ez], axis=1).astype(float)
+    nz, ny, nx = 1, 1, 6
+    eps_col = np.array([0.5, 1.0, 1.0, 0.8, 0.8, 0.6])
+    eps = np.broadcast_to(eps_col, (nz, ny, nx)).copy()
+    k = np.full((nz, ny, nx), np.inf)
+    rho_in, rho_out, rho_n = 1.02, 0.99, 1.003
+    u = np.array([0.04, -0.03, 0.02])
+    lat = oracle.Lattice3(eps, k, None, tau=0.8, bc_x=oracle.PRESSURE, rho_in=rho_in,
+                          rho_out=rho_out)
+    f = np.empty((19, nz, ny, nx))
+    for x in range(nx):
+        f[:, 0, 0, x] = oracle.feq3(rho_n, u, 1.0 if x <= 2 else 0.8)
+    lat.set_state(f)
+    lat.step(1)
+    g = lat.state()
+    for x, rho_b in ((0, rho_in), (nx - 1, rho_out)):
+        fb = g[:, 0, 0, x]
+        assert math.isclose(fb.sum(), rho_b, rel_tol=1e-14)
+        assert np.allclose(E.T @ fb, rho_b * u, rtol=0, atol=1e-15)
+        pi = np.einsum("ia,ib,i->ab", E, E, fb)
+        ref = CS2 * rho_b * np.eye(3) + rho_b * np.outer(u, u) / eps_col[x]
+        assert np.allclose(pi, ref, rtol=0, atol=1e-15), (x, pi - ref)

@@ -10,7 +10,9 @@ mathematics fix rather than against the oracle's own formulas:
 * closed forms: the uniform-domain recurrence and its Darcy limit, the
   Forchheimer fixed point (Eq. 2), the Brinkman-Darcy channel (Eq. 20), the
   cubic law and the compressible Klinkenberg-Darcy column;
-* invariants: mass conservation, symmetry, impermeable-node limit.
+* invariants: mass conservation, symmetry, impermeable-node limit, pressure
+  columns that hold their density and, next to an equilibrium, their own
+  equilibrium.
 """
 import json
 import math
@@ -545,3 +547,38 @@ def test_pressure_columns_hold_their_density():
         assert np.allclose(rho[:, 0], 1.03, rtol=1e-14, atol=0)
         assert np.allclose(rho[:, -1], 0.99, rtol=1e-14, atol=0)
         assert np.max(np.abs(rho[:, 1:-1] - 1.0)) > 1e-4  # the interior moves
+
+
+def test_pressure_column_next_to_equilibrium_is_own_equilibrium():
+    """Reading of the inlet/outlet scheme (Sec. IV.A; the non-equilibrium
+    extrapolation): a pressure column takes its own equilibrium at the
+    imposed density and the neighbour's velocity, plus the neighbour's
+    non-equilibrium part.  Next to a neighbour whose pulled populations are
+    an equilibrium, in free fluid (k = inf, no drag) without a body force,
+    the column therefore holds exactly its own equilibrium after the step:
+    density rho_b, momentum rho_b u and momentum flux
+    cs^2 rho_b I + rho_b u u / eps_b with the column's own porosity (the
+    moment conditions of Eq. 14), which the collision leaves unchanged.
+    Built with columns whose porosity differs from their neighbours'."""
+    nx, ny = 6, 1
+    eps_col = np.array([0.5, 1.0, 1.0, 0.8, 0.8, 0.6])
+    eps = np.tile(eps_col, (ny, 1))
+    k = np.full((ny, nx), np.inf)
+    rho_in, rho_out, rho_n = 1.02, 0.99, 1.003
+    u = np.array([0.04, -0.03])
+    lat = oracle.Lattice(eps, k, None, tau=0.8, bc_x=oracle.PRESSURE, rho_in=rho_in,
+                         rho_out=rho_out)
+    # columns 0-2 feed column 1 (the inlet's neighbour), 3-5 feed column 4
+    f = np.empty((9, ny, nx))
+    for x in range(nx):
+        f[:, 0, x] = oracle.feq(rho_n, u[0], u[1], 1.0 if x <= 2 else 0.8)
+    lat.set_state(f)
+    lat.step(1)
+    g = lat.state()
+    for x, rho_b in ((0, rho_in), (nx - 1, rho_out)):
+        fb = g[:, 0, x]
+        assert math.isclose(fb.sum(), rho_b, rel_tol=1e-14)
+        assert np.allclose(E.T @ fb, rho_b * u, rtol=0, atol=1e-15)
+        pi = np.einsum("ia,ib,i->ab", E, E, fb)
+        ref = CS2 * rho_b * np.eye(2) + rho_b * np.outer(u, u) / eps_col[x]
+        assert np.allclose(pi, ref, rtol=0, atol=1e-15), (x, pi - ref)
