@@ -360,6 +360,10 @@ lbk_status lbk3_create(const lbk_desc3 *d, const float *eps, const float *k, con
 lbk_status lbk3_destroy(lbk_lattice3 *lat);
 lbk_status lbk3_step(lbk_lattice3 *lat, int64_t n);
 lbk_status lbk3_time(const lbk_lattice3 *lat, int64_t *t);
+/* FP16 storage: the exponent e of the power-of-two scale 2^e the stored
+ * deviations currently carry (20 at creation, re-centred by the state checks
+ * of check_every); 0 for FP32 and BF16. */
+lbk_status lbk3_scale_exponent(const lbk_lattice3 *lat, int32_t *e);
 /* rho and the three velocity components as [nz][ny][nx] float32 device
  * buffers (any may be NULL). */
 lbk_status lbk3_read_macroscopic(lbk_lattice3 *lat, float *rho, float *ux, float *uy,

@@ -131,6 +131,7 @@ _SIG = {
     "lbk3_destroy": (ctypes.c_int, [_P]),
     "lbk3_step": (ctypes.c_int, [_P, ctypes.c_int64]),
     "lbk3_time": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "lbk3_scale_exponent": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "lbk3_read_macroscopic": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "lbk3_read_populations": (ctypes.c_int, [_P, _P]),
     "lbk3_apparent_permeability": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),

@@ -345,6 +345,14 @@ lbk_status lbk3_time(const lbk_lattice3 *lat, int64_t *t)
     return LBK_OK;
 }
 
+lbk_status lbk3_scale_exponent(const lbk_lattice3 *lat, int32_t *e)
+{
+    if (!lat || !e)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    *e = lat->scale_exp;
+    return LBK_OK;
+}
+
 lbk_status lbk3_read_macroscopic(lbk_lattice3 *lat, float *rho, float *ux, float *uy, float *uz)
 {
     if (!lat)

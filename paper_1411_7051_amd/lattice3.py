@@ -99,6 +99,13 @@ class Lattice3:
         check(_lib.load().lbk3_time(self._handle(), ctypes.byref(t)))
         return int(t.value)
 
+    @property
+    def scale_exponent(self) -> int:
+        """FP16: e of the storage scale 2^e (0 for FP32 and BF16)."""
+        e = ctypes.c_int32()
+        check(_lib.load().lbk3_scale_exponent(self._handle(), ctypes.byref(e)))
+        return int(e.value)
+
     def macroscopic(self):
         """(rho, ux, uy, uz) as [nz][ny][nx] float32 device tensors."""
         out = [torch.empty((self.nz, self.ny, self.nx), dtype=torch.float32, device=self.device)

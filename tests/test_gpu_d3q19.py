@@ -233,3 +233,29 @@ def test_pressure_planes_with_porosity_contrast(dev):
     g, r = np3(lat), ref.macro()
     assert rel_vel(g, r) <= VEL_TOL["f32"]
     assert np.max(np.abs(g[0] - r[0])) < 1e-6
+
+
+def test_fp16_scale_recentring(dev):
+    """FP16 deviations are stored times 2^e, and a state check re-centres e
+    (a power-of-two rescale, exact).  A run with checks every 40 steps (whose
+    exponent moves) and one without agree to the subnormal quantum of the
+    starting scale 2^20, carried through the steps, and the checked run is
+    still within the FP16 parity bound of the oracle."""
+    case = inputs.random_medium3(64, 16, 12, seed=741, solid_frac=0.05, pore_frac=0.05,
+                                 bc_x=2, bc_y=1, rho_in=1.01, rho_out=1.0, init=1)
+    steps = 240
+    plain = Lattice3(case.eps, case.k, case.kn0, device=dev, storage="f16", check_every=0,
+                     **case.params)
+    checked = Lattice3(case.eps, case.k, case.kn0, device=dev, storage="f16", check_every=40,
+                       **case.params)
+    e0 = plain.scale_exponent
+    plain.step(steps)
+    checked.step(steps)
+    assert plain.scale_exponent == e0 == 20 and checked.scale_exponent != e0
+    fa, fb = plain.populations(), checked.populations()
+    diff = float((fa - fb).abs().max())
+    same = float((fa == fb).double().mean())
+    print(f"max |df| {diff:.3e}, identical {same:.6f}")
+    assert diff <= steps * 16 * 2.0 ** -44
+    ref = oracle.Lattice3(case.eps, case.k, case.kn0, **case.params).step(steps)
+    assert rel_vel(np3(checked), ref.macro()) <= VEL_TOL["f16"]
