@@ -221,3 +221,44 @@ def test_pressure_plane_next_to_equilibrium_is_own_equilibrium():
         pi = np.einsum("ia,ib,i->ab", E, E, fb)
         ref = CS2 * rho_b * np.eye(3) + rho_b * np.outer(u, u) / eps_col[x]
         assert np.allclose(pi, ref, rtol=0, atol=1e-15), (x, pi - ref)
+
+
+def test_forchheimer_fixed_point():
+    """Eq. 2 with the Forchheimer term in three dimensions: a uniform periodic
+    medium driven along an arbitrary direction settles at a velocity parallel
+    to G whose magnitude solves (nu/k_a)|u| + (F_eps/sqrt(k_a))|u|^2 = |G|."""
+    eps, k, kn0, f_eps, tau = 0.6, 0.5, 0.3, 0.7, 0.9
+    G = 1e-3 * np.array([0.6, -0.48, 0.64])  # |G| = 1e-3
+    nu = (tau - 0.5) / 3
+    lat = oracle.Lattice3(*_fields(2, 2, 2, eps, k, kn0), tau=tau, gx=G[0], gy=G[1], gz=G[2],
+                          f_eps=f_eps)
+    lat.step(3000)
+    _, ux, uy, uz = lat.macro()
+    ka = k * oracle.fc(kn0)
+    a, b_, c = f_eps / math.sqrt(ka), nu / ka, -np.linalg.norm(G)
+    s = (-b_ + math.sqrt(b_ * b_ - 4 * a * c)) / (2 * a)
+    want = s * G / np.linalg.norm(G)
+    for comp, w in zip((ux, uy, uz), want):
+        assert np.allclose(comp, w, rtol=1e-10)
+    # the Forchheimer term matters at this flow rate
+    assert abs(s - ka * np.linalg.norm(G) / nu) / s > 1e-2
+
+
+def test_pressure_planes_hold_their_density():
+    """The extrapolation sets the end planes to f_eq(rho_b, u_n) + f(n) -
+    f_eq(rho_n, u_n), whose sum is rho_b whatever the neighbour's state, and
+    the collision conserves it: after every step the density of plane 0 is
+    rho_in and of plane nx-1 rho_out, on a heterogeneous medium with walls."""
+    rng = np.random.default_rng(42)
+    nz, ny, nx = 4, 5, 11
+    eps = rng.uniform(0.3, 1.0, (nz, ny, nx))
+    k = np.exp(rng.uniform(np.log(0.01), np.log(1.0), (nz, ny, nx)))
+    kn0 = rng.uniform(0.0, 2.0, (nz, ny, nx))
+    lat = oracle.Lattice3(eps, k, kn0, bc_x=oracle.PRESSURE, bc_y=oracle.WALL, bc_z=oracle.WALL,
+                          rho_in=1.03, rho_out=0.99, init=1)
+    for _ in range(3):
+        lat.step(7)
+        rho = lat.state().sum(axis=0)
+        assert np.allclose(rho[:, :, 0], 1.03, rtol=1e-14, atol=0)
+        assert np.allclose(rho[:, :, -1], 0.99, rtol=1e-14, atol=0)
+        assert np.max(np.abs(rho[:, :, 1:-1] - 1.0)) > 1e-4  # the interior moves
