@@ -4,15 +4,15 @@ arXiv:1411.7051).
 
 The fused D2Q9 sweep and its read-outs are HIP kernels for gfx950 behind the
 C ABI of ``include/lbk.h`` (``liblbk.so``, built by ``build.py``);
-``Lattice`` and ``Batch`` (ensembles stepped together) are thin ctypes
-bindings over it; ``units`` maps physical conditions (Eqs. 9-11) to lattice
-inputs.  ``inputs`` draws the seeded
-synthetic media.
+``Lattice``, ``Batch`` (ensembles stepped together) and ``Lattice3`` (the
+same model on a D3Q19 lattice) are thin ctypes bindings over it; ``units``
+maps physical conditions (Eqs. 9-11) to lattice inputs.  ``inputs`` draws the
+seeded synthetic media.
 """
 from . import inputs  # noqa: F401
 
-__all__ = ["Lattice", "Batch", "ApparentPermeability", "inputs", "units", "make_desc",
-           "workspace_bytes"]
+__all__ = ["Lattice", "Batch", "Lattice3", "ApparentPermeability", "inputs", "units",
+           "make_desc", "workspace_bytes"]
 
 
 def __getattr__(name):
@@ -22,6 +22,9 @@ def __getattr__(name):
     if name == "Batch":
         from .batch import Batch
         return Batch
+    if name == "Lattice3":
+        from .lattice3 import Lattice3
+        return Lattice3
     if name == "units":
         import importlib
         return importlib.import_module(".units", __name__)
