@@ -94,7 +94,10 @@ typedef struct lbk_lattice lbk_lattice;
  * the second-order correlation with b = -1. */
 lbk_status lbk_desc_default(lbk_desc *d);
 
-/* Bytes of device workspace lbk_create needs for this description. */
+/* Bytes of device workspace lbk_create needs for this description.
+ * Size limits (LBK_ERR_UNSUPPORTED beyond them): at most 2^30 nodes with x
+ * padded to a multiple of 64, and rows of at most 107,374,144 nodes (the
+ * kernels address a row block with 32-bit offsets). */
 lbk_status lbk_workspace_size(const lbk_desc *d, size_t *bytes);
 
 /* Create a lattice.  eps, k, kn0: [ny][nx] float32 arrays in host or device
@@ -353,6 +356,8 @@ typedef struct lbk_lattice3 lbk_lattice3;
 
 /* Defaults: periodic, FP32, tau 0.8, rho 1, no force, local Kn, Eqs. 6-7. */
 lbk_status lbk3_desc_default(lbk_desc3 *d);
+/* Limits: at most 2^30 nodes (x padded to 64), ny nz <= 2^24, rows of at
+ * most 53,687,040 nodes. */
 lbk_status lbk3_workspace_size(const lbk_desc3 *d, size_t *bytes);
 /* As lbk_create, with fields [nz][ny][nx]. */
 lbk_status lbk3_create(const lbk_desc3 *d, const float *eps, const float *k, const float *kn0,

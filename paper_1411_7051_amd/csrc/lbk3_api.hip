@@ -61,6 +61,11 @@ lbk_status check_desc3(const lbk_desc3 *d)
         (int64_t)d->ny * d->nz > (int64_t)1 << 24)
         return fail(LBK_ERR_UNSUPPORTED, "lattice of %d x %d x %d is too large", d->nx, d->ny,
                     d->nz);
+    // row blocks are reached through buffer resources with 32-bit offsets;
+    // the widest (an FP32 state row, 80 B per node) must fit
+    if ((uint64_t)align_up((size_t)d->nx, 64) * 80 > 0xFFFFFFFFull)
+        return fail(LBK_ERR_UNSUPPORTED, "rows of %d nodes exceed the 4 GiB a row block may span",
+                    d->nx);
     if (d->bc_x < 0 || d->bc_x > 2 || d->bc_y < 0 || d->bc_y > 1 || d->bc_z < 0 || d->bc_z > 1)
         return fail(LBK_ERR_INVALID_ARG, "bc_x must be 0..2, bc_y and bc_z 0..1");
     if (d->storage < 0 || d->storage > 2)

@@ -73,6 +73,11 @@ lbk_status check_desc(const lbk_desc *d)
         return fail(LBK_ERR_INVALID_ARG, "nx, ny must be >= 1 (got %d, %d)", d->nx, d->ny);
     if ((int64_t)align_up((size_t)d->nx, 64) * d->ny > (int64_t)1 << 30)
         return fail(LBK_ERR_UNSUPPORTED, "lattice of %d x %d exceeds 2^30 nodes", d->nx, d->ny);
+    // kernels reach every row block through a buffer resource with 32-bit
+    // offsets; the widest row (an FP32 state row, 40 B per node) must fit
+    if ((uint64_t)align_up((size_t)d->nx, 64) * 40 > 0xFFFFFFFFull)
+        return fail(LBK_ERR_UNSUPPORTED, "rows of %d nodes exceed the 4 GiB a row block may span",
+                    d->nx);
     if (d->bc_x < 0 || d->bc_x > 2 || d->bc_y < 0 || d->bc_y > 1)
         return fail(LBK_ERR_INVALID_ARG, "bc_x must be 0..2 and bc_y 0..1 (got %d, %d)",
                     d->bc_x, d->bc_y);

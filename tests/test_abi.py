@@ -113,6 +113,23 @@ def test_size_limit_3d():
         assert e.value.status == -5
 
 
+def test_row_width_limit():
+    """Kernels address each row block with 32-bit buffer offsets, so a row's
+    widest form (FP32 state, 40 B per node in 2-D, 80 B in 3-D) must stay
+    under 4 GiB: the widest accepted rows are 107,374,144 and 53,687,040
+    nodes (pitch a multiple of 64), whatever the storage type."""
+    from paper_1411_7051_amd.lattice3 import make_desc3, workspace_bytes3
+    for storage in ("f32", "f16"):
+        workspace_bytes(make_desc(107374144, 1, storage=storage))
+        with pytest.raises(_lib.LbkError) as e:
+            workspace_bytes(make_desc(107374145, 1, storage=storage))
+        assert e.value.status == -5
+        workspace_bytes3(make_desc3(53687040, 1, 1, storage=storage))
+        with pytest.raises(_lib.LbkError) as e:
+            workspace_bytes3(make_desc3(53687041, 1, 1, storage=storage))
+        assert e.value.status == -5
+
+
 def test_null_arguments_rejected():
     lib = _lib.load()
     assert lib.lbk_step(None, 1) == -1
