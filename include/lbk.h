@@ -76,7 +76,10 @@ typedef struct lbk_desc {
                             ramp rho_in -> rho_out along x */
     int32_t check_every; /* lbk_step checks the state for NaN/Inf (and, for
                             FP16, re-centres the scale) every this many
-                            steps; 0 = never */
+                            steps; 0 = never.  FP16 starts at the scale
+                            2^20, which holds deviations from 2^-34 to
+                            2^-4 at full precision; runs that may leave
+                            that range need checks to move the scale */
     double tau;          /* BGK relaxation time (Eq. 12), > 1/2 */
     double gx, gy;       /* external acceleration G (Eqs. 2, 8) */
     double f_eps;        /* Forchheimer geometric function (Eq. 2); 0 = Eq. 8 */
