@@ -372,3 +372,37 @@ def test_fullsize_shale_20000_steps_directional(dev, shale8192):
     print(f"20000-step gradient: <g, d> = {dot:.6e}, central difference = {fd:.6e}, "
           f"relative difference {abs(fd - dot) / abs(dot):.2e}", flush=True)
     assert abs(fd - dot) <= 1e-3 * abs(dot), (fd, dot, J0)
+
+
+def test_backward_refuses_a_stale_forward(dev):
+    """lbk_adjoint_backward differentiates the last lbk_adjoint_forward on the
+    same workspace with the lattice where that forward left it: a backward
+    with no forward, another workspace, or a step in between are rejected
+    (status LBK_ERR_INVALID_ARG) without touching the state; the forward's
+    own workspace then still gives the gradient of an undisturbed run."""
+    from paper_1411_7051_amd._lib import LbkError
+    case = inputs.random_medium(40, 12, seed=902, bc_x=inputs.PRESSURE, bc_y=inputs.WALL,
+                                rho_in=1.02, rho_out=1.0, init=1)
+    ref = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+    J_ref, ws_ref = ref.adjoint_forward(30, "k_app", 10, 10)
+    g_ref = ref.adjoint_backward(ws_ref)
+
+    lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
+    other = torch.empty(lat.adjoint_workspace_bytes(30, 10, 10), dtype=torch.uint8,
+                        device=dev)
+    with pytest.raises(LbkError) as e:
+        lat.adjoint_backward(other)  # no forward yet
+    assert e.value.status == -1
+    J, ws = lat.adjoint_forward(30, "k_app", 10, 10)
+    s30 = lat.save_state().clone()
+    with pytest.raises(LbkError) as e:
+        lat.adjoint_backward(other)  # not the forward's workspace
+    assert e.value.status == -1
+    assert torch.equal(lat.save_state(), s30)
+    g = lat.adjoint_backward(ws)  # still valid after the refusals
+    assert J == J_ref and torch.equal(g, g_ref)
+    lat.step(1)
+    with pytest.raises(LbkError) as e:
+        lat.adjoint_backward(ws)  # the lattice moved since the forward
+    assert e.value.status == -1
+    assert lat.time == 31
