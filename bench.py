@@ -177,6 +177,7 @@ def time_adjoint(n, steps, ckpt, hist, device):
     t = time.perf_counter()
     case = inputs.shale(n=n, seed=3)
     log(f"shale inputs: {case.nodes} nodes in {time.perf_counter() - t:.1f} s")
+    torch.cuda.reset_peak_memory_stats(device)
     lat = Lattice(case.eps, case.k, case.kn0, device=device, **case.params)
     st = lat.stream
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
@@ -211,6 +212,7 @@ def time_adjoint(n, steps, ckpt, hist, device):
         "ckpt_every": ckpt,
         "hist_len": hist,
         "workspace_GB": ws.numel() / 1e9,
+        "peak_device_mem_GB": torch.cuda.max_memory_allocated(device) / 1e9,
         "t_fwd_ms": t_fwd,
         "t_fwd_ckpt_ms": t_af,
         "t_grad_ms": t_bwd,
