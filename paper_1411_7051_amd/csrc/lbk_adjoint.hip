@@ -14,7 +14,8 @@
 // C depends on f only through rho = sum f and j = sum f e, so
 //   lam_f_k = (1 - omega) mu_k + G_rho + e_k . G_j
 // with G_rho, G_j the total derivatives of Psi = sum_i mu_i (omega f^eq_i + F_i)
-// through u(rho, j, ln k), F = -A u + eps G, A = eps nu / (k f_c(Kn)) and
+// through u(rho, j, ln k), F = -A u - B |u| u + eps G (Eq. 2; B = 0 without
+// the Forchheimer term), A = eps nu / (k f_c(Kn)) and
 // Kn = kn0 rho_ref / rho (so dA/d ln k = -A and dA/d ln kn0 =
 // -A Kn f_c'(Kn) / f_c, which varies with rho from step to step and needs a
 // gradient plane of its own); the linearisation point (rho, j) of every step is
@@ -34,8 +35,9 @@
 // recomputed segment (at most a few hundred steps) and folded into an FP64
 // total at the segment's end.  The
 // adjoint state and the history are each read once, so they stream
-// nontemporally.  The Forchheimer term is not differentiated (the host
-// rejects f_eps != 0).
+// nontemporally.  With the Forchheimer term on, the quadratic velocity solve
+// of Eq. 2 is differentiated as well (template flag FC; without it the
+// Darcy path alone is compiled).
 #include "lbk_adjoint.h"
 #include "lbk_kernels.h"
 

@@ -59,28 +59,6 @@ struct AdjPlan {
     int outlet;
 };
 
-// Global permeability (Sec. IV.A, Darcy's law) from read-out sums
-// (MAC_* slots over every node).
-double k_app_of(const lbk_lattice *lat, const double *sums);
-
-// Workspace offsets of a gradient over n steps, checkpoints every c1,
-// history c2 at a time (1 <= c2 <= c1).  The inner checkpoints come last:
-// the minimum (total) holds those of one segment; with ws_bytes >= total,
-// adj_keep sets how many trailing segments' inner checkpoints fit (keep)
-// and the bytes they use.
-lbk_status adj_plan(const lbk_lattice *lat, int64_t n, int64_t c1, int64_t c2, AdjPlan &P);
-void adj_keep(AdjPlan &P, size_t ws_bytes);
-// Plain sweeps the backward pass spends rebuilding inner checkpoints.
-int64_t adj_rebuild_steps(const AdjPlan &P);
-
-// Gradients need f_eps = 0 and a drive the objective can be normalised by.
-lbk_status check_objective(const lbk_lattice *lat, int objective);
-
-// J from read-out sums, and its per-node weights: J = sum a1 rho u_x +
-// a2 u_x (a1 on column nx-1 only when outlet).
-double objective_weights(const lbk_lattice *lat, int objective, const double *sums, double &a1,
-                         double &a2, int &outlet);
-
 } // namespace lbk
 
 struct lbk_lattice {
@@ -137,7 +115,8 @@ void adj_keep(AdjPlan &P, size_t ws_bytes);
 // Plain sweeps the backward pass spends rebuilding inner checkpoints.
 int64_t adj_rebuild_steps(const AdjPlan &P);
 
-// Gradients need f_eps = 0 and a drive the objective can be normalised by.
+// Gradients need a known objective and, for the global permeability, a drive
+// it can be normalised by.
 lbk_status check_objective(const lbk_lattice *lat, int objective);
 
 // J from read-out sums, and its per-node weights: J = sum a1 rho u_x +
