@@ -142,7 +142,8 @@ lbk_status lbk_apparent_permeability(lbk_lattice *lat, double *k_app);
 
 /* FP64 diagnostics: total mass sum f*, x mass flux sum rho u_x, and the
  * residual ||u - u_prev|| / ||u|| against the velocity of the previous
- * lbk_diagnostics call on this handle (+inf on the first call).  Any
+ * lbk_diagnostics call on this handle (+inf on the first call; 0 when the
+ * velocity is zero now and was zero then, +inf when it fell to zero).  Any
  * pointer may be NULL.  Synchronizes the stream. */
 lbk_status lbk_diagnostics(lbk_lattice *lat, double *mass, double *flux_x,
                            double *residual);

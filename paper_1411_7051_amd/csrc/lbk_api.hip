@@ -417,7 +417,14 @@ lbk_status lbk_diagnostics(lbk_lattice *lat, double *mass, double *flux_x, doubl
     if (s != LBK_OK)
         return s;
     const double flux = lat->host[MAC_FLUX];
-    const double res = lat->have_prev ? sqrt(lat->host[MAC_DU2] / lat->host[MAC_U2]) : INFINITY;
+    // relative change of the velocity field; a field that is zero now and
+    // was zero before has not changed (0), one that fell to zero changed
+    // by everything it had (+inf)
+    const double du2 = lat->host[MAC_DU2], u2 = lat->host[MAC_U2];
+    const double res = !lat->have_prev ? INFINITY
+                       : u2 > 0.0      ? sqrt(du2 / u2)
+                       : du2 > 0.0     ? INFINITY
+                                       : 0.0;
     lat->have_prev = true;
     if (flux_x)
         *flux_x = flux;

@@ -3,6 +3,8 @@
 FP32 storage: velocity relative L2 <= 1e-5 against the oracle after the same
 number of steps on the same seeded inputs; populations compared element by
 element.  Sizes span several 256-wide blocks with a ragged tail."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -305,3 +307,32 @@ def test_pressure_columns_with_porosity_contrast(dev):
                                rho_out=1.0, init=1)
     case = inputs.Case(eps, k, np.zeros_like(eps), params, "porosity-contrast")
     compare(gpu_run(dev, case, 400), oracle_run(case, 400))
+
+
+def test_diagnostics(dev):
+    """lbk_diagnostics: the mass is the FP64 sum of the populations; the
+    x mass flux is sum rho u_x; the residual is ||u - u_prev|| / ||u|| over
+    the velocities read out at this call and the previous one (+inf on the
+    first call, 0 with no step in between), and 0 for a lattice whose
+    velocity stays zero (at rest, no drive)."""
+    case = inputs.random_medium(300, 20, seed=31, bc_x=inputs.PRESSURE, bc_y=inputs.WALL,
+                                rho_in=1.01, rho_out=1.0, init=1)
+    lat = gpu_run(dev, case, 50)
+    m, q, r = lat.diagnostics()
+    assert math.isinf(r)
+    f = lat.populations().cpu().numpy()
+    assert m == pytest.approx(float(f.sum()), rel=1e-12)
+    rho, ux, uy = macro_np(lat)
+    assert q == pytest.approx(float((rho * ux).sum()), rel=1e-6)
+    assert lat.diagnostics()[2] == 0.0
+    lat.step(10)
+    _, _, r2 = lat.diagnostics()
+    _, ux2, uy2 = macro_np(lat)
+    want = math.sqrt((((ux2 - ux) ** 2).sum() + ((uy2 - uy) ** 2).sum()) /
+                     ((ux2 ** 2).sum() + (uy2 ** 2).sum()))
+    assert 0 < r2 == pytest.approx(want, rel=1e-9)
+    rest = Lattice(case.eps, case.k, case.kn0, device=dev)  # periodic, no drive, rest
+    rest.step(5)
+    rest.diagnostics()
+    rest.step(5)
+    assert rest.diagnostics()[2] == 0.0
