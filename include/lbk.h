@@ -137,7 +137,9 @@ lbk_status lbk_read_populations(lbk_lattice *lat, double *f);
  * (Sec. IV.A): nu <u_x> / G_x for a body-force drive;
  * eps_b nu (nx-1) <rho u_x> / (cs^2 (rho_in - rho_out)) for a pressure
  * drive, eps_b being the mean porosity of the two pressure columns.
- * Means over every node, accumulated in FP64.  Synchronizes the stream. */
+ * Means over every node, accumulated in FP64.  LBK_ERR_INVALID_ARG
+ * without a drive to normalise by (rho_in == rho_out, or gx == 0 without
+ * pressure columns).  Synchronizes the stream. */
 lbk_status lbk_apparent_permeability(lbk_lattice *lat, double *k_app);
 
 /* FP64 diagnostics: total mass sum f*, x mass flux sum rho u_x, and the
@@ -290,8 +292,8 @@ lbk_status lbk_batch_set_graph_readout(lbk_batch *b, int32_t on);
 lbk_status lbk_batch_autotune(lbk_batch *b, int32_t reps, double *best_us);
 
 /* Global permeability of every sample (as lbk_apparent_permeability of
- * that lattice, bitwise) into host k_app[n], from one batched read-out.
- * Synchronizes the stream. */
+ * that lattice, bitwise) into host k_app[n], from one batched read-out;
+ * NaN for a sample without a drive.  Synchronizes the stream. */
 lbk_status lbk_batch_apparent_permeability(lbk_batch *b, double *k_app);
 
 /* NaN/Inf check of every sample (and FP16 scale re-centring); returns

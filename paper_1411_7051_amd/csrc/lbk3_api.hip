@@ -382,6 +382,9 @@ lbk_status lbk3_apparent_permeability(lbk_lattice3 *lat, double *k_app)
 {
     if (!lat || !k_app)
         return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    if (lat->d.bc_x == LBK_BC_PRESSURE ? lat->d.rho_in == lat->d.rho_out : lat->d.gx == 0.0)
+        return fail(LBK_ERR_INVALID_ARG, "the global permeability needs rho_in != rho_out "
+                                         "(pressure drive) or gx != 0");
     lbk_status s = lbk3_read_macroscopic(lat, nullptr, nullptr, nullptr, nullptr);
     if (s != LBK_OK || (s = fetch3(lat, MAC_SLOTS, 0)) != LBK_OK)
         return s;

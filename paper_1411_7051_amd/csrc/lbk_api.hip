@@ -374,10 +374,17 @@ lbk_status lbk_read_populations(lbk_lattice *lat, double *f)
 
 } // extern "C"
 
+bool lbk::has_drive(const lbk_desc &d)
+{
+    return d.bc_x == LBK_BC_PRESSURE ? d.rho_in != d.rho_out : d.gx != 0.0;
+}
+
 double lbk::k_app_of(const lbk_lattice *lat, const double *sums)
 {
     const lbk_desc &d = lat->d;
     const double n = (double)d.nx * d.ny, nu = (d.tau - 0.5) / 3.0;
+    if (!has_drive(d))
+        return NAN;
     if (d.bc_x == LBK_BC_PRESSURE)
         return lat->eps_b * nu * (d.nx - 1) * (sums[MAC_FLUX] / n) /
                ((1.0 / 3.0) * (d.rho_in - d.rho_out));
@@ -402,6 +409,9 @@ lbk_status lbk_apparent_permeability(lbk_lattice *lat, double *k_app)
 {
     if (!lat || !k_app)
         return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    if (!has_drive(lat->d))
+        return fail(LBK_ERR_INVALID_ARG, "the global permeability needs rho_in != rho_out "
+                                         "(pressure drive) or gx != 0");
     lbk_status s = macro_sums(lat, false);
     if (s != LBK_OK)
         return s;
@@ -606,9 +616,9 @@ lbk_status lbk::check_objective(const lbk_lattice *lat, int objective)
     const lbk_desc &d = lat->d;
     if (objective != LBK_OBJ_PERMEABILITY && objective != LBK_OBJ_OUTLET_FLUX)
         return fail(LBK_ERR_INVALID_ARG, "unknown objective %d", objective);
-    if (objective == LBK_OBJ_PERMEABILITY && d.bc_x != LBK_BC_PRESSURE && d.gx == 0.0)
-        return fail(LBK_ERR_INVALID_ARG, "the global permeability needs gx != 0 or a pressure "
-                                         "drive");
+    if (objective == LBK_OBJ_PERMEABILITY && !has_drive(d))
+        return fail(LBK_ERR_INVALID_ARG, "the global permeability needs rho_in != rho_out "
+                                         "(pressure drive) or gx != 0");
     return LBK_OK;
 }
 

@@ -101,8 +101,12 @@ lbk_status check_state(lbk_lattice *lat);
 // Read-out sums (MAC_* slots) of the current state into lat->host.
 lbk_status macro_sums(lbk_lattice *lat, bool residual);
 
+// Whether the run has a drive the global permeability is normalised by: a
+// pressure difference (pressure columns) or a body force along x.
+bool has_drive(const lbk_desc &d);
+
 // Global permeability (Sec. IV.A, Darcy's law) from read-out sums
-// (MAC_* slots over every node).
+// (MAC_* slots over every node); NaN without a drive.
 double k_app_of(const lbk_lattice *lat, const double *sums);
 
 // Workspace offsets of a gradient over n steps, checkpoints every c1,

@@ -336,3 +336,31 @@ def test_diagnostics(dev):
     rest.diagnostics()
     rest.step(5)
     assert rest.diagnostics()[2] == 0.0
+
+
+def test_permeability_needs_a_drive(dev):
+    """The global permeability is normalised by the drive: without one
+    (equal pressure-column densities, or no body force along x) the call is
+    refused, in 2-D and 3-D, and a batch reports NaN for such a sample."""
+    from paper_1411_7051_amd._lib import LbkError
+    from paper_1411_7051_amd.batch import Batch
+    from paper_1411_7051_amd.lattice3 import Lattice3
+    eps, k = np.full((6, 40), 0.5, np.float32), np.full((6, 40), 0.1, np.float32)
+    flat = Lattice(eps, k, None, device=dev, bc_x=inputs.PRESSURE, rho_in=1.0, rho_out=1.0)
+    side = Lattice(eps, k, None, device=dev, gy=1e-5)
+    good = Lattice(eps, k, None, device=dev, gx=1e-5)
+    for lat in (flat, side):
+        lat.step(3)
+        with pytest.raises(LbkError) as e:
+            lat.apparent_permeability()
+        assert e.value.status == -1
+        with pytest.raises(LbkError):
+            lat.gradient(4, "k_app", ckpt_every=2)
+    good.step(3)
+    kb = Batch([good, side]).apparent_permeability()
+    assert kb[0] == good.apparent_permeability() and math.isnan(kb[1])
+    e3, k3 = np.full((3, 4, 40), 0.5, np.float32), np.full((3, 4, 40), 0.1, np.float32)
+    flat3 = Lattice3(e3, k3, None, device=dev, bc_x=inputs.PRESSURE, rho_in=1.0, rho_out=1.0)
+    with pytest.raises(LbkError) as e:
+        flat3.apparent_permeability()
+    assert e.value.status == -1
