@@ -75,11 +75,15 @@ typedef struct lbk_desc {
     int32_t init;        /* 0: rest at rho0; 1: rest on the linear density
                             ramp rho_in -> rho_out along x */
     int32_t check_every; /* lbk_step checks the state for NaN/Inf (and, for
-                            FP16, re-centres the scale) every this many
-                            steps; 0 = never.  FP16 starts at the scale
-                            2^20, which holds deviations from 2^-34 to
-                            2^-4 at full precision; runs that may leave
-                            that range need checks to move the scale */
+                            FP16, re-centres the scale) whenever the
+                            lattice's time reaches a multiple of this
+                            (default 100; 0 = never).  Each check
+                            synchronizes the stream and reads the state
+                            once (about 1% of a step's traffic at 100).
+                            FP16 starts at the scale 2^20, which holds
+                            deviations from 2^-34 to 2^-4 at full
+                            precision; runs that leave that range need
+                            checks to move the scale */
     double tau;          /* BGK relaxation time (Eq. 12), > 1/2 */
     double gx, gy;       /* external acceleration G (Eqs. 2, 8) */
     double f_eps;        /* Forchheimer geometric function (Eq. 2); 0 = Eq. 8 */
@@ -94,7 +98,7 @@ typedef struct lbk_desc {
 typedef struct lbk_lattice lbk_lattice;
 
 /* Fill *d with defaults: periodic, FP32, tau 0.8, rho 1, no force, local Kn,
- * the second-order correlation with b = -1. */
+ * the second-order correlation with b = -1, state checks every 100 steps. */
 lbk_status lbk_desc_default(lbk_desc *d);
 
 /* Bytes of device workspace lbk_create needs for this description.
@@ -229,7 +233,7 @@ lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws_bytes, flo
 /* ---------------------------------------------------------------------
  * Ensembles: many independent samples stepped together.
  *
- * A batch groups n lattices of uneven size (Sec. IV.C: heterogeneous
+ * A batch groups n lattices of uneven size (independent heterogeneous
  * samples, each with its own fields, tau, drive and Kn scale) so that one
  * kernel launch advances every sample by one step.  The launch walks a list
  * of tiles -- tile_x consecutive x by `rows` consecutive y of one sample --
@@ -245,7 +249,8 @@ lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws_bytes, flo
  * keep working as handles: read-outs, save/load and lbk_step may be used
  * between batch calls.  All of them must share storage, bc_x, bc_y and
  * the stream they were created on; the batch works on that stream.
- * check_every is not applied by lbk_batch_step (see lbk_batch_check).
+ * check_every is not applied by lbk_batch_step: a caller that wants the
+ * state checks calls lbk_batch_check at its own interval.
  * --------------------------------------------------------------------- */
 typedef struct lbk_batch lbk_batch;
 
@@ -348,7 +353,8 @@ typedef struct lbk_desc3 {
     int32_t storage;          /* lbk_storage */
     int32_t kn_local;         /* 1: Kn = kn0 * rho_ref / rho; 0: Kn = kn0 */
     int32_t init;             /* 0: rest at rho0; 1: ramp rho_in -> rho_out in x */
-    int32_t check_every;      /* NaN check (and FP16 re-scaling) interval; 0 = never */
+    int32_t check_every;      /* NaN check (and FP16 re-scaling) at multiples of this
+                                 time (default 100); 0 = never */
     int32_t correlation;      /* lbk_correlation */
     int32_t reserved;         /* must be 0 */
     double tau;
@@ -360,7 +366,8 @@ typedef struct lbk_desc3 {
 
 typedef struct lbk_lattice3 lbk_lattice3;
 
-/* Defaults: periodic, FP32, tau 0.8, rho 1, no force, local Kn, Eqs. 6-7. */
+/* Defaults: periodic, FP32, tau 0.8, rho 1, no force, local Kn, Eqs. 6-7,
+ * state checks every 100 steps. */
 lbk_status lbk3_desc_default(lbk_desc3 *d);
 /* Limits: at most 2^30 nodes (x padded to 64), ny nz <= 2^24, rows of at
  * most 53,687,040 nodes. */

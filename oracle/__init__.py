@@ -105,6 +105,8 @@ def _load():
         lib.lbo_apparent_permeability.argtypes = [ctypes.c_void_p]
         lib.lbo_get_state.argtypes = [ctypes.c_void_p, _D]
         lib.lbo_set_state.argtypes = [ctypes.c_void_p, _D]
+        lib.lbo_residual.restype = ctypes.c_double
+        lib.lbo_residual.argtypes = [_D, _D, ctypes.c_size_t]
         lib.lbo_nonfinite.restype = ctypes.c_int
         lib.lbo_nonfinite.argtypes = [ctypes.c_void_p]
         P3 = ctypes.POINTER(_Params3)
@@ -241,6 +243,18 @@ class Lattice:
 
     def nonfinite(self) -> bool:
         return bool(_load().lbo_nonfinite(self._h))
+
+
+def residual(u, u_prev) -> float:
+    """Steady-state residual ||u - u_prev||_2 / ||u||_2 (FP64) between two
+    velocity read-outs, each a sequence of component arrays of one shape
+    (ux, uy) or (ux, uy, uz); 0 when both are zero, +inf when only u_prev
+    is non-zero."""
+    a = np.ascontiguousarray(np.stack([np.asarray(c, dtype=np.float64) for c in u]).ravel())
+    b = np.ascontiguousarray(np.stack([np.asarray(c, dtype=np.float64) for c in u_prev]).ravel())
+    if a.shape != b.shape:
+        raise ValueError("u and u_prev must have the same shape")
+    return _load().lbo_residual(_ptr(a), _ptr(b), a.size)
 
 
 def objective(lat: Lattice, name: str) -> float:

@@ -36,6 +36,8 @@
  *       ramp between rho_in and rho_out.
  *   R11 Global permeability: Darcy's law over the whole domain (Sec. IV.A),
  *       see lbo_apparent_permeability.
+ *   R13 Steady state (Sec. IV.A) is measured by the relative L2 change of
+ *       the velocity field between two read-outs, see lbo_residual.
  */
 #include "lbo.h"
 
@@ -414,6 +416,25 @@ double lbo_apparent_permeability(const lbo_lattice *L)
                ((1.0 / 3.0) * (p->rho_in - p->rho_out));
     }
     return nu * u / p->gx;
+}
+
+/* Steady-state residual of R13 (Sec. IV.A runs "to steady state" without
+ * defining the measure): the relative change of the velocity field between
+ * two read-outs, ||u - u_prev||_2 / ||u||_2, in FP64 over the n values of
+ * every velocity component of every node (u and u_prev hold the components
+ * one after another).  0 when both fields are zero; +inf when u is zero
+ * and u_prev is not. */
+double lbo_residual(const double *u, const double *u_prev, size_t n)
+{
+    double dd = 0.0, uu = 0.0;
+    for (size_t j = 0; j < n; ++j) {
+        double d = u[j] - u_prev[j];
+        dd += d * d;
+        uu += u[j] * u[j];
+    }
+    if (uu == 0.0)
+        return dd == 0.0 ? 0.0 : INFINITY;
+    return sqrt(dd / uu);
 }
 
 void lbo_get_state(const lbo_lattice *L, double *f)

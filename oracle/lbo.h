@@ -35,6 +35,8 @@
 #ifndef LBO_H
 #define LBO_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -102,6 +104,12 @@ double lbo_mass(const lbo_lattice *L);
 
 /* Global (apparent) permeability of the whole domain by Darcy's law. */
 double lbo_apparent_permeability(const lbo_lattice *L);
+
+/* Steady-state residual ||u - u_prev||_2 / ||u||_2 (FP64) between two
+ * velocity read-outs of n values each (components stacked; the same
+ * function serves the D3Q19 oracle); 0 when both are zero, +inf when only
+ * u_prev is non-zero. */
+double lbo_residual(const double *u, const double *u_prev, size_t n);
 
 /* Post-collision populations f*[9][ny][nx] (copy out / copy in). */
 void lbo_get_state(const lbo_lattice *L, double *f);

@@ -9,7 +9,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbk.so")
+# LBK_LIB points the binding at another build of the same library (the
+# host-sanitizer build of the tests)
+LIB_PATH = os.environ.get("LBK_LIB", os.path.join(HERE, "liblbk.so"))
 
 LBK_OK = 0
 STATUS = {

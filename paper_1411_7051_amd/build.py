@@ -25,6 +25,13 @@ FLAGS = [
 ]
 
 
+def libs() -> list:
+    """roctx (ranges around the host-side phases: stepping, gradients, graph
+    replays), found at run time through the ROCm library directory."""
+    lib = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib")
+    return [f"-L{lib}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{lib}"]
+
+
 def hipcc() -> str:
     rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
     return os.path.join(rocm, "bin", "hipcc")
@@ -34,7 +41,7 @@ def build(verbose: bool = False, extra=()) -> str:
     """Compile every source into ``liblbk.so`` (always recompiles)."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *FLAGS, "-I", INCLUDE, *extra, "-o", tmp, *srcs]
+    cmd = [hipcc(), *FLAGS, "-I", INCLUDE, *extra, "-o", tmp, *srcs, *libs()]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

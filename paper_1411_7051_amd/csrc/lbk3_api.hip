@@ -117,7 +117,6 @@ struct lbk_lattice3 {
     int scale_exp;
     double eps_b;
     double *host;
-    int64_t since_check;
 
     char *state(int l) const { return ws + L.level[l]; }
     char *med() const { return ws + L.med; }
@@ -178,6 +177,7 @@ lbk_status lbk3_desc_default(lbk_desc3 *d)
     d->nx = d->ny = d->nz = 1;
     d->storage = LBK_F32;
     d->kn_local = 1;
+    d->check_every = 100;
     d->tau = 0.8;
     d->rho_in = d->rho_out = d->rho0 = d->rho_ref = 1.0;
     d->slip_b = -1.0;
@@ -229,7 +229,6 @@ lbk_status lbk3_create(const lbk_desc3 *d, const float *eps, const float *k, con
     lat->cur = 0;
     lat->t = 0;
     lat->scale_exp = d->storage == LBK_F16 ? 20 : 0;
-    lat->since_check = 0;
     if (hipHostMalloc((void **)&lat->host, 8 * sizeof(double), hipHostMallocDefault) !=
         hipSuccess) {
         delete lat;
@@ -325,6 +324,7 @@ lbk_status lbk3_step(lbk_lattice3 *lat, int64_t n)
     if (n < 0)
         return fail(LBK_ERR_INVALID_ARG, "n must be >= 0");
     const lbk_desc3 &d = lat->d;
+    Range range("lbk3_step");
     for (int64_t i = 0; i < n; ++i) {
         const int nxt = lat->cur ^ 1;
         HIP_TRY(launch_sweep3(d.storage, d.bc_x, d.bc_y, d.bc_z, lat->state(lat->cur),
@@ -332,8 +332,9 @@ lbk_status lbk3_step(lbk_lattice3 *lat, int64_t n)
                               lat->p3, lat->s(), lat->inv_s(), lat->stream));
         lat->cur = nxt;
         ++lat->t;
-        if (d.check_every > 0 && ++lat->since_check >= d.check_every) {
-            lat->since_check = 0;
+        // checks fall on multiples of check_every in the lattice's own time,
+        // so a run resumed from a saved state checks where the original did
+        if (d.check_every > 0 && lat->t % d.check_every == 0) {
             lbk_status s = check_state3(lat);
             if (s != LBK_OK)
                 return s;

@@ -155,6 +155,7 @@ lbk_status lbk::check_state(lbk_lattice *lat)
             if (k != 0) {
                 HIP_TRY(launch_rescale(lat->d.storage, s, lat->L.lay, lat->g, k, lat->stream));
                 lat->scale_exp += k;
+                ++lat->version;
             }
         }
     }
@@ -173,7 +174,7 @@ lbk_status lbk_desc_default(lbk_desc *d)
     d->storage = LBK_F32;
     d->kn_local = 1;
     d->init = 0;
-    d->check_every = 0;
+    d->check_every = 100;
     d->tau = 0.8;
     d->rho_in = d->rho_out = d->rho0 = d->rho_ref = 1.0;
     d->slip_b = -1.0;
@@ -225,9 +226,9 @@ lbk_status lbk_create(const lbk_desc *d, const float *eps, const float *k, const
     lat->ws = static_cast<char *>(workspace);
     lat->cur = 0;
     lat->t = 0;
+    lat->version = 0;
     lat->scale_exp = d->storage == LBK_F16 ? 20 : 0;
     lat->have_prev = false;
-    lat->since_check = 0;
     if (hipHostMalloc((void **)&lat->host, 8 * sizeof(double), hipHostMallocDefault) !=
         hipSuccess) {
         delete lat;
@@ -327,6 +328,7 @@ lbk_status lbk_step(lbk_lattice *lat, int64_t n)
     if (n < 0)
         return fail(LBK_ERR_INVALID_ARG, "n must be >= 0");
     const lbk_desc &d = lat->d;
+    Range range("lbk_step");
     for (int64_t i = 0; i < n; ++i) {
         const int nxt = lat->cur ^ 1;
         HIP_TRY(launch_sweep(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->state(nxt),
@@ -334,8 +336,10 @@ lbk_status lbk_step(lbk_lattice *lat, int64_t n)
                              lat->inv_s(), nullptr, lat->stream));
         lat->cur = nxt;
         ++lat->t;
-        if (d.check_every > 0 && ++lat->since_check >= d.check_every) {
-            lat->since_check = 0;
+        ++lat->version;
+        // checks fall on multiples of check_every in the lattice's own time,
+        // so a run resumed from a saved state checks where the original did
+        if (d.check_every > 0 && lat->t % d.check_every == 0) {
             lbk_status s = check_state(lat);
             if (s != LBK_OK)
                 return s;
@@ -493,6 +497,7 @@ lbk_status lbk_load_state(lbk_lattice *lat, const void *src)
                            bytes - 64, hipMemcpyDefault, lat->stream));
     lat->t = hdr[1];
     lat->scale_exp = (int)hdr[2];
+    ++lat->version;
     lat->have_prev = false;
     return LBK_OK;
 }
@@ -685,6 +690,7 @@ extern "C" lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64
 {
     if (!lat || !ws || !J)
         return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    Range range("adjoint forward");
     const lbk_desc &d = lat->d;
     lbk_status s0 = check_objective(lat, objective);
     if (s0 != LBK_OK)
@@ -723,6 +729,7 @@ extern "C" lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64
                                  lat->ph, lat->s(), lat->inv_s(), nullptr, st));
             lat->cur = nxt;
             ++lat->t;
+            ++lat->version;
         }
     }
     if ((s = macro_sums(lat, false)) != LBK_OK)
@@ -789,6 +796,7 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
             nseg = (b - a + P.c2 - 1) / P.c2;
         } else if (P.two_level) {
             // rebuild the inner checkpoints of this outer segment
+            Range range("adjoint rebuild");
             const char *src = level(P.outer, k);
             int r = 0;
             nseg = 0;
@@ -812,10 +820,14 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
             const char *src = P.two_level ? level(inner, j) : level(P.outer, k);
             // recompute the segment, recording each step's linearisation point
             int r = 0;
-            for (int64_t t = a2s; t < b2s; ++t) {
-                HIP_TRY(sweep(t == a2s ? src : rec[r], rec[r ^ 1], histp(t - a2s + 1)));
-                r ^= 1;
+            {
+                Range range("adjoint recompute");
+                for (int64_t t = a2s; t < b2s; ++t) {
+                    HIP_TRY(sweep(t == a2s ? src : rec[r], rec[r ^ 1], histp(t - a2s + 1)));
+                    r ^= 1;
+                }
             }
+            Range range("adjoint reverse");
             for (int64_t t = b2s; t > a2s; --t) {
                 HIP_TRY(launch_adjoint(d.bc_x, d.bc_y, lam[cur], lam[cur ^ 1], histp(t - a2s),
                                        lat->med(), lat->L.mlay, seg, seg2, lat->g, lat->ph, 0,

@@ -179,6 +179,7 @@ struct lbk_batch {
     int cus;            // compute units of the device
     int parity;         // sample i's current level is state[parity] of its descriptor
     std::vector<int> cur0, scale0;
+    std::vector<uint64_t> ver0; // each lattice's version when the tables were last set
     Shape shape;        // sweep tiling
     int64_t sweep_tiles;
     std::vector<int64_t> tile0_sweep, tile0_read;
@@ -230,14 +231,16 @@ lbk_status upload_map(lbk_batch *b, Shape sh, int *map, std::vector<int64_t> &ti
 }
 
 // Bring the device descriptor tables in line with the lattices: a lattice
-// stepped, loaded or rescaled outside the batch changes which of its levels
-// is current or its FP16 scale.
+// stepped, loaded or rescaled outside the batch changes its version (and may
+// change which of its levels is current or its FP16 scale); then the tables
+// are re-uploaded and the cached read-out sums dropped.
 lbk_status sync_tables(lbk_batch *b, bool force)
 {
     bool stale = force;
     for (int i = 0; i < b->n && !stale; ++i) {
         const lbk_lattice *l = b->lats[i];
-        stale = l->cur != (b->cur0[i] ^ b->parity) || l->scale_exp != b->scale0[i];
+        stale = l->cur != (b->cur0[i] ^ b->parity) || l->scale_exp != b->scale0[i] ||
+                l->version != b->ver0[i];
     }
     if (!stale)
         return LBK_OK;
@@ -247,6 +250,7 @@ lbk_status sync_tables(lbk_batch *b, bool force)
         lbk_lattice *l = b->lats[i];
         b->cur0[i] = l->cur ^ b->parity;
         b->scale0[i] = l->scale_exp;
+        b->ver0[i] = l->version;
         for (int k = 0; k < 2; ++k) {
             const Shape sh = k == 0 ? b->shape : kReadShape;
             SampleDesc &sd = b->host_desc[(size_t)k * b->n + i];
@@ -392,6 +396,7 @@ lbk_status lbk_batch_create(lbk_lattice *const *lats, int32_t n, void *workspace
     b->parity = 0;
     b->cur0.assign(n, 0);
     b->scale0.assign(n, 0);
+    b->ver0.assign(n, 0);
     b->shape = Shape{0, 0};
     b->sweep_tiles = 0;
     b->grid = 0;
@@ -437,6 +442,7 @@ lbk_status lbk_batch_step(lbk_batch *b, int64_t n)
         if (b->graph_steps > 0 && left >= b->graph_steps) {
             if (!b->have_exec[b->parity] && (s = record_graph(b, b->parity)) != LBK_OK)
                 return s;
+            Range range("batch graph replay");
             HIP_TRY(hipGraphLaunch(b->exec[b->parity], b->stream));
             left -= b->graph_steps; // even: the parity is unchanged
             b->sums_fresh = b->graph_readout;
@@ -451,6 +457,8 @@ lbk_status lbk_batch_step(lbk_batch *b, int64_t n)
         lbk_lattice *l = b->lats[i];
         l->cur = b->cur0[i] ^ b->parity;
         l->t += n;
+        if (n > 0)
+            b->ver0[i] = ++l->version; // the batch's own change: tables stay valid
     }
     return LBK_OK;
 }
@@ -694,6 +702,7 @@ lbk_status lbk_batch_adjoint_forward(lbk_batch *b, int objective, int64_t n_step
         return fail(LBK_ERR_INVALID_ARG, "NULL argument");
     if ((uintptr_t)ws & 255u)
         return fail(LBK_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+    Range range("batch adjoint forward");
     for (int i = 0; i < b->n; ++i) {
         lbk_status s = check_objective(b->lats[i], objective);
         if (s != LBK_OK)
@@ -839,6 +848,7 @@ lbk_status lbk_batch_adjoint_backward(lbk_batch *b, void *ws, size_t ws_bytes,
             nseg = (e - a + A.c2 - 1) / A.c2;
         } else if (A.two_level) {
             // rebuild the inner checkpoints of this outer segment
+            Range range("batch adjoint rebuild");
             LevelSel src{ADJ_OUTER, (int)k};
             int r = 0;
             nseg = 0;
@@ -864,11 +874,15 @@ lbk_status lbk_batch_adjoint_backward(lbk_batch *b, void *ws, size_t ws_bytes,
             const LevelSel src = A.two_level ? LevelSel{ADJ_INNER, i0 + (int)j}
                                              : LevelSel{ADJ_OUTER, (int)k};
             int r = 0;
-            for (int64_t t = a2s; t < b2s; ++t) {
-                HIP_TRY(rec(t == a2s ? src : LevelSel{ADJ_REC, r}, LevelSel{ADJ_REC, r ^ 1},
-                            (int)(t - a2s + 1)));
-                r ^= 1;
+            {
+                Range range("batch adjoint recompute");
+                for (int64_t t = a2s; t < b2s; ++t) {
+                    HIP_TRY(rec(t == a2s ? src : LevelSel{ADJ_REC, r}, LevelSel{ADJ_REC, r ^ 1},
+                                (int)(t - a2s + 1)));
+                    r ^= 1;
+                }
             }
+            Range range("batch adjoint reverse");
             for (int64_t t = b2s; t > a2s; --t) {
                 HIP_TRY(reverse(cur, (int)(t - a2s)));
                 cur ^= 1;

@@ -7,10 +7,22 @@
 #include "lbk.h"
 #include "lbk_kernels.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <stddef.h>
 #include <stdint.h>
 
 namespace lbk {
+
+// A named roctx range for the lifetime of the object: the phases of a call
+// (stepping, checkpointed forward, rebuild, recompute, reverse, graph
+// replay) show up as ranges in a rocprofv3 --marker-trace.  Costs a call
+// into the roctx library per range, nothing on the device.
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
 
 // Record a formatted message as the calling thread's last error; returns s.
 lbk_status fail(lbk_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
@@ -74,11 +86,13 @@ struct lbk_lattice {
     char *ws;
     int cur;       // time level holding the current state
     int64_t t;     // steps taken
+    uint64_t version; // bumped by every change of the state (steps, loads,
+                      // rescaling), so a batch can tell that its cached
+                      // tables and read-out sums no longer describe it
     int scale_exp; // FP16: stored = h * 2^scale_exp
     bool have_prev;
     double eps_b;  // mean porosity of the two pressure columns
     double *host;  // pinned scratch for results (8 doubles)
-    int64_t since_check;
     AdjPlan adj;
 
     char *state(int l) const { return ws + L.level[l]; }

@@ -20,7 +20,7 @@ PERIODIC, WALL, PRESSURE = 0, 1, 2
 
 def make_desc(nx, ny, tau=0.8, gx=0.0, gy=0.0, f_eps=0.0, bc_x=PERIODIC,
               bc_y=PERIODIC, rho_in=1.0, rho_out=1.0, rho0=1.0, rho_ref=1.0,
-              kn_local=1, init=0, storage="f32", check_every=0, correlation=0,
+              kn_local=1, init=0, storage="f32", check_every=100, correlation=0,
               slip_b=-1.0) -> Desc:
     lib = _lib.load()
     d = Desc()

@@ -57,6 +57,49 @@ def window_oracle(case, xa, xb, ya, h, steps):
 
 
 
+def window_fd_outlet_flux(case, y, x, steps, h=1e-4):
+    """FP64 central difference, in ln k at node (y, x), of the outlet flux
+    sum_y' rho u_x(y', nx - 1) after `steps` steps of a pressure-driven
+    `case`, computed on a window instead of the whole medium.  The
+    perturbation reaches outlet rows within steps + 1 links of y; the window
+    (all columns within steps + 3 of the outlet, rows within 2 steps + 5 of
+    y, cut edges wrapped) keeps those rows exact, and every other window row
+    is the same in both runs, so its (inexact) contribution cancels in the
+    difference."""
+    ny, nx = case.eps.shape
+    xa = nx - 1 - (steps + 3)
+    if x < xa:
+        raise ValueError("node outside the outlet's light cone")
+    half = 2 * steps + 5
+    hgt = min(ny, 2 * half + 1)
+    ya = (y - half) % ny if hgt < ny else 0
+    rows = (ya + np.arange(hgt)) % ny
+    r = int(np.nonzero(rows == y)[0][0])
+    eps = np.ascontiguousarray(case.eps[rows][:, xa:], dtype=np.float64)
+    kn0 = np.ascontiguousarray(case.kn0[rows][:, xa:], dtype=np.float64)
+    k = np.ascontiguousarray(case.k[rows][:, xa:], dtype=np.float64)
+    p = dict(case.params)
+    xs = np.arange(xa, nx, dtype=np.float64)
+    rho0 = ramp(case, xs)
+    p["rho_in"] = float(rho0[0])
+    p["bc_y"] = inputs.PERIODIC
+    p["init"] = 0
+    f0 = W[:, None, None] * np.broadcast_to(rho0[None, None, :], (9, hgt, nx - xa))
+    vals = []
+    for sgn in (1.0, -1.0):
+        kk = k.copy()
+        kk[r, x - xa] *= np.exp(sgn * h)
+        lat = oracle.Lattice(eps, kk, kn0, **p)
+        lat.set_state(f0)
+        lat.step(steps)
+        rho, ux, _ = lat.macro()
+        # only the outlet rows the perturbation reaches: the others are the
+        # same in both runs and would add nothing but rounding
+        reach = slice(max(0, r - steps - 1), r + steps + 2)
+        vals.append(float(np.sum(rho[reach, -1] * ux[reach, -1])))
+    return (vals[0] - vals[1]) / (2.0 * h)
+
+
 def window3_oracle(case, xa, xb, ya, h, za, d, steps):
     """D3Q19 form: the oracle on columns [xa, xb), rows ya .. ya+h-1 and
     planes za .. za+d-1 (wrapped in y and z) of `case`, from its initial

@@ -14,7 +14,28 @@ from paper_1411_7051_amd.lattice import ApparentPermeability, Lattice
 
 pytestmark = pytest.mark.gpu
 
-GRAD_TOL = 1e-3  # relative to max |dJ/d ln k| (FP32 linearisation vs FP64 FD)
+GRAD_TOL = 1e-3  # FP32 linearisation vs FP64 FD: per node, relative to |fd|,
+NODE_FLOOR = 0.1  # on every sampled node with |fd| >= NODE_FLOOR max|g|; and
+                  # on every sampled node, relative to max|g|
+
+
+def check_fd(gg, fd, scale, what=""):
+    """The adjoint at the sampled nodes against finite differences: within
+    GRAD_TOL of |fd| at each node whose |fd| is at least NODE_FLOOR of the
+    largest gradient, and within GRAD_TOL of the largest gradient at every
+    sampled node.  Prints the worst per-node relative error."""
+    gg, fd = np.asarray(gg, dtype=np.float64), np.asarray(fd, dtype=np.float64)
+    assert scale > 0
+    err = np.abs(gg - fd)
+    big = np.abs(fd) >= NODE_FLOOR * scale
+    assert big.any()
+    rel = err[big] / np.abs(fd[big])
+    print(f"{what}: worst per-node relative error {rel.max():.2e} over {int(big.sum())} "
+          f"nodes with |fd| >= {NODE_FLOOR} max|g|; worst error / max|g| "
+          f"{err.max() / scale:.2e}", flush=True)
+    assert rel.max() <= GRAD_TOL, f"{what}: per-node relative error {rel.max():.3e}"
+    assert err.max() <= GRAD_TOL * scale, f"{what}: max |adjoint - fd| = {err.max():.3e}, " \
+        f"scale {scale:.3e}"
 
 
 @pytest.fixture(scope="module")
@@ -58,23 +79,25 @@ def test_gradient_matches_oracle_fd(dev, bcx, bcy, obj):
     cand = [c for c in cand if finite[c]]
     fd = oracle.fd_gradient(case.eps, case.k, case.kn0, N, cand, obj, h=1e-4, **case.params)
     gg = np.array([g[c] for c in cand])
-    scale = np.max(np.abs(g))
-    assert scale > 0
-    err = np.max(np.abs(gg - fd))
-    assert err <= GRAD_TOL * scale, f"max |adjoint - fd| = {err:.3e}, scale {scale:.3e}"
+    check_fd(gg, fd, np.max(np.abs(g)), f"d{obj}/dlnk bc ({bcx},{bcy})")
     # pores (k = inf) and impermeable nodes have no permeability to vary
     assert np.all(g[~finite] == 0.0)
 
 
-@pytest.mark.parametrize("bcx,bcy,obj,kn_local", [(2, 1, "k_app", 1), (2, 0, "q_out", 1),
-                                                 (0, 1, "k_app", 1), (2, 1, "k_app", 0)])
-def test_kn0_gradient_matches_oracle_fd(dev, bcx, bcy, obj, kn_local):
+@pytest.mark.parametrize("bcx,bcy,obj,kn_local,rho_ref",
+                         [(2, 1, "k_app", 1, 1.0), (2, 0, "q_out", 1, 1.0),
+                          (0, 1, "k_app", 1, 1.0), (2, 1, "k_app", 0, 1.0),
+                          (2, 1, "k_app", 1, 2.0), (0, 0, "k_app", 1, 0.5)])
+def test_kn0_gradient_matches_oracle_fd(dev, bcx, bcy, obj, kn_local, rho_ref):
     """dJ / d ln kn0 (k held fixed) against oracle finite differences in ln
-    kn0; asking for it leaves dJ / d ln k bitwise unchanged."""
+    kn0; asking for it leaves dJ / d ln k bitwise unchanged.  With kn0
+    quoted at rho_ref != 1 (Kn = kn0 rho_ref / rho, whose density
+    derivative enters every reverse step), dJ / d ln k is checked against
+    finite differences too."""
     nx, ny, N = 40, 12, 25
     case = inputs.random_medium(nx, ny, seed=330 + 7 * bcx + bcy + kn_local, solid_frac=0.05,
                                 pore_frac=0.05, kn_range=(0.05, 3.0), bc_x=bcx, bc_y=bcy,
-                                kn_local=kn_local, **drive_for(bcx))
+                                kn_local=kn_local, rho_ref=rho_ref, **drive_for(bcx))
     lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
     J, gk, gn = lat.gradient(N, obj, ckpt_every=10, hist_len=4, wrt_kn0=True)
     lat2 = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
@@ -91,10 +114,16 @@ def test_kn0_gradient_matches_oracle_fd(dev, bcx, bcy, obj, kn_local):
     fd = oracle.fd_gradient(case.eps, case.k, case.kn0, N, cand, obj, h=1e-4, wrt="kn0",
                             **case.params)
     gg = np.array([gn[c] for c in cand])
-    scale = np.max(np.abs(gn))
-    assert scale > 0
-    err = np.max(np.abs(gg - fd))
-    assert err <= GRAD_TOL * scale, f"max |adjoint - fd| = {err:.3e}, scale {scale:.3e}"
+    check_fd(gg, fd, np.max(np.abs(gn)), f"d{obj}/dlnkn0 rho_ref {rho_ref}")
+    if rho_ref != 1.0:
+        gk = gk.double().cpu().numpy()
+        porous = np.isfinite(case.k) & (case.eps > 0)
+        order = np.argsort(-np.abs(gk).ravel())
+        cand = [c for c in (divmod(int(i), nx) for i in order[:8]) if porous[c]]
+        fd = oracle.fd_gradient(case.eps, case.k, case.kn0, N, cand, obj, h=1e-4, wrt="k",
+                                **case.params)
+        check_fd(np.array([gk[c] for c in cand]), fd, np.max(np.abs(gk)),
+                 f"d{obj}/dlnk rho_ref {rho_ref}")
 
 
 @pytest.mark.parametrize("corr,slip_b", [(1, -1.0), (0, -0.3), (2, -1.0)])
@@ -117,10 +146,8 @@ def test_gradient_correlations(dev, corr, slip_b):
         cand = [divmod(int(i), nx) for i in order[:5]]
         fd = oracle.fd_gradient(case.eps, case.k, case.kn0, N, cand, "k_app", h=1e-4, wrt=wrt,
                                 **case.params)
-        scale = np.max(np.abs(g))
-        assert scale > 0
-        err = np.max(np.abs(np.array([g[c] for c in cand]) - fd))
-        assert err <= GRAD_TOL * scale, (wrt, err, scale)
+        check_fd(np.array([g[c] for c in cand]), fd, np.max(np.abs(g)),
+                 f"correlation {corr} b {slip_b} wrt ln {wrt}")
 
 
 def test_whole_field_small(dev):
@@ -134,7 +161,7 @@ def test_whole_field_small(dev):
     nodes = [(y, x) for y in range(ny) for x in range(nx)]
     fd = oracle.fd_gradient(case.eps, case.k, case.kn0, N, nodes, "k_app", h=1e-4,
                             **case.params).reshape(ny, nx)
-    assert np.max(np.abs(g - fd)) <= GRAD_TOL * np.max(np.abs(fd))
+    check_fd(g.ravel(), fd.ravel(), np.max(np.abs(g)), "whole 10x6 field")
 
 
 def test_light_cone(dev):
@@ -294,22 +321,21 @@ def test_gradient_forchheimer(dev, bcx, bcy, obj):
         fd = oracle.fd_gradient(case.eps, case.k, case.kn0, N, cand, obj, h=1e-4, wrt=wrt,
                                 **case.params)
         gg = np.array([g[c] for c in cand])
-        scale = np.max(np.abs(g))
-        assert scale > 0
-        err = np.max(np.abs(gg - fd))
-        assert err <= GRAD_TOL * scale, f"{wrt}: max |adjoint - fd| = {err:.3e}, scale {scale:.3e}"
+        check_fd(gg, fd, np.max(np.abs(g)), f"Forchheimer {obj} wrt ln {wrt}")
 
 
-def test_fullsize_shale_against_gpu_fd(dev, shale8192):
+def test_fullsize_shale_against_windowed_oracle_fd(dev, shale8192):
     """Fractured shale matrix at its full 8192 x 8192 size: the adjoint
-    gradient of the outlet flux after 200 steps against FP32 central
-    differences of the HIP path itself on 16 seeded nodes with
-    |g| > 1e-3 max|g|.  Steps of 0.1 and 0.05 in ln k, combined by
-    Richardson extrapolation to cancel the O(h^2) truncation (FP32
-    rounding noise dominates for smaller steps).  Bar: 1e-3 of the largest
-    sampled |g| -- the FP32 adjoint state carries a common (density
-    sensitivity) part much larger than its momentum part in the stiff
-    matrix, which limits per-node relative accuracy where |g| is small."""
+    gradient of the outlet flux after 200 steps, at 16 seeded nodes with
+    |g| > 1e-3 max|g|, against FP64 central differences of the oracle
+    (h = 1e-4 in ln k), each computed on the window of the medium that the
+    perturbation and the outlet rows it reaches depend on (the light cone
+    of 200 steps; the rest of the flux cancels in the difference).  Bar:
+    per node, |adjoint - fd| <= 1e-3 |fd|."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle_window import window_fd_outlet_flux
+
     case = shale8192
     steps = 200
     lat = Lattice(case.eps, case.k, case.kn0, device=dev, **case.params)
@@ -321,22 +347,16 @@ def test_fullsize_shale_against_gpu_fd(dev, shale8192):
     gmax = np.abs(g).max()
     cand = np.argwhere(np.abs(g) > 1e-3 * gmax)
     pick = cand[np.random.default_rng(16).choice(len(cand), 16, replace=False)]
-    def central(y, x, h):
-        vals, lnk = [], []
-        for sgn in (1.0, -1.0):
-            kk = case.k.copy()
-            kk[y, x] = np.float32(case.k[y, x] * math.exp(sgn * h))
-            lnk.append(math.log(float(kk[y, x])) - math.log(float(case.k[y, x])))
-            l2 = Lattice(case.eps, kk, case.kn0, device=dev, **case.params).step(steps)
-            rho, ux, _ = l2.macroscopic()
-            vals.append(float((rho[:, -1].double() * ux[:, -1].double()).sum()))
-            l2.close()
-        return (vals[0] - vals[1]) / (lnk[0] - lnk[1])
-
-    bar = 1e-3 * max(abs(g[y, x]) for y, x in pick)
-    for y, x in pick:
-        fd = (4.0 * central(y, x, 0.05) - central(y, x, 0.1)) / 3.0
-        assert abs(fd - g[y, x]) <= bar, (y, x, g[y, x], fd)
+    # the oracle runs in C through ctypes, which releases the GIL
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        fd = np.array(list(ex.map(lambda yx: window_fd_outlet_flux(case, int(yx[0]), int(yx[1]),
+                                                                    steps), pick)))
+    gg = np.array([g[y, x] for y, x in pick])
+    rel = np.abs(gg - fd) / np.abs(fd)
+    for (y, x), a, b, e in zip(pick, gg, fd, rel):
+        print(f"node ({y}, {x}): adjoint {a:.6e}, oracle fd {b:.6e}, rel {e:.2e}", flush=True)
+    print(f"shale 8192^2, 200 steps: worst per-node relative error {rel.max():.2e}", flush=True)
+    assert rel.max() <= GRAD_TOL
 
 
 def test_fullsize_shale_20000_steps_directional(dev, shale8192):

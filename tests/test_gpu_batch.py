@@ -121,6 +121,39 @@ def test_graph_readout(dev):
         assert np.array_equal(a.apparent_permeability(), b.apparent_permeability())
 
 
+def test_graph_readout_after_even_outside_steps(dev):
+    """A sample stepped twice on its own after a graph replay that ended in
+    the read-out keeps the parity of its levels (and its scale), yet its
+    state changed: the batch must not serve the replay's cached sums.  The
+    same holds after a state load that returns to the same parity."""
+    cs = cases(2, 1, seed=670)
+    lats = ensemble_lattices(cs, device=dev)
+    solo = ensemble_lattices(cs, device=dev)
+    b = Batch(lats)
+    b.set_launch(128, 2, 0, 8)
+    b.set_graph_readout(True)
+    b.step(16)
+    for l in solo:
+        l.step(16)
+    assert np.array_equal(b.apparent_permeability(),
+                          np.array([l.apparent_permeability() for l in solo]))
+    b.step(8)  # ends in a replay: the sums are cached
+    for l in solo:
+        l.step(8)
+    lats[3].step(2)
+    solo[3].step(2)
+    ks = np.array([l.apparent_permeability() for l in solo])
+    assert np.array_equal(b.apparent_permeability(), ks)
+    saved = lats[5].save_state().clone()
+    b.step(8)
+    for l in solo:
+        l.step(8)
+    lats[5].load_state(saved)  # back 8 steps: same parity, same scale
+    solo[5].load_state(saved)
+    ks = np.array([l.apparent_permeability() for l in solo])
+    assert np.array_equal(b.apparent_permeability(), ks)
+
+
 def test_outside_steps_and_loads_resync(dev):
     """Lattices stepped or reloaded on their own between batch calls stay
     consistent with the batch."""

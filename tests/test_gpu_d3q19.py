@@ -106,7 +106,9 @@ def test_mass_conservation(dev):
 
 
 @pytest.mark.parametrize("extra", [dict(correlation=1), dict(correlation=2),
-                                   dict(kn_local=0, slip_b=-0.4), dict(f_eps=0.6)])
+                                   dict(kn_local=0, slip_b=-0.4), dict(f_eps=0.6),
+                                   dict(rho_ref=2.0), dict(correlation=1, rho_ref=0.5),
+                                   dict(kn_local=0, rho_ref=0.5)])
 def test_model_options(dev, extra):
     bcx = 0 if "f_eps" in extra else 2
     d = dict(gx=2e-4, gz=5e-5) if bcx == 0 else drive(2)

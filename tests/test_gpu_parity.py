@@ -115,16 +115,19 @@ def test_global_kn(dev):
     compare(gpu_run(dev, case, 300), oracle_run(case, 300))
 
 
-@pytest.mark.parametrize("corr,slip_b,kn_local", [(1, -1.0, 1), (2, -1.0, 1), (0, -0.4, 1),
-                                                 (0, 0.0, 0), (1, -1.0, 0)])
-def test_correlations(dev, corr, slip_b, kn_local):
+@pytest.mark.parametrize("corr,slip_b,kn_local,rho_ref",
+                         [(1, -1.0, 1, 1.0), (2, -1.0, 1, 1.0), (0, -0.4, 1, 1.0),
+                          (0, 0.0, 0, 1.0), (1, -1.0, 0, 1.0), (0, -1.0, 1, 2.0),
+                          (1, -1.0, 1, 0.5), (0, -1.0, 0, 0.5)])
+def test_correlations(dev, corr, slip_b, kn_local, rho_ref):
     """Selectable slip correlation (Eqs. 6-7 with slip coefficient b, Eqs.
-    4-5, none) against the oracle on a pressure-driven heterogeneous
-    medium with Kn up to 3."""
+    4-5, none), a local or a fixed Kn, and kn0 quoted at a reference density
+    other than 1 (Kn = kn0 rho_ref / rho; no effect with a fixed Kn), against
+    the oracle on a pressure-driven heterogeneous medium with Kn up to 3."""
     case = inputs.random_medium(130, 21, seed=60 + corr, solid_frac=0.05, pore_frac=0.05,
                                 kn_range=(0.0, 3.0), bc_x=2, bc_y=1, rho_in=1.02,
                                 rho_out=1.0, init=1, correlation=corr, slip_b=slip_b,
-                                kn_local=kn_local)
+                                kn_local=kn_local, rho_ref=rho_ref)
     lat = gpu_run(dev, case, 300)
     ref = oracle_run(case, 300)
     compare(lat, ref)
@@ -336,6 +339,28 @@ def test_diagnostics(dev):
     rest.diagnostics()
     rest.step(5)
     assert rest.diagnostics()[2] == 0.0
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-5), ("f16", 2e-3)])
+def test_residual_against_oracle(dev, storage, tol):
+    """The steady-state residual of lbk_diagnostics against the oracle's
+    (R13): ||u(200) - u(100)|| / ||u(200)|| on a heterogeneous
+    pressure-driven lattice with walls, free-fluid and impermeable nodes,
+    m = 100 steps apart (even, so the alternating stiff mode cancels)."""
+    case = inputs.random_medium(300, 21, seed=33, solid_frac=0.05, pore_frac=0.05,
+                                bc_x=inputs.PRESSURE, bc_y=inputs.WALL, rho_in=1.01,
+                                rho_out=1.0, init=1)
+    lat = gpu_run(dev, case, 100, storage=storage)
+    lat.diagnostics()
+    lat.step(100)
+    _, _, r = lat.diagnostics()
+    ref = oracle_run(case, 100)
+    u_prev = ref.macro()[1:]
+    ref.step(100)
+    rr = oracle.residual(ref.macro()[1:], u_prev)
+    print(f"residual {storage}: HIP {r:.9e}, oracle {rr:.9e}", flush=True)
+    assert 0.0 < rr < 1.0
+    assert abs(r / rr - 1) < tol
 
 
 def test_permeability_needs_a_drive(dev):

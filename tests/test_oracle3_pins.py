@@ -137,6 +137,29 @@ def test_klinkenberg_darcy_column():
     assert abs(lat.apparent_permeability() / k / integral - 1) < 2e-3
 
 
+@pytest.mark.parametrize("kn_local,rho_ref", [(0, 2.0), (1, 0.5), (1, 2.0)])
+def test_klinkenberg_darcy_column_kn_reference(kn_local, rho_ref):
+    """Where Kn is evaluated (Eq. 5 with Eq. 10), in three dimensions: with Kn
+    held at kn0 the drag is uniform and k_app = k f_c(kn0) whatever rho_ref;
+    with a local Kn quoted at rho_ref, k_app = k (1/(rho_in - rho_out))
+    int f_c(kn0 rho_ref / rho) d rho.  The alternatives (local where it
+    should be global, rho_ref dropped) miss by far more than the tolerance."""
+    k, kn0 = 0.01, 0.5
+    lat = oracle.Lattice3(*_fields(2, 1, 40, 0.5, k, kn0), tau=0.8, bc_x=oracle.PRESSURE,
+                          rho_in=2.0, rho_out=1.0, init=1, kn_local=kn_local,
+                          rho_ref=rho_ref).step(25000)
+    ratio = lat.apparent_permeability() / k
+
+    def column(scale):
+        return quad(lambda r: oracle.fc(kn0 * scale / r), 1.0, 2.0, epsabs=1e-13)[0]
+
+    want = oracle.fc(kn0) if kn_local == 0 else column(rho_ref)
+    assert abs(ratio / want - 1) < 2e-3
+    for w in ([column(1.0), column(rho_ref)] if kn_local == 0 else
+              [column(1.0), oracle.fc(kn0), oracle.fc(kn0 * rho_ref)]):
+        assert abs(ratio / w - 1) > 1e-2
+
+
 def test_rejects_invalid():
     with pytest.raises(ValueError):
         oracle.Lattice3(*_fields(2, 2, 2, 1.5, 1.0))

@@ -226,6 +226,48 @@ def test_uniform_domain_recurrence_and_darcy_limit(axis, eps, k, kn0):
     assert np.allclose(along, ka * G / nu, rtol=1e-9)
 
 
+@pytest.mark.parametrize("eps,k,kn0,m", [(0.5, 1.0, 0.0, 100), (0.3, 0.2, 0.4, 10),
+                                         (0.9, 0.05, 2.0, 2)])
+def test_residual_uniform_domain_closed_form(eps, k, kn0, m):
+    """The steady-state residual (R13) between read-outs n - m and n on the
+    uniform periodic medium, where u_n = u* + (u_0 - u*) q^n (the recurrence
+    above), so ||u_n - u_{n-m}|| / ||u_n|| =
+    |u_0 - u*| |q^n - q^(n-m)| / |u* + (u_0 - u*) q^n| exactly; the field is
+    uniform, so the node count and the zero cross component drop out."""
+    tau, G = 0.8, 1e-5
+    nu = (tau - 0.5) / 3
+    ka = k * oracle.fc(kn0)
+    A = eps * nu / ka
+    q = (1 - A / 2) / (1 + A / 2)
+    ustar = ka * G / nu
+    u0 = 0.5 * eps * G / (1 + A / 2)
+    lat = oracle.Lattice(*_uniform(5, 3, eps, k, kn0), tau=tau, gx=G)
+    n = 0
+    prev = None
+    for _ in range(4):
+        _, ux, uy = lat.macro()
+        if prev is not None:
+            r = oracle.residual((ux, uy), prev)
+            un = ustar + (u0 - ustar) * q ** n
+            want = abs(u0 - ustar) * abs(q ** n - q ** (n - m)) / abs(un)
+            # FP64 raw populations carry u to about 1e-12 relative, so the
+            # difference of two read-outs is exact to about 1e-11 of |u|
+            assert abs(r - want) <= 1e-10 + 1e-8 * want, (r, want)
+        prev = (ux, uy)
+        lat.step(m)
+        n += m
+
+
+def test_residual_zero_fields():
+    """The residual's degenerate cases: a velocity field that stays zero has
+    residual 0; one that falls to zero, +inf; a doubling, 1/2."""
+    z = np.zeros((3, 4))
+    o = np.ones((3, 4))
+    assert oracle.residual((z, z), (z, z)) == 0.0
+    assert math.isinf(oracle.residual((z, z), (o, z)))
+    assert oracle.residual((2 * o, z), (o, z)) == pytest.approx(0.5, rel=1e-15)
+
+
 def test_forchheimer_fixed_point():
     """Eq. 2 with the Forchheimer term: a uniform periodic medium settles at
     (nu/k_a) u + (F_eps/sqrt(k_a)) u^2 = G."""
@@ -376,6 +418,43 @@ def test_klinkenberg_darcy_column(kn0):
     assert abs(rho[0, 0] - 2.0) < 1e-14 and abs(rho[0, -1] - 1.0) < 1e-14
     flux = (rho * ux)[:, 1:-1]  # interior: the end columns carry the BC
     assert np.allclose(flux, flux.mean(), rtol=1e-6)
+
+
+@pytest.mark.parametrize("kn_local,rho_ref", [(0, 1.0), (0, 2.0), (1, 0.5), (1, 2.0)])
+def test_klinkenberg_darcy_column_kn_reference(kn_local, rho_ref):
+    """Where Kn is evaluated (Eq. 5 with Eq. 10: lambda ~ 1/p, so Kn falls as
+    the density rises from the density rho_ref at which kn0 is quoted).  The
+    same compressible column with a 2:1 density ratio:
+    - Kn held at kn0 (no local dependence): the drag is uniform, the density
+      falls linearly and k_app = k f_c(kn0) exactly, whatever rho_ref;
+    - local Kn quoted at rho_ref: k_app = k (1/(rho_in - rho_out))
+      int f_c(kn0 rho_ref / rho) d rho.
+    Each expectation is computed apart from the oracle's own Kn expression,
+    and the alternatives (local Kn where it should be global, rho_ref
+    dropped, a global Kn at the reference) are shown to miss by far more
+    than the tolerance."""
+    ny, nx, k, kn0 = 1, 48, 0.01, 0.5
+    lat = oracle.Lattice(*_uniform(nx, ny, 0.5, k, kn0), tau=0.8,
+                         bc_x=oracle.PRESSURE, rho_in=2.0, rho_out=1.0, init=1,
+                         kn_local=kn_local, rho_ref=rho_ref).step(30000)
+    ratio = lat.apparent_permeability() / k
+
+    def column(scale):
+        return quad(lambda r: oracle.fc(kn0 * scale / r), 1.0, 2.0, epsabs=1e-13)[0]
+
+    want = oracle.fc(kn0) if kn_local == 0 else column(rho_ref)
+    assert abs(ratio / want - 1) < 2e-3
+    wrong = [column(1.0), column(rho_ref)] if kn_local == 0 else \
+        [column(1.0), oracle.fc(kn0), oracle.fc(kn0 * rho_ref)]
+    for w in wrong:
+        if abs(w / want - 1) > 1e-9:
+            assert abs(ratio / w - 1) > 1e-2
+    if kn_local == 0:
+        # uniform drag: the density profile is linear between the columns
+        rho, ux, _ = lat.macro()
+        x = np.arange(nx)
+        lin = 2.0 + (1.0 - 2.0) * x / (nx - 1)
+        assert np.max(np.abs(rho[0, 1:-1] - lin[1:-1])) < 2e-3
 
 
 def test_first_order_klinkenberg_column():
