@@ -146,6 +146,23 @@ lbk_status lbk_read_populations(lbk_lattice *lat, double *f);
  * pressure columns).  Synchronizes the stream. */
 lbk_status lbk_apparent_permeability(lbk_lattice *lat, double *k_app);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the value of
+ * lbk_apparent_permeability, within FP64 rounding of the sums (the
+ * read-out walks the lattice with a fixed grid of at most 2048 workgroups,
+ * so the partial sums are grouped differently).  It calls no hipMalloc,
+ * hipFree or other allocating routine and uses neither the lattice's
+ * workspace nor its pinned host buffer: its partial sums live in a fixed
+ * device array of 12,294 doubles (98 KB) that the library holds on each
+ * GPU it runs on until the process ends, and the result is copied straight
+ * into *k_app.  Every lattice size fits that array; a layout that did not
+ * would be refused with LBK_ERR_UNSUPPORTED.  All calls on one GPU share
+ * the array: calls that overlap in time on one GPU (other host threads,
+ * lattices on other streams) race and must be serialized by the caller.
+ * Makes the lattice's device current for the call.  LBK_ERR_INVALID_ARG
+ * without a drive.  Synchronizes the stream. */
+lbk_status lbk_apparent_permeability_noalloc(lbk_lattice *lat, double *k_app);
+
 /* FP64 diagnostics: total mass sum f*, x mass flux sum rho u_x, and the
  * residual ||u - u_prev|| / ||u|| against the velocity of the previous
  * lbk_diagnostics call on this handle (+inf on the first call; 0 when the

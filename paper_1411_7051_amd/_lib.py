@@ -82,6 +82,7 @@ _SIG = {
     "lbk_read_macroscopic": (ctypes.c_int, [_P, _P, _P, _P]),
     "lbk_read_populations": (ctypes.c_int, [_P, _P]),
     "lbk_apparent_permeability": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "lbk_apparent_permeability_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
     "lbk_diagnostics": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double)]),

@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbk.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 SOURCES = ["lbk_kernels.hip", "lbk_adjoint.hip", "lbk_api.hip", "lbk_batch.hip",
-           "lbk3_kernels.hip", "lbk3_api.hip"]
+           "lbk3_kernels.hip", "lbk3_api.hip", "lbk_noalloc.hip"]
 HEADERS = ["lbk_device.h", "lbk_kernels.h", "lbk_adjoint.h", "lbk_host.h", "lbk3_kernels.h"]
 
 FLAGS = [

@@ -223,6 +223,7 @@ lbk_status lbk_create(const lbk_desc *d, const float *eps, const float *k, const
     lat->L = L;
     lat->g = Geom{d->nx, d->ny, L.pitch};
     lat->stream = static_cast<hipStream_t>(stream);
+    lat->device = dev;
     lat->ws = static_cast<char *>(workspace);
     lat->cur = 0;
     lat->t = 0;

@@ -83,6 +83,7 @@ struct lbk_lattice {
     Geom g;
     Physics ph;
     hipStream_t stream;
+    int device;    // the HIP device current at create
     char *ws;
     int cur;       // time level holding the current state
     int64_t t;     // steps taken

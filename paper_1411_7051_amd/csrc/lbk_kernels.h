@@ -70,6 +70,14 @@ hipError_t launch_macro(int storage, int bcx, int bcy, const char *src, const La
                         float s, float inv_s, float *rho_out, float *ux_out, float *uy_out,
                         float *ux_prev, float *uy_prev, double *partials, hipStream_t st);
 
+// The read-out sums of launch_macro (no outputs, no residual) over a fixed
+// grid of `grid` workgroups that walk the lattice: partials
+// [MAC_SLOTS][grid].
+hipError_t launch_macro_strided(int storage, int bcx, int bcy, const char *src,
+                                const Layout &lay, const char *med, const MLayout &mlay,
+                                const Geom &g, const Physics &ph, float s, float inv_s, int grid,
+                                double *partials, hipStream_t st);
+
 // Mass / max|h| / non-finite partials [ST_SLOTS][blocks] of a state.
 hipError_t launch_state_sums(int storage, const char *src, const Layout &lay, const Geom &g,
                              float inv_s, double *partials, hipStream_t st);

@@ -282,6 +282,28 @@ __device__ __forceinline__ double block_reduce(double v, double *sh)
     return r;
 }
 
+// Read-out of node (x, y): post-stream density (FP64, with its residual)
+// and velocity (Eqs. 16-17 after the boundary override).
+template <typename T, int BCX, int BCY>
+__device__ __forceinline__ void readout_node(const char *src, const Layout &lay, const char *med,
+                                             const MLayout &mlay, const Geom &g,
+                                             const Physics &ph, float s, float inv_s, int y,
+                                             uint32_t x, double &rp, float &ux, float &uy)
+{
+    const Rows R = rows_of<BCY>(src, lay, g, y);
+    const Med md{med_row(med, mlay, y), mlay.slot, 2 * mlay.slot};
+    float d[9], inc, r;
+    const float rho = post_stream<T, BCX>(R, lay, md, g, ph, s, inv_s, x, d, inc, r);
+    float jx, jy, Fx, Fy;
+    momentum(d, jx, jy);
+    if (Elem<T>::kScaled) {
+        jx *= inv_s;
+        jy *= inv_s;
+    }
+    velocity(ph, rho, jx, jy, md.eps(x), md.drag(x), md.kn0(x), ux, uy, Fx, Fy);
+    rp = (double)rho + (double)r;
+}
+
 template <typename T, int BCX, int BCY>
 __global__ __launch_bounds__(kBlock) void macro_kernel(const char *src, Layout lay,
                                                         const char *med, MLayout mlay, Geom g,
@@ -294,18 +316,9 @@ __global__ __launch_bounds__(kBlock) void macro_kernel(const char *src, Layout l
     const Node nd = node_of(bpr);
     double v[MAC_SLOTS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (nd.x < (uint32_t)g.nx) {
-        const Rows R = rows_of<BCY>(src, lay, g, nd.y);
-        const Med md{med_row(med, mlay, nd.y), mlay.slot, 2 * mlay.slot};
-        float d[9], inc, r;
-        const float rho = post_stream<T, BCX>(R, lay, md, g, ph, s, inv_s, nd.x, d, inc, r);
-        float jx, jy, ux, uy, Fx, Fy;
-        momentum(d, jx, jy);
-        if (Elem<T>::kScaled) {
-            jx *= inv_s;
-            jy *= inv_s;
-        }
-        velocity(ph, rho, jx, jy, md.eps(nd.x), md.drag(nd.x), md.kn0(nd.x), ux, uy, Fx, Fy);
-        const double rp = (double)rho + (double)r;
+        double rp;
+        float ux, uy;
+        readout_node<T, BCX, BCY>(src, lay, med, mlay, g, ph, s, inv_s, nd.y, nd.x, rp, ux, uy);
         const uint32_t o = (uint32_t)nd.y * (uint32_t)g.nx + nd.x;
         if (rho_out)
             rho_out[o] = (float)rp;
@@ -331,6 +344,41 @@ __global__ __launch_bounds__(kBlock) void macro_kernel(const char *src, Layout l
         const double rr = block_reduce<SumOp>(v[k], sh);
         if (threadIdx.x == 0)
             partials[(int64_t)k * gridDim.x + nd.L] = rr;
+    }
+}
+
+// The read-out sums of macro_kernel (no field outputs, no residual) with a
+// fixed grid: workgroup b walks the lattice's 256-node blocks b, b + G, ...
+// and writes one partial per slot, partials[k][b], so the partial count is
+// the grid size whatever the lattice size.
+template <typename T, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) void macro_strided_kernel(const char *src, Layout lay,
+                                                                const char *med, MLayout mlay,
+                                                                Geom g, Physics ph, float s,
+                                                                float inv_s, int bpr, int nblocks,
+                                                                double *partials)
+{
+    __shared__ double sh[kBlock / 64];
+    double v[MAC_SLOTS] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int L = blockIdx.x; L < nblocks; L += gridDim.x) {
+        const int y = L / bpr;
+        const uint32_t x = (uint32_t)(L - y * bpr) * kBlock + threadIdx.x;
+        if (x < (uint32_t)g.nx) {
+            double rp;
+            float ux, uy;
+            readout_node<T, BCX, BCY>(src, lay, med, mlay, g, ph, s, inv_s, y, x, rp, ux, uy);
+            v[MAC_FLUX] += rp * (double)ux;
+            v[MAC_UX] += ux;
+            v[MAC_U2] += (double)ux * ux + (double)uy * uy;
+            v[MAC_RHO] += rp;
+            v[MAC_QOUT] += (x == (uint32_t)g.nx - 1) ? rp * (double)ux : 0.0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < MAC_SLOTS; ++k) {
+        const double rr = block_reduce<SumOp>(v[k], sh);
+        if (threadIdx.x == 0)
+            partials[(int64_t)k * gridDim.x + blockIdx.x] = rr;
     }
 }
 
@@ -561,6 +609,17 @@ static hipError_t macro_t(const char *src, const Layout &lay, const char *med,
     return hipGetLastError();
 }
 
+template <typename T, int BCX, int BCY>
+static hipError_t macro_strided_t(const char *src, const Layout &lay, const char *med,
+                                  const MLayout &mlay, const Geom &g, const Physics &ph, float s,
+                                  float inv_s, int grid, double *partials, hipStream_t st)
+{
+    const Launch l = launch_of(g);
+    hipLaunchKernelGGL((macro_strided_kernel<T, BCX, BCY>), dim3(grid), dim3(kBlock), 0, st, src,
+                       lay, med, mlay, g, ph, s, inv_s, l.blocks_per_row, l.blocks, partials);
+    return hipGetLastError();
+}
+
 // Dispatch a (storage, bc_x, bc_y) triple to a template instance.
 #define LBK_DISPATCH_BC(FN, T, ...)                                                          \
     switch (bcx * 2 + bcy) {                                                                 \
@@ -622,6 +681,16 @@ hipError_t launch_macro(int storage, int bcx, int bcy, const char *src, const La
         return hipErrorInvalidValue;
     LBK_DISPATCH(macro_t, src, lay, med, mlay, g, ph, s, inv_s, rho_out, ux_out, uy_out,
                  ux_prev, uy_prev, partials, st)
+}
+
+hipError_t launch_macro_strided(int storage, int bcx, int bcy, const char *src,
+                                const Layout &lay, const char *med, const MLayout &mlay,
+                                const Geom &g, const Physics &ph, float s, float inv_s, int grid,
+                                double *partials, hipStream_t st)
+{
+    if (bcy < 0 || bcy > 1 || grid < 1)
+        return hipErrorInvalidValue;
+    LBK_DISPATCH(macro_strided_t, src, lay, med, mlay, g, ph, s, inv_s, grid, partials, st)
 }
 
 hipError_t launch_state_sums(int storage, const char *src, const Layout &lay, const Geom &g,
