@@ -41,18 +41,22 @@ LAYOUT_BYTES = {"f32": 92, "f16": 56, "bf16": 56}
 
 
 PROFILE = os.path.join(ROOT, "profiles", "sweep_discs4096.md")
+# FP32 lattices from this many nodes on take the two-step pass (the library's
+# automatic pass mode)
+TWO_STEP_NODES = 1 << 22
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(storage, ms_per_step, nodes):
-    """HBM traffic of one sweep launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what it
-    reads for a plain copy of known size), as GB/s over this run's measured
-    launch time.  None if the summary is missing, covers another lattice, or
-    was taken on kernel sources that have changed since."""
+def measured_traffic(storage, launch_ms, nodes):
+    """HBM traffic of one launch of the storage type's sweep (for FP32 the
+    two-step pass) from the committed rocprofv3 counter summary (FETCH_SIZE
+    and WRITE_SIZE per dispatch, each scaled by what it reads for a plain
+    copy of known size), as GB/s over this run's measured launch time.  None
+    if the summary is missing, covers another lattice, or was taken on
+    kernel sources that have changed since."""
     try:
         text = open(PROFILE).read()
         blob = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
@@ -62,12 +66,24 @@ def measured_traffic(storage, ms_per_step, nodes):
             return None, None
         pd = blob["per_dispatch"][storage]
         byts = (pd["fetch_kib"] * blob["fetch_scale"] + pd["write_kib"] * blob["write_scale"]) * 1024
-        return byts / (ms_per_step * 1e-3) / 1e9, byts
+        return byts / (launch_ms * 1e-3) / 1e9, byts
     except (OSError, KeyError, AttributeError, ValueError):
         return None, None
 
 
-def time_storage(case, storage, steps, warmup, device):
+REPS = 5  # timed repetitions of every GPU leg; median, min and max reported
+
+
+def spread(ms_list):
+    """Median, min and max of repeated timings (ms)."""
+    v = sorted(ms_list)
+    return {"median": v[len(v) // 2], "min": v[0], "max": v[-1], "reps": len(v)}
+
+
+def time_storage(case, storage, steps, warmup, device, single=0):
+    """`REPS` timed runs of `steps` steps (two-step passes) on the lattice's
+    stream, HIP events around each; with `single` > 0 also that many single
+    sweeps (one lbk_step(1) call each) for comparison."""
     import torch
     from paper_1411_7051_amd.lattice import Lattice
 
@@ -76,28 +92,70 @@ def time_storage(case, storage, steps, warmup, device):
     lat.step(warmup)
     torch.cuda.synchronize(device)
     stream = lat.stream
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record(stream)
-    lat.step(steps)
-    t1.record(stream)
-    torch.cuda.synchronize(device)
-    ms = t0.elapsed_time(t1)
-    kapp = lat.apparent_permeability()
+    times = []
+    for _ in range(REPS):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        lat.step(steps)
+        t1.record(stream)
+        torch.cuda.synchronize(device)
+        times.append(t0.elapsed_time(t1))
+    single_ms = None
+    if single > 0:
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(single):
+            lat.step(1)
+        t1.record(stream)
+        torch.cuda.synchronize(device)
+        single_ms = t0.elapsed_time(t1) / single
     lat.close()
     del lat
     torch.cuda.empty_cache()
     nodes = case.nodes
+    sp = spread(times)
+    ms = sp["median"]
     mlups = nodes * steps / (ms * 1e-3) / 1e6
     ms_step = ms / steps
-    return {
+    out = {
         "storage": storage,
         "mlups": mlups,
         "ms_per_step": ms_step,
-        "alg_GBps": mlups * ALG_BYTES[storage] / 1e3,
-        "layout_GBps": mlups * LAYOUT_BYTES[storage] / 1e3,
-        "k_app_after": kapp,
+        "ms_per_step_min": sp["min"] / steps,
+        "ms_per_step_max": sp["max"] / steps,
+        "reps": REPS,
+        # two steps per pass: the pass moves ALG_BYTES per node
+        "pass_alg_GBps": nodes * ALG_BYTES[storage] / (2 * ms_step * 1e-3) / 1e9,
+        "per_step_alg_GBps": mlups * ALG_BYTES[storage] / 1e3,
     }
+    if single_ms is not None:
+        out["single_sweep_ms"] = single_ms
+        out["single_sweep_mlups"] = nodes / (single_ms * 1e-3) / 1e6
+        out["single_sweep_alg_GBps"] = nodes * ALG_BYTES[storage] / (single_ms * 1e-3) / 1e9
+    return out
+
+
+def storage_accuracy(case, storages, steps, device):
+    """Global permeability after a fixed `steps` (untimed) from the start
+    for each storage type on the same lattice, and its error relative to
+    FP32."""
+    import torch
+    from paper_1411_7051_amd.lattice import Lattice
+
+    k = {}
+    for st in storages:
+        lat = Lattice(case.eps, case.k, case.kn0, device=device, storage=st, **case.params)
+        lat.step(steps)
+        k[st] = lat.apparent_permeability()
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    out = {"steps": steps, "k_app": k}
+    if "f32" in k:
+        out["rel_vs_f32"] = {st: v / k["f32"] - 1 for st, v in k.items()}
+    return out
 
 
 def copy_bandwidth(device, mib=1024, reps=20):
@@ -126,28 +184,7 @@ def copy_bandwidth(device, mib=1024, reps=20):
     return 2.0 * 4 * n * reps / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(case, target_s=15.0):
-    """The FP64 oracle, single-threaded, on a 384 x 384 window of the same
-    medium (same fields and boundary conditions), as many steps as fit in
-    about ``target_s`` seconds."""
-    import numpy as np
-
-    import oracle
-    from paper_1411_7051_amd import inputs
-
-    oracle.build(force=False)
-    n = 384
-    sub = inputs.Case(np.ascontiguousarray(case.eps[:n, :n]),
-                      np.ascontiguousarray(case.k[:n, :n]),
-                      np.ascontiguousarray(case.kn0[:n, :n]), case.params)
-    lat = oracle.Lattice(sub.eps, sub.k, sub.kn0, **sub.params)
-    t = time.perf_counter()
-    lat.step(2)
-    probe = time.perf_counter() - t
-    steps = max(2, int(target_s / max(probe / 2, 1e-6)))
-    t = time.perf_counter()
-    lat.step(steps)
-    dt = time.perf_counter() - t
+def _host_cpu():
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -155,15 +192,90 @@ def cpu_baseline(case, target_s=15.0):
                          "")
     except OSError:
         pass
-    return {
-        "value": n * n * steps / dt / 1e6,
-        "unit": "MLUPS",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"{n}x{n} window of the same medium, {steps} FP64 steps in {dt:.1f} s",
-        "host_cpu": model,
-        "host_cpus_visible": len(os.sched_getaffinity(0)),
-    }
+    return {"host_cpu": model, "host_nproc": os.cpu_count(),
+            "host_cpus_visible": len(os.sched_getaffinity(0))}
+
+
+def _oracle_rate(case, steps=None, target_s=None):
+    """Time the serial FP64 oracle on `case` (steady_clock around the step
+    loop only): `steps` steps, or as many as fit in about `target_s`."""
+    import oracle
+
+    lat = oracle.Lattice(case.eps, case.k, case.kn0, **case.params)
+    if steps is None:
+        t = time.perf_counter()
+        lat.step(2)
+        probe = time.perf_counter() - t
+        steps = max(2, int(target_s / max(probe / 2, 1e-6)))
+    t = time.perf_counter()
+    lat.step(steps)
+    dt = time.perf_counter() - t
+    return lat, steps, dt, case.nodes * steps / dt / 1e6
+
+
+def _window(case, n, name):
+    import numpy as np
+    from paper_1411_7051_amd import inputs
+
+    return inputs.Case(np.ascontiguousarray(case.eps[:n, :n]),
+                       np.ascontiguousarray(case.k[:n, :n]),
+                       np.ascontiguousarray(case.kn0[:n, :n]), case.params, name)
+
+
+def oracle_legs(n_discs, quick=False):
+    """Everything the CPU oracle does for the benchmark, in one process of
+    its own (it runs on one host core while the GPU legs run):
+    - cpu_baseline: the headline workload's medium, a 384 x 384 window of
+      the 4096 x 4096 discs, as many FP64 steps as fit in about 15 s;
+    - the other configurations timed as the measurement plan states: the
+      64 x 32 channel for 10,000 steps, the 1024 x 512 Klinkenberg channel
+      (Kn 0.1) for 2,000 steps, a 1024 x 1024 window of the 8192 x 8192
+      shale for 5 steps;
+    - the reference global permeability of a 256 x 256 copy of the disc
+      medium (radii scaled by 1/16) after 2,000 steps, for the FP32 / FP16 /
+      BF16 accuracy legs."""
+    from paper_1411_7051_amd import inputs
+
+    oracle_build()
+    out = {}
+    case = inputs.discs(n=n_discs, seed=2)
+    win = _window(case, 384, "discs-window384")
+    _, steps, dt, rate = _oracle_rate(win, target_s=15.0)
+    out["cpu_baseline"] = {
+        "value": rate, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+        "sample": f"384x384 window of the same medium, {steps} FP64 steps in {dt:.1f} s",
+        **_host_cpu()}
+    configs = {}
+    plan = [("channel64x32", lambda: inputs.channel(64, 32, eps=0.5, k=1.024, gx=1e-6),
+             10000 if not quick else 200),
+            ("channel1024x512_kn0.1", lambda: inputs.channel(1024, 512, eps=0.5, k=1.024,
+                                                             kn0=0.1, drive="pressure"),
+             2000 if not quick else 4),
+            ("shale8192_window1024", lambda: _window(inputs.shale(n=8192, seed=3), 1024,
+                                                     "shale-window1024"), 5)]
+    for name, make, steps in plan:
+        c = make()
+        _, steps, dt, rate = _oracle_rate(c, steps=steps)
+        configs[name] = {"nodes": c.nodes, "steps": steps, "seconds": dt, "mlups": rate}
+    out["oracle_configs"] = configs
+    small = inputs.discs(n=256, seed=2)
+    acc_steps = 2000 if not quick else 20
+    lat, _, dt, _ = _oracle_rate(small, steps=acc_steps)
+    out["oracle_discs256"] = {"steps": acc_steps, "k_app": lat.apparent_permeability(),
+                              "seconds": dt}
+    return out
+
+
+def oracle_build():
+    import oracle
+    oracle.build(force=False)
+
+
+def _oracle_child(q, n_discs, quick):
+    try:
+        q.put(("ok", oracle_legs(n_discs, quick)))
+    except Exception as e:  # report, never hang the parent
+        q.put(("error", repr(e)))
 
 
 def time_adjoint(n, steps, ckpt, hist, device):
@@ -228,7 +340,7 @@ def time_adjoint(n, steps, ckpt, hist, device):
 
 
 def time_ensemble(n_samples, steps, storages, graph_steps, device, launch=None, grad_steps=0,
-                  grad_ckpt=500):
+                  grad_ckpt=500, check_every=100):
     """Batched ensemble of uneven samples (seed 4): per-sample lattices
     stepped together by one launch per step, launch shape from the tuner,
     steps replayed from HIP graphs, for each storage type in ``storages``
@@ -259,16 +371,30 @@ def time_ensemble(n_samples, steps, storages, graph_steps, device, launch=None, 
         b.step(2 * graph_steps)  # records the graphs
         torch.cuda.synchronize(device)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        ev[0].record(st)
-        b.step(steps)
-        ev[1].record(st)
-        torch.cuda.synchronize(device)
-        ms = ev[0].elapsed_time(ev[1])
+        times = []
+        for _ in range(REPS):
+            # the production setting: a state check (NaN/Inf, FP16 scale)
+            # of every sample once per check interval
+            ev[0].record(st)
+            done = 0
+            while done < steps:
+                n = min(check_every - (done % check_every), steps - done)
+                b.step(n)
+                done += n
+                if done % check_every == 0:
+                    b.check()
+            ev[1].record(st)
+            torch.cuda.synchronize(device)
+            times.append(ev[0].elapsed_time(ev[1]))
+        sp = spread(times)
+        ms = sp["median"]
         kapps[storage] = b.apparent_permeability()
         mlups = nodes * steps / (ms * 1e-3) / 1e6
         runs[storage] = {
             "launch": {"tile_x": tile_x, "rows": rows, "grid": grid, "graph_steps": graph_steps},
-            "autotune_best_us": tune_us, "ms_per_step": ms / steps, "mlups": mlups,
+            "autotune_best_us": tune_us, "ms_per_step": ms / steps,
+            "ms_per_step_min": sp["min"] / steps, "ms_per_step_max": sp["max"] / steps,
+            "reps": REPS, "check_every": check_every, "mlups": mlups,
             "alg_GBps": mlups * ALG_BYTES[storage] / 1e3,
             "alg_frac": mlups * ALG_BYTES[storage] / 1e3 / HBM_PEAK_GBS}
         if si == 0:
@@ -344,14 +470,19 @@ def time_d3q19(n, steps, warmup, storages, device):
         lat = Lattice3(case.eps, case.k, case.kn0, device=device, storage=st, **case.params)
         lat.step(warmup)
         torch.cuda.synchronize(device)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(lat.stream)
-        lat.step(steps)
-        e1.record(lat.stream)
-        torch.cuda.synchronize(device)
-        ms = e0.elapsed_time(e1)
+        times = []
+        for _ in range(REPS):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(lat.stream)
+            lat.step(steps)
+            e1.record(lat.stream)
+            torch.cuda.synchronize(device)
+            times.append(e0.elapsed_time(e1))
+        sp = spread(times)
+        ms = sp["median"]
         mlups = case.nodes * steps / (ms * 1e-3) / 1e6
-        runs[st] = {"ms_per_step": ms / steps, "mlups": mlups,
+        runs[st] = {"ms_per_step": ms / steps, "ms_per_step_min": sp["min"] / steps,
+                    "ms_per_step_max": sp["max"] / steps, "reps": REPS, "mlups": mlups,
                     "alg_GBps": mlups * ALG_BYTES3[st] / 1e3,
                     "alg_frac": mlups * ALG_BYTES3[st] / 1e3 / HBM_PEAK_GBS,
                     "layout_GBps": mlups * LAYOUT_BYTES3[st] / 1e3,
@@ -414,6 +545,12 @@ def main():
     ap.add_argument("--n", type=int, default=4096, help="lattice side")
     ap.add_argument("--storages", default="f32,f16,bf16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--quick-cpu", action="store_true",
+                    help="oracle legs on a few steps only (checks the plumbing)")
+    ap.add_argument("--single-steps", type=int, default=100,
+                    help="single sweeps (one step per launch) timed for comparison (0: skip)")
+    ap.add_argument("--accuracy-steps", type=int, default=1000,
+                    help="untimed steps before the FP16/BF16 vs FP32 permeability comparison")
     ap.add_argument("--adjoint-n", type=int, default=8192, help="shale lattice side")
     ap.add_argument("--adjoint-steps", type=int, default=20000,
                     help="steps of the gradient (the configuration's 20,000)")
@@ -467,23 +604,39 @@ def main():
         print(json.dumps({"calib_copy_bytes": n, "copies": 10}), flush=True)
         return
 
+    # the CPU oracle legs run in a process of their own, on one host core,
+    # while the GPU legs run
+    child, q = None, None
+    if not args.no_cpu:
+        import multiprocessing as mp
+        ctx = mp.get_context("spawn")
+        q = ctx.Queue()
+        child = ctx.Process(target=_oracle_child, args=(q, args.n, args.quick_cpu), daemon=True)
+        child.start()
+
     t = time.perf_counter()
     case = inputs.discs(n=args.n, seed=2)
     log(f"inputs: {case.nodes} nodes in {time.perf_counter() - t:.1f} s")
 
     runs = {}
     for st in args.storages.split(","):
-        r = time_storage(case, st, args.steps, args.warmup, dev)
-        log(f"{st}: {r['mlups']:.0f} MLUPS, {r['ms_per_step']:.4f} ms/step, "
-            f"{r['alg_GBps']:.0f} GB/s algorithmic")
+        r = time_storage(case, st, args.steps, args.warmup, dev, single=args.single_steps)
+        log(f"{st}: {r['mlups']:.0f} MLUPS (median of {REPS}), {r['ms_per_step']:.4f} ms/step "
+            f"[{r['ms_per_step_min']:.4f}, {r['ms_per_step_max']:.4f}]; single sweeps "
+            f"{r.get('single_sweep_ms', float('nan')):.4f} ms")
         runs[st] = r
-    if "f32" in runs:
-        for r in runs.values():
-            r["k_app_rel_vs_f32"] = r["k_app_after"] / runs["f32"]["k_app_after"] - 1
+    acc = storage_accuracy(case, args.storages.split(","), args.accuracy_steps, dev)
+    small = inputs.discs(n=256, seed=2)
+    acc_small = storage_accuracy(small, args.storages.split(","), 2000, dev)
     head = runs.get("f32") or next(iter(runs.values()))
     st = head["storage"]
-    achieved = head["alg_GBps"]
-    traffic, traffic_bytes = measured_traffic(st, head["ms_per_step"], case.nodes)
+    # dominant kernel: FP32 lattices of 2^22 nodes and more step through the
+    # two-step pass (one launch per two steps), the others one sweep a step
+    two = st == "f32" and case.nodes >= TWO_STEP_NODES
+    per_launch = 2 if two else 1
+    launch_ms = per_launch * head["ms_per_step"]
+    achieved = case.nodes * ALG_BYTES[st] / (launch_ms * 1e-3) / 1e9
+    traffic, traffic_bytes = measured_traffic(st, launch_ms, case.nodes)
     roof = {
         "bound": "hbm",
         "achieved": achieved,
@@ -492,9 +645,15 @@ def main():
         "frac": achieved / HBM_PEAK_GBS,
         "traffic": traffic,
         "traffic_bytes_per_launch": traffic_bytes,
-        "kernel": f"sweep_kernel<{st}> (pressure x, periodic y)",
-        "bytes_per_node": ALG_BYTES[st],
-        "layout_bytes_per_node": LAYOUT_BYTES[st],
+        "kernel": (f"sweep2_kernel<{st}> (two steps per launch" if two else
+                   f"sweep_kernel<{st}> (one step per launch") + "; pressure x, periodic y)",
+        "bytes_per_node_per_launch": ALG_BYTES[st],
+        "steps_per_launch": per_launch,
+        "launch_ms": launch_ms,
+        "layout_bytes_per_node_per_launch": LAYOUT_BYTES[st],
+        # the HBM rate a one-step-per-launch sweep would need for this rate
+        "single_step_equivalent_GBps": head["mlups"] * ALG_BYTES[st] / 1e3,
+        "single_step_equivalent_frac": head["mlups"] * ALG_BYTES[st] / 1e3 / HBM_PEAK_GBS,
         "copy_GBps": copy_bandwidth(dev),
     }
     log(f"plain streaming kernel (b = a * 1, 1 GiB f32): {roof['copy_GBps']:.0f} GB/s "
@@ -534,9 +693,32 @@ def main():
             f"Kn {r['kn']}: {r['k_app_over_k']:.4f} ({r['rel_diff']:+.2%})" for r in kn["rows"]))
         log("Klinkenberg channel runs: " + ", ".join(
             f"{r['steps']} steps at {r['mlups']:.0f} MLUPS" for r in kn["rows"]))
-    cpu = None if args.no_cpu else cpu_baseline(case)
-    if cpu:
-        log(f"cpu oracle: {cpu['value']:.2f} MLUPS ({cpu['sample']})")
+    cpu, oracle_out = None, None
+    if child is not None:
+        import queue as _queue
+        try:
+            status, res = q.get(timeout=900)
+        except _queue.Empty:
+            status, res = "error", "oracle legs did not finish in 900 s"
+        child.join(timeout=30)
+        if status == "ok":
+            oracle_out = res
+            cpu = res["cpu_baseline"]
+            log(f"cpu oracle: {cpu['value']:.2f} MLUPS ({cpu['sample']}); " + ", ".join(
+                f"{k}: {v['mlups']:.2f} MLUPS ({v['steps']} steps)"
+                for k, v in res["oracle_configs"].items()))
+        else:
+            log(f"cpu oracle legs failed: {res}")
+    accuracy = {"discs4096_vs_f32": acc, "discs256_vs_oracle": None}
+    if oracle_out is not None:
+        ko = oracle_out["oracle_discs256"]["k_app"]
+        accuracy["discs256_vs_oracle"] = {
+            "steps": 2000, "oracle_k_app": ko, "k_app": acc_small["k_app"],
+            "rel_vs_oracle": {s_: v / ko - 1 for s_, v in acc_small["k_app"].items()}}
+        log("k_app on the 256^2 discs after 2000 steps vs the FP64 oracle: " + ", ".join(
+            f"{s_} {v:+.2e}" for s_, v in accuracy["discs256_vs_oracle"]["rel_vs_oracle"].items()))
+    log(f"k_app on the 4096^2 discs after {acc['steps']} steps vs FP32: " + ", ".join(
+        f"{s_} {v:+.2e}" for s_, v in acc.get("rel_vs_f32", {}).items()))
     out = {
         "metric": METRIC,
         "value": head["mlups"],
@@ -562,6 +744,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "storage_runs": runs,
+        "storage_accuracy": accuracy,
+        "oracle_configs": oracle_out["oracle_configs"] if oracle_out else None,
         "adjoint": adj,
         "ensemble": ens,
         "klinkenberg_channel": kn,

@@ -66,6 +66,19 @@ typedef enum lbk_correlation {
     LBK_FC_NONE = 2         /* no slip correction: k_a = k */
 } lbk_correlation;
 
+/* How lbk_step (and the gradients' recomputing sweeps) advance an FP32
+ * lattice: two time steps per pass, the intermediate level kept in
+ * registers (bitwise the result of two single sweeps), or one step per
+ * sweep.  The two-step pass reads and writes the state once per two steps;
+ * it pays off on lattices large enough to fill the device.  FP16 and BF16
+ * lattices always take single sweeps (the two-step pass is not faster
+ * there). */
+typedef enum lbk_pass_mode {
+    LBK_PASS_AUTO = 0,     /* two-step passes for lattices of >= 2^22 nodes */
+    LBK_PASS_TWO_STEP = 1, /* two-step passes whatever the size */
+    LBK_PASS_SINGLE = 2    /* single sweeps */
+} lbk_pass_mode;
+
 /* Run description (Sec. IV: plates, heterogeneous media, fractured shale). */
 typedef struct lbk_desc {
     int32_t nx, ny;      /* lattice size; nx >= 3 with pressure boundaries */
@@ -92,7 +105,7 @@ typedef struct lbk_desc {
     double rho_ref;      /* density at which kn0 is quoted */
     double slip_b;       /* slip coefficient b of Eq. 6, <= 0 (default -1) */
     int32_t correlation; /* lbk_correlation */
-    int32_t reserved;    /* must be 0 */
+    int32_t pass_mode;   /* lbk_pass_mode: how lbk_step advances FP32 lattices */
 } lbk_desc;
 
 typedef struct lbk_lattice lbk_lattice;

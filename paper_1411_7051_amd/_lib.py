@@ -25,6 +25,7 @@ STATUS = {
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 OBJECTIVE = {"k_app": 0, "q_out": 1}
 CORRELATION = {"bkc": 0, "klinkenberg": 1, "none": 2}
+PASS_MODE = {"auto": 0, "two_step": 1, "single": 2}
 
 
 class LbkError(RuntimeError):
@@ -47,7 +48,7 @@ class Desc(ctypes.Structure):
         ("rho_in", ctypes.c_double), ("rho_out", ctypes.c_double),
         ("rho0", ctypes.c_double), ("rho_ref", ctypes.c_double),
         ("slip_b", ctypes.c_double),
-        ("correlation", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("correlation", ctypes.c_int32), ("pass_mode", ctypes.c_int32),
     ]
 
 

@@ -106,8 +106,8 @@ lbk_status check_desc(const lbk_desc *d)
         return fail(LBK_ERR_INVALID_ARG, "correlation must be 0..2 (got %d)", d->correlation);
     if (!(d->slip_b <= 0.0) || !isfinite(d->slip_b))
         return fail(LBK_ERR_INVALID_ARG, "slip_b must be finite and <= 0 (got %g)", d->slip_b);
-    if (d->reserved != 0)
-        return fail(LBK_ERR_INVALID_ARG, "reserved must be 0");
+    if (d->pass_mode < LBK_PASS_AUTO || d->pass_mode > LBK_PASS_SINGLE)
+        return fail(LBK_ERR_INVALID_ARG, "pass_mode must be 0..2 (got %d)", d->pass_mode);
     return LBK_OK;
 }
 
@@ -119,6 +119,33 @@ void split(double v, float &hi, float &lo)
 }
 
 } // namespace
+
+// n steps of the lattice on stream st: for the storage types that use it,
+// pairs of steps fused into one pass (launch_sweep2, bitwise two single
+// sweeps) and a single sweep if n is odd; otherwise n single sweeps.
+lbk_status lbk::advance(lbk_lattice *lat, int64_t n, hipStream_t st)
+{
+    const lbk_desc &d = lat->d;
+    for (int64_t i = 0; two_step_pass(lat) && i + 1 < n; i += 2) {
+        const int nxt = lat->cur ^ 1;
+        HIP_TRY(launch_sweep2(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->state(nxt),
+                              lat->L.lay, lat->med(), lat->L.mlay, lat->g, lat->ph, lat->s(),
+                              lat->inv_s(), kBand2, nullptr, nullptr, st));
+        lat->cur = nxt;
+        lat->t += 2;
+        ++lat->version;
+    }
+    for (int64_t i = two_step_pass(lat) ? n - (n & 1) : 0; i < n; ++i) {
+        const int nxt = lat->cur ^ 1;
+        HIP_TRY(launch_sweep(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->state(nxt),
+                             lat->L.lay, lat->med(), lat->L.mlay, lat->g, lat->ph, lat->s(),
+                             lat->inv_s(), nullptr, st));
+        lat->cur = nxt;
+        ++lat->t;
+        ++lat->version;
+    }
+    return LBK_OK;
+}
 
 // Run a reduction's finish kernel and copy `slots` doubles to lat->host.
 lbk_status lbk::fetch(lbk_lattice *lat, int slots, unsigned max_mask)
@@ -330,21 +357,18 @@ lbk_status lbk_step(lbk_lattice *lat, int64_t n)
         return fail(LBK_ERR_INVALID_ARG, "n must be >= 0");
     const lbk_desc &d = lat->d;
     Range range("lbk_step");
-    for (int64_t i = 0; i < n; ++i) {
-        const int nxt = lat->cur ^ 1;
-        HIP_TRY(launch_sweep(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->state(nxt),
-                             lat->L.lay, lat->med(), lat->L.mlay, lat->g, lat->ph, lat->s(),
-                             lat->inv_s(), nullptr, lat->stream));
-        lat->cur = nxt;
-        ++lat->t;
-        ++lat->version;
+    while (n > 0) {
         // checks fall on multiples of check_every in the lattice's own time,
         // so a run resumed from a saved state checks where the original did
-        if (d.check_every > 0 && lat->t % d.check_every == 0) {
-            lbk_status s = check_state(lat);
-            if (s != LBK_OK)
-                return s;
-        }
+        int64_t chunk = n;
+        if (d.check_every > 0)
+            chunk = std::min(chunk, d.check_every - lat->t % d.check_every);
+        lbk_status s = advance(lat, chunk, lat->stream);
+        if (s != LBK_OK)
+            return s;
+        n -= chunk;
+        if (d.check_every > 0 && lat->t % d.check_every == 0 && (s = check_state(lat)) != LBK_OK)
+            return s;
     }
     return LBK_OK;
 }
@@ -692,7 +716,6 @@ extern "C" lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64
     if (!lat || !ws || !J)
         return fail(LBK_ERR_INVALID_ARG, "NULL argument");
     Range range("adjoint forward");
-    const lbk_desc &d = lat->d;
     lbk_status s0 = check_objective(lat, objective);
     if (s0 != LBK_OK)
         return s0;
@@ -718,19 +741,15 @@ extern "C" lbk_status lbk_adjoint_forward(lbk_lattice *lat, int objective, int64
         // checkpoints now rather than recomputing them in the backward pass
         const int64_t kept = k - (P.k1 - P.keep);
         const bool keep_inner = P.two_level && kept >= 0;
-        for (int64_t i = 0; i < steps; ++i) {
-            if (keep_inner && i % P.c2 == 0)
+        const int64_t run = keep_inner ? P.c2 : steps; // steps between kept states
+        for (int64_t i = 0; i < steps; i += run) {
+            if (keep_inner)
                 HIP_TRY(hipMemcpyAsync(w + P.inner + (size_t)kept * P.inner_seg +
                                            (size_t)(i / P.c2) * P.level_bytes,
                                        lat->state(lat->cur), P.level_bytes,
                                        hipMemcpyDeviceToDevice, st));
-            const int nxt = lat->cur ^ 1;
-            HIP_TRY(launch_sweep(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur),
-                                 lat->state(nxt), lat->L.lay, lat->med(), lat->L.mlay, lat->g,
-                                 lat->ph, lat->s(), lat->inv_s(), nullptr, st));
-            lat->cur = nxt;
-            ++lat->t;
-            ++lat->version;
+            if ((s = advance(lat, std::min(run, steps - i), st)) != LBK_OK)
+                return s;
         }
     }
     if ((s = macro_sums(lat, false)) != LBK_OK)
@@ -772,6 +791,13 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
         return launch_sweep(d.storage, d.bc_x, d.bc_y, src, dst, lat->L.lay, lat->med(),
                             lat->L.mlay, lat->g, lat->ph, lat->s(), lat->inv_s(), hist, st);
     };
+    // two steps src -> dst in one pass, recording both when hist1 is given
+    const bool two = two_step_pass(lat);
+    auto sweep2 = [&](const char *src, char *dst, float *hist1, float *hist2) {
+        return launch_sweep2(d.storage, d.bc_x, d.bc_y, src, dst, lat->L.lay, lat->med(),
+                             lat->L.mlay, lat->g, lat->ph, lat->s(), lat->inv_s(), kBand2, hist1,
+                             hist2, st);
+    };
     const float a1 = (float)P.a1, a2 = (float)P.a2;
 
     HIP_TRY(hipMemsetAsync(grad, 0, (size_t)d.ny * lat->L.pitch * 8, st));
@@ -807,8 +833,15 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
                 const int64_t steps = std::min(P.c2, b - t);
                 if (t + steps >= b)
                     break; // the last inner segment needs no further state
-                for (int64_t i = 0; i < steps; ++i) {
-                    HIP_TRY(sweep(i == 0 ? level(inner, nseg) : rec[r], rec[r ^ 1], nullptr));
+                for (int64_t i = 0; i < steps;) {
+                    const char *from = i == 0 ? level(inner, nseg) : rec[r];
+                    if (two && i + 1 < steps) {
+                        HIP_TRY(sweep2(from, rec[r ^ 1], nullptr, nullptr));
+                        i += 2;
+                    } else {
+                        HIP_TRY(sweep(from, rec[r ^ 1], nullptr));
+                        ++i;
+                    }
                     r ^= 1;
                 }
                 src = rec[r];
@@ -823,8 +856,15 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
             int r = 0;
             {
                 Range range("adjoint recompute");
-                for (int64_t t = a2s; t < b2s; ++t) {
-                    HIP_TRY(sweep(t == a2s ? src : rec[r], rec[r ^ 1], histp(t - a2s + 1)));
+                for (int64_t t = a2s; t < b2s;) {
+                    const char *from = t == a2s ? src : rec[r];
+                    if (two && t + 1 < b2s) {
+                        HIP_TRY(sweep2(from, rec[r ^ 1], histp(t - a2s + 1), histp(t - a2s + 2)));
+                        t += 2;
+                    } else {
+                        HIP_TRY(sweep(from, rec[r ^ 1], histp(t - a2s + 1)));
+                        ++t;
+                    }
                     r ^= 1;
                 }
             }

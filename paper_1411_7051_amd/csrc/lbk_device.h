@@ -92,6 +92,18 @@ __device__ __forceinline__ void st_f32(Rsrc r, uint32_t voff, uint32_t soff, flo
         __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, 0);
 }
 
+// v as an opaque FP32 register value.  The compiler may otherwise fold the
+// rounding of an FP32 result to FP16 into the arithmetic that produced it
+// (a mixed-precision FMA that rounds once, straight to FP16), and may do so
+// in one kernel and not in another; every FP16 store and its register
+// stand-in round through this, so all kernels round first to FP32 and then
+// to FP16, identically.
+__device__ __forceinline__ float f32_reg(float v)
+{
+    asm("" : "+v"(v));
+    return v;
+}
+
 // Storage element types, loaded and stored in the storage's own unit
 // (scaled for FP16).
 template <typename T> struct Elem;
@@ -106,6 +118,8 @@ template <> struct Elem<float> {
     {
         __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, kNT);
     }
+    // the value a store followed by a load returns
+    static __device__ __forceinline__ float round(float v) { return v; }
 };
 template <> struct Elem<__half> {
     static constexpr bool kScaled = true;
@@ -117,8 +131,12 @@ template <> struct Elem<__half> {
     }
     static __device__ __forceinline__ void st(Rsrc r, uint32_t voff, uint32_t soff, float v)
     {
-        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, (int)voff,
-                                              (int)soff, kNT);
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(f32_reg(v))), r,
+                                              (int)voff, (int)soff, kNT);
+    }
+    static __device__ __forceinline__ float round(float v)
+    {
+        return __half2float(__float2half_rn(f32_reg(v)));
     }
 };
 template <> struct Elem<__hip_bfloat16> {
@@ -135,7 +153,27 @@ template <> struct Elem<__hip_bfloat16> {
         __builtin_amdgcn_raw_buffer_store_b16(*reinterpret_cast<const uint16_t *>(&b), r,
                                               (int)voff, (int)soff, kNT);
     }
+    static __device__ __forceinline__ float round(float v)
+    {
+        const __hip_bfloat16 b = __float2bfloat16(v);
+        return __uint_as_float((uint32_t)(*reinterpret_cast<const uint16_t *>(&b)) << 16);
+    }
 };
+
+// Value of v held by the lane DX to the left (DX = 1: lane - 1) or right
+// (DX = -1: lane + 1) within the wave64, through a whole-wave DPP shift
+// (wave_shr:1 / wave_shl:1); DX = 0 is v itself.  The lane at the wave's
+// edge, which has no such neighbour, gets 0.
+template <int DX> __device__ __forceinline__ float lane_from(float v)
+{
+    if (DX == 1)
+        return __int_as_float(
+            __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+    if (DX == -1)
+        return __int_as_float(
+            __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+    return v;
+}
 
 // -------------------------------------------------------------- layouts
 

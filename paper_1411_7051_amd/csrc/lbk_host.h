@@ -106,6 +106,35 @@ struct lbk_lattice {
 
 namespace lbk {
 
+// Rows per band of the two-step sweep.  Short bands keep the waves that run
+// at once on nearby rows (a band of 6 recomputes 2 of every 8 intermediate
+// rows, yet measured fastest on a 4096 x 4096 lattice: tall bands spread the
+// concurrent accesses over the whole level and ran 25% slower).
+#ifndef LBK_BAND2
+#define LBK_BAND2 6
+#endif
+constexpr int kBand2 = LBK_BAND2;
+
+// Lattices from this many nodes on take two-step passes under
+// LBK_PASS_AUTO: below it too few waves run to hide the march's latency
+// (1024 x 512: 38 against 48 GLUPS for single sweeps).
+constexpr int64_t kTwoStepNodes = (int64_t)1 << 22;
+
+// Whether steps of this lattice go through the two-step pass: FP32 storage
+// only (FP16 and BF16 single sweeps measured 1-2% faster than the two-step
+// pass, which is bound by its arithmetic there), as pass_mode asks.
+inline bool two_step_pass(const lbk_lattice *lat)
+{
+    const lbk_desc &d = lat->d;
+    return d.storage == LBK_F32 &&
+           (d.pass_mode == LBK_PASS_TWO_STEP ||
+            (d.pass_mode == LBK_PASS_AUTO && (int64_t)d.nx * d.ny >= kTwoStepNodes));
+}
+
+// n >= 0 steps of the lattice on stream st (pairs through the two-step
+// sweep); advances time and version.
+lbk_status advance(lbk_lattice *lat, int64_t n, hipStream_t st);
+
 // Finish kernel over the handle's partials, `slots` doubles into lat->host
 // (synchronizes the stream).
 lbk_status fetch(lbk_lattice *lat, int slots, unsigned max_mask);

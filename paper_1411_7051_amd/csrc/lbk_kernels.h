@@ -62,6 +62,17 @@ hipError_t launch_sweep(int storage, int bcx, int bcy, const char *src, char *ds
                         const Layout &lay, const char *med, const MLayout &mlay, const Geom &g,
                         const Physics &ph, float s, float inv_s, float *hist, hipStream_t st);
 
+// Two steps src -> dst in one pass (bitwise the result of two launch_sweep
+// calls through an intermediate level), the old and intermediate levels
+// held in registers: waves own strips of 60 columns and march along bands of
+// `band` >= 1 rows.  src and dst must be different levels.  With hist1 and
+// hist2 (both or neither) the two steps' linearisation points are recorded
+// as launch_sweep records one.  FP32 storage only (storage 0).
+hipError_t launch_sweep2(int storage, int bcx, int bcy, const char *src, char *dst,
+                         const Layout &lay, const char *med, const MLayout &mlay, const Geom &g,
+                         const Physics &ph, float s, float inv_s, int band, float *hist1,
+                         float *hist2, hipStream_t st);
+
 // Macroscopic read-out ([ny][nx] outputs, any may be null) and FP64 partials
 // [MAC_SLOTS][blocks].  If u_prev ([ny][pitch]) is given it is read for the
 // residual and then overwritten with the current velocity.

@@ -64,6 +64,50 @@ struct Med {
     __device__ __forceinline__ float kn0(uint32_t x) const { return ld_f32(r, x * 4, slot2); }
 };
 
+// Pressure-column override (non-equilibrium extrapolation from the
+// neighbouring column): on entry d, rho, inc, r are the neighbour's pulled
+// deviations, density and density residual and en, dragn, kn0n its medium;
+// on return d holds the boundary node's deviations relative to the imposed
+// density rb (returned), inc = 0 and r its density residual:
+//   f_i = f_eq_i(rho_b, u_n; eps_b) + f_i(n) - f_eq_i(rho_n, u_n; eps_n)
+template <typename T>
+__device__ __forceinline__ float extrapolate(const Physics &ph, float s, float inv_s, bool in,
+                                             float eb, float en, float dragn, float kn0n,
+                                             float rho, float (&d)[9], float &inc, float &r)
+{
+    float jx, jy, ux, uy, Fx, Fy;
+    momentum(d, jx, jy);
+    if (Elem<T>::kScaled) {
+        jx *= inv_s;
+        jy *= inv_s;
+    }
+    velocity(ph, rho, jx, jy, en, dragn, kn0n, ux, uy, Fx, Fy);
+    const float rb = in ? ph.rin_hi : ph.rout_hi;
+    const float rbl = in ? ph.rin_lo : ph.rout_lo;
+    // f_eq_i(rho_b, u; eps_b) - f_eq_i(rho_n, u; eps_n) of Eq. 14 as
+    // w_i [a e.u + b (4.5 (e.u)^2 - 1.5 u.u)], each equilibrium's
+    // deviation from w_i rho vanishing at eps = 0
+    const bool sb = !(eb > 0.0f), sn = !(en > 0.0f);
+    const float a = 3.0f * ((sb ? 0.0f : rb) - (sn ? 0.0f : rho));
+    const float b = (sb ? 0.0f : rb * __builtin_amdgcn_rcpf(eb)) -
+                    (sn ? 0.0f : rho * __builtin_amdgcn_rcpf(en));
+    const float uu = ux * ux + uy * uy;
+    const float c = (rbl - r) - inc; // w_i (rbl - r) - w_i inc, over w_i
+    float sum = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        // physical deviation of the boundary node from w_i rb
+        const float eu = ex_of(i) * ux + ey_of(i) * uy;
+        const float q = c + b * (4.5f * eu * eu - 1.5f * uu) + a * eu;
+        const float v = w_of(i) * q + (Elem<T>::kScaled ? d[i] * inv_s : d[i]);
+        sum += v;
+        d[i] = Elem<T>::kScaled ? v * s : v;
+    }
+    inc = 0.0f;
+    r = sum;
+    return rb;
+}
+
 // Post-stream deviations d_i (storage unit) of node (x, y) after the
 // boundary override, relative to rho - inc; returns the FP32 density rho
 // and sets inc and the density residual r (physical unit).  A pressure-
@@ -82,44 +126,23 @@ __device__ __forceinline__ float post_stream(const Rows &R, const Layout &L, con
     pull<T, BCX>(R, L, g, s, xs, rc, d);
     const float rho = density<T>(rc, d, inv_s, inc, r);
     if (BCX == BC_PRESSURE && bnode) {
-        // non-equilibrium extrapolation from the neighbouring column (d,
-        // rho, inc, r are the neighbour's):
-        // f_i = f_eq_i(rho_b, u_n; eps_b) + f_i(n) - f_eq_i(rho_n, u_n; eps_n)
-        float jx, jy, ux, uy, Fx, Fy;
-        momentum(d, jx, jy);
-        if (Elem<T>::kScaled) {
-            jx *= inv_s;
-            jy *= inv_s;
-        }
         const float en = md.eps(xs), eb = md.eps(x);
-        velocity(ph, rho, jx, jy, en, md.drag(xs), md.kn0(xs), ux, uy, Fx, Fy);
-        const bool in = (x == 0);
-        const float rb = in ? ph.rin_hi : ph.rout_hi;
-        const float rbl = in ? ph.rin_lo : ph.rout_lo;
-        // f_eq_i(rho_b, u; eps_b) - f_eq_i(rho_n, u; eps_n) of Eq. 14 as
-        // w_i [a e.u + b (4.5 (e.u)^2 - 1.5 u.u)], each equilibrium's
-        // deviation from w_i rho vanishing at eps = 0
-        const bool sb = !(eb > 0.0f), sn = !(en > 0.0f);
-        const float a = 3.0f * ((sb ? 0.0f : rb) - (sn ? 0.0f : rho));
-        const float b = (sb ? 0.0f : rb * __builtin_amdgcn_rcpf(eb)) -
-                        (sn ? 0.0f : rho * __builtin_amdgcn_rcpf(en));
-        const float uu = ux * ux + uy * uy;
-        const float c = (rbl - r) - inc; // w_i (rbl - r) - w_i inc, over w_i
-        float sum = 0.0f;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            // physical deviation of the boundary node from w_i rb
-            const float eu = ex_of(i) * ux + ey_of(i) * uy;
-            const float q = c + b * (4.5f * eu * eu - 1.5f * uu) + a * eu;
-            const float v = w_of(i) * q + (Elem<T>::kScaled ? d[i] * inv_s : d[i]);
-            sum += v;
-            d[i] = Elem<T>::kScaled ? v * s : v;
-        }
-        inc = 0.0f;
-        r = sum;
-        return rb;
+        return extrapolate<T>(ph, s, inv_s, x == 0, eb, en, md.drag(xs), md.kn0(xs), rho, d, inc,
+                              r);
     }
     return rho;
+}
+
+// Linearisation point (rho, jx, jy) of one step at node (x, y) into a
+// history slot [y][3][pitch] (FP32), for the adjoint.
+__device__ __forceinline__ void record(float *hist, const Geom &g, int y, uint32_t x, float rho,
+                                       float jx, float jy)
+{
+    const uint32_t hrow = 3u * (uint32_t)g.pitch * 4u, hsl = (uint32_t)g.pitch * 4u;
+    const Rsrc hr = make_rsrc(reinterpret_cast<char *>(hist) + (uint64_t)y * hrow, hrow);
+    st_f32(hr, x * 4, 0, rho, true);
+    st_f32(hr, x * 4, hsl, jx, true);
+    st_f32(hr, x * 4, 2 * hsl, jy, true);
 }
 
 // Full update of node (x, y): pull, boundary override, moments, velocity,
@@ -140,14 +163,8 @@ __device__ __forceinline__ void sweep_node(const char *src, char *dst, const Lay
         jx *= inv_s;
         jy *= inv_s;
     }
-    if (HIST) {
-        // linearisation point of this step for the adjoint: (rho, jx, jy)
-        const uint32_t hrow = 3u * (uint32_t)g.pitch * 4u, hsl = (uint32_t)g.pitch * 4u;
-        const Rsrc hr = make_rsrc(reinterpret_cast<char *>(hist) + (uint64_t)y * hrow, hrow);
-        st_f32(hr, x * 4, 0, rho, true);
-        st_f32(hr, x * 4, hsl, jx, true);
-        st_f32(hr, x * 4, 2 * hsl, jy, true);
-    }
+    if (HIST)
+        record(hist, g, y, x, rho, jx, jy);
     const float eps = md.eps(x);
     velocity(ph, rho, jx, jy, eps, md.drag(x), md.kn0(x), ux, uy, Fx, Fy);
     float hs[9];
@@ -170,6 +187,285 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const char *src, char *ds
     if (nd.x >= (uint32_t)g.nx)
         return;
     sweep_node<T, BCX, BCY, HIST>(src, dst, lay, med, mlay, g, ph, s, inv_s, hist, nd.y, nd.x);
+}
+
+// ------------------------------------------------------ two steps a pass
+//
+// sweep2_kernel advances the lattice by two time steps in one pass, with the
+// old level and the intermediate level both held in registers: per node and
+// two steps the state is read once and written once.  Each wave owns a strip
+// of kStrip2 consecutive columns and a band of rows and marches along y; its
+// 64 lanes hold the strip's columns and two more on either side.  Three rows
+// of the old level (each loaded once) feed the first step of one
+// intermediate row; three intermediate rows feed the second step of one row,
+// which is stored.  The x-neighbours of a pull come from the adjacent lanes
+// through whole-wave DPP shifts, so each step loses one column on either
+// side: the old level is complete on lanes 0..63, the intermediate level on
+// lanes 1..62 and the result on lanes 2..61.  Both steps are the single-step
+// node update with the neighbour values taken from registers instead of
+// HBM, and the intermediate values are rounded to the storage type exactly as
+// a store and a reload would round them, so the result is bitwise that of two
+// single sweeps.  The four halo columns of each strip and the halo rows at
+// each band's ends are computed by the neighbouring strips and bands too.
+
+// Columns a wave stores.
+constexpr int kStrip2 = 60;
+
+// One node of a level as a pull reads it: density and deviations (storage
+// unit, as stored), with the node's medium.
+struct Mid {
+    float rho, h[9];
+    float eps, drag, kn0;
+};
+
+// Node (x, y) of a stored level and its medium.
+template <typename T>
+__device__ __forceinline__ void load_node(const char *src, const Layout &lay, const char *med,
+                                          const MLayout &mlay, int y, uint32_t x, Mid &m)
+{
+    const Rsrc row = make_rsrc(src + (uint64_t)y * lay.row, (uint32_t)lay.row);
+    // default cache policy: a strip's 64-column loads share their first and
+    // last cache lines with the neighbouring strips, which read them about
+    // the same time (nontemporal loads fetched those lines twice)
+    m.rho = ld_f32(row, x * 4, 0);
+    constexpr uint32_t es = sizeof(T);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        m.h[i] = Elem<T>::template ld<0>(row, x * es, lay.h_off + i * lay.h_slot);
+    const Rsrc mr = med_row(med, mlay, y);
+    m.eps = ld_f32(mr, x * 4, 0);
+    m.drag = ld_f32(mr, x * 4, mlay.slot);
+    m.kn0 = ld_f32(mr, x * 4, 2 * mlay.slot);
+}
+
+// The pull of this lane's node from the rows y - 1 (dn), y (c) and y + 1 (up)
+// of the previous level: the arithmetic of pull() with the neighbour values
+// taken from registers and adjacent lanes.
+template <typename T, int BCX>
+__device__ __forceinline__ void pull_mid(const Mid &dn, const Mid &c, const Mid &up, bool wym,
+                                         bool wyp, bool wxm, bool wxp, float s, float &rc,
+                                         float (&d)[9])
+{
+    rc = c.rho;
+    d[0] = c.h[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        const int ex = ex_of(i), ey = ey_of(i);
+        const bool wall_y = (ey == 1 && wym) || (ey == -1 && wyp); // uniform
+        const Mid &m = ey == 1 ? dn : (ey == -1 ? up : c);
+        const float ws = Elem<T>::kScaled ? w_of(i) * s : w_of(i);
+        float rn, h;
+        if (wall_y) {
+            rn = c.rho;
+            h = c.h[opp_of(i)];
+        } else if (ex == 1) {
+            rn = lane_from<1>(m.rho);
+            h = lane_from<1>(m.h[i]);
+        } else if (ex == -1) {
+            rn = lane_from<-1>(m.rho);
+            h = lane_from<-1>(m.h[i]);
+        } else {
+            rn = m.rho;
+            h = m.h[i];
+        }
+        d[i] = ws * (rn - rc) + h;
+        if (BCX == BC_WALL) {
+            const bool wall_x = (ex == 1 && wxm) || (ex == -1 && wxp); // per lane, edges only
+            if (wall_x)
+                d[i] = c.h[opp_of(i)];
+        }
+    }
+}
+
+// Lane-dependent facts of a strip: which column a lane holds and what kind.
+struct Lanes {
+    uint32_t x;     // the lane's column, wrapped (periodic) or clamped
+    bool wxm, wxp;  // x walls on either side of the column
+    bool bin, bout; // the inlet / outlet pressure column
+    bool has_b;     // uniform: the wave may hold a pressure column
+};
+
+// One step of this lane's node at row y from three rows of the previous
+// level in registers: pull, pressure-column override from the neighbouring
+// lane's pull, moments, velocity and collide -- sweep_node's update.
+// Returns the new density, the unrounded deviations hs and, for the
+// history, (jx, jy).
+template <typename T, int BCX>
+__device__ __forceinline__ float step_from(const Physics &ph, float s, float inv_s, const Mid &dn,
+                                           const Mid &c, const Mid &up, bool wym, bool wyp,
+                                           const Lanes &ln, float (&hs)[9], float &jx, float &jy)
+{
+    float d[9], rc, inc, r;
+    pull_mid<T, BCX>(dn, c, up, wym, wyp, ln.wxm, ln.wxp, s, rc, d);
+    float en = 0.0f, dragn = 0.0f, kn0n = 0.0f;
+    if (BCX == BC_PRESSURE && ln.has_b) {
+        // a pressure column pulls at its neighbour: take that lane's pull
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const float lf = lane_from<-1>(d[i]), rf = lane_from<1>(d[i]);
+            d[i] = ln.bin ? lf : (ln.bout ? rf : d[i]);
+        }
+        const float rl = lane_from<-1>(rc), rr = lane_from<1>(rc);
+        rc = ln.bin ? rl : (ln.bout ? rr : rc);
+        const float el = lane_from<-1>(c.eps), er = lane_from<1>(c.eps);
+        const float dl = lane_from<-1>(c.drag), dr = lane_from<1>(c.drag);
+        const float kl = lane_from<-1>(c.kn0), kr = lane_from<1>(c.kn0);
+        en = ln.bin ? el : er;
+        dragn = ln.bin ? dl : dr;
+        kn0n = ln.bin ? kl : kr;
+    }
+    float rho = density<T>(rc, d, inv_s, inc, r);
+    if (BCX == BC_PRESSURE && (ln.bin || ln.bout))
+        rho = extrapolate<T>(ph, s, inv_s, ln.bin, c.eps, en, dragn, kn0n, rho, d, inc, r);
+    momentum(d, jx, jy);
+    if (Elem<T>::kScaled) {
+        jx *= inv_s;
+        jy *= inv_s;
+    }
+    float ux, uy, Fx, Fy;
+    velocity(ph, rho, jx, jy, c.eps, c.drag, c.kn0, ux, uy, Fx, Fy);
+    collide<T>(ph, rho, inc, r, d, ux, uy, Fx, Fy, c.eps, s, hs);
+    return rho;
+}
+
+// First step of row y: the intermediate node as the second step reads it.
+template <typename T, int BCX, bool HIST>
+__device__ __forceinline__ void first_step(const Physics &ph, float s, float inv_s, const Geom &g,
+                                           const Mid &dn, const Mid &c, const Mid &up, bool wym,
+                                           bool wyp, const Lanes &ln, int y, float *hist,
+                                           bool rec, Mid &m)
+{
+    float hs[9], jx, jy;
+    m.rho = step_from<T, BCX>(ph, s, inv_s, dn, c, up, wym, wyp, ln, hs, jx, jy);
+    if (HIST && rec)
+        record(hist, g, y, ln.x, m.rho, jx, jy);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        m.h[i] = Elem<T>::round(hs[i]);
+    m.eps = c.eps;
+    m.drag = c.drag;
+    m.kn0 = c.kn0;
+}
+
+template <typename T, int BCX, int BCY, bool HIST>
+__global__ __launch_bounds__(kBlock) void sweep2_kernel(const char *__restrict__ src,
+                                                         char *__restrict__ dst, Layout lay,
+                                                         const char *__restrict__ med,
+                                                         MLayout mlay, Geom g, Physics ph,
+                                                         float s, float inv_s, int band,
+                                                         int groups, float *__restrict__ hist1,
+                                                         float *__restrict__ hist2)
+{
+    // logical block: band-major, four strips (one per wave) per block
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int bnd = L / groups;
+    const int strip = (L - bnd * groups) * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    const int nstrips = (g.nx + kStrip2 - 1) / kStrip2;
+    if (strip >= nstrips)
+        return; // the whole wave
+    // lane l holds column strip * kStrip2 - 2 + l: lanes 2..kStrip2+1 the
+    // strip's own columns, two halo columns on either side
+    const int xr = strip * kStrip2 - 2 + lane;
+    Lanes ln;
+    if (BCX == BC_PERIODIC)
+        ln.x = (uint32_t)(((xr % g.nx) + g.nx) % g.nx);
+    else
+        ln.x = (uint32_t)(xr < 0 ? 0 : (xr >= g.nx ? g.nx - 1 : xr)); // beyond: unused copies
+    // A pressure column takes its neighbour's pull, which the second step
+    // completes on lanes 2..kStrip2+1 only: an outlet column at lane 2 is
+    // left to the previous strip, where it sits at lane kStrip2 + 2.
+    bool owned = lane >= 2 && lane <= kStrip2 + 1 && xr < g.nx;
+    if (BCX == BC_PRESSURE && xr == g.nx - 1)
+        owned = lane >= 3 && lane <= kStrip2 + 2;
+    ln.wxm = BCX == BC_WALL && ln.x == 0;
+    ln.wxp = BCX == BC_WALL && ln.x == (uint32_t)g.nx - 1;
+    ln.bin = BCX == BC_PRESSURE && xr == 0;
+    ln.bout = BCX == BC_PRESSURE && xr == g.nx - 1;
+    ln.has_b = BCX == BC_PRESSURE && (strip == 0 || strip >= nstrips - 2);
+    const int y0 = bnd * band, y1 = min(y0 + band, g.ny);
+    auto exists = [&](int y) { return BCY == BC_PERIODIC || (y >= 0 && y < g.ny); };
+    auto wrap = [&](int y) { return BCY == BC_PERIODIC ? ((y % g.ny) + g.ny) % g.ny : y; };
+    // a row index that always exists (rows beyond a wall: the last row; its
+    // values are loaded but never used, since the pull bounces back there)
+    auto held = [&](int y) { return BCY == BC_PERIODIC ? wrap(y) : min(y, g.ny - 1); };
+    auto wall_lo = [&](int y) { return BCY == BC_WALL && y == 0; };
+    auto wall_hi = [&](int y) { return BCY == BC_WALL && y == g.ny - 1; };
+    // Every lane stores, so that the stores are not inside a branch: a lane
+    // that does not own its column repeats the store of the wave's first
+    // owning lane (same address, same value).  With no branch around them
+    // the compiler counts exactly how many stores follow a prefetched row's
+    // loads and waits for those loads alone, not for the stores too.
+    const uint64_t om = __builtin_amdgcn_ballot_w64(owned);
+    if (om == 0)
+        return; // an outlet strip whose only column the previous strip stores
+    const int q = (int)__builtin_ctzll(om);
+    const uint32_t xq = (uint32_t)__builtin_amdgcn_readlane((int)ln.x, q);
+    const uint32_t xst = owned ? ln.x : xq;
+    auto same = [&](float v) {
+        const float vq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
+        return owned ? v : vq;
+    };
+
+    // For the current output row y: old level rows y .. y + 2 in use, rows
+    // y + 3 and y + 4 in flight (loads are issued two rows ahead of their
+    // use, which keeps enough of them outstanding per wave to cover HBM
+    // latency), intermediate rows y - 1 .. y + 1 (m0..m2).
+    Mid a1{}, a2{}, a3{}, a4{}, a5{}, m0{}, m1{}, m2{};
+    if (exists(y0 - 2))
+        load_node<T>(src, lay, med, mlay, wrap(y0 - 2), ln.x, a4);
+    if (exists(y0 - 1))
+        load_node<T>(src, lay, med, mlay, wrap(y0 - 1), ln.x, a5);
+    load_node<T>(src, lay, med, mlay, y0, ln.x, a1);
+    if (exists(y0 + 1))
+        load_node<T>(src, lay, med, mlay, wrap(y0 + 1), ln.x, a2);
+    if (exists(y0 - 1))
+        first_step<T, BCX, HIST>(ph, s, inv_s, g, a4, a5, a1, wall_lo(y0 - 1), wall_hi(y0 - 1),
+                                 ln, wrap(y0 - 1), hist1, false, m0);
+    first_step<T, BCX, HIST>(ph, s, inv_s, g, a5, a1, a2, wall_lo(y0), wall_hi(y0), ln, y0,
+                             hist1, owned, m1);
+    load_node<T>(src, lay, med, mlay, held(y0 + 2), ln.x, a3);
+    load_node<T>(src, lay, med, mlay, held(y0 + 3), ln.x, a4);
+    // One output row: u0..u2 are the old rows y .. y + 2, nx receives row
+    // y + 4.  The loop below calls it with the five old-row registers in
+    // rotated roles, so no loaded value is ever copied (a copy would make
+    // the wave wait for its load -- and for the stores issued after it --
+    // at that point rather than at the value's first use).
+    auto row = [&](int y, const Mid &u0, const Mid &u1, const Mid &u2, Mid &nx) {
+        load_node<T>(src, lay, med, mlay, held(y + 4), ln.x, nx);
+        if (exists(y + 1))
+            first_step<T, BCX, HIST>(ph, s, inv_s, g, u0, u1, u2, wall_lo(y + 1),
+                                     wall_hi(y + 1), ln, wrap(y + 1), hist1,
+                                     owned && y + 1 < y1, m2);
+        float hs[9], jx, jy;
+        const float rho =
+            step_from<T, BCX>(ph, s, inv_s, m0, m1, m2, wall_lo(y), wall_hi(y), ln, hs, jx, jy);
+        if (HIST && owned)
+            record(hist2, g, y, ln.x, rho, jx, jy);
+        const Rsrc out = make_rsrc(dst + (uint64_t)y * lay.row, (uint32_t)lay.row);
+        st_f32(out, xst * 4, 0, same(rho), true);
+        constexpr uint32_t es = sizeof(T);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            Elem<T>::st(out, xst * es, lay.h_off + i * lay.h_slot, same(hs[i]));
+        m0 = m1;
+        m1 = m2;
+    };
+    for (int y = y0; y < y1; y += 5) {
+        row(y, a1, a2, a3, a5);
+        if (y + 1 >= y1)
+            break;
+        row(y + 1, a2, a3, a4, a1);
+        if (y + 2 >= y1)
+            break;
+        row(y + 2, a3, a4, a5, a2);
+        if (y + 3 >= y1)
+            break;
+        row(y + 3, a4, a5, a1, a3);
+        if (y + 4 >= y1)
+            break;
+        row(y + 4, a5, a1, a2, a4);
+    }
 }
 
 // -------------------------------------------------------------- batches
@@ -596,6 +892,29 @@ static hipError_t sweep_t(const char *src, char *dst, const Layout &lay, const c
 }
 
 template <typename T, int BCX, int BCY>
+static hipError_t sweep2_t(const char *src, char *dst, const Layout &lay, const char *med,
+                           const MLayout &mlay, const Geom &g, const Physics &ph, float s,
+                           float inv_s, int band, float *hist1, float *hist2, hipStream_t st)
+{
+    if (band < 1 || (hist1 == nullptr) != (hist2 == nullptr))
+        return hipErrorInvalidValue;
+    const int nstrips = (g.nx + kStrip2 - 1) / kStrip2;
+    const int groups = (nstrips + kBlock / 64 - 1) / (kBlock / 64);
+    const int64_t blocks = (int64_t)groups * ((g.ny + band - 1) / band);
+    if (blocks > 0x7fffffff)
+        return hipErrorInvalidValue;
+    if (hist1)
+        hipLaunchKernelGGL((sweep2_kernel<T, BCX, BCY, true>), dim3((unsigned)blocks),
+                           dim3(kBlock), 0, st, src, dst, lay, med, mlay, g, ph, s, inv_s, band,
+                           groups, hist1, hist2);
+    else
+        hipLaunchKernelGGL((sweep2_kernel<T, BCX, BCY, false>), dim3((unsigned)blocks),
+                           dim3(kBlock), 0, st, src, dst, lay, med, mlay, g, ph, s, inv_s, band,
+                           groups, hist1, hist2);
+    return hipGetLastError();
+}
+
+template <typename T, int BCX, int BCY>
 static hipError_t macro_t(const char *src, const Layout &lay, const char *med,
                           const MLayout &mlay, const Geom &g, const Physics &ph, float s,
                           float inv_s,
@@ -670,6 +989,18 @@ hipError_t launch_sweep(int storage, int bcx, int bcy, const char *src, char *ds
     if (bcy < 0 || bcy > 1)
         return hipErrorInvalidValue;
     LBK_DISPATCH(sweep_t, src, dst, lay, med, mlay, g, ph, s, inv_s, hist, st)
+}
+
+hipError_t launch_sweep2(int storage, int bcx, int bcy, const char *src, char *dst,
+                         const Layout &lay, const char *med, const MLayout &mlay, const Geom &g,
+                         const Physics &ph, float s, float inv_s, int band, float *hist1,
+                         float *hist2, hipStream_t st)
+{
+    // FP32 only: for FP16 and BF16 storage two single sweeps are as fast
+    if (storage != 0 || bcy < 0 || bcy > 1)
+        return hipErrorInvalidValue;
+    LBK_DISPATCH_BC(sweep2_t, float, src, dst, lay, med, mlay, g, ph, s, inv_s, band, hist1,
+                    hist2, st)
 }
 
 hipError_t launch_macro(int storage, int bcx, int bcy, const char *src, const Layout &lay,

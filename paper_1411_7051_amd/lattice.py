@@ -21,7 +21,7 @@ PERIODIC, WALL, PRESSURE = 0, 1, 2
 def make_desc(nx, ny, tau=0.8, gx=0.0, gy=0.0, f_eps=0.0, bc_x=PERIODIC,
               bc_y=PERIODIC, rho_in=1.0, rho_out=1.0, rho0=1.0, rho_ref=1.0,
               kn_local=1, init=0, storage="f32", check_every=100, correlation=0,
-              slip_b=-1.0) -> Desc:
+              slip_b=-1.0, pass_mode=0) -> Desc:
     lib = _lib.load()
     d = Desc()
     check(lib.lbk_desc_default(ctypes.byref(d)))
@@ -35,6 +35,8 @@ def make_desc(nx, ny, tau=0.8, gx=0.0, gy=0.0, f_eps=0.0, bc_x=PERIODIC,
     d.correlation = (_lib.CORRELATION[correlation] if isinstance(correlation, str)
                      else int(correlation))
     d.slip_b = float(slip_b)
+    d.pass_mode = (_lib.PASS_MODE[pass_mode] if isinstance(pass_mode, str)
+                   else int(pass_mode))
     return d
 
 
@@ -58,7 +60,7 @@ class Lattice:
     ``eps``, ``k``, ``kn0``: [ny][nx] arrays (numpy or torch); ``k`` may be
     +inf.  Keyword parameters are those of ``lbk_desc`` (tau, gx, gy, f_eps,
     bc_x, bc_y, rho_in, rho_out, rho0, rho_ref, kn_local, init, storage,
-    check_every, correlation, slip_b)."""
+    check_every, correlation, slip_b, pass_mode)."""
 
     def __init__(self, eps, k, kn0=None, device: Optional[torch.device] = None,
                  **params):

@@ -57,6 +57,8 @@ def test_workspace_size_scales_with_lattice():
     (dict(f_eps=-1.0), "f_eps"),
     (dict(correlation=3), "correlation"),
     (dict(slip_b=0.5), "slip_b"),
+    (dict(pass_mode=3), "pass_mode"),
+    (dict(pass_mode=-1), "pass_mode"),
 ])
 def test_invalid_descriptions_rejected(kw, msg):
     d = make_desc(16, 8, **kw)
