@@ -41,7 +41,7 @@ LAYOUT_BYTES = {"f32": 92, "f16": 56, "bf16": 56}
 
 
 PROFILE = os.path.join(ROOT, "profiles", "sweep_discs4096.md")
-# FP32 lattices from this many nodes on take the two-step pass (the library's
+# lattices from this many nodes on take the two-step pass (the library's
 # automatic pass mode)
 TWO_STEP_NODES = 1 << 22
 
@@ -630,9 +630,9 @@ def main():
     acc_small = storage_accuracy(small, args.storages.split(","), 2000, dev)
     head = runs.get("f32") or next(iter(runs.values()))
     st = head["storage"]
-    # dominant kernel: FP32 lattices of 2^22 nodes and more step through the
+    # dominant kernel: lattices of 2^22 nodes and more step through the
     # two-step pass (one launch per two steps), the others one sweep a step
-    two = st == "f32" and case.nodes >= TWO_STEP_NODES
+    two = case.nodes >= TWO_STEP_NODES
     per_launch = 2 if two else 1
     launch_ms = per_launch * head["ms_per_step"]
     achieved = case.nodes * ALG_BYTES[st] / (launch_ms * 1e-3) / 1e9

@@ -66,13 +66,11 @@ typedef enum lbk_correlation {
     LBK_FC_NONE = 2         /* no slip correction: k_a = k */
 } lbk_correlation;
 
-/* How lbk_step (and the gradients' recomputing sweeps) advance an FP32
- * lattice: two time steps per pass, the intermediate level kept in
- * registers (bitwise the result of two single sweeps), or one step per
+/* How lbk_step (and a gradient's recomputing sweeps and reverse steps)
+ * advance a lattice: two time steps per pass, the intermediate level kept
+ * in registers (bitwise the result of two single sweeps), or one step per
  * sweep.  The two-step pass reads and writes the state once per two steps;
- * it pays off on lattices large enough to fill the device.  FP16 and BF16
- * lattices always take single sweeps (the two-step pass is not faster
- * there). */
+ * it pays off on lattices large enough to fill the device. */
 typedef enum lbk_pass_mode {
     LBK_PASS_AUTO = 0,     /* two-step passes for lattices of >= 2^22 nodes */
     LBK_PASS_TWO_STEP = 1, /* two-step passes whatever the size */
@@ -105,7 +103,7 @@ typedef struct lbk_desc {
     double rho_ref;      /* density at which kn0 is quoted */
     double slip_b;       /* slip coefficient b of Eq. 6, <= 0 (default -1) */
     int32_t correlation; /* lbk_correlation */
-    int32_t pass_mode;   /* lbk_pass_mode: how lbk_step advances FP32 lattices */
+    int32_t pass_mode;   /* lbk_pass_mode: one or two steps per pass */
 } lbk_desc;
 
 typedef struct lbk_lattice lbk_lattice;

@@ -274,8 +274,8 @@ __device__ __forceinline__ void collide3(const Physics &ph, float rho, float inc
 #pragma unroll
     for (int i = 1; i < 19; i += 2) {
         const float w = w3(i);
-        const float eu = ex3(i) * u[0] + ey3(i) * u[1] + ez3(i) * u[2];
-        const float q = cg * (ex3(i) * F[0] + ey3(i) * F[1] + ez3(i) * F[2]);
+        const float eu = edot(ex3(i), ey3(i), ez3(i), u[0], u[1], u[2]);
+        const float q = cg * edot(ex3(i), ey3(i), ez3(i), F[0], F[1], F[2]);
         const float P = om * eu + q;
         const float E = eu * (P + q);
         const float X = (w * Kb) * E + w * C;
@@ -341,7 +341,7 @@ __device__ __forceinline__ float post_stream3(const Rows3 &R, const Layout &L, c
         d[0] = Elem<T>::kScaled ? v0 * s : v0;
 #pragma unroll
         for (int i = 1; i < 19; i += 2) {
-            const float eu = ex3(i) * u[0] + ey3(i) * u[1] + ez3(i) * u[2];
+            const float eu = edot(ex3(i), ey3(i), ez3(i), u[0], u[1], u[2]);
             const float q = c + b * (4.5f * eu * eu - 1.5f * uu), t = a * eu;
             const float v1 = w3(i) * (q + t) + phys(d[i]);
             const float v2 = w3(i) * (q - t) + phys(d[i + 1]);

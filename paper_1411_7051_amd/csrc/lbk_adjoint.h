@@ -17,6 +17,15 @@ hipError_t launch_adjoint(int bcx, int bcy, const float *mu_in, float *mu_out, c
                           const Geom &g, const Physics &ph, int terminal, float a1, float a2,
                           int outlet, hipStream_t st);
 
+// Two reverse steps in one pass, bitwise two launch_adjoint calls (terminal
+// = 0) through an intermediate adjoint state that stays in registers:
+// mu_in = mu_n -> mu_out = mu_{n-2} (different arrays), hist1 / hist0 the
+// histories of steps n and n - 1; rows marched in bands of `band` >= 1.
+hipError_t launch_adjoint2(int bcx, int bcy, const float *mu_in, float *mu_out,
+                           const float *hist1, const float *hist0, const char *med,
+                           const MLayout &mlay, float *grad, float *grad2, const Geom &g,
+                           const Physics &ph, int band, hipStream_t st);
+
 // total[y][x] += seg[y][x]; seg[y][x] = 0 ([y][pitch]).
 hipError_t launch_grad_fold(float *seg, double *total, const Geom &g, hipStream_t st);
 

@@ -76,8 +76,11 @@ __device__ __forceinline__ NodeFwd node_fwd(const Physics &ph, float rho, float 
     n.ie = n.solid ? 0.0f : __builtin_amdgcn_rcpf(eps);
     n.rinv = __builtin_amdgcn_rcpf(rho);
     const float kn = ph.kn_local ? kn0 * (ph.rho_ref * n.rinv) : kn0;
+    float t = 0.0f; // Kn^0.4348 of the second-order correlation, once
+    if (ph.corr == CORR_BKC)
+        t = fc_pow(kn);
     float num, den; // f_c = den / num, as in the sweep
-    fc_parts(ph, kn, num, den);
+    fc_parts_t(ph, kn, t, num, den);
     const float dn = drag * num;
     n.A = dn * __builtin_amdgcn_rcpf(den);   // drag / f_c
     n.c0 = 1.0f + 0.5f * n.A;
@@ -108,7 +111,6 @@ __device__ __forceinline__ NodeFwd node_fwd(const Physics &ph, float rho, float 
     // Kn f_c'/f_c = 4 Kn / (1 + 4 Kn).
     float dAk = 0.0f;
     if (kn > 0.0f && ph.corr == CORR_BKC) {
-        const float t = __builtin_amdgcn_exp2f(0.4348f * __builtin_amdgcn_logf(kn));
         const float a = t + 0.170f;
         const float q = 1.0f + ph.slip_nb * kn;
         const float p1 = a + 1.358f * t * kn, p2 = 1.0f + ph.slip_c * kn;
@@ -124,25 +126,41 @@ __device__ __forceinline__ NodeFwd node_fwd(const Physics &ph, float rho, float 
 }
 
 // w-weighted moments of a 9-vector: L0 = sum w l, L1 = sum w l e,
-// L2 = sum w l e e (symmetric; xx, yy, xy).
+// L2 = sum w l e e (symmetric; xx, yy, xy), from the sums and differences
+// of opposite directions, each weight class applied once.
 struct Mom {
     float m0, m1x, m1y, mxx, myy, mxy;
 };
 __device__ __forceinline__ Mom moments(const float (&l)[9])
 {
-    Mom m{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const float wl = w_of(i) * l[i];
-        const int ex = ex_of(i), ey = ey_of(i);
-        m.m0 += wl;
-        m.m1x += ex * wl;
-        m.m1y += ey * wl;
-        m.mxx += (ex * ex) * wl;
-        m.myy += (ey * ey) * wl;
-        m.mxy += (ex * ey) * wl;
-    }
+    // e_5 = (1, 1), e_6 = (-1, 1), e_7 = (-1, -1), e_8 = (1, -1)
+    const float a13 = l[1] + l[3], d13 = l[1] - l[3];
+    const float a24 = l[2] + l[4], d24 = l[2] - l[4];
+    const float a57 = l[5] + l[7], d57 = l[5] - l[7];
+    const float a68 = l[6] + l[8], d68 = l[6] - l[8];
+    const float sd = a57 + a68;
+    const float w0 = w_of(0), w1 = w_of(1), w2 = w_of(5);
+    Mom m;
+    m.m0 = w0 * l[0] + w1 * (a13 + a24) + w2 * sd;
+    m.m1x = w1 * d13 + w2 * (d57 - d68);
+    m.m1y = w1 * d24 + w2 * (d57 + d68);
+    m.mxx = w1 * a13 + w2 * sd;
+    m.myy = w1 * a24 + w2 * sd;
+    m.mxy = w2 * (a57 - a68);
     return m;
+}
+
+// out_i = k v_i + c + e_i . (gx, gy) for the nine directions (v = NULL: k
+// v_i left out), the direction-class sums formed once.
+template <bool V>
+__device__ __forceinline__ void spread(float k, const float *v, float c, float gx, float gy,
+                                       float (&out)[9])
+{
+    const float px = c + gx, mx = c - gx;
+    const float t[9] = {c, px, c + gy, mx, c - gy, px + gy, mx + gy, mx - gy, px - gy};
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+        out[i] = V ? k * v[i] + t[i] : t[i];
 }
 
 // Chain rule from the partials of a node function Psi(rho, u, F) (explicit
@@ -224,10 +242,7 @@ __device__ __forceinline__ Grads collide_adj(const Physics &ph, const NodeFwd &n
     const float PFx = rho * cg * (3.0f * L.m1x + 9.0f * ie * L2ux - 3.0f * ie * L.m0 * ux);
     const float PFy = rho * cg * (3.0f * L.m1y + 9.0f * ie * L2uy - 3.0f * ie * L.m0 * uy);
     const Grads G = chain(n, Pr, Pux, Puy, PFx, PFy);
-    const float keep = 1.0f - om;
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-        lf[i] = keep * mu[i] + G.rho + ex_of(i) * G.jx + ey_of(i) * G.jy;
+    spread<true>(1.0f - om, mu, G.rho, G.jx, G.jy, lf);
     return G;
 }
 
@@ -238,9 +253,7 @@ __device__ __forceinline__ Grads readout_adj(const NodeFwd &n, float a1, float a
     Grads G{0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     if (!n.solid && (a1 != 0.0f || a2 != 0.0f))
         G = chain(n, a1 * n.ux, a1 * n.rho + a2, 0.0f, 0.0f, 0.0f);
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-        lf[i] = G.rho + ex_of(i) * G.jx + ey_of(i) * G.jy;
+    spread<false>(0.0f, nullptr, G.rho, G.jx, G.jy, lf);
     return G;
 }
 
@@ -276,9 +289,11 @@ __device__ __forceinline__ float2 nee_adj(const NodeFwd &n, float rho_b, float e
         gx = gy = gl = gk = 0.0f;
         gr = -phin_over_rho;
     }
+    float add[9];
+    spread<true>(1.0f, lb, gr, gx, gy, add);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-        lfn[i] += lb[i] + gr + ex_of(i) * gx + ey_of(i) * gy;
+        lfn[i] += add[i];
     return make_float2(gl, gk);
 }
 
@@ -459,6 +474,326 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float 
                                a2, outlet, y, x);
 }
 
+// ------------------------------------------------ two reverse steps per pass
+//
+// adjoint2_kernel takes mu_n to mu_{n-2} in one pass, bitwise what two
+// adjoint_kernel launches through mu_{n-1} give, with mu_{n-1} never
+// leaving registers.  In gather form a reverse step reads
+//   mu_{n-1}(x, j) = lam_f_j(x + e_j),
+// lam_f_{opp j}(x) where x + e_j lies beyond a wall (bounce-back), and 0
+// where x + e_j lies beyond a pressure column; lam_f itself is local to its
+// node (plus, at the column next to a pressure column, that column's
+// contribution through the non-equilibrium extrapolation).  As in the
+// forward two-step pass, a wave holds a strip of 64 columns (60 of its own
+// and two halo columns on either side, x neighbours through DPP lane shifts)
+// and marches down a band of rows; lam_f of step n, mu_{n-1} and lam_f of
+// step n-1 of the rows around the current one stay in registers, and each
+// gradient entry collects both steps' terms before it is written once.
+namespace {
+
+constexpr int kStripA = 60;
+
+// Lane-dependent facts of a strip of the reverse pass.
+struct ALanes {
+    uint32_t x;         // the lane's column, wrapped (periodic) or clamped
+    bool wxm, wxp;      // wall x: the column is the first / last
+    bool first, last;   // pressure x: the inlet / outlet column
+    bool cl, cr;        // pressure x: the column next to the inlet / outlet
+    bool has_b;         // uniform: the wave may hold any of these
+    bool bgrad;         // pressure columns receive gradient terms (nx >= 3)
+};
+
+// A row's inputs at this lane's column, in two parts loaded at different
+// times: what the reverse of step n needs (mu_n, the history of step n and
+// the medium) and what the reverse of step n - 1 adds (the history of step
+// n - 1 and the medium again).  Each part is loaded straight into the
+// registers where it is used, and nothing loaded is copied to another
+// register, so no load is waited for before its use.
+struct RowA {
+    float mu[9], h1[3], md[3];
+};
+struct RowB {
+    float h0[3], md[3];
+};
+// After the reverse of step n, and after that of step n - 1: lam_f and the
+// gradient terms.
+struct AMid {
+    float lf[9], gl, gk;
+};
+
+// lam_f and the ln k / ln kn0 terms of one reverse step at this lane's node
+// (adjoint_node's arithmetic, with a pressure column's contribution taken
+// from the neighbouring lane rather than recomputed).
+template <int BCX, bool FC>
+__device__ __forceinline__ void local_adj(const Physics &ph, const float (&mu)[9], const float (&h)[3],
+                                          const float (&md)[3], const ALanes &ln,
+                                          float (&lf)[9], float &gl, float &gk)
+{
+    const NodeFwd n = node_fwd<FC>(ph, h[0], h[1], h[2], md[0], md[1], md[2]);
+    const Grads G = collide_adj(ph, n, mu, lf);
+    gl = G.lnk;
+    gk = G.lnkn;
+    if (BCX != BC_PRESSURE)
+        return;
+    if (ln.has_b) {
+        // the pressure columns' lam_f as computed so far (never changed by
+        // the carries below, which only touch the columns next to them)
+        float lb[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            lb[i] = lane_from<1>(lf[i]);
+        float rb = lane_from<1>(n.rho), eb = lane_from<1>(n.eps);
+        if (ln.cl) {
+            const float2 q = nee_adj(n, rb, eb, lb, lf);
+            gl += q.x;
+            gk += q.y;
+        }
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            lb[i] = lane_from<-1>(lf[i]);
+        rb = lane_from<-1>(n.rho);
+        eb = lane_from<-1>(n.eps);
+        if (ln.cr) {
+            const float2 q = nee_adj(n, rb, eb, lb, lf);
+            gl += q.x;
+            gk += q.y;
+        }
+    }
+    if (ln.first || ln.last) {
+        // forward values pulled into a pressure column are discarded
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            lf[i] = 0.0f;
+        if (!ln.bgrad)
+            gl = gk = 0.0f;
+    }
+}
+
+// mu of this lane's node from lam_f of rows y - 1 (dn), y (c), y + 1 (up).
+// wym / wyp: the row below / above lies beyond a wall.
+template <int BCX>
+__device__ __forceinline__ void gather(const float (&dn)[9], const float (&c)[9],
+                                       const float (&up)[9], bool wym, bool wyp,
+                                       const ALanes &ln, float (&mu)[9])
+{
+    mu[0] = c[0];
+#pragma unroll
+    for (int j = 1; j < 9; ++j) {
+        const int ex = ex_of(j), ey = ey_of(j);
+        const bool wall_y = (ey == 1 && wyp) || (ey == -1 && wym); // uniform
+        const float(&r)[9] = ey == 1 ? up : (ey == -1 ? dn : c);
+        float v;
+        if (wall_y)
+            v = c[opp_of(j)];
+        else if (ex == 1)
+            v = lane_from<-1>(r[j]);
+        else if (ex == -1)
+            v = lane_from<1>(r[j]);
+        else
+            v = r[j];
+        if (BCX == BC_WALL) {
+            const bool out_x = (ex == 1 && ln.wxp) || (ex == -1 && ln.wxm);
+            if (out_x)
+                v = c[opp_of(j)];
+        }
+        if (BCX == BC_PRESSURE) {
+            const bool out_x = (ex == 1 && ln.last) || (ex == -1 && ln.first);
+            if (out_x)
+                v = 0.0f;
+        }
+        mu[j] = v;
+    }
+}
+
+} // namespace
+
+// Two reverse steps: mu_in = mu_n -> mu_out = mu_{n-2}, hist1 / hist0 the
+// histories of steps n and n - 1, grad / grad2 as in adjoint_node.  Rows
+// are marched in bands of `band`; a block holds four strips.
+#ifndef LBK_ADJ2_WAVES
+#define LBK_ADJ2_WAVES 1
+#endif
+template <int BCX, int BCY, bool KN, bool FC>
+__global__ __launch_bounds__(256, LBK_ADJ2_WAVES) void adjoint2_kernel(
+    const float *__restrict__ mu_in, float *__restrict__ mu_out, const float *__restrict__ hist1,
+    const float *__restrict__ hist0, const char *__restrict__ med, MLayout mlay,
+    float *__restrict__ grad, float *__restrict__ grad2, Geom g, Physics ph, int band, int groups)
+{
+    const int L = xcd_remap_a(blockIdx.x, gridDim.x);
+    const int bnd = L / groups;
+    const int strip = (L - bnd * groups) * 4 + (int)(threadIdx.x >> 6);
+    const int lane = (int)(threadIdx.x & 63);
+    const int nx = g.nx, ny = g.ny;
+    const int nstrips = (nx + kStripA - 1) / kStripA;
+    if (strip >= nstrips)
+        return; // the whole wave
+    // Strip s owns columns [c0, c1).  With pressure columns the last strip
+    // starts at most at nx - 4: the column next to the outlet then never
+    // sits at lane 63 of a strip that owns the column two to its left, whose
+    // result would need the outlet column's values from beyond the wave.
+    int c0 = strip * kStripA, c1 = min(c0 + kStripA, nx);
+    if (BCX == BC_PRESSURE) {
+        const int cl = max(0, min(kStripA * (nstrips - 1), nx - 4));
+        if (strip == nstrips - 1)
+            c0 = cl;
+        else if (strip == nstrips - 2)
+            c1 = cl;
+    }
+    const int xr = c0 - 2 + lane;
+    const bool owned = xr >= c0 && xr < c1;
+    ALanes ln;
+    if (BCX == BC_PERIODIC)
+        ln.x = (uint32_t)(((xr % nx) + nx) % nx);
+    else
+        ln.x = (uint32_t)(xr < 0 ? 0 : (xr >= nx ? nx - 1 : xr)); // beyond: unused copies
+    ln.wxm = BCX == BC_WALL && xr == 0;
+    ln.wxp = BCX == BC_WALL && xr == nx - 1;
+    ln.first = BCX == BC_PRESSURE && xr == 0;
+    ln.last = BCX == BC_PRESSURE && xr == nx - 1;
+    ln.cl = BCX == BC_PRESSURE && nx >= 3 && xr == 1;
+    ln.cr = BCX == BC_PRESSURE && nx >= 3 && xr == nx - 2;
+    ln.has_b = BCX == BC_PRESSURE && (strip == 0 || strip >= nstrips - 2);
+    ln.bgrad = nx >= 3;
+    const int y0 = bnd * band, y1 = min(y0 + band, ny);
+    auto exists = [&](int y) { return BCY == BC_PERIODIC || (y >= 0 && y < ny); };
+    auto wrap = [&](int y) { return BCY == BC_PERIODIC ? ((y % ny) + ny) % ny : y; };
+    // a row that always exists (beyond a wall: the nearest row, loaded but
+    // never used, since the gather bounces back there)
+    auto held = [&](int y) {
+        return BCY == BC_PERIODIC ? wrap(y) : (y < 0 ? 0 : (y >= ny ? ny - 1 : y));
+    };
+    auto wall_lo = [&](int y) { return BCY == BC_WALL && y == 0; };
+    auto wall_hi = [&](int y) { return BCY == BC_WALL && y == ny - 1; };
+    // Unconditional stores (see sweep2_kernel): a lane that does not own
+    // its column repeats the store of the wave's first owning lane.
+    const uint64_t om = __builtin_amdgcn_ballot_w64(owned);
+    if (om == 0)
+        return;
+    const int q = (int)__builtin_ctzll(om);
+    const uint32_t xq = (uint32_t)__builtin_amdgcn_readlane((int)ln.x, q);
+    const uint32_t xst = owned ? ln.x : xq;
+    auto same = [&](float v) {
+        const float vq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
+        return owned ? v : vq;
+    };
+
+    const uint64_t lrow = 9ull * g.pitch * 4, hrow = 3ull * g.pitch * 4;
+    const uint64_t grow = (uint64_t)g.pitch * 4;
+    const uint32_t slot = (uint32_t)g.pitch * 4;
+    const uint32_t xo = ln.x * 4;
+    // Loads keep the default cache policy: a strip's first and last cache
+    // lines are shared with the neighbouring strips, which read them about
+    // the same time.
+    auto med_row = [&](int yh) {
+        return make_rsrc(med + (uint64_t)yh * mlay.row, (uint32_t)mlay.row);
+    };
+    auto load_a = [&](int y, RowA &r) {
+        const int yh = held(y);
+        const Rsrc lr = rsrc_row(mu_in, lrow, yh);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            r.mu[i] = ld_f32(lr, xo, i * slot);
+        const Rsrc hr = rsrc_row(hist1, hrow, yh), mr = med_row(yh);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            r.h1[k] = ld_f32(hr, xo, k * slot);
+            r.md[k] = ld_f32(mr, xo, k * mlay.slot);
+        }
+    };
+    auto load_b = [&](int y, RowB &r) {
+        const int yh = held(y);
+        const Rsrc hr = rsrc_row(hist0, hrow, yh), mr = med_row(yh);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            r.h0[k] = ld_f32(hr, xo, k * slot);
+            r.md[k] = ld_f32(mr, xo, k * mlay.slot);
+        }
+    };
+    auto step_a = [&](const RowA &r, AMid &a) {
+        local_adj<BCX, FC>(ph, r.mu, r.h1, r.md, ln, a.lf, a.gl, a.gk);
+    };
+    auto step_b = [&](int y, const AMid &dn, const AMid &c, const AMid &up, const RowB &r,
+                      AMid &b) {
+        float mu[9];
+        gather<BCX>(dn.lf, c.lf, up.lf, wall_lo(y), wall_hi(y), ln, mu);
+        local_adj<BCX, FC>(ph, mu, r.h0, r.md, ln, b.lf, b.gl, b.gk);
+    };
+    // Output row y from lam_f of step n - 1 of rows y - 1 .. y + 1; the
+    // gradient entries add the terms of step n (a) and then of step n - 1
+    // (c), in the order of two single reverse steps.
+    auto emit = [&](int y, const AMid &dn, const AMid &c, const AMid &up, const AMid &a,
+                    float gp, float gk) {
+        float mu[9];
+        gather<BCX>(dn.lf, c.lf, up.lf, wall_lo(y), wall_hi(y), ln, mu);
+        const Rsrc orow = rsrc_row(mu_out, lrow, y);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            st_f32(orow, xst * 4, i * slot, same(mu[i]), false);
+        st_f32(rsrc_row(grad, grow, y), xst * 4, 0, same((gp + a.gl) + c.gl), false);
+        if (KN)
+            st_f32(rsrc_row(grad2, grow, y), xst * 4, 0, same((gk + a.gk) + c.gk), false);
+    };
+
+    // For output row y: lam_f of step n of rows y .. y + 2 (A slots), of
+    // step n - 1 of rows y - 1 .. y + 1 (B slots).  The first input parts
+    // of rows y + 2 .. y + 4 and the second parts of rows y + 1 .. y + 3 are
+    // in flight (three slots each, reloaded as soon as consumed).
+    RowA P, Q, S;
+    RowB U, V, W;
+    AMid A0{}, A1{}, A2{}, B0{}, B1{}, B2{};
+    load_a(y0 - 2, P);
+    load_a(y0 - 1, Q);
+    load_a(y0, S);
+    load_b(y0 - 1, U);
+    load_b(y0, V);
+    load_b(y0 + 2, W);
+    if (exists(y0 - 2))
+        step_a(P, A0);
+    load_a(y0 + 1, P);
+    if (exists(y0 - 1))
+        step_a(Q, A1);
+    load_a(y0 + 2, Q);
+    step_a(S, A2);
+    load_a(y0 + 3, S);
+    if (exists(y0 - 1))
+        step_b(wrap(y0 - 1), A0, A1, A2, U, B0);
+    load_b(y0 + 1, U);
+    if (exists(y0 + 1))
+        step_a(P, A0);
+    load_a(y0 + 4, P);
+    step_b(y0, A1, A2, A0, V, B1);
+    load_b(y0 + 3, V);
+    // One output row y, the slots in rotated roles (period 3).
+    // The gradient entries of row y are read at the start of its row, a
+    // whole row's arithmetic before they are needed.
+    auto row = [&](int y, RowA &ra, AMid &na, const AMid &adn, const AMid &ac, RowB &rb,
+                   AMid &nb, const AMid &bdn, const AMid &bc) {
+        const float gp = ld_f32(rsrc_row(grad, grow, y), xo, 0);
+        const float gk = KN ? ld_f32(rsrc_row(grad2, grow, y), xo, 0) : 0.0f;
+        if (exists(y + 2))
+            step_a(ra, na);
+        load_a(y + 5, ra);
+        if (exists(y + 1))
+            step_b(wrap(y + 1), adn, ac, na, rb, nb);
+        load_b(y + 4, rb);
+        emit(y, bdn, bc, nb, adn, gp, gk);
+    };
+    // Whole periods in the loop, the last one or two rows after it: a loop
+    // with exits between its rows made the compiler copy loaded values at
+    // the back edge, waiting there for the loads just issued.
+    int y = y0;
+    for (; y + 3 <= y1; y += 3) {
+        row(y, Q, A1, A2, A0, U, B2, B0, B1);
+        row(y + 1, S, A2, A0, A1, W, B0, B1, B2);
+        row(y + 2, P, A0, A1, A2, V, B1, B2, B0);
+    }
+    if (y < y1) {
+        row(y, Q, A1, A2, A0, U, B2, B0, B1);
+        if (y + 1 < y1)
+            row(y + 1, S, A2, A0, A1, W, B0, B1, B2);
+    }
+}
+
 // total += seg; seg = 0 (end of a recomputed segment)
 __global__ __launch_bounds__(256) void grad_fold_kernel(float *seg, double *total, Geom g,
                                                          int bpr)
@@ -525,6 +860,51 @@ hipError_t launch_adjoint(int bcx, int bcy, const float *mu_in, float *mu_out, c
     default: return hipErrorInvalidValue;
     }
 #undef LBK_ADJ
+}
+
+template <int BCX, int BCY>
+static hipError_t adj2_t(const float *mu_in, float *mu_out, const float *hist1,
+                         const float *hist0, const char *med, const MLayout &mlay, float *grad,
+                         float *grad2, const Geom &g, const Physics &ph, int band, hipStream_t st)
+{
+    const int nstrips = (g.nx + kStripA - 1) / kStripA;
+    const int groups = (nstrips + 3) / 4;
+    const int blocks = groups * ((g.ny + band - 1) / band);
+#define LBK_ADJ2K(KN, FC)                                                                    \
+    hipLaunchKernelGGL((adjoint2_kernel<BCX, BCY, KN, FC>), dim3(blocks), dim3(256), 0, st,    \
+                       mu_in, mu_out, hist1, hist0, med, mlay, grad, grad2, g, ph, band, groups)
+    const bool fc = ph.feps != 0.0f;
+    if (grad2 && fc)
+        LBK_ADJ2K(true, true);
+    else if (grad2)
+        LBK_ADJ2K(true, false);
+    else if (fc)
+        LBK_ADJ2K(false, true);
+    else
+        LBK_ADJ2K(false, false);
+#undef LBK_ADJ2K
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint2(int bcx, int bcy, const float *mu_in, float *mu_out,
+                           const float *hist1, const float *hist0, const char *med,
+                           const MLayout &mlay, float *grad, float *grad2, const Geom &g,
+                           const Physics &ph, int band, hipStream_t st)
+{
+    if (band < 1 || mu_in == mu_out)
+        return hipErrorInvalidValue;
+#define LBK_ADJ2(X, Y)                                                                       \
+    adj2_t<X, Y>(mu_in, mu_out, hist1, hist0, med, mlay, grad, grad2, g, ph, band, st)
+    switch (bcx * 2 + bcy) {
+    case 0: return LBK_ADJ2(BC_PERIODIC, BC_PERIODIC);
+    case 1: return LBK_ADJ2(BC_PERIODIC, BC_WALL);
+    case 2: return LBK_ADJ2(BC_WALL, BC_PERIODIC);
+    case 3: return LBK_ADJ2(BC_WALL, BC_WALL);
+    case 4: return LBK_ADJ2(BC_PRESSURE, BC_PERIODIC);
+    case 5: return LBK_ADJ2(BC_PRESSURE, BC_WALL);
+    default: return hipErrorInvalidValue;
+    }
+#undef LBK_ADJ2
 }
 
 hipError_t launch_grad_fold(float *seg, double *total, const Geom &g, hipStream_t st)

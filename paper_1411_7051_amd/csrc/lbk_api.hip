@@ -120,9 +120,9 @@ void split(double v, float &hi, float &lo)
 
 } // namespace
 
-// n steps of the lattice on stream st: for the storage types that use it,
-// pairs of steps fused into one pass (launch_sweep2, bitwise two single
-// sweeps) and a single sweep if n is odd; otherwise n single sweeps.
+// n steps of the lattice on stream st: when the lattice takes two-step
+// passes, pairs of steps fused into one pass (launch_sweep2, bitwise two
+// single sweeps) and a single sweep if n is odd; otherwise n single sweeps.
 lbk_status lbk::advance(lbk_lattice *lat, int64_t n, hipStream_t st)
 {
     const lbk_desc &d = lat->d;
@@ -130,7 +130,7 @@ lbk_status lbk::advance(lbk_lattice *lat, int64_t n, hipStream_t st)
         const int nxt = lat->cur ^ 1;
         HIP_TRY(launch_sweep2(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->state(nxt),
                               lat->L.lay, lat->med(), lat->L.mlay, lat->g, lat->ph, lat->s(),
-                              lat->inv_s(), kBand2, nullptr, nullptr, st));
+                              lat->inv_s(), band2_of(d.storage), nullptr, nullptr, st));
         lat->cur = nxt;
         lat->t += 2;
         ++lat->version;
@@ -795,8 +795,8 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
     const bool two = two_step_pass(lat);
     auto sweep2 = [&](const char *src, char *dst, float *hist1, float *hist2) {
         return launch_sweep2(d.storage, d.bc_x, d.bc_y, src, dst, lat->L.lay, lat->med(),
-                             lat->L.mlay, lat->g, lat->ph, lat->s(), lat->inv_s(), kBand2, hist1,
-                             hist2, st);
+                             lat->L.mlay, lat->g, lat->ph, lat->s(), lat->inv_s(),
+                             band2_of(d.storage), hist1, hist2, st);
     };
     const float a1 = (float)P.a1, a2 = (float)P.a2;
 
@@ -869,10 +869,18 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
                 }
             }
             Range range("adjoint reverse");
-            for (int64_t t = b2s; t > a2s; --t) {
-                HIP_TRY(launch_adjoint(d.bc_x, d.bc_y, lam[cur], lam[cur ^ 1], histp(t - a2s),
-                                       lat->med(), lat->L.mlay, seg, seg2, lat->g, lat->ph, 0,
-                                       a1, a2, P.outlet, st));
+            for (int64_t t = b2s; t > a2s;) {
+                if (two && t - 1 > a2s) {
+                    HIP_TRY(launch_adjoint2(d.bc_x, d.bc_y, lam[cur], lam[cur ^ 1],
+                                            histp(t - a2s), histp(t - 1 - a2s), lat->med(),
+                                            lat->L.mlay, seg, seg2, lat->g, lat->ph, kBandA, st));
+                    t -= 2;
+                } else {
+                    HIP_TRY(launch_adjoint(d.bc_x, d.bc_y, lam[cur], lam[cur ^ 1],
+                                           histp(t - a2s), lat->med(), lat->L.mlay, seg, seg2,
+                                           lat->g, lat->ph, 0, a1, a2, P.outlet, st));
+                    --t;
+                }
                 cur ^= 1;
             }
             HIP_TRY(launch_grad_fold(seg, grad, lat->g, st));

@@ -49,6 +49,26 @@ __host__ __device__ constexpr int opp_of(int i)
 {
     return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5);
 }
+// e . a for a lattice velocity e (components -1, 0, 1): the terms of zero
+// components are left out rather than multiplied by 0 (a product the
+// compiler must keep, since 0 * inf is NaN); the others are summed in order.
+__device__ __forceinline__ float edot(int ex, int ey, int ez, float ax, float ay, float az)
+{
+    float v = 0.0f;
+    bool first = true;
+    if (ex != 0) {
+        v = ex * ax;
+        first = false;
+    }
+    if (ey != 0) {
+        v = first ? ey * ay : v + ey * ay;
+        first = false;
+    }
+    if (ez != 0)
+        v = first ? ez * az : v + ez * az;
+    return v;
+}
+
 // Weights stated with Eq. 14.
 __host__ __device__ constexpr float w_of(int i)
 {
@@ -114,9 +134,10 @@ template <> struct Elem<float> {
     {
         return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, AUX));
     }
+    template <int AUX = kNT>
     static __device__ __forceinline__ void st(Rsrc r, uint32_t voff, uint32_t soff, float v)
     {
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, kNT);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, AUX);
     }
     // the value a store followed by a load returns
     static __device__ __forceinline__ float round(float v) { return v; }
@@ -129,10 +150,11 @@ template <> struct Elem<__half> {
         const uint16_t u = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, AUX);
         return __half2float(__ushort_as_half(u));
     }
+    template <int AUX = kNT>
     static __device__ __forceinline__ void st(Rsrc r, uint32_t voff, uint32_t soff, float v)
     {
         __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(f32_reg(v))), r,
-                                              (int)voff, (int)soff, kNT);
+                                              (int)voff, (int)soff, AUX);
     }
     static __device__ __forceinline__ float round(float v)
     {
@@ -147,11 +169,12 @@ template <> struct Elem<__hip_bfloat16> {
         const uint16_t u = __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, AUX);
         return __uint_as_float((uint32_t)u << 16);
     }
+    template <int AUX = kNT>
     static __device__ __forceinline__ void st(Rsrc r, uint32_t voff, uint32_t soff, float v)
     {
         const __hip_bfloat16 b = __float2bfloat16(v); // round to nearest even
         __builtin_amdgcn_raw_buffer_store_b16(*reinterpret_cast<const uint16_t *>(&b), r,
-                                              (int)voff, (int)soff, kNT);
+                                              (int)voff, (int)soff, AUX);
     }
     static __device__ __forceinline__ float round(float v)
     {
@@ -202,10 +225,15 @@ enum { CORR_BKC = 0, CORR_KLINKENBERG = 1, CORR_NONE = 2 };
 //     1 + 4 Kn / (1 - b Kn) = (1 + (4 - b) Kn) / (1 - b Kn);
 //   CORR_KLINKENBERG (Eqs. 4-5): 1 + 4 Kn;  CORR_NONE: 1.
 // t = exp2(0.4348 log2 Kn) is 0 at Kn = 0, so f_c(0) = 1.
-__device__ __forceinline__ void fc_parts(const Physics &ph, float kn, float &num, float &den)
+__device__ __forceinline__ float fc_pow(float kn)
+{
+    return __builtin_amdgcn_exp2f(0.4348f * __builtin_amdgcn_logf(kn));
+}
+// fc_parts with t = fc_pow(kn) given (used only by CORR_BKC).
+__device__ __forceinline__ void fc_parts_t(const Physics &ph, float kn, float t, float &num,
+                                           float &den)
 {
     if (ph.corr == CORR_BKC) {
-        const float t = __builtin_amdgcn_exp2f(0.4348f * __builtin_amdgcn_logf(kn));
         const float a = t + 0.170f;
         num = a * (1.0f + ph.slip_nb * kn);
         den = (a + 1.358f * t * kn) * (1.0f + ph.slip_c * kn);
@@ -216,6 +244,13 @@ __device__ __forceinline__ void fc_parts(const Physics &ph, float kn, float &num
         num = 1.0f;
         den = 1.0f;
     }
+}
+__device__ __forceinline__ void fc_parts(const Physics &ph, float kn, float &num, float &den)
+{
+    if (ph.corr == CORR_BKC)
+        fc_parts_t(ph, kn, fc_pow(kn), num, den);
+    else
+        fc_parts_t(ph, kn, 0.0f, num, den);
 }
 
 // Lattice extent; `pitch` = elements per row slot (a multiple of 64).
@@ -439,8 +474,8 @@ __device__ __forceinline__ void collide(const Physics &ph, float rho, float inc,
         if (i == 3 || i == 4)
             continue; // pairs (1,3) (2,4) (5,7) (6,8)
         const float w = w_of(i);
-        const float eu = ex_of(i) * ux + ey_of(i) * uy;
-        const float q = cg * (ex_of(i) * Fx + ey_of(i) * Fy);
+        const float eu = edot(ex_of(i), ey_of(i), 0, ux, uy, 0.0f);
+        const float q = cg * edot(ex_of(i), ey_of(i), 0, Fx, Fy, 0.0f);
         const float P = om * eu + q;
         const float E = eu * (P + q);
         const float X = (w * Kb) * E + w * C;

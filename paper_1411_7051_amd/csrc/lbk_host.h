@@ -106,29 +106,38 @@ struct lbk_lattice {
 
 namespace lbk {
 
-// Rows per band of the two-step sweep.  Short bands keep the waves that run
-// at once on nearby rows (a band of 6 recomputes 2 of every 8 intermediate
-// rows, yet measured fastest on a 4096 x 4096 lattice: tall bands spread the
-// concurrent accesses over the whole level and ran 25% slower).
+// Rows per band of the two-step sweep, by storage.  Short bands keep the
+// waves that run at once on nearby rows (a band of 8 recomputes 2 of every
+// 10 intermediate rows, yet FP32 measured fastest at 6 to 8 on a 4096 x 4096
+// lattice: tall bands spread the concurrent accesses over the whole level
+// and ran up to 25% slower); FP16 and BF16, with half the bytes per row,
+// measured fastest at 10 to 12.
 #ifndef LBK_BAND2
-#define LBK_BAND2 6
+#define LBK_BAND2 8
 #endif
-constexpr int kBand2 = LBK_BAND2;
+#ifndef LBK_BAND2_HALF
+#define LBK_BAND2_HALF 10
+#endif
+inline int band2_of(int storage) { return storage == LBK_F32 ? LBK_BAND2 : LBK_BAND2_HALF; }
+// Rows per band of the two-step reverse pass.
+#ifndef LBK_BANDA
+#define LBK_BANDA 16
+#endif
+constexpr int kBandA = LBK_BANDA;
 
 // Lattices from this many nodes on take two-step passes under
 // LBK_PASS_AUTO: below it too few waves run to hide the march's latency
 // (1024 x 512: 38 against 48 GLUPS for single sweeps).
 constexpr int64_t kTwoStepNodes = (int64_t)1 << 22;
 
-// Whether steps of this lattice go through the two-step pass: FP32 storage
-// only (FP16 and BF16 single sweeps measured 1-2% faster than the two-step
-// pass, which is bound by its arithmetic there), as pass_mode asks.
+// Whether steps of this lattice go through the two-step pass (and the
+// reverse steps of its gradients through the two-step reverse pass), as
+// pass_mode asks.
 inline bool two_step_pass(const lbk_lattice *lat)
 {
     const lbk_desc &d = lat->d;
-    return d.storage == LBK_F32 &&
-           (d.pass_mode == LBK_PASS_TWO_STEP ||
-            (d.pass_mode == LBK_PASS_AUTO && (int64_t)d.nx * d.ny >= kTwoStepNodes));
+    return d.pass_mode == LBK_PASS_TWO_STEP ||
+           (d.pass_mode == LBK_PASS_AUTO && (int64_t)d.nx * d.ny >= kTwoStepNodes);
 }
 
 // n >= 0 steps of the lattice on stream st (pairs through the two-step

@@ -67,7 +67,7 @@ hipError_t launch_sweep(int storage, int bcx, int bcy, const char *src, char *ds
 // held in registers: waves own strips of 60 columns and march along bands of
 // `band` >= 1 rows.  src and dst must be different levels.  With hist1 and
 // hist2 (both or neither) the two steps' linearisation points are recorded
-// as launch_sweep records one.  FP32 storage only (storage 0).
+// as launch_sweep records one.
 hipError_t launch_sweep2(int storage, int bcx, int bcy, const char *src, char *dst,
                          const Layout &lay, const char *med, const MLayout &mlay, const Geom &g,
                          const Physics &ph, float s, float inv_s, int band, float *hist1,

@@ -1,13 +1,12 @@
 """The two-step pass (two time steps per launch, the old and intermediate
-levels in registers) against single steps, through the C ABI: an FP32
-lattice with pass_mode LBK_PASS_TWO_STEP runs lbk_step(n) as n/2 two-step
-passes (and one single sweep if n is odd), so it must end bitwise where n
-single sweeps (LBK_PASS_SINGLE) leave the same lattice.  Sizes around the
-60-column strips and the 6-row bands, every boundary combination; FP16 and
-BF16 (which always take single sweeps) must agree the same way.  A gradient
-whose recomputing sweeps take two-step passes equals the single-sweep one
-bitwise, and the automatic mode picks the two-step pass on large lattices
-only."""
+levels in registers) against single steps, through the C ABI: a lattice
+with pass_mode LBK_PASS_TWO_STEP runs lbk_step(n) as n/2 two-step passes
+(and one single sweep if n is odd), so it must end bitwise where n single
+sweeps (LBK_PASS_SINGLE) leave the same lattice, for FP32, FP16 and BF16
+storage.  Sizes around the 60-column strips and the 8- and 10-row bands,
+every boundary combination.  A gradient whose recomputing sweeps take
+two-step passes equals the single-sweep one bitwise, and the automatic mode
+picks the two-step pass on large lattices only."""
 import numpy as np
 import pytest
 import torch
@@ -105,16 +104,16 @@ def test_two_step_recording_sweeps_bitwise(dev):
 
 
 def test_auto_mode_matches_both(dev):
-    """LBK_PASS_AUTO steps a 2048 x 2048 FP32 lattice (2^22 nodes) with
-    two-step passes and a 2047 x 2048 one with single sweeps; either way the
+    """LBK_PASS_AUTO steps a 2048 x 2048 lattice (2^22 nodes) with two-step
+    passes and a 2047 x 2048 one with single sweeps; either way the
     state equals the other modes' bitwise."""
-    for nx in (2048, 2047):
+    for nx, storage in ((2048, "f32"), (2047, "f32"), (2048, "f16")):
         case = inputs.random_medium(nx, 2048, seed=94, solid_frac=0.02, pore_frac=0.02,
                                     bc_x=2, rho_in=1.01, rho_out=1.0, init=1)
         states = []
         for mode in ("auto", "single", "two_step"):
             lat = Lattice(case.eps, case.k, case.kn0, device=dev, pass_mode=mode,
-                          **case.params)
+                          storage=storage, **case.params)
             lat.step(4)
             states.append(lat.save_state())
             lat.close()
