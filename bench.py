@@ -72,6 +72,7 @@ def measured_traffic(storage, launch_ms, nodes):
 
 
 REPS = 5  # timed repetitions of every GPU leg; median, min and max reported
+SPINUP_S = 0.25  # untimed steps before the timed repetitions of a sweep leg
 
 
 def spread(ms_list):
@@ -91,6 +92,14 @@ def time_storage(case, storage, steps, warmup, device, single=0):
                   **case.params)
     lat.step(warmup)
     torch.cuda.synchronize(device)
+    # clock spin-up: untimed steps for SPINUP_S seconds, so that the timed
+    # repetitions (a few ms each) see the device at the clocks it holds over
+    # a long run rather than while it ramps up from idle
+    spin, t = 0, time.perf_counter()
+    while time.perf_counter() - t < SPINUP_S:
+        lat.step(steps)
+        torch.cuda.synchronize(device)
+        spin += steps
     stream = lat.stream
     times = []
     for _ in range(REPS):
@@ -126,6 +135,7 @@ def time_storage(case, storage, steps, warmup, device, single=0):
         "ms_per_step_min": sp["min"] / steps,
         "ms_per_step_max": sp["max"] / steps,
         "reps": REPS,
+        "spinup_steps": spin,
         # two steps per pass: the pass moves ALG_BYTES per node
         "pass_alg_GBps": nodes * ALG_BYTES[storage] / (2 * ms_step * 1e-3) / 1e9,
         "per_step_alg_GBps": mlups * ALG_BYTES[storage] / 1e3,
