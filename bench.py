@@ -401,7 +401,8 @@ def time_ensemble(n_samples, steps, storages, graph_steps, device, launch=None, 
         kapps[storage] = b.apparent_permeability()
         mlups = nodes * steps / (ms * 1e-3) / 1e6
         runs[storage] = {
-            "launch": {"tile_x": tile_x, "rows": rows, "grid": grid, "graph_steps": graph_steps},
+            "launch": {"tile_x": tile_x, "rows": rows, "grid": grid, "graph_steps": graph_steps,
+                       "steps_per_launch": b.steps_per_launch},
             "autotune_best_us": tune_us, "ms_per_step": ms / steps,
             "ms_per_step_min": sp["min"] / steps, "ms_per_step_max": sp["max"] / steps,
             "reps": REPS, "check_every": check_every, "mlups": mlups,

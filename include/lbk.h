@@ -263,7 +263,8 @@ lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws_bytes, flo
  *
  * A batch groups n lattices of uneven size (independent heterogeneous
  * samples, each with its own fields, tau, drive and Kn scale) so that one
- * kernel launch advances every sample by one step.  The launch walks a list
+ * kernel launch advances every sample by one step (or two, see
+ * lbk_batch_set_pass_mode).  The launch walks a list
  * of tiles -- tile_x consecutive x by `rows` consecutive y of one sample --
  * that covers all samples; either one workgroup per tile or a persistent
  * grid of `grid` workgroups each taking a contiguous run of tiles.  Steps
@@ -308,6 +309,21 @@ lbk_status lbk_batch_set_launch(lbk_batch *b, int32_t tile_x, int32_t rows, int3
 lbk_status lbk_batch_get_launch(const lbk_batch *b, int32_t *tile_x, int32_t *rows,
                                 int32_t *grid, int32_t *graph_steps);
 
+/* Steps per launch, as pass_mode does for a lattice (lbk_pass_mode):
+ * LBK_PASS_TWO_STEP: two-step passes, the tile list then holding groups of
+ * four 60-column strips by a band of rows of each sample (tile_x, rows and
+ * grid apply to single steps only, such as the last of an odd count);
+ * LBK_PASS_SINGLE: one step per launch; LBK_PASS_AUTO (the default):
+ * two-step passes for batches of 2^22 nodes and more, until
+ * lbk_batch_autotune has timed both and keeps the faster.  Either way each
+ * sample ends bitwise where single steps take it.  Drops recorded graphs
+ * when the choice changes. */
+lbk_status lbk_batch_set_pass_mode(lbk_batch *b, int32_t pass_mode);
+/* The pass mode set, and the steps per launch in use (1 or 2); either
+ * pointer may be NULL. */
+lbk_status lbk_batch_get_pass_mode(const lbk_batch *b, int32_t *pass_mode,
+                                   int32_t *steps_per_launch);
+
 /* on != 0: every graph replay ends with the per-sample read-out reductions
  * (the FP64 sums behind lbk_batch_apparent_permeability), so that after
  * steps that end in a replay the permeabilities need only a copy of the
@@ -317,7 +333,8 @@ lbk_status lbk_batch_set_graph_readout(lbk_batch *b, int32_t on);
 /* Time every candidate -- tile_x in {64, 128, 256} x rows in {1, 4, 8, 16}
  * x one workgroup per tile or persistent grids of 2, 4 and 8 workgroups
  * per compute unit -- over `reps` >= 1 steps each, and keep the fastest
- * (graph_steps unchanged).
+ * (graph_steps unchanged); with pass_mode LBK_PASS_AUTO also the two-step
+ * pass (reps passes), kept when its time per step is lower.
  * The samples' states are left untouched: the timed launches re-read the
  * current time level and overwrite only the other one.  best_us (may be
  * NULL) receives the fastest mean time per step in microseconds.

@@ -112,6 +112,9 @@ _SIG = {
                                             ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_int32)]),
     "lbk_batch_set_graph_readout": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "lbk_batch_set_pass_mode": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "lbk_batch_get_pass_mode": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32),
+                                               ctypes.POINTER(ctypes.c_int32)]),
     "lbk_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "lbk_batch_apparent_permeability": (ctypes.c_int, [_P, _P]),
     "lbk_batch_check": (ctypes.c_int, [_P]),

@@ -70,6 +70,20 @@ class Batch:
         check(_lib.load().lbk_batch_set_launch(self._handle(), int(tile_x), int(rows), int(grid),
                                                int(graph_steps)))
 
+    def set_pass_mode(self, mode: str = "auto") -> None:
+        """Steps per launch: "two_step", "single" or "auto" (two-step passes
+        for batches of 2^22 nodes and more until ``autotune`` keeps the
+        faster); every choice gives the same states bit for bit."""
+        check(_lib.load().lbk_batch_set_pass_mode(self._handle(), _lib.PASS_MODE[mode]))
+
+    @property
+    def steps_per_launch(self) -> int:
+        """1 or 2: whether steps currently go through the two-step pass."""
+        m, k = ctypes.c_int32(), ctypes.c_int32()
+        check(_lib.load().lbk_batch_get_pass_mode(self._handle(), ctypes.byref(m),
+                                                  ctypes.byref(k)))
+        return int(k.value)
+
     def set_graph_readout(self, on: bool = True) -> None:
         """Make every graph replay end with the per-sample read-out sums."""
         check(_lib.load().lbk_batch_set_graph_readout(self._handle(), int(bool(on))))
@@ -91,24 +105,27 @@ class Batch:
         return hashlib.sha1(key.encode()).hexdigest()[:16]
 
     def autotune(self, reps: int = 10, cache: Optional[str] = None) -> float:
-        """Pick the fastest (tile_x, rows, grid) for this batch, leaving the
-        samples' states untouched; returns the mean step time in microseconds
-        (NaN when taken from ``cache``, a JSON file of signature ->
-        [tile_x, rows, grid, us])."""
+        """Pick the fastest (tile_x, rows, grid) for this batch and, in the
+        automatic pass mode, whether two-step passes beat it, leaving the
+        samples' states untouched; returns the mean step time in
+        microseconds (NaN when taken from ``cache``, a JSON file of
+        signature -> [tile_x, rows, grid, steps per launch, us])."""
         sig = self.signature()
         table = {}
         if cache and os.path.exists(cache):
             with open(cache) as f:
                 table = json.load(f)
-            if sig in table:
-                tile_x, rows, grid, _ = table[sig]
+            entry = table.get(sig)
+            if entry is not None and len(entry) == 5:
+                tile_x, rows, grid, per_launch, _ = entry
                 self.set_launch(tile_x, rows, grid, self.launch[3])
+                self.set_pass_mode("two_step" if per_launch == 2 else "single")
                 return float("nan")
         us = ctypes.c_double()
         check(_lib.load().lbk_batch_autotune(self._handle(), int(reps), ctypes.byref(us)))
         if cache:
             tile_x, rows, grid, _ = self.launch
-            table[sig] = [tile_x, rows, grid, float(us.value)]
+            table[sig] = [tile_x, rows, grid, self.steps_per_launch, float(us.value)]
             tmp = cache + ".tmp"
             with open(tmp, "w") as f:
                 json.dump(table, f, indent=1, sort_keys=True)

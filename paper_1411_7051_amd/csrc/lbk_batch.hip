@@ -48,12 +48,31 @@ int64_t total_tiles(lbk_lattice *const *lats, int n, Shape sh)
     return t;
 }
 
+// Two-step pass tiling: groups of four 60-column strips (one workgroup) by
+// bands of band2_of(storage) rows.
+int groups_of(int nx) { return ((nx + kStrip2 - 1) / kStrip2 + kBlock / 64 - 1) / (kBlock / 64); }
+
+int64_t tiles2_of(const lbk_lattice *l)
+{
+    const int band = band2_of(l->d.storage);
+    return (int64_t)groups_of(l->d.nx) * ((l->d.ny + band - 1) / band);
+}
+
+int64_t total_tiles2(lbk_lattice *const *lats, int n)
+{
+    int64_t t = 0;
+    for (int i = 0; i < n; ++i)
+        t += tiles2_of(lats[i]);
+    return t;
+}
+
 // Workspace regions: descriptor table and tile -> sample map of the sweep
-// (sized for the finest allowed tiling) and of the read-out; read-out
-// partials [MAC_SLOTS][read tiles] and per-sample sums [n][MAC_SLOTS].
+// (sized for the finest allowed tiling), of the two-step pass and of the
+// read-out; read-out partials [MAC_SLOTS][read tiles] and per-sample sums
+// [n][MAC_SLOTS].
 struct BatchLayout {
-    size_t desc_sweep, map_sweep, desc_read, map_read;
-    int64_t max_sweep_tiles, read_tiles;
+    size_t desc_sweep, map_sweep, desc_sweep2, map_sweep2, desc_read, map_read;
+    int64_t max_sweep_tiles, sweep2_tiles, read_tiles;
     size_t partials, results, total;
 };
 
@@ -90,9 +109,12 @@ BatchLayout batch_layout(lbk_lattice *const *lats, int n)
         return at;
     };
     B.max_sweep_tiles = total_tiles(lats, n, kFinest);
+    B.sweep2_tiles = total_tiles2(lats, n);
     B.read_tiles = total_tiles(lats, n, kReadShape);
     B.desc_sweep = take((size_t)n * sizeof(SampleDesc));
     B.map_sweep = take((size_t)B.max_sweep_tiles * sizeof(int));
+    B.desc_sweep2 = take((size_t)n * sizeof(SampleDesc));
+    B.map_sweep2 = take((size_t)B.sweep2_tiles * sizeof(int));
     B.desc_read = take((size_t)n * sizeof(SampleDesc));
     B.map_read = take((size_t)B.read_tiles * sizeof(int));
     B.partials = take((size_t)MAC_SLOTS * (size_t)B.read_tiles * sizeof(double));
@@ -182,8 +204,10 @@ struct lbk_batch {
     std::vector<uint64_t> ver0; // each lattice's version when the tables were last set
     Shape shape;        // sweep tiling
     int64_t sweep_tiles;
-    std::vector<int64_t> tile0_sweep, tile0_read;
-    SampleDesc *host_desc; // pinned staging, [2][n]: sweep, read-out
+    std::vector<int64_t> tile0_sweep, tile0_read, tile0_sweep2;
+    int pass_mode;         // lbk_pass_mode asked for
+    int tuned_two;         // -1: not tuned; else the tuner's choice (AUTO)
+    SampleDesc *host_desc; // pinned staging, [3][n]: sweep, read-out, two-step pass
     double *host_res;      // pinned, [n][MAC_SLOTS]
     int grid, graph_steps;
     hipGraphExec_t exec[2]; // graphs starting at parity 0 / 1
@@ -193,12 +217,28 @@ struct lbk_batch {
     BatchAdj adj;           // the last batched gradient's forward pass
 
     SampleDesc *desc_sweep() const { return reinterpret_cast<SampleDesc *>(ws + B.desc_sweep); }
+    SampleDesc *desc_sweep2() const { return reinterpret_cast<SampleDesc *>(ws + B.desc_sweep2); }
+    int *map_sweep2() const { return reinterpret_cast<int *>(ws + B.map_sweep2); }
     SampleDesc *desc_read() const { return reinterpret_cast<SampleDesc *>(ws + B.desc_read); }
     int *map_sweep() const { return reinterpret_cast<int *>(ws + B.map_sweep); }
     int *map_read() const { return reinterpret_cast<int *>(ws + B.map_read); }
     double *partials() const { return reinterpret_cast<double *>(ws + B.partials); }
     double *results() const { return reinterpret_cast<double *>(ws + B.results); }
     const lbk_desc &d0() const { return lats[0]->d; }
+    // whether steps go through the two-step pass (in pairs)
+    bool two() const
+    {
+        if (pass_mode == LBK_PASS_TWO_STEP)
+            return true;
+        if (pass_mode == LBK_PASS_SINGLE)
+            return false;
+        if (tuned_two >= 0)
+            return tuned_two != 0;
+        int64_t nodes = 0;
+        for (const lbk_lattice *l : lats)
+            nodes += (int64_t)l->d.nx * l->d.ny;
+        return nodes >= kTwoStepNodes;
+    }
 };
 
 namespace {
@@ -212,17 +252,17 @@ void drop_graphs(lbk_batch *b)
         }
 }
 
-// Upload the tile -> sample map of tiling `sh` into `map`; tile0[i] gets
-// the first tile of sample i.  Synchronous.
+// Upload the tile -> sample map of tiling `sh` (rows 0: the two-step
+// pass's tiling) into `map`; tile0[i] gets the first tile of sample i.
+// Synchronous.
 lbk_status upload_map(lbk_batch *b, Shape sh, int *map, std::vector<int64_t> &tile0,
                       int64_t &ntiles)
 {
     std::vector<int> h;
-    h.reserve((size_t)total_tiles(b->lats.data(), b->n, sh));
     tile0.assign(b->n, 0);
     for (int i = 0; i < b->n; ++i) {
         tile0[i] = (int64_t)h.size();
-        h.insert(h.end(), (size_t)tiles_of(b->lats[i], sh), i);
+        h.insert(h.end(), (size_t)(sh.rows ? tiles_of(b->lats[i], sh) : tiles2_of(b->lats[i])), i);
     }
     ntiles = (int64_t)h.size();
     HIP_TRY(hipStreamSynchronize(b->stream));
@@ -251,7 +291,7 @@ lbk_status sync_tables(lbk_batch *b, bool force)
         b->cur0[i] = l->cur ^ b->parity;
         b->scale0[i] = l->scale_exp;
         b->ver0[i] = l->version;
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < 3; ++k) {
             const Shape sh = k == 0 ? b->shape : kReadShape;
             SampleDesc &sd = b->host_desc[(size_t)k * b->n + i];
             sd.state[b->parity] = l->state(l->cur);
@@ -263,14 +303,17 @@ lbk_status sync_tables(lbk_batch *b, bool force)
             sd.ph = l->ph;
             sd.s = l->s();
             sd.inv_s = l->inv_s();
-            sd.tile0 = (int)(k == 0 ? b->tile0_sweep[i] : b->tile0_read[i]);
-            sd.tpr = tiles_per_row(l->d.nx, sh.tile_x);
+            sd.tile0 = (int)(k == 0 ? b->tile0_sweep[i]
+                                    : (k == 1 ? b->tile0_read[i] : b->tile0_sweep2[i]));
+            sd.tpr = k == 2 ? groups_of(l->d.nx) : tiles_per_row(l->d.nx, sh.tile_x);
         }
     }
     HIP_TRY(hipMemcpyAsync(b->desc_sweep(), b->host_desc, (size_t)b->n * sizeof(SampleDesc),
                            hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipMemcpyAsync(b->desc_read(), b->host_desc + b->n, (size_t)b->n * sizeof(SampleDesc),
                            hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->desc_sweep2(), b->host_desc + 2 * (size_t)b->n,
+                           (size_t)b->n * sizeof(SampleDesc), hipMemcpyHostToDevice, b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     return LBK_OK;
 }
@@ -296,6 +339,14 @@ hipError_t sweep_once(lbk_batch *b, int parity, int grid, hipStream_t st)
                               st);
 }
 
+// Two steps of every sample, parity -> parity ^ 1.
+hipError_t sweep2_once(lbk_batch *b, int parity, hipStream_t st)
+{
+    const lbk_desc &d = b->d0();
+    return launch_batch_sweep2(d.storage, d.bc_x, d.bc_y, b->desc_sweep2(), b->map_sweep2(),
+                               (int)b->B.sweep2_tiles, parity, band2_of(d.storage), st);
+}
+
 // Per-sample read-out sums of the state at `parity` into results().
 hipError_t readout(lbk_batch *b, int parity, hipStream_t st)
 {
@@ -309,16 +360,27 @@ hipError_t readout(lbk_batch *b, int parity, hipStream_t st)
     return e;
 }
 
-// Record graph_steps launches starting at `parity` on the private stream
+// Parity after a graph replay of graph_steps steps from `parity`: single
+// steps flip it each step (an even count), two-step passes once a pass.
+int parity_after_graph(const lbk_batch *b, int parity)
+{
+    return b->two() ? parity ^ ((b->graph_steps / 2) & 1) : parity;
+}
+
+// Record graph_steps steps starting at `parity` on the private stream
 // (and, with graph_readout, the read-out of the state they end in).
 lbk_status record_graph(lbk_batch *b, int parity)
 {
     HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
-    for (int i = 0; i < b->graph_steps && e == hipSuccess; ++i)
-        e = sweep_once(b, parity ^ (i & 1), b->grid, b->cap);
+    if (b->two())
+        for (int i = 0; i < b->graph_steps / 2 && e == hipSuccess; ++i)
+            e = sweep2_once(b, parity ^ (i & 1), b->cap);
+    else
+        for (int i = 0; i < b->graph_steps && e == hipSuccess; ++i)
+            e = sweep_once(b, parity ^ (i & 1), b->grid, b->cap);
     if (e == hipSuccess && b->graph_readout)
-        e = readout(b, parity, b->cap); // graph_steps is even
+        e = readout(b, parity_after_graph(b, parity), b->cap);
     hipGraph_t graph = nullptr;
     const hipError_t e2 = hipStreamEndCapture(b->cap, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -405,14 +467,19 @@ lbk_status lbk_batch_create(lbk_lattice *const *lats, int32_t n, void *workspace
     b->sums_fresh = false;
     int64_t read_tiles = 0;
     if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
-        hipHostMalloc((void **)&b->host_desc, (size_t)2 * n * sizeof(SampleDesc),
+        hipHostMalloc((void **)&b->host_desc, (size_t)3 * n * sizeof(SampleDesc),
                       hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void **)&b->host_res, (size_t)n * MAC_SLOTS * sizeof(double),
                       hipHostMallocDefault) != hipSuccess) {
         destroy_batch(b);
         return fail(LBK_ERR_DEVICE, "stream or pinned host allocation failed");
     }
+    b->pass_mode = LBK_PASS_AUTO;
+    b->tuned_two = -1;
+    int64_t sweep2_tiles = 0;
     if ((s = upload_map(b, kReadShape, b->map_read(), b->tile0_read, read_tiles)) != LBK_OK ||
+        (s = upload_map(b, Shape{kStrip2, 0}, b->map_sweep2(), b->tile0_sweep2,
+                        sweep2_tiles)) != LBK_OK ||
         (s = set_shape(b, Shape{kBlock, 1})) != LBK_OK) {
         destroy_batch(b);
         return s;
@@ -438,14 +505,21 @@ lbk_status lbk_batch_step(lbk_batch *b, int64_t n)
     if (s != LBK_OK)
         return s;
     int64_t left = n;
+    const bool two = b->two();
     while (left > 0) {
         if (b->graph_steps > 0 && left >= b->graph_steps) {
             if (!b->have_exec[b->parity] && (s = record_graph(b, b->parity)) != LBK_OK)
                 return s;
             Range range("batch graph replay");
             HIP_TRY(hipGraphLaunch(b->exec[b->parity], b->stream));
-            left -= b->graph_steps; // even: the parity is unchanged
+            left -= b->graph_steps;
+            b->parity = parity_after_graph(b, b->parity);
             b->sums_fresh = b->graph_readout;
+        } else if (two && left >= 2) {
+            HIP_TRY(sweep2_once(b, b->parity, b->stream));
+            b->parity ^= 1;
+            left -= 2;
+            b->sums_fresh = false;
         } else {
             HIP_TRY(sweep_once(b, b->parity, b->grid, b->stream));
             b->parity ^= 1;
@@ -513,6 +587,32 @@ lbk_status lbk_batch_set_graph_readout(lbk_batch *b, int32_t on)
     return LBK_OK;
 }
 
+lbk_status lbk_batch_set_pass_mode(lbk_batch *b, int32_t pass_mode)
+{
+    if (!b)
+        return fail(LBK_ERR_INVALID_ARG, "batch is NULL");
+    if (pass_mode < LBK_PASS_AUTO || pass_mode > LBK_PASS_SINGLE)
+        return fail(LBK_ERR_INVALID_ARG, "pass_mode must be 0..2 (got %d)", pass_mode);
+    const bool before = b->two();
+    b->pass_mode = pass_mode;
+    b->tuned_two = -1;
+    if (b->two() != before)
+        drop_graphs(b);
+    return LBK_OK;
+}
+
+lbk_status lbk_batch_get_pass_mode(const lbk_batch *b, int32_t *pass_mode,
+                                   int32_t *steps_per_launch)
+{
+    if (!b)
+        return fail(LBK_ERR_INVALID_ARG, "batch is NULL");
+    if (pass_mode)
+        *pass_mode = b->pass_mode;
+    if (steps_per_launch)
+        *steps_per_launch = b->two() ? 2 : 1;
+    return LBK_OK;
+}
+
 lbk_status lbk_batch_autotune(lbk_batch *b, int32_t reps, double *best_us)
 {
     if (!b)
@@ -560,6 +660,28 @@ lbk_status lbk_batch_autotune(lbk_batch *b, int32_t reps, double *best_us)
             }
         }
     }
+    // the two-step pass against the best single step, per step (automatic
+    // pass mode only)
+    int two = -1;
+    if (s == LBK_OK && e == hipSuccess && b->pass_mode == LBK_PASS_AUTO) {
+        e = sweep2_once(b, b->parity, b->stream);
+        if (e == hipSuccess)
+            e = hipEventRecord(ev[0], b->stream);
+        for (int k = 0; k < reps && e == hipSuccess; ++k)
+            e = sweep2_once(b, b->parity, b->stream);
+        if (e == hipSuccess)
+            e = hipEventRecord(ev[1], b->stream);
+        if (e == hipSuccess)
+            e = hipEventSynchronize(ev[1]);
+        float ms = 0.0f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        if (e == hipSuccess) {
+            two = ms / (2.0 * reps) < best ? 1 : 0;
+            if (two)
+                best = ms / (2.0 * reps);
+        }
+    }
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
     if (s != LBK_OK)
@@ -569,6 +691,10 @@ lbk_status lbk_batch_autotune(lbk_batch *b, int32_t reps, double *best_us)
     if ((s = lbk_batch_set_launch(b, best_shape.tile_x, best_shape.rows, best_grid,
                                   b->graph_steps)) != LBK_OK)
         return s;
+    if (two >= 0 && two != b->tuned_two) {
+        drop_graphs(b);
+        b->tuned_two = two;
+    }
     if (best_us)
         *best_us = best * 1e3;
     return LBK_OK;

@@ -18,6 +18,10 @@ struct Launch {
 
 Launch launch_of(const Geom &g);
 
+// Columns a wave of the two-step pass stores (its strip; the wave's other
+// four lanes hold halo columns).
+constexpr int kStrip2 = 60;
+
 // Largest batch tile width (workgroup size) of the batched sweep.
 constexpr int kBatchMaxTile = 256;
 
@@ -162,6 +166,15 @@ hipError_t launch_batch_rec_sweep(int storage, int bcx, int bcy, const AdjSample
 hipError_t launch_batch_sweep(int storage, int bcx, int bcy, const SampleDesc *samples,
                               const int *tile_sample, int ntiles, int parity, int tile_x,
                               int rows, int grid, hipStream_t st);
+
+// Two-step pass of every sample of a batch, parity -> parity ^ 1: tiles of
+// four 60-column strips by `band` rows, one workgroup (kBlock) per tile, in
+// the band-major order of the single-lattice pass; the descriptors'
+// tile0/tpr must describe that tiling (tpr = groups of four strips per
+// band).
+hipError_t launch_batch_sweep2(int storage, int bcx, int bcy, const SampleDesc *samples,
+                               const int *tile_sample, int ntiles, int parity, int band,
+                               hipStream_t st);
 
 // Read-out partials of every sample over tiles of kBlock nodes
 // ([MAC_SLOTS][ntiles]) and their per-sample fixed-order sums

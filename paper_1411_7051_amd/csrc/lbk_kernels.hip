@@ -208,9 +208,6 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(const char *src, char *ds
 // single sweeps.  The four halo columns of each strip and the halo rows at
 // each band's ends are computed by the neighbouring strips and bands too.
 
-// Columns a wave stores.
-constexpr int kStrip2 = 60;
-
 // One node of a level as a pull reads it: density and deviations (storage
 // unit, as stored), with the node's medium.
 struct Mid {
@@ -347,19 +344,16 @@ __device__ __forceinline__ void first_step(const Physics &ph, float s, float inv
     m.kn0 = c.kn0;
 }
 
+// The two-step pass of one wave: strip `strip` (60 columns) of band `bnd`
+// (rows bnd * band ..) of one lattice.
 template <typename T, int BCX, int BCY, bool HIST>
-__global__ __launch_bounds__(kBlock) void sweep2_kernel(const char *__restrict__ src,
-                                                         char *__restrict__ dst, Layout lay,
-                                                         const char *__restrict__ med,
-                                                         MLayout mlay, Geom g, Physics ph,
-                                                         float s, float inv_s, int band,
-                                                         int groups, float *__restrict__ hist1,
-                                                         float *__restrict__ hist2)
+__device__ __forceinline__ void sweep2_strip(const char *__restrict__ src,
+                                             char *__restrict__ dst, const Layout &lay,
+                                             const char *__restrict__ med, const MLayout &mlay,
+                                             const Geom &g, const Physics &ph, float s,
+                                             float inv_s, int band, int bnd, int strip,
+                                             float *__restrict__ hist1, float *__restrict__ hist2)
 {
-    // logical block: band-major, four strips (one per wave) per block
-    const int L = xcd_remap(blockIdx.x, gridDim.x);
-    const int bnd = L / groups;
-    const int strip = (L - bnd * groups) * (kBlock / 64) + (int)(threadIdx.x >> 6);
     const int lane = (int)(threadIdx.x & 63);
     const int nstrips = (g.nx + kStrip2 - 1) / kStrip2;
     if (strip >= nstrips)
@@ -471,6 +465,23 @@ __global__ __launch_bounds__(kBlock) void sweep2_kernel(const char *__restrict__
     }
 }
 
+template <typename T, int BCX, int BCY, bool HIST>
+__global__ __launch_bounds__(kBlock) void sweep2_kernel(const char *__restrict__ src,
+                                                         char *__restrict__ dst, Layout lay,
+                                                         const char *__restrict__ med,
+                                                         MLayout mlay, Geom g, Physics ph,
+                                                         float s, float inv_s, int band,
+                                                         int groups, float *__restrict__ hist1,
+                                                         float *__restrict__ hist2)
+{
+    // logical block: band-major, four strips (one per wave) per block
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int bnd = L / groups;
+    const int strip = (L - bnd * groups) * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    sweep2_strip<T, BCX, BCY, HIST>(src, dst, lay, med, mlay, g, ph, s, inv_s, band, bnd, strip,
+                                    hist1, hist2);
+}
+
 // -------------------------------------------------------------- batches
 //
 // A batch steps many independent lattices (samples of uneven size, each
@@ -519,6 +530,26 @@ __global__ __launch_bounds__(kBatchMaxTile) void batch_sweep_kernel(
         batch_tile<T, BCX, BCY>(samples, tile_sample, rows, parity,
                                 xcd_remap(blockIdx.x, gridDim.x));
     }
+}
+
+// Two-step pass of every sample of a batch, parity -> parity ^ 1 (two time
+// steps): the tile list holds one entry per (sample, band, group of four
+// strips); a sample's descriptor gives its first tile and its groups per
+// band (tpr).  Each sample's result is bitwise its own two-step pass.
+template <typename T, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) void batch_sweep2_kernel(
+    const SampleDesc *__restrict__ samples, const int *__restrict__ tile_sample, int band,
+    int parity)
+{
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const SampleDesc sd = samples[tile_sample[t]];
+    const int rel = t - sd.tile0;
+    const int bnd = rel / sd.tpr;
+    const int strip = (rel - bnd * sd.tpr) * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    const char *src = parity ? sd.state[1] : sd.state[0];
+    char *dst = parity ? sd.state[0] : sd.state[1];
+    sweep2_strip<T, BCX, BCY, false>(src, dst, sd.lay, sd.med, sd.mlay, sd.g, sd.ph, sd.s,
+                                     sd.inv_s, band, bnd, strip, nullptr, nullptr);
 }
 
 // Recomputing sweep of a batched gradient: the same node update between two
@@ -1106,6 +1137,26 @@ hipError_t launch_batch_sweep(int storage, int bcx, int bcy, const SampleDesc *s
     if (ntiles == 0)
         return hipSuccess;
     LBK_DISPATCH(batch_sweep_t, samples, tile_sample, ntiles, parity, tile_x, rows, grid, st)
+}
+
+template <typename T, int BCX, int BCY>
+static hipError_t batch_sweep2_t(const SampleDesc *samples, const int *tile_sample, int ntiles,
+                                 int parity, int band, hipStream_t st)
+{
+    hipLaunchKernelGGL((batch_sweep2_kernel<T, BCX, BCY>), dim3(ntiles), dim3(kBlock), 0, st,
+                       samples, tile_sample, band, parity);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sweep2(int storage, int bcx, int bcy, const SampleDesc *samples,
+                               const int *tile_sample, int ntiles, int parity, int band,
+                               hipStream_t st)
+{
+    if (bcy < 0 || bcy > 1 || band < 1 || ntiles < 0)
+        return hipErrorInvalidValue;
+    if (ntiles == 0)
+        return hipSuccess;
+    LBK_DISPATCH(batch_sweep2_t, samples, tile_sample, ntiles, parity, band, st)
 }
 
 hipError_t launch_batch_macro(int storage, int bcx, int bcy, const SampleDesc *samples,

@@ -204,6 +204,65 @@ def test_autotune_leaves_state_untouched(dev, tmp_path):
     assert b2.launch[:3] == (tile, rows, grid)
 
 
+SIZES2 = SIZES + [(61, 11), (123, 17), (183, 21), (241, 40)]
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("bcx,bcy", [(0, 0), (0, 1), (1, 1), (2, 0), (2, 1)])
+def test_batch_two_step_bitwise_equals_solo(dev, storage, bcx, bcy):
+    """Two-step passes over the batch (pass mode "two_step"): every sample
+    ends bitwise where single steps take it alone, with direct passes, an
+    odd step count, and graph replays of an odd and an even number of
+    passes (6 and 8 steps) with the read-out recorded."""
+    cs = cases(bcx, bcy, seed=520, sizes=SIZES2)
+    if bcx == inputs.PRESSURE:
+        cs = [c for c in cs if c.eps.shape[1] >= 3]
+    lats = ensemble_lattices(cs, device=dev, storage=storage)
+    solo = ensemble_lattices(cs, device=dev, storage=storage, pass_mode="single")
+    b = Batch(lats)
+    b.set_pass_mode("two_step")
+    assert b.steps_per_launch == 2
+    total = 0
+    for n, graph in ((23, 0), (12, 6), (6, 6), (16, 8), (5, 8)):
+        b.set_launch(128, 1, 0, graph)
+        b.set_graph_readout(graph > 0)
+        b.step(n)
+        total += n
+        for l in solo:
+            l.step(n)
+        assert_same(lats, solo)
+        kb = b.apparent_permeability()
+        ks = np.array([l.apparent_permeability() for l in solo])
+        assert np.array_equal(kb, ks), (n, graph)
+    assert lats[0].time == total
+
+
+def test_batch_pass_mode_auto_and_tuner(dev, tmp_path):
+    """The automatic pass mode takes single steps below 2^22 nodes; the tuner
+    times the two-step pass too, keeps the states untouched and records its
+    choice in the cache, which a second batch of the same shape then uses."""
+    cs = cases(2, 1, seed=540, sizes=SIZES2)
+    lats = ensemble_lattices(cs, device=dev, storage="f16")
+    b = Batch(lats)
+    assert b.steps_per_launch == 1
+    b.step(5)
+    before = [l.save_state().clone() for l in lats]
+    us = b.autotune(reps=3, cache=str(tmp_path / "tune2.json"))
+    assert us > 0 and b.steps_per_launch in (1, 2)
+    for l, s in zip(lats, before):
+        assert torch.equal(l.save_state(), s)
+    b2 = Batch(ensemble_lattices(cs, device=dev, storage="f16"))
+    assert np.isnan(b2.autotune(cache=str(tmp_path / "tune2.json")))
+    assert b2.steps_per_launch == b.steps_per_launch
+    solo = ensemble_lattices(cs, device=dev, storage="f16")
+    b.step(9)
+    for l in solo:
+        l.step(14)
+    assert_same(lats, solo)
+    b.set_pass_mode("single")
+    assert b.steps_per_launch == 1
+
+
 def test_batch_against_oracle(dev):
     cs = cases(2, 1, seed=850, sizes=[(300, 17), (70, 40), (513, 6)])
     lats = ensemble_lattices(cs, device=dev)
