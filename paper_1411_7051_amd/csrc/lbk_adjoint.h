@@ -41,6 +41,15 @@ hipError_t launch_batch_adjoint(int bcx, int bcy, const AdjSampleDesc *samples,
                                 const int *tile_sample, int ntiles, int tile_x, int rows,
                                 int lam_in, int hist_slot, int kn, int fc, hipStream_t st);
 
+// Two reverse steps of every sample of a batched gradient, lam[lam_in] ->
+// lam[lam_in ^ 1] (lam_in 0 or 1), histories in slots hist_slot and
+// hist_slot - 1 (hist_slot >= 1), over the batch's two-step tiling (tiles of
+// four 60-column strips by `band` rows; the descriptors' tile0 / tpr must
+// describe it); bitwise two launch_batch_adjoint calls.
+hipError_t launch_batch_adjoint2(int bcx, int bcy, const AdjSampleDesc *samples,
+                                 const int *tile_sample, int ntiles, int band, int lam_in,
+                                 int hist_slot, int kn, int fc, hipStream_t st);
+
 // Gradient planes of every sample: op 0 clears segments and totals, op 1
 // folds segments into totals (and clears them), op 2 writes the totals to
 // the output planes.

@@ -491,8 +491,6 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const float *mu_in, float 
 // gradient entry collects both steps' terms before it is written once.
 namespace {
 
-constexpr int kStripA = 60;
-
 // Lane-dependent facts of a strip of the reverse pass.
 struct ALanes {
     uint32_t x;         // the lane's column, wrapped (periodic) or clamped
@@ -610,30 +608,26 @@ __device__ __forceinline__ void gather(const float (&dn)[9], const float (&c)[9]
 // Two reverse steps: mu_in = mu_n -> mu_out = mu_{n-2}, hist1 / hist0 the
 // histories of steps n and n - 1, grad / grad2 as in adjoint_node.  Rows
 // are marched in bands of `band`; a block holds four strips.
-#ifndef LBK_ADJ2_WAVES
-#define LBK_ADJ2_WAVES 1
-#endif
+// The pass of one wave: strip `strip` of band `bnd` of one lattice.
 template <int BCX, int BCY, bool KN, bool FC>
-__global__ __launch_bounds__(256, LBK_ADJ2_WAVES) void adjoint2_kernel(
+__device__ __forceinline__ void adjoint2_strip(
     const float *__restrict__ mu_in, float *__restrict__ mu_out, const float *__restrict__ hist1,
-    const float *__restrict__ hist0, const char *__restrict__ med, MLayout mlay,
-    float *__restrict__ grad, float *__restrict__ grad2, Geom g, Physics ph, int band, int groups)
+    const float *__restrict__ hist0, const char *__restrict__ med, const MLayout &mlay,
+    float *__restrict__ grad, float *__restrict__ grad2, const Geom &g, const Physics &ph,
+    int band, int bnd, int strip)
 {
-    const int L = xcd_remap_a(blockIdx.x, gridDim.x);
-    const int bnd = L / groups;
-    const int strip = (L - bnd * groups) * 4 + (int)(threadIdx.x >> 6);
     const int lane = (int)(threadIdx.x & 63);
     const int nx = g.nx, ny = g.ny;
-    const int nstrips = (nx + kStripA - 1) / kStripA;
+    const int nstrips = (nx + kStrip2 - 1) / kStrip2;
     if (strip >= nstrips)
         return; // the whole wave
     // Strip s owns columns [c0, c1).  With pressure columns the last strip
     // starts at most at nx - 4: the column next to the outlet then never
     // sits at lane 63 of a strip that owns the column two to its left, whose
     // result would need the outlet column's values from beyond the wave.
-    int c0 = strip * kStripA, c1 = min(c0 + kStripA, nx);
+    int c0 = strip * kStrip2, c1 = min(c0 + kStrip2, nx);
     if (BCX == BC_PRESSURE) {
-        const int cl = max(0, min(kStripA * (nstrips - 1), nx - 4));
+        const int cl = max(0, min(kStrip2 * (nstrips - 1), nx - 4));
         if (strip == nstrips - 1)
             c0 = cl;
         else if (strip == nstrips - 2)
@@ -794,6 +788,20 @@ __global__ __launch_bounds__(256, LBK_ADJ2_WAVES) void adjoint2_kernel(
     }
 }
 
+template <int BCX, int BCY, bool KN, bool FC>
+__global__ __launch_bounds__(256) void adjoint2_kernel(
+    const float *__restrict__ mu_in, float *__restrict__ mu_out, const float *__restrict__ hist1,
+    const float *__restrict__ hist0, const char *__restrict__ med, MLayout mlay,
+    float *__restrict__ grad, float *__restrict__ grad2, Geom g, Physics ph, int band, int groups)
+{
+    // logical block: band-major, four strips (one per wave) per block
+    const int L = xcd_remap_a(blockIdx.x, gridDim.x);
+    const int bnd = L / groups;
+    const int strip = (L - bnd * groups) * 4 + (int)(threadIdx.x >> 6);
+    adjoint2_strip<BCX, BCY, KN, FC>(mu_in, mu_out, hist1, hist0, med, mlay, grad, grad2, g, ph,
+                                     band, bnd, strip);
+}
+
 // total += seg; seg = 0 (end of a recomputed segment)
 __global__ __launch_bounds__(256) void grad_fold_kernel(float *seg, double *total, Geom g,
                                                          int bpr)
@@ -867,7 +875,7 @@ static hipError_t adj2_t(const float *mu_in, float *mu_out, const float *hist1,
                          const float *hist0, const char *med, const MLayout &mlay, float *grad,
                          float *grad2, const Geom &g, const Physics &ph, int band, hipStream_t st)
 {
-    const int nstrips = (g.nx + kStripA - 1) / kStripA;
+    const int nstrips = (g.nx + kStrip2 - 1) / kStrip2;
     const int groups = (nstrips + 3) / 4;
     const int blocks = groups * ((g.ny + band - 1) / band);
 #define LBK_ADJ2K(KN, FC)                                                                    \
@@ -963,6 +971,30 @@ __global__ __launch_bounds__(256) void batch_adjoint_kernel(
                                    sd.ph, terminal ? 1 : 0, sd.a1, sd.a2, sd.outlet, y, x);
 }
 
+// Two reverse steps of every sample, lam[lam_in] -> lam[lam_in ^ 1], the
+// histories in slots hist_slot (the later step) and hist_slot - 1: tiles of
+// four strips by `band` rows (the batch's two-step tiling: tile0 / tpr give
+// a sample's first tile and its groups of four strips per band).
+template <int BCX, int BCY, bool KN, bool FC>
+__global__ __launch_bounds__(256) void batch_adjoint2_kernel(
+    const AdjSampleDesc *__restrict__ samples, const int *__restrict__ tile_sample, int band,
+    int lam_in, int hist_slot)
+{
+    const int t = xcd_remap_a(blockIdx.x, gridDim.x);
+    const AdjSampleDesc sd = samples[tile_sample[t]];
+    const int rel = t - sd.tile0;
+    const int bnd = rel / sd.tpr;
+    const int strip = (rel - bnd * sd.tpr) * 4 + (int)(threadIdx.x >> 6);
+    const float *mu_in = lam_in ? sd.lam[1] : sd.lam[0];
+    float *mu_out = lam_in ? sd.lam[0] : sd.lam[1];
+    const char *h = reinterpret_cast<const char *>(sd.hist);
+    const float *hist1 = reinterpret_cast<const float *>(h + (uint64_t)hist_slot * sd.hist_bytes);
+    const float *hist0 =
+        reinterpret_cast<const float *>(h + (uint64_t)(hist_slot - 1) * sd.hist_bytes);
+    adjoint2_strip<BCX, BCY, KN, FC>(mu_in, mu_out, hist1, hist0, sd.med, sd.mlay, sd.seg,
+                                     KN ? sd.seg2 : nullptr, sd.g, sd.ph, band, bnd, strip);
+}
+
 // op 0: clear the segment and total planes; 1: fold segment into total;
 // 2: write the totals to the output planes.  kn: the ln kn0 plane too.
 __global__ __launch_bounds__(256) void batch_grad_kernel(const AdjSampleDesc *__restrict__ samples,
@@ -1032,6 +1064,47 @@ hipError_t launch_batch_adjoint(int bcx, int bcy, const AdjSampleDesc *samples,
     default: return hipErrorInvalidValue;
     }
 #undef LBK_BADJ
+}
+
+template <int BCX, int BCY>
+static hipError_t batch_adj2_t(const AdjSampleDesc *samples, const int *tile_sample, int ntiles,
+                               int band, int lam_in, int hist_slot, int kn, int fc,
+                               hipStream_t st)
+{
+#define LBK_BADJ2K(KN, FC)                                                                   \
+    hipLaunchKernelGGL((batch_adjoint2_kernel<BCX, BCY, KN, FC>), dim3(ntiles), dim3(256), 0,  \
+                       st, samples, tile_sample, band, lam_in, hist_slot)
+    if (kn && fc)
+        LBK_BADJ2K(true, true);
+    else if (kn)
+        LBK_BADJ2K(true, false);
+    else if (fc)
+        LBK_BADJ2K(false, true);
+    else
+        LBK_BADJ2K(false, false);
+#undef LBK_BADJ2K
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_adjoint2(int bcx, int bcy, const AdjSampleDesc *samples,
+                                 const int *tile_sample, int ntiles, int band, int lam_in,
+                                 int hist_slot, int kn, int fc, hipStream_t st)
+{
+    if (ntiles < 0 || band < 1 || lam_in < 0 || lam_in > 1 || hist_slot < 1)
+        return hipErrorInvalidValue;
+    if (ntiles == 0)
+        return hipSuccess;
+#define LBK_BADJ2(X, Y) batch_adj2_t<X, Y>(samples, tile_sample, ntiles, band, lam_in, hist_slot, kn, fc, st)
+    switch (bcx * 2 + bcy) {
+    case 0: return LBK_BADJ2(BC_PERIODIC, BC_PERIODIC);
+    case 1: return LBK_BADJ2(BC_PERIODIC, BC_WALL);
+    case 2: return LBK_BADJ2(BC_WALL, BC_PERIODIC);
+    case 3: return LBK_BADJ2(BC_WALL, BC_WALL);
+    case 4: return LBK_BADJ2(BC_PRESSURE, BC_PERIODIC);
+    case 5: return LBK_BADJ2(BC_PRESSURE, BC_WALL);
+    default: return hipErrorInvalidValue;
+    }
+#undef LBK_BADJ2
 }
 
 hipError_t launch_batch_grad(const AdjSampleDesc *samples, const int *tile_sample, int ntiles,

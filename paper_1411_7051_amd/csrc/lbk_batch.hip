@@ -146,7 +146,8 @@ struct BatchAdj {
 size_t batch_adj_place(BatchAdj &A, int64_t keep)
 {
     const int n = (int)A.plans.size();
-    size_t o = align_up((size_t)n * sizeof(AdjSampleDesc), 256);
+    // descriptor tables: the sweep's tiling, then the two-step tiling
+    size_t o = align_up((size_t)2 * n * sizeof(AdjSampleDesc), 256);
     for (int i = 0; i < n; ++i) {
         AdjPlan &P = A.plans[i];
         P.total = P.inner + (size_t)(keep > 1 ? keep : 1) * P.inner_seg;
@@ -906,8 +907,9 @@ lbk_status lbk_batch_adjoint_backward(lbk_batch *b, void *ws, size_t ws_bytes,
     }
     char *w = static_cast<char *>(ws);
     hipStream_t st = b->stream;
-    // descriptor table of this pass (the sweep's tiling, one workgroup per tile)
-    std::vector<AdjSampleDesc> h(b->n);
+    // descriptor tables of this pass: the sweep's tiling (one workgroup per
+    // tile), then the same descriptors over the two-step tiling
+    std::vector<AdjSampleDesc> h(2 * (size_t)b->n);
     for (int i = 0; i < b->n; ++i) {
         lbk_lattice *l = b->lats[i];
         const AdjPlan &P = A.plans[i];
@@ -940,6 +942,10 @@ lbk_status lbk_batch_adjoint_backward(lbk_batch *b, void *ws, size_t ws_bytes,
         sd.outlet = A.outlet[i];
         sd.tile0 = (int)b->tile0_sweep[i];
         sd.tpr = tiles_per_row(l->d.nx, b->shape.tile_x);
+        AdjSampleDesc &s2 = h[(size_t)b->n + i];
+        s2 = sd;
+        s2.tile0 = (int)b->tile0_sweep2[i];
+        s2.tpr = groups_of(l->d.nx);
     }
     AdjSampleDesc *table = reinterpret_cast<AdjSampleDesc *>(w + A.table);
     HIP_TRY(hipMemcpyAsync(table, h.data(), h.size() * sizeof(AdjSampleDesc),
@@ -951,12 +957,25 @@ lbk_status lbk_batch_adjoint_backward(lbk_batch *b, void *ws, size_t ws_bytes,
         return launch_batch_rec_sweep(d.storage, d.bc_x, d.bc_y, table, map, nt, tx, rows, src,
                                       dst, slot, st);
     };
+    // pairs of steps through the two-step passes (bitwise the same) when
+    // the batch steps that way
+    const bool two = b->two();
+    const AdjSampleDesc *table2 = table + b->n;
+    const int nt2 = (int)b->B.sweep2_tiles, band = band2_of(d.storage);
+    auto rec2 = [&](LevelSel src, LevelSel dst, int slot) {
+        return launch_batch_rec_sweep2(d.storage, d.bc_x, d.bc_y, table2, b->map_sweep2(), nt2,
+                                       band, src, dst, slot, st);
+    };
     int fc = 0;
     for (int i = 0; i < b->n; ++i)
         fc |= b->lats[i]->d.f_eps != 0.0;
     auto reverse = [&](int lam_in, int slot) {
         return launch_batch_adjoint(d.bc_x, d.bc_y, table, map, nt, tx, rows, lam_in, slot, knf,
                                     fc, st);
+    };
+    auto reverse2 = [&](int lam_in, int slot) {
+        return launch_batch_adjoint2(d.bc_x, d.bc_y, table2, b->map_sweep2(), nt2, band, lam_in,
+                                     slot, knf, fc, st);
     };
     HIP_TRY(launch_batch_grad(table, map, nt, tx, rows, 0, knf, st));
     // read-out of J at step n: linearisation point of the pull of S_n
@@ -985,9 +1004,16 @@ lbk_status lbk_batch_adjoint_backward(lbk_batch *b, void *ws, size_t ws_bytes,
                 const int64_t steps = std::min(A.c2, e - t);
                 if (t + steps >= e)
                     break;
-                for (int64_t i = 0; i < steps; ++i) {
-                    HIP_TRY(rec(i == 0 ? LevelSel{ADJ_INNER, (int)nseg} : LevelSel{ADJ_REC, r},
-                                LevelSel{ADJ_REC, r ^ 1}, -1));
+                for (int64_t i = 0; i < steps;) {
+                    const LevelSel from =
+                        i == 0 ? LevelSel{ADJ_INNER, (int)nseg} : LevelSel{ADJ_REC, r};
+                    if (two && i + 1 < steps) {
+                        HIP_TRY(rec2(from, LevelSel{ADJ_REC, r ^ 1}, -1));
+                        i += 2;
+                    } else {
+                        HIP_TRY(rec(from, LevelSel{ADJ_REC, r ^ 1}, -1));
+                        ++i;
+                    }
                     r ^= 1;
                 }
                 src = LevelSel{ADJ_REC, r};
@@ -1002,15 +1028,27 @@ lbk_status lbk_batch_adjoint_backward(lbk_batch *b, void *ws, size_t ws_bytes,
             int r = 0;
             {
                 Range range("batch adjoint recompute");
-                for (int64_t t = a2s; t < b2s; ++t) {
-                    HIP_TRY(rec(t == a2s ? src : LevelSel{ADJ_REC, r}, LevelSel{ADJ_REC, r ^ 1},
-                                (int)(t - a2s + 1)));
+                for (int64_t t = a2s; t < b2s;) {
+                    const LevelSel from = t == a2s ? src : LevelSel{ADJ_REC, r};
+                    if (two && t + 1 < b2s) {
+                        HIP_TRY(rec2(from, LevelSel{ADJ_REC, r ^ 1}, (int)(t - a2s + 1)));
+                        t += 2;
+                    } else {
+                        HIP_TRY(rec(from, LevelSel{ADJ_REC, r ^ 1}, (int)(t - a2s + 1)));
+                        ++t;
+                    }
                     r ^= 1;
                 }
             }
             Range range("batch adjoint reverse");
-            for (int64_t t = b2s; t > a2s; --t) {
-                HIP_TRY(reverse(cur, (int)(t - a2s)));
+            for (int64_t t = b2s; t > a2s;) {
+                if (two && t - 1 > a2s) {
+                    HIP_TRY(reverse2(cur, (int)(t - a2s)));
+                    t -= 2;
+                } else {
+                    HIP_TRY(reverse(cur, (int)(t - a2s)));
+                    --t;
+                }
                 cur ^= 1;
             }
             HIP_TRY(launch_batch_grad(table, map, nt, tx, rows, 1, knf, st));

@@ -158,6 +158,14 @@ hipError_t launch_batch_rec_sweep(int storage, int bcx, int bcy, const AdjSample
                                   const int *tile_sample, int ntiles, int tile_x, int rows,
                                   LevelSel src, LevelSel dst, int hist_slot, hipStream_t st);
 
+// Two recomputing steps of every sample of a batched gradient in one pass
+// (bitwise two launch_batch_rec_sweep calls): level src -> dst, recording
+// into history slots hist_slot and hist_slot + 1 (hist_slot < 0: none),
+// over the batch's two-step tiling (see launch_batch_sweep2).
+hipError_t launch_batch_rec_sweep2(int storage, int bcx, int bcy, const AdjSampleDesc *samples,
+                                   const int *tile_sample, int ntiles, int band, LevelSel src,
+                                   LevelSel dst, int hist_slot, hipStream_t st);
+
 // One step of every sample of a batch, parity -> parity ^ 1, over tiles of
 // tile_x (a multiple of 64 up to kBatchMaxTile: the workgroup size) by rows
 // nodes; the descriptors' tile0/tpr must describe that tiling.  grid > 0:

@@ -583,6 +583,36 @@ __global__ __launch_bounds__(kBatchMaxTile) void batch_rec_sweep_kernel(
                                       sd.inv_s, hist, y, x);
 }
 
+// Two recomputing steps of every sample of a batched gradient in one pass:
+// level src -> level dst, recording the two steps' histories into slots
+// hist_slot and hist_slot + 1 (hist_slot < 0: none); the batch's two-step
+// tiling.
+template <typename T, int BCX, int BCY, bool HIST>
+__global__ __launch_bounds__(kBlock) void batch_rec_sweep2_kernel(
+    const AdjSampleDesc *__restrict__ samples, const int *__restrict__ tile_sample, int band,
+    LevelSel src_sel, LevelSel dst_sel, int hist_slot)
+{
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const AdjSampleDesc sd = samples[tile_sample[t]];
+    const int rel = t - sd.tile0;
+    const int bnd = rel / sd.tpr;
+    const int strip = (rel - bnd * sd.tpr) * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    auto region = [&](int r) {
+        return r == ADJ_CUR ? sd.region[0]
+                            : (r == ADJ_OUTER ? sd.region[1]
+                                              : (r == ADJ_INNER ? sd.region[2] : sd.region[3]));
+    };
+    const char *src = region(src_sel.region) + (uint64_t)src_sel.index * sd.level_bytes;
+    char *dst = region(dst_sel.region) + (uint64_t)dst_sel.index * sd.level_bytes;
+    char *h = reinterpret_cast<char *>(sd.hist);
+    float *hist1 = HIST ? reinterpret_cast<float *>(h + (uint64_t)hist_slot * sd.hist_bytes)
+                        : nullptr;
+    float *hist2 = HIST ? reinterpret_cast<float *>(h + (uint64_t)(hist_slot + 1) * sd.hist_bytes)
+                        : nullptr;
+    sweep2_strip<T, BCX, BCY, HIST>(src, dst, sd.lay, sd.med, sd.mlay, sd.g, sd.ph, sd.s,
+                                    sd.inv_s, band, bnd, strip, hist1, hist2);
+}
+
 // ----------------------------------------------------------- reductions
 
 struct SumOp {
@@ -1137,6 +1167,31 @@ hipError_t launch_batch_sweep(int storage, int bcx, int bcy, const SampleDesc *s
     if (ntiles == 0)
         return hipSuccess;
     LBK_DISPATCH(batch_sweep_t, samples, tile_sample, ntiles, parity, tile_x, rows, grid, st)
+}
+
+template <typename T, int BCX, int BCY>
+static hipError_t batch_rec_sweep2_t(const AdjSampleDesc *samples, const int *tile_sample,
+                                     int ntiles, int band, LevelSel src, LevelSel dst,
+                                     int hist_slot, hipStream_t st)
+{
+    if (hist_slot >= 0)
+        hipLaunchKernelGGL((batch_rec_sweep2_kernel<T, BCX, BCY, true>), dim3(ntiles),
+                           dim3(kBlock), 0, st, samples, tile_sample, band, src, dst, hist_slot);
+    else
+        hipLaunchKernelGGL((batch_rec_sweep2_kernel<T, BCX, BCY, false>), dim3(ntiles),
+                           dim3(kBlock), 0, st, samples, tile_sample, band, src, dst, hist_slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_rec_sweep2(int storage, int bcx, int bcy, const AdjSampleDesc *samples,
+                                   const int *tile_sample, int ntiles, int band, LevelSel src,
+                                   LevelSel dst, int hist_slot, hipStream_t st)
+{
+    if (bcy < 0 || bcy > 1 || band < 1 || ntiles < 0)
+        return hipErrorInvalidValue;
+    if (ntiles == 0)
+        return hipSuccess;
+    LBK_DISPATCH(batch_rec_sweep2_t, samples, tile_sample, ntiles, band, src, dst, hist_slot, st)
 }
 
 template <typename T, int BCX, int BCY>
