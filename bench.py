@@ -406,8 +406,13 @@ def time_ensemble(n_samples, steps, storages, graph_steps, device, launch=None, 
             "autotune_best_us": tune_us, "ms_per_step": ms / steps,
             "ms_per_step_min": sp["min"] / steps, "ms_per_step_max": sp["max"] / steps,
             "reps": REPS, "check_every": check_every, "mlups": mlups,
+            # one-read-one-write bytes per node-step at this rate (what a
+            # one-step-per-launch sweep would move), and per launch of the
+            # pass in use (a two-step pass moves ALG_BYTES for two steps)
             "alg_GBps": mlups * ALG_BYTES[storage] / 1e3,
-            "alg_frac": mlups * ALG_BYTES[storage] / 1e3 / HBM_PEAK_GBS}
+            "alg_frac": mlups * ALG_BYTES[storage] / 1e3 / HBM_PEAK_GBS,
+            "pass_alg_GBps": mlups * ALG_BYTES[storage] / 1e3 / b.steps_per_launch,
+            "pass_alg_frac": mlups * ALG_BYTES[storage] / 1e3 / b.steps_per_launch / HBM_PEAK_GBS}
         if si == 0:
             loop_steps = max(2, steps // 10)
             ev[2].record(st)
