@@ -345,14 +345,20 @@ __device__ __forceinline__ void first_step(const Physics &ph, float s, float inv
 }
 
 // The two-step pass of one wave: strip `strip` (60 columns) of band `bnd`
-// (rows bnd * band ..) of one lattice.
-template <typename T, int BCX, int BCY, bool HIST>
-__device__ __forceinline__ void sweep2_strip(const char *__restrict__ src,
-                                             char *__restrict__ dst, const Layout &lay,
-                                             const char *__restrict__ med, const MLayout &mlay,
-                                             const Geom &g, const Physics &ph, float s,
-                                             float inv_s, int band, int bnd, int strip,
-                                             float *__restrict__ hist1, float *__restrict__ hist2)
+// (rows bnd * band ..) of one lattice, marched downwards (DIR = 1: from the
+// band's first row) or upwards (DIR = -1: from its last).  Neighbouring
+// bands march in opposite directions, so two bands read the rows they share
+// (each band's two halo rows on either side) at the same time -- both at
+// their start or both at their end -- while the L2 still holds them.
+template <typename T, int BCX, int BCY, bool HIST, int DIR>
+__device__ __forceinline__ void sweep2_strip_dir(const char *__restrict__ src,
+                                                 char *__restrict__ dst, const Layout &lay,
+                                                 const char *__restrict__ med,
+                                                 const MLayout &mlay, const Geom &g,
+                                                 const Physics &ph, float s, float inv_s,
+                                                 int band, int bnd, int strip,
+                                                 float *__restrict__ hist1,
+                                                 float *__restrict__ hist2)
 {
     const int lane = (int)(threadIdx.x & 63);
     const int nstrips = (g.nx + kStrip2 - 1) / kStrip2;
@@ -377,12 +383,16 @@ __device__ __forceinline__ void sweep2_strip(const char *__restrict__ src,
     ln.bin = BCX == BC_PRESSURE && xr == 0;
     ln.bout = BCX == BC_PRESSURE && xr == g.nx - 1;
     ln.has_b = BCX == BC_PRESSURE && (strip == 0 || strip >= nstrips - 2);
-    const int y0 = bnd * band, y1 = min(y0 + band, g.ny);
+    const int y0 = bnd * band, y1 = min(y0 + band, g.ny), nb = y1 - y0;
+    // physical row of march position m (positions 0 .. nb - 1 are the band)
+    auto Y = [&](int m) { return DIR > 0 ? y0 + m : y1 - 1 - m; };
     auto exists = [&](int y) { return BCY == BC_PERIODIC || (y >= 0 && y < g.ny); };
     auto wrap = [&](int y) { return BCY == BC_PERIODIC ? ((y % g.ny) + g.ny) % g.ny : y; };
-    // a row index that always exists (rows beyond a wall: the last row; its
-    // values are loaded but never used, since the pull bounces back there)
-    auto held = [&](int y) { return BCY == BC_PERIODIC ? wrap(y) : min(y, g.ny - 1); };
+    // a row index that always exists (rows beyond a wall: the nearest row;
+    // its values are loaded but never used, since the pull bounces back there)
+    auto held = [&](int y) {
+        return BCY == BC_PERIODIC ? wrap(y) : (y < 0 ? 0 : (y >= g.ny ? g.ny - 1 : y));
+    };
     auto wall_lo = [&](int y) { return BCY == BC_WALL && y == 0; };
     auto wall_hi = [&](int y) { return BCY == BC_WALL && y == g.ny - 1; };
     // Every lane stores, so that the stores are not inside a branch: a lane
@@ -400,40 +410,46 @@ __device__ __forceinline__ void sweep2_strip(const char *__restrict__ src,
         const float vq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
         return owned ? v : vq;
     };
+    // The steps in march order: p, c, n are the rows at positions m - 1, m,
+    // m + 1, which are the physical rows below, at and above (DIR = 1) or
+    // above, at and below (DIR = -1).
+    auto first = [&](const Mid &p, const Mid &c, const Mid &n, int m, bool rec, Mid &out) {
+        const int y = Y(m);
+        first_step<T, BCX, HIST>(ph, s, inv_s, g, DIR > 0 ? p : n, c, DIR > 0 ? n : p,
+                                 wall_lo(y), wall_hi(y), ln, wrap(y), hist1, rec, out);
+    };
 
-    // For the current output row y: old level rows y .. y + 2 in use, rows
-    // y + 3 and y + 4 in flight (loads are issued two rows ahead of their
-    // use, which keeps enough of them outstanding per wave to cover HBM
-    // latency), intermediate rows y - 1 .. y + 1 (m0..m2).
+    // For the current output position m: old rows at positions m .. m + 2
+    // in use, m + 3 and m + 4 in flight (loads are issued two rows ahead of
+    // their use, which keeps enough of them outstanding per wave to cover
+    // HBM latency), intermediate rows m - 1 .. m + 1 (m0..m2).
     Mid a1{}, a2{}, a3{}, a4{}, a5{}, m0{}, m1{}, m2{};
-    if (exists(y0 - 2))
-        load_node<T>(src, lay, med, mlay, wrap(y0 - 2), ln.x, a4);
-    if (exists(y0 - 1))
-        load_node<T>(src, lay, med, mlay, wrap(y0 - 1), ln.x, a5);
-    load_node<T>(src, lay, med, mlay, y0, ln.x, a1);
-    if (exists(y0 + 1))
-        load_node<T>(src, lay, med, mlay, wrap(y0 + 1), ln.x, a2);
-    if (exists(y0 - 1))
-        first_step<T, BCX, HIST>(ph, s, inv_s, g, a4, a5, a1, wall_lo(y0 - 1), wall_hi(y0 - 1),
-                                 ln, wrap(y0 - 1), hist1, false, m0);
-    first_step<T, BCX, HIST>(ph, s, inv_s, g, a5, a1, a2, wall_lo(y0), wall_hi(y0), ln, y0,
-                             hist1, owned, m1);
-    load_node<T>(src, lay, med, mlay, held(y0 + 2), ln.x, a3);
-    load_node<T>(src, lay, med, mlay, held(y0 + 3), ln.x, a4);
-    // One output row: u0..u2 are the old rows y .. y + 2, nx receives row
-    // y + 4.  The loop below calls it with the five old-row registers in
-    // rotated roles, so no loaded value is ever copied (a copy would make
-    // the wave wait for its load -- and for the stores issued after it --
-    // at that point rather than at the value's first use).
-    auto row = [&](int y, const Mid &u0, const Mid &u1, const Mid &u2, Mid &nx) {
-        load_node<T>(src, lay, med, mlay, held(y + 4), ln.x, nx);
-        if (exists(y + 1))
-            first_step<T, BCX, HIST>(ph, s, inv_s, g, u0, u1, u2, wall_lo(y + 1),
-                                     wall_hi(y + 1), ln, wrap(y + 1), hist1,
-                                     owned && y + 1 < y1, m2);
+    if (exists(Y(-2)))
+        load_node<T>(src, lay, med, mlay, wrap(Y(-2)), ln.x, a4);
+    if (exists(Y(-1)))
+        load_node<T>(src, lay, med, mlay, wrap(Y(-1)), ln.x, a5);
+    load_node<T>(src, lay, med, mlay, Y(0), ln.x, a1);
+    if (exists(Y(1)))
+        load_node<T>(src, lay, med, mlay, wrap(Y(1)), ln.x, a2);
+    if (exists(Y(-1)))
+        first(a4, a5, a1, -1, false, m0);
+    first(a5, a1, a2, 0, owned, m1);
+    load_node<T>(src, lay, med, mlay, held(Y(2)), ln.x, a3);
+    load_node<T>(src, lay, med, mlay, held(Y(3)), ln.x, a4);
+    // One output row: u0..u2 are the old rows at positions m .. m + 2, nx
+    // receives position m + 4.  The loop below calls it with the five
+    // old-row registers in rotated roles, so no loaded value is ever copied
+    // (a copy would make the wave wait for its load -- and for the stores
+    // issued after it -- at that point rather than at the value's first use).
+    auto row = [&](int m, const Mid &u0, const Mid &u1, const Mid &u2, Mid &nx) {
+        load_node<T>(src, lay, med, mlay, held(Y(m + 4)), ln.x, nx);
+        if (exists(Y(m + 1)))
+            first(u0, u1, u2, m + 1, owned && m + 1 < nb, m2);
+        const int y = Y(m);
         float hs[9], jx, jy;
-        const float rho =
-            step_from<T, BCX>(ph, s, inv_s, m0, m1, m2, wall_lo(y), wall_hi(y), ln, hs, jx, jy);
+        const float rho = step_from<T, BCX>(ph, s, inv_s, DIR > 0 ? m0 : m2, m1,
+                                            DIR > 0 ? m2 : m0, wall_lo(y), wall_hi(y), ln, hs,
+                                            jx, jy);
         if (HIST && owned)
             record(hist2, g, y, ln.x, rho, jx, jy, false);
         const Rsrc out = make_rsrc(dst + (uint64_t)y * lay.row, (uint32_t)lay.row);
@@ -448,21 +464,38 @@ __device__ __forceinline__ void sweep2_strip(const char *__restrict__ src,
         m0 = m1;
         m1 = m2;
     };
-    for (int y = y0; y < y1; y += 5) {
-        row(y, a1, a2, a3, a5);
-        if (y + 1 >= y1)
+    for (int m = 0; m < nb; m += 5) {
+        row(m, a1, a2, a3, a5);
+        if (m + 1 >= nb)
             break;
-        row(y + 1, a2, a3, a4, a1);
-        if (y + 2 >= y1)
+        row(m + 1, a2, a3, a4, a1);
+        if (m + 2 >= nb)
             break;
-        row(y + 2, a3, a4, a5, a2);
-        if (y + 3 >= y1)
+        row(m + 2, a3, a4, a5, a2);
+        if (m + 3 >= nb)
             break;
-        row(y + 3, a4, a5, a1, a3);
-        if (y + 4 >= y1)
+        row(m + 3, a4, a5, a1, a3);
+        if (m + 4 >= nb)
             break;
-        row(y + 4, a5, a1, a2, a4);
+        row(m + 4, a5, a1, a2, a4);
     }
+}
+
+// The two-step pass of one wave: even bands march downwards, odd upwards.
+template <typename T, int BCX, int BCY, bool HIST>
+__device__ __forceinline__ void sweep2_strip(const char *__restrict__ src,
+                                             char *__restrict__ dst, const Layout &lay,
+                                             const char *__restrict__ med, const MLayout &mlay,
+                                             const Geom &g, const Physics &ph, float s,
+                                             float inv_s, int band, int bnd, int strip,
+                                             float *__restrict__ hist1, float *__restrict__ hist2)
+{
+    if (bnd & 1)
+        sweep2_strip_dir<T, BCX, BCY, HIST, -1>(src, dst, lay, med, mlay, g, ph, s, inv_s, band,
+                                                bnd, strip, hist1, hist2);
+    else
+        sweep2_strip_dir<T, BCX, BCY, HIST, 1>(src, dst, lay, med, mlay, g, ph, s, inv_s, band,
+                                               bnd, strip, hist1, hist2);
 }
 
 template <typename T, int BCX, int BCY, bool HIST>
