@@ -9,7 +9,7 @@ namespace lbk {
 // One reverse step of the lattice (terminal = 0), or the adjoint of the
 // read-out of J = sum_x a1 rho u_x + a2 u_x (terminal = 1; a1 only on column
 // nx-1 when outlet = 1).  mu_in / mu_out: adjoint states [y][9][pitch] FP32;
-// hist: (rho, jx, jy) [y][3][pitch] of the forward step being reversed;
+// hist: (rho, jx, jy) [y][pitch][3] of the forward step being reversed;
 // grad: FP32 [y][pitch] d J / d ln k, accumulated over a segment; grad2:
 // likewise d J / d ln kn0, or NULL to skip that plane.
 hipError_t launch_adjoint(int bcx, int bcy, const float *mu_in, float *mu_out, const float *hist,

@@ -30,7 +30,7 @@
 // forward values were discarded.
 //
 // Layouts (row blocks, `pitch` elements per slot, FP32): adjoint state
-// [y][9][pitch]; history [y][3][pitch] = (rho, jx, jy); gradient
+// [y][9][pitch]; history [y][pitch][3] = (rho, jx, jy) per node; gradient
 // [y][pitch] (one plane per parameter field) accumulated in FP32 over one
 // recomputed segment (at most a few hundred steps) and folded into an FP64
 // total at the segment's end.  The
@@ -308,7 +308,7 @@ __device__ __forceinline__ Rsrc rsrc_row(const void *base, uint64_t row_bytes, i
 // One reverse step (or, with terminal != 0, the read-out of J).
 //   mu_in  [y][9][pitch]  adjoint of S_n (ignored when terminal)
 //   mu_out [y][9][pitch]  adjoint of S_{n-1} (written by push)
-//   hist   [y][3][pitch]  (rho, jx, jy) of step n's post-stream populations
+//   hist   [y][pitch][3]  (rho, jx, jy) of step n's post-stream populations
 //   grad   [y][pitch]     FP32, accumulates d J / d ln k over a segment
 //   grad2  [y][pitch]     FP32, d J / d ln kn0 likewise (KN only)
 // Objective: J = sum_x a1(x) rho u_x + a2 u_x with a1(x) = a1 (all nodes,
@@ -330,10 +330,10 @@ __device__ __forceinline__ void adjoint_node(const float *mu_in, float *mu_out, 
     float *grow_k = KN ? grad2 + (uint64_t)y * g.pitch : nullptr;
 
     auto load_node = [&](uint32_t xx) {
-        const float rho = ld_f32_nt(hr, xx * 4, 0), jx = ld_f32_nt(hr, xx * 4, slot),
-                    jy = ld_f32_nt(hr, xx * 4, 2 * slot);
-        return node_fwd<FC>(ph, rho, jx, jy, ld_f32(mr, xx * 4, 0), ld_f32(mr, xx * 4, mlay.slot),
-                        ld_f32(mr, xx * 4, 2 * mlay.slot));
+        float h[3];
+        ld_hist<kNT>(hr, xx * 12, h);
+        return node_fwd<FC>(ph, h[0], h[1], h[2], ld_f32(mr, xx * 4, 0),
+                            ld_f32(mr, xx * 4, mlay.slot), ld_f32(mr, xx * 4, 2 * mlay.slot));
     };
     auto node_adj = [&](const NodeFwd &n, uint32_t xx, float (&lf)[9]) {
         if (terminal) {
@@ -688,20 +688,18 @@ __device__ __forceinline__ void adjoint2_strip(
         for (int i = 0; i < 9; ++i)
             r.mu[i] = ld_f32(lr, xo, i * slot);
         const Rsrc hr = rsrc_row(hist1, hrow, yh), mr = med_row(yh);
+        ld_hist<0>(hr, ln.x * 12, r.h1);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            r.h1[k] = ld_f32(hr, xo, k * slot);
+        for (int k = 0; k < 3; ++k)
             r.md[k] = ld_f32(mr, xo, k * mlay.slot);
-        }
     };
     auto load_b = [&](int y, RowB &r) {
         const int yh = held(y);
         const Rsrc hr = rsrc_row(hist0, hrow, yh), mr = med_row(yh);
+        ld_hist<0>(hr, ln.x * 12, r.h0);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            r.h0[k] = ld_f32(hr, xo, k * slot);
+        for (int k = 0; k < 3; ++k)
             r.md[k] = ld_f32(mr, xo, k * mlay.slot);
-        }
     };
     auto step_a = [&](const RowA &r, AMid &a) {
         local_adj<BCX, FC>(ph, r.mu, r.h1, r.md, ln, a.lf, a.gl, a.gk);

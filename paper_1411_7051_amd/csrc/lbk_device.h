@@ -112,6 +112,27 @@ __device__ __forceinline__ void st_f32(Rsrc r, uint32_t voff, uint32_t soff, flo
         __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)voff, (int)soff, 0);
 }
 
+// The adjoint's history of one node: (rho, jx, jy) as three consecutive FP32
+// values, moved with one 96-bit access.
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+template <int AUX>
+__device__ __forceinline__ void ld_hist(Rsrc r, uint32_t voff, float (&h)[3])
+{
+    const u32x3 v = __builtin_amdgcn_raw_buffer_load_b96(r, (int)voff, 0, AUX);
+    h[0] = __uint_as_float(v.x);
+    h[1] = __uint_as_float(v.y);
+    h[2] = __uint_as_float(v.z);
+}
+template <int AUX>
+__device__ __forceinline__ void st_hist(Rsrc r, uint32_t voff, float rho, float jx, float jy)
+{
+    u32x3 v;
+    v.x = __float_as_uint(rho);
+    v.y = __float_as_uint(jx);
+    v.z = __float_as_uint(jy);
+    __builtin_amdgcn_raw_buffer_store_b96(v, r, (int)voff, 0, AUX);
+}
+
 // v as an opaque FP32 register value.  The compiler may otherwise fold the
 // rounding of an FP32 result to FP16 into the arithmetic that produced it
 // (a mixed-precision FMA that rounds once, straight to FP16), and may do so

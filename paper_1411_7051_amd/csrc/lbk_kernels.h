@@ -61,7 +61,7 @@ enum {
 };
 
 // One sweep src -> dst; if hist is non-null also write this step's
-// linearisation point (rho, jx, jy) as [y][3][pitch] FP32 for the adjoint.
+// linearisation point (rho, jx, jy) as [y][pitch][3] FP32 for the adjoint.
 hipError_t launch_sweep(int storage, int bcx, int bcy, const char *src, char *dst,
                         const Layout &lay, const char *med, const MLayout &mlay, const Geom &g,
                         const Physics &ph, float s, float inv_s, float *hist, hipStream_t st);

@@ -134,15 +134,17 @@ __device__ __forceinline__ float post_stream(const Rows &R, const Layout &L, con
 }
 
 // Linearisation point (rho, jx, jy) of one step at node (x, y) into a
-// history slot [y][3][pitch] (FP32), for the adjoint; nt: streaming stores.
+// history slot [y][pitch][3] (FP32, the node's three values together), for
+// the adjoint; nt: streaming stores.
 __device__ __forceinline__ void record(float *hist, const Geom &g, int y, uint32_t x, float rho,
                                        float jx, float jy, bool nt = true)
 {
-    const uint32_t hrow = 3u * (uint32_t)g.pitch * 4u, hsl = (uint32_t)g.pitch * 4u;
+    const uint32_t hrow = 3u * (uint32_t)g.pitch * 4u;
     const Rsrc hr = make_rsrc(reinterpret_cast<char *>(hist) + (uint64_t)y * hrow, hrow);
-    st_f32(hr, x * 4, 0, rho, nt);
-    st_f32(hr, x * 4, hsl, jx, nt);
-    st_f32(hr, x * 4, 2 * hsl, jy, nt);
+    if (nt)
+        st_hist<kNT>(hr, x * 12, rho, jx, jy);
+    else
+        st_hist<0>(hr, x * 12, rho, jx, jy);
 }
 
 // Full update of node (x, y): pull, boundary override, moments, velocity,
