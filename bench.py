@@ -41,9 +41,6 @@ LAYOUT_BYTES = {"f32": 92, "f16": 56, "bf16": 56}
 
 
 PROFILE = os.path.join(ROOT, "profiles", "sweep_discs4096.md")
-# lattices from this many nodes on take the two-step pass (the library's
-# automatic pass mode)
-TWO_STEP_NODES = 1 << 22
 
 
 def log(msg):
@@ -90,6 +87,7 @@ def time_storage(case, storage, steps, warmup, device, single=0):
 
     lat = Lattice(case.eps, case.k, case.kn0, device=device, storage=storage,
                   **case.params)
+    per_launch = lat.steps_per_launch
     lat.step(warmup)
     torch.cuda.synchronize(device)
     # clock spin-up: untimed steps for SPINUP_S seconds, so that the timed
@@ -136,8 +134,9 @@ def time_storage(case, storage, steps, warmup, device, single=0):
         "ms_per_step_max": sp["max"] / steps,
         "reps": REPS,
         "spinup_steps": spin,
-        # two steps per pass: the pass moves ALG_BYTES per node
-        "pass_alg_GBps": nodes * ALG_BYTES[storage] / (2 * ms_step * 1e-3) / 1e9,
+        "steps_per_launch": per_launch,
+        # a launch (a two-step pass or a sweep) moves ALG_BYTES per node
+        "pass_alg_GBps": nodes * ALG_BYTES[storage] / (per_launch * ms_step * 1e-3) / 1e9,
         "per_step_alg_GBps": mlups * ALG_BYTES[storage] / 1e3,
     }
     if single_ms is not None:
@@ -646,10 +645,10 @@ def main():
     acc_small = storage_accuracy(small, args.storages.split(","), 2000, dev)
     head = runs.get("f32") or next(iter(runs.values()))
     st = head["storage"]
-    # dominant kernel: lattices of 2^22 nodes and more step through the
-    # two-step pass (one launch per two steps), the others one sweep a step
-    two = case.nodes >= TWO_STEP_NODES
-    per_launch = 2 if two else 1
+    # dominant kernel: the two-step pass (one launch per two steps) where
+    # the library's automatic pass mode takes it, else one sweep a step
+    per_launch = head["steps_per_launch"]
+    two = per_launch == 2
     launch_ms = per_launch * head["ms_per_step"]
     achieved = case.nodes * ALG_BYTES[st] / (launch_ms * 1e-3) / 1e9
     traffic, traffic_bytes = measured_traffic(st, launch_ms, case.nodes)

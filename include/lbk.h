@@ -72,7 +72,7 @@ typedef enum lbk_correlation {
  * sweep.  The two-step pass reads and writes the state once per two steps;
  * it pays off on lattices large enough to fill the device. */
 typedef enum lbk_pass_mode {
-    LBK_PASS_AUTO = 0,     /* two-step passes for lattices of >= 2^22 nodes */
+    LBK_PASS_AUTO = 0,     /* two-step passes from 2^20 nodes (FP32), 2^22 (FP16/BF16) */
     LBK_PASS_TWO_STEP = 1, /* two-step passes whatever the size */
     LBK_PASS_SINGLE = 2    /* single sweeps */
 } lbk_pass_mode;
@@ -104,6 +104,13 @@ typedef struct lbk_desc {
     double slip_b;       /* slip coefficient b of Eq. 6, <= 0 (default -1) */
     int32_t correlation; /* lbk_correlation */
     int32_t pass_mode;   /* lbk_pass_mode: one or two steps per pass */
+    int32_t band;        /* rows per band of the two-step passes, forward
+                            and reverse, 1..1024; 0 (default) = by size and
+                            storage: 8 rows forward at FP32, 10 at FP16/BF16,
+                            16 in reverse, halved down to 2 while a pass
+                            would have fewer than 8192 waves.  Any band
+                            gives the same result bitwise.  A batch ignores
+                            it (its passes take the default bands) */
 } lbk_desc;
 
 typedef struct lbk_lattice lbk_lattice;
@@ -132,11 +139,18 @@ lbk_status lbk_create(const lbk_desc *d, const float *eps, const float *k,
 /* Release the handle (not the workspace).  NULL is accepted. */
 lbk_status lbk_destroy(lbk_lattice *lat);
 
-/* Advance n >= 0 time steps of Eq. 12 (one fused sweep launch per step). */
+/* Advance n >= 0 time steps of Eq. 12: one fused sweep launch per step,
+ * or per two steps in two-step passes (lbk_steps_per_launch), an odd count
+ * ending in one single sweep. */
 lbk_status lbk_step(lbk_lattice *lat, int64_t n);
 
 /* Number of steps taken since create (or since the loaded state). */
 lbk_status lbk_time(const lbk_lattice *lat, int64_t *t);
+
+/* Steps each launch of lbk_step advances, 1 or 2, as the descriptor's
+ * pass_mode and the lattice's size and storage decide (the reverse steps of
+ * gradients follow the same choice). */
+lbk_status lbk_steps_per_launch(const lbk_lattice *lat, int32_t *steps);
 
 /* Macroscopic read-out at the current time (Eqs. 16-17 on the post-stream
  * populations, after the boundary override): density and velocity as

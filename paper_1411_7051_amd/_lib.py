@@ -49,6 +49,7 @@ class Desc(ctypes.Structure):
         ("rho0", ctypes.c_double), ("rho_ref", ctypes.c_double),
         ("slip_b", ctypes.c_double),
         ("correlation", ctypes.c_int32), ("pass_mode", ctypes.c_int32),
+        ("band", ctypes.c_int32),
     ]
 
 
@@ -80,6 +81,7 @@ _SIG = {
     "lbk_destroy": (ctypes.c_int, [_P]),
     "lbk_step": (ctypes.c_int, [_P, ctypes.c_int64]),
     "lbk_time": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "lbk_steps_per_launch": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32)]),
     "lbk_read_macroscopic": (ctypes.c_int, [_P, _P, _P, _P]),
     "lbk_read_populations": (ctypes.c_int, [_P, _P]),
     "lbk_apparent_permeability": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),

@@ -108,6 +108,8 @@ lbk_status check_desc(const lbk_desc *d)
         return fail(LBK_ERR_INVALID_ARG, "slip_b must be finite and <= 0 (got %g)", d->slip_b);
     if (d->pass_mode < LBK_PASS_AUTO || d->pass_mode > LBK_PASS_SINGLE)
         return fail(LBK_ERR_INVALID_ARG, "pass_mode must be 0..2 (got %d)", d->pass_mode);
+    if (d->band < 0 || d->band > 1024)
+        return fail(LBK_ERR_INVALID_ARG, "band must be 0..1024 (got %d)", d->band);
     return LBK_OK;
 }
 
@@ -130,7 +132,7 @@ lbk_status lbk::advance(lbk_lattice *lat, int64_t n, hipStream_t st)
         const int nxt = lat->cur ^ 1;
         HIP_TRY(launch_sweep2(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->state(nxt),
                               lat->L.lay, lat->med(), lat->L.mlay, lat->g, lat->ph, lat->s(),
-                              lat->inv_s(), band2_of(d.storage), nullptr, nullptr, st));
+                              lat->inv_s(), fwd_band(d), nullptr, nullptr, st));
         lat->cur = nxt;
         lat->t += 2;
         ++lat->version;
@@ -378,6 +380,14 @@ lbk_status lbk_time(const lbk_lattice *lat, int64_t *t)
     if (!lat || !t)
         return fail(LBK_ERR_INVALID_ARG, "NULL argument");
     *t = lat->t;
+    return LBK_OK;
+}
+
+lbk_status lbk_steps_per_launch(const lbk_lattice *lat, int32_t *steps)
+{
+    if (!lat || !steps)
+        return fail(LBK_ERR_INVALID_ARG, "NULL argument");
+    *steps = two_step_pass(lat) ? 2 : 1;
     return LBK_OK;
 }
 
@@ -796,7 +806,7 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
     auto sweep2 = [&](const char *src, char *dst, float *hist1, float *hist2) {
         return launch_sweep2(d.storage, d.bc_x, d.bc_y, src, dst, lat->L.lay, lat->med(),
                              lat->L.mlay, lat->g, lat->ph, lat->s(), lat->inv_s(),
-                             band2_of(d.storage), hist1, hist2, st);
+                             fwd_band(d), hist1, hist2, st);
     };
     const float a1 = (float)P.a1, a2 = (float)P.a2;
 
@@ -873,7 +883,8 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
                 if (two && t - 1 > a2s) {
                     HIP_TRY(launch_adjoint2(d.bc_x, d.bc_y, lam[cur], lam[cur ^ 1],
                                             histp(t - a2s), histp(t - 1 - a2s), lat->med(),
-                                            lat->L.mlay, seg, seg2, lat->g, lat->ph, kBandA, st));
+                                            lat->L.mlay, seg, seg2, lat->g, lat->ph,
+                                            rev_band(d), st));
                     t -= 2;
                 } else {
                     HIP_TRY(launch_adjoint(d.bc_x, d.bc_y, lam[cur], lam[cur ^ 1],

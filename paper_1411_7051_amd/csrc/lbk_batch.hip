@@ -238,7 +238,7 @@ struct lbk_batch {
         int64_t nodes = 0;
         for (const lbk_lattice *l : lats)
             nodes += (int64_t)l->d.nx * l->d.ny;
-        return nodes >= kTwoStepNodes;
+        return nodes >= kTwoStepBatchNodes;
     }
 };
 

@@ -125,10 +125,46 @@ inline int band2_of(int storage) { return storage == LBK_F32 ? LBK_BAND2 : LBK_B
 #endif
 constexpr int kBandA = LBK_BANDA;
 
+// Waves a two-step pass should at least have: two rounds of the 256 compute
+// units at three waves per SIMD, with some to spare.
+constexpr int64_t kMinWaves2 = 8192;
+
+// The band of a two-step pass over an nx x ny lattice: `band`, halved (down
+// to 2) while the pass would have fewer than kMinWaves2 waves.  On a
+// 2048 x 1024 lattice bands of 4 or 2 rows ran at 85-86 GLUPS against 78
+// with 8 (and 64 with single sweeps).
+inline int band_for(int nx, int ny, int band)
+{
+    const int64_t strips = (nx + kStrip2 - 1) / kStrip2;
+    while (band > 2 && strips * ((ny + band - 1) / band) < kMinWaves2)
+        band = (band + 1) / 2;
+    return band;
+}
+
+// Bands of a lattice's forward and reverse two-step passes: the
+// descriptor's band, else by size and storage.
+inline int fwd_band(const lbk_desc &d)
+{
+    return d.band > 0 ? d.band : band_for(d.nx, d.ny, band2_of(d.storage));
+}
+inline int rev_band(const lbk_desc &d) { return d.band > 0 ? d.band : band_for(d.nx, d.ny, kBandA); }
+
 // Lattices from this many nodes on take two-step passes under
-// LBK_PASS_AUTO: below it too few waves run to hide the march's latency
-// (1024 x 512: 38 against 48 GLUPS for single sweeps).
-constexpr int64_t kTwoStepNodes = (int64_t)1 << 22;
+// LBK_PASS_AUTO.  Below it too few waves run to hide the march's latency,
+// and a level fits the 256 MB on-package cache, so single sweeps are not
+// bound by HBM: FP32 on 1024 x 512, 52 GLUPS with single sweeps, 48-51 with
+// two-step passes; on 1024 x 1024, 61 against 70.  FP16 and BF16, whose
+// single sweeps move half the bytes, switch later: 93 against 85 GLUPS on
+// 2048 x 1024, 104 against 111 on 2048 x 2048.
+inline int64_t two_step_nodes(int storage)
+{
+    return storage == LBK_F32 ? (int64_t)1 << 20 : (int64_t)1 << 22;
+}
+// The same for a batch, counting the nodes of all its samples.  Batches keep
+// their bands at band2_of and their samples are often small, with more strip
+// and band edges per node, so they switch later; lbk_batch_autotune times
+// both passes and settles it per batch.
+constexpr int64_t kTwoStepBatchNodes = (int64_t)1 << 22;
 
 // Whether steps of this lattice go through the two-step pass (and the
 // reverse steps of its gradients through the two-step reverse pass), as
@@ -137,7 +173,7 @@ inline bool two_step_pass(const lbk_lattice *lat)
 {
     const lbk_desc &d = lat->d;
     return d.pass_mode == LBK_PASS_TWO_STEP ||
-           (d.pass_mode == LBK_PASS_AUTO && (int64_t)d.nx * d.ny >= kTwoStepNodes);
+           (d.pass_mode == LBK_PASS_AUTO && (int64_t)d.nx * d.ny >= two_step_nodes(d.storage));
 }
 
 // n >= 0 steps of the lattice on stream st (pairs through the two-step

@@ -254,10 +254,7 @@ __device__ __forceinline__ void pull_mid(const Mid &dn, const Mid &c, const Mid 
         const Mid &m = ey == 1 ? dn : (ey == -1 ? up : c);
         const float ws = Elem<T>::kScaled ? w_of(i) * s : w_of(i);
         float rn, h;
-        if (wall_y) {
-            rn = c.rho;
-            h = c.h[opp_of(i)];
-        } else if (ex == 1) {
+        if (ex == 1) {
             rn = lane_from<1>(m.rho);
             h = lane_from<1>(m.h[i]);
         } else if (ex == -1) {
@@ -266,6 +263,12 @@ __device__ __forceinline__ void pull_mid(const Mid &dn, const Mid &c, const Mid 
         } else {
             rn = m.rho;
             h = m.h[i];
+        }
+        // a wall bounces the pull back: a select, not a branch, so that no
+        // control flow splits the row's loads from their uses
+        if (ey != 0) {
+            rn = wall_y ? c.rho : rn;
+            h = wall_y ? c.h[opp_of(i)] : h;
         }
         d[i] = ws * (rn - rc) + h;
         if (BCX == BC_WALL) {
@@ -388,10 +391,11 @@ __device__ __forceinline__ void sweep2_strip_dir(const char *__restrict__ src,
     const int y0 = bnd * band, y1 = min(y0 + band, g.ny), nb = y1 - y0;
     // physical row of march position m (positions 0 .. nb - 1 are the band)
     auto Y = [&](int m) { return DIR > 0 ? y0 + m : y1 - 1 - m; };
-    auto exists = [&](int y) { return BCY == BC_PERIODIC || (y >= 0 && y < g.ny); };
     auto wrap = [&](int y) { return BCY == BC_PERIODIC ? ((y % g.ny) + g.ny) % g.ny : y; };
-    // a row index that always exists (rows beyond a wall: the nearest row;
-    // its values are loaded but never used, since the pull bounces back there)
+    // A row index that always exists.  A row beyond a wall reads the
+    // nearest row and its first step is computed from those values all the
+    // same (never recorded, and discarded where the pull bounces back), so
+    // that no branch splits the march.
     auto held = [&](int y) {
         return BCY == BC_PERIODIC ? wrap(y) : (y < 0 ? 0 : (y >= g.ny ? g.ny - 1 : y));
     };
@@ -425,16 +429,12 @@ __device__ __forceinline__ void sweep2_strip_dir(const char *__restrict__ src,
     // in use, m + 3 and m + 4 in flight (loads are issued two rows ahead of
     // their use, which keeps enough of them outstanding per wave to cover
     // HBM latency), intermediate rows m - 1 .. m + 1 (m0..m2).
-    Mid a1{}, a2{}, a3{}, a4{}, a5{}, m0{}, m1{}, m2{};
-    if (exists(Y(-2)))
-        load_node<T>(src, lay, med, mlay, wrap(Y(-2)), ln.x, a4);
-    if (exists(Y(-1)))
-        load_node<T>(src, lay, med, mlay, wrap(Y(-1)), ln.x, a5);
+    Mid a1, a2, a3, a4, a5, m0, m1, m2;
+    load_node<T>(src, lay, med, mlay, held(Y(-2)), ln.x, a4);
+    load_node<T>(src, lay, med, mlay, held(Y(-1)), ln.x, a5);
     load_node<T>(src, lay, med, mlay, Y(0), ln.x, a1);
-    if (exists(Y(1)))
-        load_node<T>(src, lay, med, mlay, wrap(Y(1)), ln.x, a2);
-    if (exists(Y(-1)))
-        first(a4, a5, a1, -1, false, m0);
+    load_node<T>(src, lay, med, mlay, held(Y(1)), ln.x, a2);
+    first(a4, a5, a1, -1, false, m0);
     first(a5, a1, a2, 0, owned, m1);
     load_node<T>(src, lay, med, mlay, held(Y(2)), ln.x, a3);
     load_node<T>(src, lay, med, mlay, held(Y(3)), ln.x, a4);
@@ -445,8 +445,7 @@ __device__ __forceinline__ void sweep2_strip_dir(const char *__restrict__ src,
     // issued after it -- at that point rather than at the value's first use).
     auto row = [&](int m, const Mid &u0, const Mid &u1, const Mid &u2, Mid &nx) {
         load_node<T>(src, lay, med, mlay, held(Y(m + 4)), ln.x, nx);
-        if (exists(Y(m + 1)))
-            first(u0, u1, u2, m + 1, owned && m + 1 < nb, m2);
+        first(u0, u1, u2, m + 1, owned && m + 1 < nb, m2);
         const int y = Y(m);
         float hs[9], jx, jy;
         const float rho = step_from<T, BCX>(ph, s, inv_s, DIR > 0 ? m0 : m2, m1,

@@ -21,7 +21,7 @@ PERIODIC, WALL, PRESSURE = 0, 1, 2
 def make_desc(nx, ny, tau=0.8, gx=0.0, gy=0.0, f_eps=0.0, bc_x=PERIODIC,
               bc_y=PERIODIC, rho_in=1.0, rho_out=1.0, rho0=1.0, rho_ref=1.0,
               kn_local=1, init=0, storage="f32", check_every=100, correlation=0,
-              slip_b=-1.0, pass_mode=0) -> Desc:
+              slip_b=-1.0, pass_mode=0, band=0) -> Desc:
     lib = _lib.load()
     d = Desc()
     check(lib.lbk_desc_default(ctypes.byref(d)))
@@ -37,6 +37,7 @@ def make_desc(nx, ny, tau=0.8, gx=0.0, gy=0.0, f_eps=0.0, bc_x=PERIODIC,
     d.slip_b = float(slip_b)
     d.pass_mode = (_lib.PASS_MODE[pass_mode] if isinstance(pass_mode, str)
                    else int(pass_mode))
+    d.band = int(band)
     return d
 
 
@@ -60,7 +61,7 @@ class Lattice:
     ``eps``, ``k``, ``kn0``: [ny][nx] arrays (numpy or torch); ``k`` may be
     +inf.  Keyword parameters are those of ``lbk_desc`` (tau, gx, gy, f_eps,
     bc_x, bc_y, rho_in, rho_out, rho0, rho_ref, kn_local, init, storage,
-    check_every, correlation, slip_b, pass_mode)."""
+    check_every, correlation, slip_b, pass_mode, band)."""
 
     def __init__(self, eps, k, kn0=None, device: Optional[torch.device] = None,
                  **params):
@@ -117,6 +118,14 @@ class Lattice:
         t = ctypes.c_int64()
         check(_lib.load().lbk_time(self._handle(), ctypes.byref(t)))
         return int(t.value)
+
+    @property
+    def steps_per_launch(self) -> int:
+        """1 (single sweeps) or 2 (two-step passes), as pass_mode and the
+        lattice's size and storage decide."""
+        n = ctypes.c_int32()
+        check(_lib.load().lbk_steps_per_launch(self._handle(), ctypes.byref(n)))
+        return int(n.value)
 
     # -- read-out
     def macroscopic(self):

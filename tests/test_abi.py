@@ -29,9 +29,10 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_desc_struct_layout():
-    # 8 int32, 9 doubles, 2 int32: 32 + 72 + 8 bytes, no padding
-    assert ctypes.sizeof(_lib.Desc) == 112
+    # 8 int32, 9 doubles, 3 int32: 32 + 72 + 12 bytes, 4 of tail padding
+    assert ctypes.sizeof(_lib.Desc) == 120
     assert _lib.Desc.slip_b.offset == 96 and _lib.Desc.correlation.offset == 104
+    assert _lib.Desc.band.offset == 112
 
 
 def test_workspace_size_scales_with_lattice():
@@ -59,6 +60,8 @@ def test_workspace_size_scales_with_lattice():
     (dict(slip_b=0.5), "slip_b"),
     (dict(pass_mode=3), "pass_mode"),
     (dict(pass_mode=-1), "pass_mode"),
+    (dict(band=-1), "band"),
+    (dict(band=1025), "band"),
 ])
 def test_invalid_descriptions_rejected(kw, msg):
     d = make_desc(16, 8, **kw)

@@ -3,8 +3,8 @@ adjoint state in registers) against single reverse steps, through the C ABI:
 a gradient taken with pass_mode LBK_PASS_TWO_STEP reverses its segments in
 pairs of steps (and one single step where a segment's length is odd), so it
 must equal the gradient of LBK_PASS_SINGLE bitwise.  Sizes around the
-60-column strips (a pressure outlet next to a strip's edge included) and
-the 6-row bands, every boundary combination, both objectives, the ln kn0
+60-column strips (a pressure outlet next to a strip's edge included), bands
+of 1 to 17 rows, every boundary combination, both objectives, the ln kn0
 plane, the Forchheimer term and the slip correlations."""
 import pytest
 import torch
@@ -30,11 +30,11 @@ def dev():
     return d
 
 
-def grads(dev, case, storage, steps, ckpt, hist, objective="k_app"):
+def grads(dev, case, storage, steps, ckpt, hist, objective="k_app", band=0):
     out = []
     for mode in ("single", "two_step"):
         lat = Lattice(case.eps, case.k, case.kn0, device=dev, storage=storage, check_every=0,
-                      pass_mode=mode, **case.params)
+                      pass_mode=mode, band=band if mode == "two_step" else 0, **case.params)
         lat.step(3)
         out.append(lat.gradient(steps, objective, ckpt_every=ckpt, hist_len=hist,
                                 wrt_kn0=True))
@@ -84,3 +84,19 @@ def test_two_step_reverse_model_options(dev, extra):
                                 kn_range=(0.0, 2.0), bc_x=2, bc_y=0, rho_in=1.02, rho_out=1.0,
                                 init=1, **extra)
     assert_same(grads(dev, case, "f32", 10, 10, 10), str(extra))
+
+
+@pytest.mark.parametrize("band", [1, 3, 6, 16, 17])
+def test_two_step_reverse_bands(dev, band):
+    """Bands of any height reverse to the same gradient: the whole-period
+    loop of 16 rows with every remainder, and bands taller than the
+    lattice."""
+    for bcx, bcy in ((2, 0), (2, 1), (0, 1)):
+        for nx, ny in ((63, 31), (121, 40), (183, 7)):
+            drive = (dict(rho_in=1.03, rho_out=1.0, init=1) if bcx == inputs.PRESSURE
+                     else dict(gx=1e-4, gy=-3e-5))
+            case = inputs.random_medium(nx, ny, seed=nx * 37 + ny + band, solid_frac=0.08,
+                                        pore_frac=0.08, kn_range=(0.0, 2.0), bc_x=bcx,
+                                        bc_y=bcy, **drive)
+            assert_same(grads(dev, case, "f32", 9, 9, 9, band=band),
+                        f"{nx}x{ny} bc ({bcx},{bcy}) band {band}")

@@ -3,10 +3,10 @@ levels in registers) against single steps, through the C ABI: a lattice
 with pass_mode LBK_PASS_TWO_STEP runs lbk_step(n) as n/2 two-step passes
 (and one single sweep if n is odd), so it must end bitwise where n single
 sweeps (LBK_PASS_SINGLE) leave the same lattice, for FP32, FP16 and BF16
-storage.  Sizes around the 60-column strips and the 8- and 10-row bands,
-every boundary combination.  A gradient whose recomputing sweeps take
-two-step passes equals the single-sweep one bitwise, and the automatic mode
-picks the two-step pass on large lattices only."""
+storage.  Sizes around the 60-column strips, bands of 1 to 16 rows, every
+boundary combination.  A gradient whose recomputing sweeps take two-step
+passes equals the single-sweep one bitwise, and the automatic mode picks
+the two-step pass on large lattices only."""
 import numpy as np
 import pytest
 import torch
@@ -30,13 +30,14 @@ def dev():
     return d
 
 
-def pair(dev, case, storage, steps):
+def pair(dev, case, storage, steps, band=0):
     """a: single sweeps (one lbk_step(1) call each); b: lbk_step(steps) with
-    two-step passes requested whatever the lattice size."""
+    two-step passes requested whatever the lattice size (bands of `band`
+    rows; 0: the library's choice)."""
     a = Lattice(case.eps, case.k, case.kn0, device=dev, storage=storage, check_every=0,
                 pass_mode="single", **case.params)
     b = Lattice(case.eps, case.k, case.kn0, device=dev, storage=storage, check_every=0,
-                pass_mode="two_step", **case.params)
+                pass_mode="two_step", band=band, **case.params)
     for _ in range(steps):
         a.step(1)
     b.step(steps)
@@ -63,6 +64,26 @@ def test_two_step_pass_is_bitwise_two_single_steps(dev, storage, bcx, bcy):
                             f"max |diff| {float((fa - fb).abs().max()):.3e}")
             a.close()
             b.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("band", [1, 3, 5, 8, 10, 16])
+def test_two_step_pass_bands(dev, storage, band):
+    """Any band gives the same state: the march unrolled over five rows with
+    every remainder, bands taller than the lattice, walls at a band's
+    ends."""
+    for bcx, bcy in ((2, 0), (2, 1), (0, 1), (1, 1)):
+        for nx, ny in ((61, 6), (63, 31), (121, 40), (300, 37)):
+            drive = (dict(rho_in=1.03, rho_out=1.0, init=1) if bcx == inputs.PRESSURE
+                     else dict(gx=1e-4, gy=-3e-5))
+            case = inputs.random_medium(nx, ny, seed=nx * 41 + ny + band, solid_frac=0.08,
+                                        pore_frac=0.08, kn_range=(0.0, 2.0), bc_x=bcx,
+                                        bc_y=bcy, **drive)
+            for steps in (2, 7):
+                a, b, sa, sb = pair(dev, case, storage, steps, band)
+                assert torch.equal(sa, sb), (nx, ny, bcx, bcy, steps)
+                a.close()
+                b.close()
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16"])
@@ -104,16 +125,19 @@ def test_two_step_recording_sweeps_bitwise(dev):
 
 
 def test_auto_mode_matches_both(dev):
-    """LBK_PASS_AUTO steps a 2048 x 2048 lattice (2^22 nodes) with two-step
-    passes and a 2047 x 2048 one with single sweeps; either way the
-    state equals the other modes' bitwise."""
-    for nx, storage in ((2048, "f32"), (2047, "f32"), (2048, "f16")):
-        case = inputs.random_medium(nx, 2048, seed=94, solid_frac=0.02, pore_frac=0.02,
+    """LBK_PASS_AUTO takes two-step passes from 2^20 nodes at FP32 and from
+    2^22 at FP16 (bands shortened to fill the device), single sweeps below;
+    either way the state equals the other modes' bitwise."""
+    for nx, ny, storage, two in ((1024, 1024, "f32", True), (1023, 1024, "f32", False),
+                                 (2048, 1024, "f16", False), (2048, 2048, "f16", True)):
+        case = inputs.random_medium(nx, ny, seed=94, solid_frac=0.02, pore_frac=0.02,
                                     bc_x=2, rho_in=1.01, rho_out=1.0, init=1)
         states = []
         for mode in ("auto", "single", "two_step"):
             lat = Lattice(case.eps, case.k, case.kn0, device=dev, pass_mode=mode,
                           storage=storage, **case.params)
+            expect = {"auto": 2 if two else 1, "single": 1, "two_step": 2}[mode]
+            assert lat.steps_per_launch == expect, (nx, ny, storage, mode)
             lat.step(4)
             states.append(lat.save_state())
             lat.close()
