@@ -48,8 +48,8 @@ def log(msg):
 
 
 def measured_traffic(storage, launch_ms, nodes):
-    """HBM traffic of one launch of the storage type's sweep (for FP32 the
-    two-step pass) from the committed rocprofv3 counter summary (FETCH_SIZE
+    """HBM traffic of one launch of the storage type's pass (the automatic
+    pass mode's multi-step pass) from the committed rocprofv3 counter summary (FETCH_SIZE
     and WRITE_SIZE per dispatch, each scaled by what it reads for a plain
     copy of known size), as GB/s over this run's measured launch time.  None
     if the summary is missing, covers another lattice, or was taken on
@@ -79,9 +79,11 @@ def spread(ms_list):
 
 
 def time_storage(case, storage, steps, warmup, device, single=0):
-    """`REPS` timed runs of `steps` steps (two-step passes) on the lattice's
-    stream, HIP events around each; with `single` > 0 also that many single
-    sweeps (one lbk_step(1) call each) for comparison."""
+    """`REPS` timed runs of `steps` steps (the automatic pass mode's
+    multi-step passes) on the lattice's stream, HIP events around each, then
+    `REPS` runs of whole passes alone for the pass's launch time; with
+    `single` > 0 also that many single sweeps (one lbk_step(1) call each)
+    for comparison."""
     import torch
     from paper_1411_7051_amd.lattice import Lattice
 
@@ -108,6 +110,20 @@ def time_storage(case, storage, steps, warmup, device, single=0):
         t1.record(stream)
         torch.cuda.synchronize(device)
         times.append(t0.elapsed_time(t1))
+    # the pass's own launch time: whole passes only, from a time at a
+    # multiple of the lattice's check interval (100 steps), so that no
+    # check or remainder pass falls inside
+    launch = []
+    for _ in range(REPS if per_launch > 1 else 0):
+        lat.step((-lat.time) % 100)
+        n = per_launch * (99 // per_launch)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        lat.step(n)
+        t1.record(stream)
+        torch.cuda.synchronize(device)
+        launch.append(t0.elapsed_time(t1) / (n // per_launch))
     single_ms = None
     if single > 0:
         t0 = torch.cuda.Event(enable_timing=True)
@@ -135,10 +151,15 @@ def time_storage(case, storage, steps, warmup, device, single=0):
         "reps": REPS,
         "spinup_steps": spin,
         "steps_per_launch": per_launch,
-        # a launch (a two-step pass or a sweep) moves ALG_BYTES per node
+        # a launch (a multi-step pass or a sweep) moves ALG_BYTES per node
         "pass_alg_GBps": nodes * ALG_BYTES[storage] / (per_launch * ms_step * 1e-3) / 1e9,
         "per_step_alg_GBps": mlups * ALG_BYTES[storage] / 1e3,
     }
+    if launch:
+        ls = spread(launch)
+        out["launch_ms"] = ls["median"]
+        out["launch_ms_min"] = ls["min"]
+        out["launch_ms_max"] = ls["max"]
     if single_ms is not None:
         out["single_sweep_ms"] = single_ms
         out["single_sweep_mlups"] = nodes / (single_ms * 1e-3) / 1e6
@@ -299,6 +320,21 @@ def time_adjoint(n, steps, ckpt, hist, device):
     case = inputs.shale(n=n, seed=3)
     log(f"shale inputs: {case.nodes} nodes in {time.perf_counter() - t:.1f} s")
     torch.cuda.reset_peak_memory_stats(device)
+    # the forward in the gradient's own pass structure (two-step passes, as
+    # the recording and reverse passes take), timed on 2000 steps and scaled
+    lat2 = Lattice(case.eps, case.k, case.kn0, device=device, pass_mode="two_step",
+                   **case.params)
+    lat2.step(20)
+    e2 = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    n2 = min(steps, 2000)
+    e2[0].record(lat2.stream)
+    lat2.step(n2)
+    e2[1].record(lat2.stream)
+    torch.cuda.synchronize(device)
+    t_fwd2 = e2[0].elapsed_time(e2[1]) * steps / n2
+    lat2.close()
+    del lat2
+    torch.cuda.empty_cache()
     lat = Lattice(case.eps, case.k, case.kn0, device=device, **case.params)
     st = lat.stream
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
@@ -335,10 +371,16 @@ def time_adjoint(n, steps, ckpt, hist, device):
         "workspace_GB": ws.numel() / 1e9,
         "peak_device_mem_GB": torch.cuda.max_memory_allocated(device) / 1e9,
         "t_fwd_ms": t_fwd,
+        "fwd_steps_per_launch": lat.steps_per_launch,
         "t_fwd_ckpt_ms": t_af,
         "t_grad_ms": t_bwd,
         "grad_over_fwd": t_bwd / t_fwd,
         "total_over_fwd": (t_af + t_bwd) / t_fwd,
+        # against a forward in two-step passes (the passes the gradient's
+        # recording and reverse steps take), from 2000 steps scaled
+        "t_fwd_two_step_ms": t_fwd2,
+        "grad_over_fwd_two_step": t_bwd / t_fwd2,
+        "total_over_fwd_two_step": (t_af + t_bwd) / t_fwd2,
         "J": J,
         "max_abs_grad": gmax,
     }
@@ -645,11 +687,11 @@ def main():
     acc_small = storage_accuracy(small, args.storages.split(","), 2000, dev)
     head = runs.get("f32") or next(iter(runs.values()))
     st = head["storage"]
-    # dominant kernel: the two-step pass (one launch per two steps) where
-    # the library's automatic pass mode takes it, else one sweep a step
+    # dominant kernel: the multi-step pass (one launch per three or two
+    # steps) where the library's automatic pass mode takes it, else one
+    # sweep a step; its launch time from whole passes alone
     per_launch = head["steps_per_launch"]
-    two = per_launch == 2
-    launch_ms = per_launch * head["ms_per_step"]
+    launch_ms = head.get("launch_ms", per_launch * head["ms_per_step"])
     achieved = case.nodes * ALG_BYTES[st] / (launch_ms * 1e-3) / 1e9
     traffic, traffic_bytes = measured_traffic(st, launch_ms, case.nodes)
     roof = {
@@ -660,15 +702,18 @@ def main():
         "frac": achieved / HBM_PEAK_GBS,
         "traffic": traffic,
         "traffic_bytes_per_launch": traffic_bytes,
-        "kernel": (f"sweep2_kernel<{st}> (two steps per launch" if two else
-                   f"sweep_kernel<{st}> (one step per launch") + "; pressure x, periodic y)",
+        "kernel": {3: f"sweep3x_kernel<{st}> (three steps per launch",
+                   2: f"sweep2_kernel<{st}> (two steps per launch"}.get(
+                       per_launch, f"sweep_kernel<{st}> (one step per launch") +
+                  "; pressure x, periodic y)",
         "bytes_per_node_per_launch": ALG_BYTES[st],
         "steps_per_launch": per_launch,
         "launch_ms": launch_ms,
         "layout_bytes_per_node_per_launch": LAYOUT_BYTES[st],
-        # the HBM rate a one-step-per-launch sweep would need for this rate
-        "single_step_equivalent_GBps": head["mlups"] * ALG_BYTES[st] / 1e3,
-        "single_step_equivalent_frac": head["mlups"] * ALG_BYTES[st] / 1e3 / HBM_PEAK_GBS,
+        # the HBM rate a one-step-per-launch sweep would need for this
+        # pass's rate
+        "single_step_equivalent_GBps": per_launch * achieved,
+        "single_step_equivalent_frac": per_launch * achieved / HBM_PEAK_GBS,
         "copy_GBps": copy_bandwidth(dev),
     }
     log(f"plain streaming kernel (b = a * 1, 1 GiB f32): {roof['copy_GBps']:.0f} GB/s "
@@ -678,7 +723,10 @@ def main():
         adj = time_adjoint(args.adjoint_n, args.adjoint_steps, args.adjoint_ckpt,
                            args.adjoint_hist, dev)
         log(f"adjoint: t_grad/t_fwd = {adj['grad_over_fwd']:.2f}, "
-            f"(t_fwd + t_grad)/t_fwd = {adj['total_over_fwd']:.2f}")
+            f"(t_fwd + t_grad)/t_fwd = {adj['total_over_fwd']:.2f} "
+            f"({adj['fwd_steps_per_launch']} steps per forward launch); against two-step "
+            f"forward passes {adj['grad_over_fwd_two_step']:.2f} and "
+            f"{adj['total_over_fwd_two_step']:.2f}")
     ens = None
     if not args.no_ensemble:
         fixed = (tuple(int(v) for v in args.ensemble_launch.split(","))

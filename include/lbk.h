@@ -67,14 +67,19 @@ typedef enum lbk_correlation {
 } lbk_correlation;
 
 /* How lbk_step (and a gradient's recomputing sweeps and reverse steps)
- * advance a lattice: two time steps per pass, the intermediate level kept
- * in registers (bitwise the result of two single sweeps), or one step per
- * sweep.  The two-step pass reads and writes the state once per two steps;
- * it pays off on lattices large enough to fill the device. */
+ * advance a lattice: two or three time steps per pass, the intermediate
+ * levels kept in registers (bitwise the result of as many single sweeps),
+ * or one step per sweep.  A multi-step pass reads and writes the state
+ * once per pass; it pays off on lattices large enough to fill the device. */
 typedef enum lbk_pass_mode {
-    LBK_PASS_AUTO = 0,     /* two-step passes from 2^20 nodes (FP32), 2^22 (FP16/BF16) */
+    LBK_PASS_AUTO = 0,     /* three-step passes from 2^22 nodes (FP32), 2^24
+                              (FP16/BF16); two-step passes from 2^20 (FP32),
+                              2^22 (FP16/BF16); single sweeps below */
     LBK_PASS_TWO_STEP = 1, /* two-step passes whatever the size */
-    LBK_PASS_SINGLE = 2    /* single sweeps */
+    LBK_PASS_SINGLE = 2,   /* single sweeps */
+    LBK_PASS_THREE_STEP = 3 /* lbk_step: three-step passes whatever the size (a
+                               remainder of n in a two-step pass or a single
+                               sweep); gradients: two-step passes */
 } lbk_pass_mode;
 
 /* Run description (Sec. IV: plates, heterogeneous media, fractured shale). */
@@ -103,11 +108,12 @@ typedef struct lbk_desc {
     double rho_ref;      /* density at which kn0 is quoted */
     double slip_b;       /* slip coefficient b of Eq. 6, <= 0 (default -1) */
     int32_t correlation; /* lbk_correlation */
-    int32_t pass_mode;   /* lbk_pass_mode: one or two steps per pass */
-    int32_t band;        /* rows per band of the two-step passes, forward
+    int32_t pass_mode;   /* lbk_pass_mode: one, two or three steps per pass */
+    int32_t band;        /* rows per band of the multi-step passes, forward
                             and reverse, 1..1024; 0 (default) = by size and
-                            storage: 8 rows forward at FP32, 10 at FP16/BF16,
-                            16 in reverse, halved down to 2 while a pass
+                            storage: two-step passes 8 rows at FP32, 10 at
+                            FP16/BF16, three-step passes 12 and 24, 16 in
+                            reverse, halved down to 2 while a pass
                             would have fewer than 8192 waves.  Any band
                             gives the same result bitwise.  A batch ignores
                             it (its passes take the default bands) */
@@ -147,9 +153,10 @@ lbk_status lbk_step(lbk_lattice *lat, int64_t n);
 /* Number of steps taken since create (or since the loaded state). */
 lbk_status lbk_time(const lbk_lattice *lat, int64_t *t);
 
-/* Steps each launch of lbk_step advances, 1 or 2, as the descriptor's
+/* Steps each launch of lbk_step advances, 1, 2 or 3, as the descriptor's
  * pass_mode and the lattice's size and storage decide (the reverse steps of
- * gradients follow the same choice). */
+ * gradients follow the same choice, taking two where lbk_step takes
+ * three). */
 lbk_status lbk_steps_per_launch(const lbk_lattice *lat, int32_t *steps);
 
 /* Macroscopic read-out at the current time (Eqs. 16-17 on the post-stream
@@ -331,7 +338,8 @@ lbk_status lbk_batch_get_launch(const lbk_batch *b, int32_t *tile_x, int32_t *ro
  * two-step passes for batches of 2^22 nodes and more, until
  * lbk_batch_autotune has timed both and keeps the faster.  Either way each
  * sample ends bitwise where single steps take it.  Drops recorded graphs
- * when the choice changes. */
+ * when the choice changes.  Batches have no three-step pass:
+ * LBK_PASS_THREE_STEP is rejected (LBK_ERR_INVALID_ARG). */
 lbk_status lbk_batch_set_pass_mode(lbk_batch *b, int32_t pass_mode);
 /* The pass mode set, and the steps per launch in use (1 or 2); either
  * pointer may be NULL. */

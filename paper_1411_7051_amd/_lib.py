@@ -25,7 +25,7 @@ STATUS = {
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 OBJECTIVE = {"k_app": 0, "q_out": 1}
 CORRELATION = {"bkc": 0, "klinkenberg": 1, "none": 2}
-PASS_MODE = {"auto": 0, "two_step": 1, "single": 2}
+PASS_MODE = {"auto": 0, "two_step": 1, "single": 2, "three_step": 3}
 
 
 class LbkError(RuntimeError):

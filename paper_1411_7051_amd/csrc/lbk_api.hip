@@ -106,8 +106,8 @@ lbk_status check_desc(const lbk_desc *d)
         return fail(LBK_ERR_INVALID_ARG, "correlation must be 0..2 (got %d)", d->correlation);
     if (!(d->slip_b <= 0.0) || !isfinite(d->slip_b))
         return fail(LBK_ERR_INVALID_ARG, "slip_b must be finite and <= 0 (got %g)", d->slip_b);
-    if (d->pass_mode < LBK_PASS_AUTO || d->pass_mode > LBK_PASS_SINGLE)
-        return fail(LBK_ERR_INVALID_ARG, "pass_mode must be 0..2 (got %d)", d->pass_mode);
+    if (d->pass_mode < LBK_PASS_AUTO || d->pass_mode > LBK_PASS_THREE_STEP)
+        return fail(LBK_ERR_INVALID_ARG, "pass_mode must be 0..3 (got %d)", d->pass_mode);
     if (d->band < 0 || d->band > 1024)
         return fail(LBK_ERR_INVALID_ARG, "band must be 0..1024 (got %d)", d->band);
     return LBK_OK;
@@ -122,13 +122,26 @@ void split(double v, float &hi, float &lo)
 
 } // namespace
 
-// n steps of the lattice on stream st: when the lattice takes two-step
-// passes, pairs of steps fused into one pass (launch_sweep2, bitwise two
-// single sweeps) and a single sweep if n is odd; otherwise n single sweeps.
+// n steps of the lattice on stream st: when the lattice takes three-step
+// passes, triples of steps fused into one pass (launch_sweep3x), the rest
+// in a two-step pass or a single sweep; when it takes two-step passes,
+// pairs of steps fused into one pass (launch_sweep2) and a single sweep if
+// n is odd; otherwise n single sweeps.  Every pass is bitwise the single
+// sweeps it replaces.
 lbk_status lbk::advance(lbk_lattice *lat, int64_t n, hipStream_t st)
 {
     const lbk_desc &d = lat->d;
-    for (int64_t i = 0; two_step_pass(lat) && i + 1 < n; i += 2) {
+    int64_t i = 0;
+    for (; three_step_pass(lat) && i + 2 < n; i += 3) {
+        const int nxt = lat->cur ^ 1;
+        HIP_TRY(launch_sweep3x(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur),
+                               lat->state(nxt), lat->L.lay, lat->med(), lat->L.mlay, lat->g,
+                               lat->ph, lat->s(), lat->inv_s(), fwd_band3(d), st));
+        lat->cur = nxt;
+        lat->t += 3;
+        ++lat->version;
+    }
+    for (; two_step_pass(lat) && i + 1 < n; i += 2) {
         const int nxt = lat->cur ^ 1;
         HIP_TRY(launch_sweep2(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->state(nxt),
                               lat->L.lay, lat->med(), lat->L.mlay, lat->g, lat->ph, lat->s(),
@@ -137,7 +150,7 @@ lbk_status lbk::advance(lbk_lattice *lat, int64_t n, hipStream_t st)
         lat->t += 2;
         ++lat->version;
     }
-    for (int64_t i = two_step_pass(lat) ? n - (n & 1) : 0; i < n; ++i) {
+    for (; i < n; ++i) {
         const int nxt = lat->cur ^ 1;
         HIP_TRY(launch_sweep(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur), lat->state(nxt),
                              lat->L.lay, lat->med(), lat->L.mlay, lat->g, lat->ph, lat->s(),
@@ -387,7 +400,7 @@ lbk_status lbk_steps_per_launch(const lbk_lattice *lat, int32_t *steps)
 {
     if (!lat || !steps)
         return fail(LBK_ERR_INVALID_ARG, "NULL argument");
-    *steps = two_step_pass(lat) ? 2 : 1;
+    *steps = three_step_pass(lat) ? 3 : (two_step_pass(lat) ? 2 : 1);
     return LBK_OK;
 }
 
@@ -801,8 +814,9 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
         return launch_sweep(d.storage, d.bc_x, d.bc_y, src, dst, lat->L.lay, lat->med(),
                             lat->L.mlay, lat->g, lat->ph, lat->s(), lat->inv_s(), hist, st);
     };
-    // two steps src -> dst in one pass, recording both when hist1 is given
-    const bool two = two_step_pass(lat);
+    // two steps src -> dst in one pass, recording both when hist1 is given;
+    // rebuilt inner checkpoints (no history) take lbk_step's passes
+    const bool two = two_step_pass(lat), three = three_step_pass(lat);
     auto sweep2 = [&](const char *src, char *dst, float *hist1, float *hist2) {
         return launch_sweep2(d.storage, d.bc_x, d.bc_y, src, dst, lat->L.lay, lat->med(),
                              lat->L.mlay, lat->g, lat->ph, lat->s(), lat->inv_s(),
@@ -845,7 +859,13 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
                     break; // the last inner segment needs no further state
                 for (int64_t i = 0; i < steps;) {
                     const char *from = i == 0 ? level(inner, nseg) : rec[r];
-                    if (two && i + 1 < steps) {
+                    if (three && i + 2 < steps) {
+                        HIP_TRY(launch_sweep3x(d.storage, d.bc_x, d.bc_y, from, rec[r ^ 1],
+                                               lat->L.lay, lat->med(), lat->L.mlay, lat->g,
+                                               lat->ph, lat->s(), lat->inv_s(), fwd_band3(d),
+                                               st));
+                        i += 3;
+                    } else if (two && i + 1 < steps) {
                         HIP_TRY(sweep2(from, rec[r ^ 1], nullptr, nullptr));
                         i += 2;
                     } else {

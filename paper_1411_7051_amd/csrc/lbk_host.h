@@ -119,6 +119,17 @@ namespace lbk {
 #define LBK_BAND2_HALF 10
 #endif
 inline int band2_of(int storage) { return storage == LBK_F32 ? LBK_BAND2 : LBK_BAND2_HALF; }
+// Rows per band of the three-step pass: FP32 ran at 117.7 / 119.6 / 122.5 /
+// 121.7 / 117.3 GLUPS with bands of 8 / 10 / 12 / 16 / 24 rows on the
+// 4096 x 4096 disc medium; FP16 at 119.5 / 125.1 / 126.9 / 127.4 with 8 /
+// 12 / 20 / 24 (BF16 alike).
+#ifndef LBK_BAND3
+#define LBK_BAND3 12
+#endif
+#ifndef LBK_BAND3_HALF
+#define LBK_BAND3_HALF 24
+#endif
+inline int band3_of(int storage) { return storage == LBK_F32 ? LBK_BAND3 : LBK_BAND3_HALF; }
 // Rows per band of the two-step reverse pass.
 #ifndef LBK_BANDA
 #define LBK_BANDA 16
@@ -133,9 +144,9 @@ constexpr int64_t kMinWaves2 = 8192;
 // to 2) while the pass would have fewer than kMinWaves2 waves.  On a
 // 2048 x 1024 lattice bands of 4 or 2 rows ran at 85-86 GLUPS against 78
 // with 8 (and 64 with single sweeps).
-inline int band_for(int nx, int ny, int band)
+inline int band_for(int nx, int ny, int band, int strip = kStrip2)
 {
-    const int64_t strips = (nx + kStrip2 - 1) / kStrip2;
+    const int64_t strips = (nx + strip - 1) / strip;
     while (band > 2 && strips * ((ny + band - 1) / band) < kMinWaves2)
         band = (band + 1) / 2;
     return band;
@@ -148,6 +159,10 @@ inline int fwd_band(const lbk_desc &d)
     return d.band > 0 ? d.band : band_for(d.nx, d.ny, band2_of(d.storage));
 }
 inline int rev_band(const lbk_desc &d) { return d.band > 0 ? d.band : band_for(d.nx, d.ny, kBandA); }
+inline int fwd_band3(const lbk_desc &d)
+{
+    return d.band > 0 ? d.band : band_for(d.nx, d.ny, band3_of(d.storage), kStrip3);
+}
 
 // Lattices from this many nodes on take two-step passes under
 // LBK_PASS_AUTO.  Below it too few waves run to hide the march's latency,
@@ -172,8 +187,28 @@ constexpr int64_t kTwoStepBatchNodes = (int64_t)1 << 22;
 inline bool two_step_pass(const lbk_lattice *lat)
 {
     const lbk_desc &d = lat->d;
-    return d.pass_mode == LBK_PASS_TWO_STEP ||
+    return d.pass_mode == LBK_PASS_TWO_STEP || d.pass_mode == LBK_PASS_THREE_STEP ||
            (d.pass_mode == LBK_PASS_AUTO && (int64_t)d.nx * d.ny >= two_step_nodes(d.storage));
+}
+
+// Lattices from this many nodes on take three-step passes under
+// LBK_PASS_AUTO.  FP32, against two-step passes: 110.6 against 88.0 GLUPS on
+// 4096 x 2048, 94.1 against 80.5 on 2048 x 2048, but 79.9 against 90.2 on
+// 2048 x 1024.  FP16 gains only where bands of 24 rows still leave the
+// device enough waves: 127.4 against 123.0 GLUPS on 4096 x 4096, while on
+// 4096 x 2048 (shorter bands) 112.2 against 115.5.
+inline int64_t three_step_nodes(int storage)
+{
+    return storage == LBK_F32 ? (int64_t)1 << 22 : (int64_t)1 << 24;
+}
+
+// Whether lbk_step advances this lattice three steps per launch (the
+// gradients' recording and reverse passes still take two).
+inline bool three_step_pass(const lbk_lattice *lat)
+{
+    const lbk_desc &d = lat->d;
+    return d.pass_mode == LBK_PASS_THREE_STEP ||
+           (d.pass_mode == LBK_PASS_AUTO && (int64_t)d.nx * d.ny >= three_step_nodes(d.storage));
 }
 
 // n >= 0 steps of the lattice on stream st (pairs through the two-step

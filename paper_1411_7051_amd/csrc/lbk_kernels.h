@@ -21,6 +21,8 @@ Launch launch_of(const Geom &g);
 // Columns a wave of the two-step pass stores (its strip; the wave's other
 // four lanes hold halo columns).
 constexpr int kStrip2 = 60;
+// Columns a wave of the three-step pass stores (six halo lanes).
+constexpr int kStrip3 = 58;
 
 // Largest batch tile width (workgroup size) of the batched sweep.
 constexpr int kBatchMaxTile = 256;
@@ -76,6 +78,14 @@ hipError_t launch_sweep2(int storage, int bcx, int bcy, const char *src, char *d
                          const Layout &lay, const char *med, const MLayout &mlay, const Geom &g,
                          const Physics &ph, float s, float inv_s, int band, float *hist1,
                          float *hist2, hipStream_t st);
+
+// Three steps src -> dst in one pass (bitwise the result of three
+// launch_sweep calls), the old level and two intermediate levels held in
+// registers: waves own strips of 58 columns and march along bands of
+// `band` >= 1 rows.  src and dst must be different levels.
+hipError_t launch_sweep3x(int storage, int bcx, int bcy, const char *src, char *dst,
+                          const Layout &lay, const char *med, const MLayout &mlay, const Geom &g,
+                          const Physics &ph, float s, float inv_s, int band, hipStream_t st);
 
 // Macroscopic read-out ([ny][nx] outputs, any may be null) and FP64 partials
 // [MAC_SLOTS][blocks].  If u_prev ([ny][pitch]) is given it is read for the

@@ -217,12 +217,15 @@ struct Mid {
     float eps, drag, kn0;
 };
 
-// Node (x, y) of a stored level and its medium.
+// Node (x, y) of a stored level and its medium.  A row the march loads
+// ahead but will not use (live = false, uniform) gets empty buffer
+// resources: its loads return 0 without touching memory.
 template <typename T>
 __device__ __forceinline__ void load_node(const char *src, const Layout &lay, const char *med,
-                                          const MLayout &mlay, int y, uint32_t x, Mid &m)
+                                          const MLayout &mlay, int y, uint32_t x, Mid &m,
+                                          bool live = true)
 {
-    const Rsrc row = make_rsrc(src + (uint64_t)y * lay.row, (uint32_t)lay.row);
+    const Rsrc row = make_rsrc(src + (uint64_t)y * lay.row, live ? (uint32_t)lay.row : 0u);
     // default cache policy: a strip's 64-column loads share their first and
     // last cache lines with the neighbouring strips, which read them about
     // the same time (nontemporal loads fetched those lines twice)
@@ -231,7 +234,7 @@ __device__ __forceinline__ void load_node(const char *src, const Layout &lay, co
 #pragma unroll
     for (int i = 0; i < 9; ++i)
         m.h[i] = Elem<T>::template ld<0>(row, x * es, lay.h_off + i * lay.h_slot);
-    const Rsrc mr = med_row(med, mlay, y);
+    const Rsrc mr = make_rsrc(med + (uint64_t)y * mlay.row, live ? (uint32_t)mlay.row : 0u);
     m.eps = ld_f32(mr, x * 4, 0);
     m.drag = ld_f32(mr, x * 4, mlay.slot);
     m.kn0 = ld_f32(mr, x * 4, 2 * mlay.slot);
@@ -437,14 +440,15 @@ __device__ __forceinline__ void sweep2_strip_dir(const char *__restrict__ src,
     first(a4, a5, a1, -1, false, m0);
     first(a5, a1, a2, 0, owned, m1);
     load_node<T>(src, lay, med, mlay, held(Y(2)), ln.x, a3);
-    load_node<T>(src, lay, med, mlay, held(Y(3)), ln.x, a4);
+    load_node<T>(src, lay, med, mlay, held(Y(3)), ln.x, a4, nb >= 2);
     // One output row: u0..u2 are the old rows at positions m .. m + 2, nx
     // receives position m + 4.  The loop below calls it with the five
     // old-row registers in rotated roles, so no loaded value is ever copied
     // (a copy would make the wave wait for its load -- and for the stores
     // issued after it -- at that point rather than at the value's first use).
     auto row = [&](int m, const Mid &u0, const Mid &u1, const Mid &u2, Mid &nx) {
-        load_node<T>(src, lay, med, mlay, held(Y(m + 4)), ln.x, nx);
+        // the last output row needs old rows up to position nb + 1
+        load_node<T>(src, lay, med, mlay, held(Y(m + 4)), ln.x, nx, m + 4 <= nb + 1);
         first(u0, u1, u2, m + 1, owned && m + 1 < nb, m2);
         const int y = Y(m);
         float hs[9], jx, jy;
@@ -514,6 +518,160 @@ __global__ __launch_bounds__(kBlock) void sweep2_kernel(const char *__restrict__
     const int strip = (L - bnd * groups) * (kBlock / 64) + (int)(threadIdx.x >> 6);
     sweep2_strip<T, BCX, BCY, HIST>(src, dst, lay, med, mlay, g, ph, s, inv_s, band, bnd, strip,
                                     hist1, hist2);
+}
+
+// sweep3x_kernel advances the lattice by three time steps in one pass: the
+// two-step pass with a second intermediate level.  A wave's 64 lanes hold a
+// strip of kStrip3 columns and three halo columns on either side; the first
+// intermediate level is complete on lanes 1..62, the second on 2..61 and
+// the result on 3..60, which the strip owns.  Per output row y the wave
+// keeps the old rows y + 1 .. y + 3 (y + 4 and y + 5 in flight), the first
+// intermediate rows y .. y + 2 and the second y - 1 .. y + 1.  Every
+// intermediate level is rounded as a store would round it, so the pass is
+// bitwise three single sweeps.  It records no history (the gradients'
+// recording passes take two steps).
+template <typename T, int BCX, int BCY, int DIR>
+__device__ __forceinline__ void sweep3x_strip_dir(const char *__restrict__ src,
+                                                  char *__restrict__ dst, const Layout &lay,
+                                                  const char *__restrict__ med,
+                                                  const MLayout &mlay, const Geom &g,
+                                                  const Physics &ph, float s, float inv_s,
+                                                  int band, int bnd, int strip)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const int nstrips = (g.nx + kStrip3 - 1) / kStrip3;
+    if (strip >= nstrips)
+        return; // the whole wave
+    // lane l holds column strip * kStrip3 - 3 + l: lanes 3..kStrip3+2 the
+    // strip's own columns, three halo columns on either side
+    const int xr = strip * kStrip3 - 3 + lane;
+    Lanes ln;
+    if (BCX == BC_PERIODIC)
+        ln.x = (uint32_t)(((xr % g.nx) + g.nx) % g.nx);
+    else
+        ln.x = (uint32_t)(xr < 0 ? 0 : (xr >= g.nx ? g.nx - 1 : xr)); // beyond: unused copies
+    // A pressure column takes its neighbour's pull, which the third step
+    // completes on lanes 3..kStrip3+2 only: an outlet column at lane 3 is
+    // left to the previous strip, where it sits at lane kStrip3 + 3.
+    bool owned = lane >= 3 && lane <= kStrip3 + 2 && xr < g.nx;
+    if (BCX == BC_PRESSURE && xr == g.nx - 1)
+        owned = lane >= 4 && lane <= kStrip3 + 3;
+    ln.wxm = BCX == BC_WALL && ln.x == 0;
+    ln.wxp = BCX == BC_WALL && ln.x == (uint32_t)g.nx - 1;
+    ln.bin = BCX == BC_PRESSURE && xr == 0;
+    ln.bout = BCX == BC_PRESSURE && xr == g.nx - 1;
+    ln.has_b = BCX == BC_PRESSURE && (strip == 0 || strip >= nstrips - 2);
+    const int y0 = bnd * band, y1 = min(y0 + band, g.ny), nb = y1 - y0;
+    auto Y = [&](int m) { return DIR > 0 ? y0 + m : y1 - 1 - m; };
+    auto wrap = [&](int y) { return BCY == BC_PERIODIC ? ((y % g.ny) + g.ny) % g.ny : y; };
+    // rows beyond a wall: as in the two-step pass, computed from the
+    // nearest row and discarded by the bounce-back selects
+    auto held = [&](int y) {
+        return BCY == BC_PERIODIC ? wrap(y) : (y < 0 ? 0 : (y >= g.ny ? g.ny - 1 : y));
+    };
+    auto wall_lo = [&](int y) { return BCY == BC_WALL && y == 0; };
+    auto wall_hi = [&](int y) { return BCY == BC_WALL && y == g.ny - 1; };
+    const uint64_t om = __builtin_amdgcn_ballot_w64(owned);
+    if (om == 0)
+        return; // an outlet strip whose only column the previous strip stores
+    const int q = (int)__builtin_ctzll(om);
+    const uint32_t xq = (uint32_t)__builtin_amdgcn_readlane((int)ln.x, q);
+    const uint32_t xst = owned ? ln.x : xq;
+    auto same = [&](float v) {
+        const float vq = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), q));
+        return owned ? v : vq;
+    };
+    // One step of the row at march position m from the rows at m - 1, m,
+    // m + 1 of the level below (old or intermediate), rounded as stored.
+    auto step = [&](const Mid &p, const Mid &c, const Mid &n, int m, Mid &out) {
+        const int y = Y(m);
+        first_step<T, BCX, false>(ph, s, inv_s, g, DIR > 0 ? p : n, c, DIR > 0 ? n : p,
+                                  wall_lo(y), wall_hi(y), ln, wrap(y), nullptr, false, out);
+    };
+    auto load = [&](int m, Mid &out) {
+        // the last output row needs old rows up to position nb + 2
+        load_node<T>(src, lay, med, mlay, held(Y(m)), ln.x, out, m <= nb + 2);
+    };
+
+    // old rows a1..a5, first intermediate level p0..p2, second q0..q2
+    Mid a1, a2, a3, a4, a5, p0, p1, p2, q0, q1, q2;
+    load(-3, a1);
+    load(-2, a2);
+    load(-1, a3);
+    load(0, a4);
+    load(1, a5);
+    step(a1, a2, a3, -2, p0);
+    load(2, a1);
+    step(a2, a3, a4, -1, p1);
+    load(3, a2);
+    step(a3, a4, a5, 0, p2);
+    step(p0, p1, p2, -1, q0);
+    load(4, a3);
+    p0 = p1;
+    p1 = p2;
+    step(a4, a5, a1, 1, p2);
+    step(p0, p1, p2, 0, q1);
+    p0 = p1;
+    p1 = p2;
+    // One output row m: u1..u3 are the old rows at positions m + 1 .. m + 3,
+    // nx receives position m + 5; p0, p1 hold the first level's rows m,
+    // m + 1 and q0, q1 the second level's rows m - 1, m.
+    auto row = [&](int m, const Mid &u1, const Mid &u2, const Mid &u3, Mid &nx) {
+        load(m + 5, nx);
+        step(u1, u2, u3, m + 2, p2);
+        step(p0, p1, p2, m + 1, q2);
+        const int y = Y(m);
+        float hs[9], jx, jy;
+        const float rho = step_from<T, BCX>(ph, s, inv_s, DIR > 0 ? q0 : q2, q1,
+                                            DIR > 0 ? q2 : q0, wall_lo(y), wall_hi(y), ln, hs,
+                                            jx, jy);
+        const Rsrc out = make_rsrc(dst + (uint64_t)y * lay.row, (uint32_t)lay.row);
+        st_f32(out, xst * 4, 0, same(rho), false);
+        constexpr uint32_t es = sizeof(T);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            Elem<T>::template st<0>(out, xst * es, lay.h_off + i * lay.h_slot, same(hs[i]));
+        p0 = p1;
+        p1 = p2;
+        q0 = q1;
+        q1 = q2;
+    };
+    for (int m = 0; m < nb; m += 5) {
+        row(m, a5, a1, a2, a4);
+        if (m + 1 >= nb)
+            break;
+        row(m + 1, a1, a2, a3, a5);
+        if (m + 2 >= nb)
+            break;
+        row(m + 2, a2, a3, a4, a1);
+        if (m + 3 >= nb)
+            break;
+        row(m + 3, a3, a4, a5, a2);
+        if (m + 4 >= nb)
+            break;
+        row(m + 4, a4, a5, a1, a3);
+    }
+}
+
+template <typename T, int BCX, int BCY>
+__global__ __launch_bounds__(kBlock) void sweep3x_kernel(const char *__restrict__ src,
+                                                          char *__restrict__ dst, Layout lay,
+                                                          const char *__restrict__ med,
+                                                          MLayout mlay, Geom g, Physics ph,
+                                                          float s, float inv_s, int band,
+                                                          int groups)
+{
+    // logical block: band-major, four strips (one per wave) per block;
+    // neighbouring bands march in opposite directions
+    const int L = xcd_remap(blockIdx.x, gridDim.x);
+    const int bnd = L / groups;
+    const int strip = (L - bnd * groups) * (kBlock / 64) + (int)(threadIdx.x >> 6);
+    if (bnd & 1)
+        sweep3x_strip_dir<T, BCX, BCY, -1>(src, dst, lay, med, mlay, g, ph, s, inv_s, band, bnd,
+                                           strip);
+    else
+        sweep3x_strip_dir<T, BCX, BCY, 1>(src, dst, lay, med, mlay, g, ph, s, inv_s, band, bnd,
+                                          strip);
 }
 
 // -------------------------------------------------------------- batches
@@ -1013,6 +1171,23 @@ static hipError_t sweep2_t(const char *src, char *dst, const Layout &lay, const 
 }
 
 template <typename T, int BCX, int BCY>
+static hipError_t sweep3x_t(const char *src, char *dst, const Layout &lay, const char *med,
+                            const MLayout &mlay, const Geom &g, const Physics &ph, float s,
+                            float inv_s, int band, hipStream_t st)
+{
+    if (band < 1)
+        return hipErrorInvalidValue;
+    const int nstrips = (g.nx + kStrip3 - 1) / kStrip3;
+    const int groups = (nstrips + kBlock / 64 - 1) / (kBlock / 64);
+    const int64_t blocks = (int64_t)groups * ((g.ny + band - 1) / band);
+    if (blocks > 0x7fffffff)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL((sweep3x_kernel<T, BCX, BCY>), dim3((unsigned)blocks), dim3(kBlock), 0,
+                       st, src, dst, lay, med, mlay, g, ph, s, inv_s, band, groups);
+    return hipGetLastError();
+}
+
+template <typename T, int BCX, int BCY>
 static hipError_t macro_t(const char *src, const Layout &lay, const char *med,
                           const MLayout &mlay, const Geom &g, const Physics &ph, float s,
                           float inv_s,
@@ -1097,6 +1272,15 @@ hipError_t launch_sweep2(int storage, int bcx, int bcy, const char *src, char *d
     if (bcy < 0 || bcy > 1)
         return hipErrorInvalidValue;
     LBK_DISPATCH(sweep2_t, src, dst, lay, med, mlay, g, ph, s, inv_s, band, hist1, hist2, st)
+}
+
+hipError_t launch_sweep3x(int storage, int bcx, int bcy, const char *src, char *dst,
+                          const Layout &lay, const char *med, const MLayout &mlay, const Geom &g,
+                          const Physics &ph, float s, float inv_s, int band, hipStream_t st)
+{
+    if (bcy < 0 || bcy > 1)
+        return hipErrorInvalidValue;
+    LBK_DISPATCH(sweep3x_t, src, dst, lay, med, mlay, g, ph, s, inv_s, band, st)
 }
 
 hipError_t launch_macro(int storage, int bcx, int bcy, const char *src, const Layout &lay,

@@ -121,8 +121,8 @@ class Lattice:
 
     @property
     def steps_per_launch(self) -> int:
-        """1 (single sweeps) or 2 (two-step passes), as pass_mode and the
-        lattice's size and storage decide."""
+        """1 (single sweeps), 2 or 3 (two- or three-step passes), as
+        pass_mode and the lattice's size and storage decide."""
         n = ctypes.c_int32()
         check(_lib.load().lbk_steps_per_launch(self._handle(), ctypes.byref(n)))
         return int(n.value)

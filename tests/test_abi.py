@@ -58,7 +58,7 @@ def test_workspace_size_scales_with_lattice():
     (dict(f_eps=-1.0), "f_eps"),
     (dict(correlation=3), "correlation"),
     (dict(slip_b=0.5), "slip_b"),
-    (dict(pass_mode=3), "pass_mode"),
+    (dict(pass_mode=4), "pass_mode"),
     (dict(pass_mode=-1), "pass_mode"),
     (dict(band=-1), "band"),
     (dict(band=1025), "band"),
