@@ -136,7 +136,8 @@ lbk_status lbk::advance(lbk_lattice *lat, int64_t n, hipStream_t st)
         const int nxt = lat->cur ^ 1;
         HIP_TRY(launch_sweep3x(d.storage, d.bc_x, d.bc_y, lat->state(lat->cur),
                                lat->state(nxt), lat->L.lay, lat->med(), lat->L.mlay, lat->g,
-                               lat->ph, lat->s(), lat->inv_s(), fwd_band3(d), st));
+                               lat->ph, lat->s(), lat->inv_s(), fwd_band3(d), nullptr,
+                               nullptr, nullptr, st));
         lat->cur = nxt;
         lat->t += 3;
         ++lat->version;
@@ -815,12 +816,20 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
                             lat->L.mlay, lat->g, lat->ph, lat->s(), lat->inv_s(), hist, st);
     };
     // two steps src -> dst in one pass, recording both when hist1 is given;
-    // rebuilt inner checkpoints (no history) take lbk_step's passes
+    // rebuilt inner checkpoints (no history) and recorded segments take
+    // lbk_step's passes (the reverse steps pairs)
     const bool two = two_step_pass(lat), three = three_step_pass(lat);
     auto sweep2 = [&](const char *src, char *dst, float *hist1, float *hist2) {
         return launch_sweep2(d.storage, d.bc_x, d.bc_y, src, dst, lat->L.lay, lat->med(),
                              lat->L.mlay, lat->g, lat->ph, lat->s(), lat->inv_s(),
                              fwd_band(d), hist1, hist2, st);
+    };
+    // three steps src -> dst in one pass, recording all three when hist1
+    // is given
+    auto sweep3 = [&](const char *src, char *dst, float *hist1, float *hist2, float *hist3) {
+        return launch_sweep3x(d.storage, d.bc_x, d.bc_y, src, dst, lat->L.lay, lat->med(),
+                              lat->L.mlay, lat->g, lat->ph, lat->s(), lat->inv_s(),
+                              fwd_band3(d), hist1, hist2, hist3, st);
     };
     const float a1 = (float)P.a1, a2 = (float)P.a2;
 
@@ -860,10 +869,7 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
                 for (int64_t i = 0; i < steps;) {
                     const char *from = i == 0 ? level(inner, nseg) : rec[r];
                     if (three && i + 2 < steps) {
-                        HIP_TRY(launch_sweep3x(d.storage, d.bc_x, d.bc_y, from, rec[r ^ 1],
-                                               lat->L.lay, lat->med(), lat->L.mlay, lat->g,
-                                               lat->ph, lat->s(), lat->inv_s(), fwd_band3(d),
-                                               st));
+                        HIP_TRY(sweep3(from, rec[r ^ 1], nullptr, nullptr, nullptr));
                         i += 3;
                     } else if (two && i + 1 < steps) {
                         HIP_TRY(sweep2(from, rec[r ^ 1], nullptr, nullptr));
@@ -888,7 +894,11 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
                 Range range("adjoint recompute");
                 for (int64_t t = a2s; t < b2s;) {
                     const char *from = t == a2s ? src : rec[r];
-                    if (two && t + 1 < b2s) {
+                    if (three && t + 2 < b2s) {
+                        HIP_TRY(sweep3(from, rec[r ^ 1], histp(t - a2s + 1), histp(t - a2s + 2),
+                                       histp(t - a2s + 3)));
+                        t += 3;
+                    } else if (two && t + 1 < b2s) {
                         HIP_TRY(sweep2(from, rec[r ^ 1], histp(t - a2s + 1), histp(t - a2s + 2)));
                         t += 2;
                     } else {

@@ -82,10 +82,13 @@ hipError_t launch_sweep2(int storage, int bcx, int bcy, const char *src, char *d
 // Three steps src -> dst in one pass (bitwise the result of three
 // launch_sweep calls), the old level and two intermediate levels held in
 // registers: waves own strips of 58 columns and march along bands of
-// `band` >= 1 rows.  src and dst must be different levels.
+// `band` >= 1 rows.  src and dst must be different levels.  With hist1..3
+// (all or none) the three steps' linearisation points are recorded as
+// launch_sweep records one.
 hipError_t launch_sweep3x(int storage, int bcx, int bcy, const char *src, char *dst,
                           const Layout &lay, const char *med, const MLayout &mlay, const Geom &g,
-                          const Physics &ph, float s, float inv_s, int band, hipStream_t st);
+                          const Physics &ph, float s, float inv_s, int band, float *hist1,
+                          float *hist2, float *hist3, hipStream_t st);
 
 // Macroscopic read-out ([ny][nx] outputs, any may be null) and FP64 partials
 // [MAC_SLOTS][blocks].  If u_prev ([ny][pitch]) is given it is read for the

@@ -528,15 +528,18 @@ __global__ __launch_bounds__(kBlock) void sweep2_kernel(const char *__restrict__
 // keeps the old rows y + 1 .. y + 3 (y + 4 and y + 5 in flight), the first
 // intermediate rows y .. y + 2 and the second y - 1 .. y + 1.  Every
 // intermediate level is rounded as a store would round it, so the pass is
-// bitwise three single sweeps.  It records no history (the gradients'
-// recording passes take two steps).
-template <typename T, int BCX, int BCY, int DIR>
+// bitwise three single sweeps.  With HIST it records the three steps'
+// linearisation points for the adjoint, each row by the band that owns it.
+template <typename T, int BCX, int BCY, bool HIST, int DIR>
 __device__ __forceinline__ void sweep3x_strip_dir(const char *__restrict__ src,
                                                   char *__restrict__ dst, const Layout &lay,
                                                   const char *__restrict__ med,
                                                   const MLayout &mlay, const Geom &g,
                                                   const Physics &ph, float s, float inv_s,
-                                                  int band, int bnd, int strip)
+                                                  int band, int bnd, int strip,
+                                                  float *__restrict__ hist1,
+                                                  float *__restrict__ hist2,
+                                                  float *__restrict__ hist3)
 {
     const int lane = (int)(threadIdx.x & 63);
     const int nstrips = (g.nx + kStrip3 - 1) / kStrip3;
@@ -582,11 +585,13 @@ __device__ __forceinline__ void sweep3x_strip_dir(const char *__restrict__ src,
         return owned ? v : vq;
     };
     // One step of the row at march position m from the rows at m - 1, m,
-    // m + 1 of the level below (old or intermediate), rounded as stored.
-    auto step = [&](const Mid &p, const Mid &c, const Mid &n, int m, Mid &out) {
+    // m + 1 of the level below (old or intermediate), rounded as stored;
+    // recorded into hist where rec (a row of this band, an owned lane).
+    auto step = [&](const Mid &p, const Mid &c, const Mid &n, int m, float *hist, bool rec,
+                    Mid &out) {
         const int y = Y(m);
-        first_step<T, BCX, false>(ph, s, inv_s, g, DIR > 0 ? p : n, c, DIR > 0 ? n : p,
-                                  wall_lo(y), wall_hi(y), ln, wrap(y), nullptr, false, out);
+        first_step<T, BCX, HIST>(ph, s, inv_s, g, DIR > 0 ? p : n, c, DIR > 0 ? n : p,
+                                 wall_lo(y), wall_hi(y), ln, wrap(y), hist, rec, out);
     };
     auto load = [&](int m, Mid &out) {
         // the last output row needs old rows up to position nb + 2
@@ -600,17 +605,17 @@ __device__ __forceinline__ void sweep3x_strip_dir(const char *__restrict__ src,
     load(-1, a3);
     load(0, a4);
     load(1, a5);
-    step(a1, a2, a3, -2, p0);
+    step(a1, a2, a3, -2, hist1, false, p0);
     load(2, a1);
-    step(a2, a3, a4, -1, p1);
+    step(a2, a3, a4, -1, hist1, false, p1);
     load(3, a2);
-    step(a3, a4, a5, 0, p2);
-    step(p0, p1, p2, -1, q0);
+    step(a3, a4, a5, 0, hist1, owned, p2);
+    step(p0, p1, p2, -1, hist2, false, q0);
     load(4, a3);
     p0 = p1;
     p1 = p2;
-    step(a4, a5, a1, 1, p2);
-    step(p0, p1, p2, 0, q1);
+    step(a4, a5, a1, 1, hist1, owned && 1 < nb, p2);
+    step(p0, p1, p2, 0, hist2, owned, q1);
     p0 = p1;
     p1 = p2;
     // One output row m: u1..u3 are the old rows at positions m + 1 .. m + 3,
@@ -618,13 +623,15 @@ __device__ __forceinline__ void sweep3x_strip_dir(const char *__restrict__ src,
     // m + 1 and q0, q1 the second level's rows m - 1, m.
     auto row = [&](int m, const Mid &u1, const Mid &u2, const Mid &u3, Mid &nx) {
         load(m + 5, nx);
-        step(u1, u2, u3, m + 2, p2);
-        step(p0, p1, p2, m + 1, q2);
+        step(u1, u2, u3, m + 2, hist1, owned && m + 2 < nb, p2);
+        step(p0, p1, p2, m + 1, hist2, owned && m + 1 < nb, q2);
         const int y = Y(m);
         float hs[9], jx, jy;
         const float rho = step_from<T, BCX>(ph, s, inv_s, DIR > 0 ? q0 : q2, q1,
                                             DIR > 0 ? q2 : q0, wall_lo(y), wall_hi(y), ln, hs,
                                             jx, jy);
+        if (HIST && owned)
+            record(hist3, g, y, ln.x, rho, jx, jy, false);
         const Rsrc out = make_rsrc(dst + (uint64_t)y * lay.row, (uint32_t)lay.row);
         st_f32(out, xst * 4, 0, same(rho), false);
         constexpr uint32_t es = sizeof(T);
@@ -653,13 +660,15 @@ __device__ __forceinline__ void sweep3x_strip_dir(const char *__restrict__ src,
     }
 }
 
-template <typename T, int BCX, int BCY>
+template <typename T, int BCX, int BCY, bool HIST>
 __global__ __launch_bounds__(kBlock) void sweep3x_kernel(const char *__restrict__ src,
                                                           char *__restrict__ dst, Layout lay,
                                                           const char *__restrict__ med,
                                                           MLayout mlay, Geom g, Physics ph,
                                                           float s, float inv_s, int band,
-                                                          int groups)
+                                                          int groups, float *__restrict__ hist1,
+                                                          float *__restrict__ hist2,
+                                                          float *__restrict__ hist3)
 {
     // logical block: band-major, four strips (one per wave) per block;
     // neighbouring bands march in opposite directions
@@ -667,11 +676,11 @@ __global__ __launch_bounds__(kBlock) void sweep3x_kernel(const char *__restrict_
     const int bnd = L / groups;
     const int strip = (L - bnd * groups) * (kBlock / 64) + (int)(threadIdx.x >> 6);
     if (bnd & 1)
-        sweep3x_strip_dir<T, BCX, BCY, -1>(src, dst, lay, med, mlay, g, ph, s, inv_s, band, bnd,
-                                           strip);
+        sweep3x_strip_dir<T, BCX, BCY, HIST, -1>(src, dst, lay, med, mlay, g, ph, s, inv_s, band,
+                                                 bnd, strip, hist1, hist2, hist3);
     else
-        sweep3x_strip_dir<T, BCX, BCY, 1>(src, dst, lay, med, mlay, g, ph, s, inv_s, band, bnd,
-                                          strip);
+        sweep3x_strip_dir<T, BCX, BCY, HIST, 1>(src, dst, lay, med, mlay, g, ph, s, inv_s, band,
+                                                bnd, strip, hist1, hist2, hist3);
 }
 
 // -------------------------------------------------------------- batches
@@ -1173,17 +1182,25 @@ static hipError_t sweep2_t(const char *src, char *dst, const Layout &lay, const 
 template <typename T, int BCX, int BCY>
 static hipError_t sweep3x_t(const char *src, char *dst, const Layout &lay, const char *med,
                             const MLayout &mlay, const Geom &g, const Physics &ph, float s,
-                            float inv_s, int band, hipStream_t st)
+                            float inv_s, int band, float *hist1, float *hist2, float *hist3,
+                            hipStream_t st)
 {
-    if (band < 1)
+    const bool hist = hist1 != nullptr;
+    if (band < 1 || (hist2 != nullptr) != hist || (hist3 != nullptr) != hist)
         return hipErrorInvalidValue;
     const int nstrips = (g.nx + kStrip3 - 1) / kStrip3;
     const int groups = (nstrips + kBlock / 64 - 1) / (kBlock / 64);
     const int64_t blocks = (int64_t)groups * ((g.ny + band - 1) / band);
     if (blocks > 0x7fffffff)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((sweep3x_kernel<T, BCX, BCY>), dim3((unsigned)blocks), dim3(kBlock), 0,
-                       st, src, dst, lay, med, mlay, g, ph, s, inv_s, band, groups);
+    if (hist)
+        hipLaunchKernelGGL((sweep3x_kernel<T, BCX, BCY, true>), dim3((unsigned)blocks),
+                           dim3(kBlock), 0, st, src, dst, lay, med, mlay, g, ph, s, inv_s, band,
+                           groups, hist1, hist2, hist3);
+    else
+        hipLaunchKernelGGL((sweep3x_kernel<T, BCX, BCY, false>), dim3((unsigned)blocks),
+                           dim3(kBlock), 0, st, src, dst, lay, med, mlay, g, ph, s, inv_s, band,
+                           groups, hist1, hist2, hist3);
     return hipGetLastError();
 }
 
@@ -1276,11 +1293,13 @@ hipError_t launch_sweep2(int storage, int bcx, int bcy, const char *src, char *d
 
 hipError_t launch_sweep3x(int storage, int bcx, int bcy, const char *src, char *dst,
                           const Layout &lay, const char *med, const MLayout &mlay, const Geom &g,
-                          const Physics &ph, float s, float inv_s, int band, hipStream_t st)
+                          const Physics &ph, float s, float inv_s, int band, float *hist1,
+                          float *hist2, float *hist3, hipStream_t st)
 {
     if (bcy < 0 || bcy > 1)
         return hipErrorInvalidValue;
-    LBK_DISPATCH(sweep3x_t, src, dst, lay, med, mlay, g, ph, s, inv_s, band, st)
+    LBK_DISPATCH(sweep3x_t, src, dst, lay, med, mlay, g, ph, s, inv_s, band, hist1, hist2, hist3,
+                 st)
 }
 
 hipError_t launch_macro(int storage, int bcx, int bcy, const char *src, const Layout &lay,

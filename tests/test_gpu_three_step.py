@@ -142,3 +142,31 @@ def test_auto_mode_three_step_thresholds(dev):
             states.append(lat.save_state())
             lat.close()
         assert torch.equal(states[0], states[1]), (nx, ny, storage)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("bcx,bcy", [(0, 0), (1, 1), (2, 0), (2, 1)])
+def test_three_step_recording_bitwise(dev, storage, bcx, bcy):
+    """The recording passes of a three-step lattice take three steps and
+    record all three: J and both gradient planes equal the single-sweep
+    ones bitwise, for inner segments of every length modulo 3, both
+    objectives and bands that do and do not divide the lattice."""
+    drive = (dict(rho_in=1.02, rho_out=1.0, init=1) if bcx == inputs.PRESSURE
+             else dict(gx=1e-5, gy=-3e-6))
+    case = inputs.random_medium(121, 37, seed=97 + bcx, solid_frac=0.05, pore_frac=0.05,
+                                kn_range=(0.0, 2.0), bc_x=bcx, bc_y=bcy, **drive)
+    for steps, ckpt, hist, objective, band in ((29, 13, 6, "k_app", 0), (31, 16, 7, "q_out", 5),
+                                               (30, 15, 8, "k_app", 12)):
+        if objective == "q_out" and bcx != inputs.PRESSURE:
+            objective = "k_app"
+        out = []
+        for mode in ("single", "three_step"):
+            lat = Lattice(case.eps, case.k, case.kn0, device=dev, storage=storage,
+                          pass_mode=mode, band=band if mode == "three_step" else 0,
+                          **case.params)
+            out.append(lat.gradient(steps, objective, ckpt_every=ckpt, hist_len=hist,
+                                    wrt_kn0=True))
+            lat.close()
+        assert out[0][0] == out[1][0], (steps, ckpt, hist)
+        assert torch.equal(out[0][1], out[1][1]) and torch.equal(out[0][2], out[1][2]), \
+            (steps, ckpt, hist, objective, band)
