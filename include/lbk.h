@@ -79,7 +79,8 @@ typedef enum lbk_pass_mode {
     LBK_PASS_SINGLE = 2,   /* single sweeps */
     LBK_PASS_THREE_STEP = 3 /* lbk_step: three-step passes whatever the size (a
                                remainder of n in a two-step pass or a single
-                               sweep); gradients: two-step passes */
+                               sweep); gradients record in three-step passes
+                               and reverse in two-step passes */
 } lbk_pass_mode;
 
 /* Run description (Sec. IV: plates, heterogeneous media, fractured shale). */
@@ -154,9 +155,9 @@ lbk_status lbk_step(lbk_lattice *lat, int64_t n);
 lbk_status lbk_time(const lbk_lattice *lat, int64_t *t);
 
 /* Steps each launch of lbk_step advances, 1, 2 or 3, as the descriptor's
- * pass_mode and the lattice's size and storage decide (the reverse steps of
- * gradients follow the same choice, taking two where lbk_step takes
- * three). */
+ * pass_mode and the lattice's size and storage decide (a gradient's
+ * recording passes follow the same choice, its reverse steps take two where
+ * lbk_step takes three). */
 lbk_status lbk_steps_per_launch(const lbk_lattice *lat, int32_t *steps);
 
 /* Macroscopic read-out at the current time (Eqs. 16-17 on the post-stream

@@ -678,16 +678,22 @@ __device__ __forceinline__ void adjoint2_strip(
     // Loads keep the default cache policy: a strip's first and last cache
     // lines are shared with the neighbouring strips, which read them about
     // the same time.
-    auto med_row = [&](int yh) {
-        return make_rsrc(med + (uint64_t)yh * mlay.row, (uint32_t)mlay.row);
+    // The march loads ahead of its needs; rows past them (first parts
+    // beyond y1 + 1, second parts beyond y1: the last output row's) get
+    // empty buffer resources, so their loads return 0 without touching
+    // memory.
+    auto row_of = [&](const void *base, uint64_t bytes, int yh, bool live) {
+        return make_rsrc(static_cast<const char *>(base) + (uint64_t)yh * bytes,
+                         live ? (uint32_t)bytes : 0u);
     };
     auto load_a = [&](int y, RowA &r) {
         const int yh = held(y);
-        const Rsrc lr = rsrc_row(mu_in, lrow, yh);
+        const bool live = y <= y1 + 1;
+        const Rsrc lr = row_of(mu_in, lrow, yh, live);
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             r.mu[i] = ld_f32(lr, xo, i * slot);
-        const Rsrc hr = rsrc_row(hist1, hrow, yh), mr = med_row(yh);
+        const Rsrc hr = row_of(hist1, hrow, yh, live), mr = row_of(med, mlay.row, yh, live);
         ld_hist<0>(hr, ln.x * 12, r.h1);
 #pragma unroll
         for (int k = 0; k < 3; ++k)
@@ -695,7 +701,8 @@ __device__ __forceinline__ void adjoint2_strip(
     };
     auto load_b = [&](int y, RowB &r) {
         const int yh = held(y);
-        const Rsrc hr = rsrc_row(hist0, hrow, yh), mr = med_row(yh);
+        const bool live = y <= y1;
+        const Rsrc hr = row_of(hist0, hrow, yh, live), mr = row_of(med, mlay.row, yh, live);
         ld_hist<0>(hr, ln.x * 12, r.h0);
 #pragma unroll
         for (int k = 0; k < 3; ++k)

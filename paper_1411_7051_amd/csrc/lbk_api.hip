@@ -817,7 +817,7 @@ extern "C" lbk_status lbk_adjoint_backward(lbk_lattice *lat, void *ws, size_t ws
     };
     // two steps src -> dst in one pass, recording both when hist1 is given;
     // rebuilt inner checkpoints (no history) and recorded segments take
-    // lbk_step's passes (the reverse steps pairs)
+    // lbk_step's passes, the reverse steps pairs
     const bool two = two_step_pass(lat), three = three_step_pass(lat);
     auto sweep2 = [&](const char *src, char *dst, float *hist1, float *hist2) {
         return launch_sweep2(d.storage, d.bc_x, d.bc_y, src, dst, lat->L.lay, lat->med(),

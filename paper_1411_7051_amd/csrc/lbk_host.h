@@ -202,8 +202,8 @@ inline int64_t three_step_nodes(int storage)
     return storage == LBK_F32 ? (int64_t)1 << 22 : (int64_t)1 << 24;
 }
 
-// Whether lbk_step advances this lattice three steps per launch (the
-// gradients' recording and reverse passes still take two).
+// Whether lbk_step advances this lattice three steps per launch (so do its
+// gradients' rebuilding and recording passes; the reverse passes take two).
 inline bool three_step_pass(const lbk_lattice *lat)
 {
     const lbk_desc &d = lat->d;

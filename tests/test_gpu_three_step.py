@@ -5,7 +5,7 @@ three-step passes and the remainder as a two-step pass or a single sweep,
 so it must end bitwise where n single sweeps (LBK_PASS_SINGLE) leave the
 same lattice, for FP32, FP16 and BF16 storage.  Sizes around the 58-column
 strips, bands of 1 to 16 rows, every boundary combination; a gradient of
-such a lattice (whose recording passes take two steps) equals the
+such a lattice (recording three steps per pass, reversing two) equals the
 single-sweep one bitwise."""
 import numpy as np
 import pytest
@@ -110,8 +110,8 @@ def test_three_step_pass_discs_window(dev):
 
 
 def test_three_step_lattice_gradient_bitwise(dev):
-    """A gradient of a three-step lattice records and reverses in two-step
-    passes and recomputes with lbk_step's passes: it equals the single-sweep
+    """A gradient of a three-step lattice rebuilds and records in three-step
+    passes and reverses in two-step passes: it equals the single-sweep
     gradient bitwise."""
     case = inputs.random_medium(300, 40, seed=95, solid_frac=0.05, pore_frac=0.05,
                                 bc_x=2, bc_y=1, rho_in=1.02, rho_out=1.0, init=1)
