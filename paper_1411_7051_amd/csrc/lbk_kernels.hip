@@ -670,12 +670,15 @@ __global__ __launch_bounds__(kBlock) void sweep3x_kernel(const char *__restrict_
                                                           float *__restrict__ hist2,
                                                           float *__restrict__ hist3)
 {
-    // logical block: band-major, four strips (one per wave) per block;
-    // neighbouring bands march in opposite directions
+    // logical block: band-major, four strips (one per wave) per block.  At
+    // FP32 neighbouring bands march in opposite directions (122.5 against
+    // 117.0 GLUPS marching all one way, 4096 x 4096 discs, bands of 12); the
+    // 16-bit passes, bound by instruction issue, march all one way (133.7
+    // against 127.4 GLUPS, bands of 24), which halves their code.
     const int L = xcd_remap(blockIdx.x, gridDim.x);
     const int bnd = L / groups;
     const int strip = (L - bnd * groups) * (kBlock / 64) + (int)(threadIdx.x >> 6);
-    if (bnd & 1)
+    if (sizeof(T) == 4 && (bnd & 1))
         sweep3x_strip_dir<T, BCX, BCY, HIST, -1>(src, dst, lay, med, mlay, g, ph, s, inv_s, band,
                                                  bnd, strip, hist1, hist2, hist3);
     else
