@@ -170,3 +170,25 @@ def test_three_step_recording_bitwise(dev, storage, bcx, bcy):
         assert out[0][0] == out[1][0], (steps, ckpt, hist)
         assert torch.equal(out[0][1], out[1][1]) and torch.equal(out[0][2], out[1][2]), \
             (steps, ckpt, hist, objective, band)
+
+
+def test_batch_refuses_three_step_mode(dev):
+    """Batches have no three-step pass: the mode is refused and the batch
+    keeps stepping as before, bitwise its lattices' single sweeps."""
+    from paper_1411_7051_amd import _lib
+    from paper_1411_7051_amd.batch import Batch
+    case = _case(61, 31, 2, 0, 98)
+    lats = [Lattice(case.eps, case.k, case.kn0, device=dev, check_every=0, **case.params)
+            for _ in range(2)]
+    solo = Lattice(case.eps, case.k, case.kn0, device=dev, check_every=0, pass_mode="single",
+                   **case.params)
+    b = Batch(lats)
+    with pytest.raises(_lib.LbkError):
+        b.set_pass_mode("three_step")
+    b.step(4)
+    solo.step(4)
+    for lat in lats:
+        assert torch.equal(lat.save_state(), solo.save_state())
+    b.close()
+    for lat in lats + [solo]:
+        lat.close()
