@@ -68,6 +68,27 @@ def measured_traffic(storage, launch_ms, nodes):
         return None, None
 
 
+def measured_valu_issue(storage, launch_ms, nodes):
+    """Fraction of the device's vector-ALU issue rate that one launch of
+    the storage type's pass uses: its VALU instruction count from the
+    committed counter summary (SQ_INSTS_VALU per dispatch) over 256 compute
+    units x 2.4 GHz x this run's launch time (a compute unit issues at most
+    one wave64 VALU instruction per cycle).  None under the same
+    conditions as measured_traffic."""
+    try:
+        text = open(PROFILE).read()
+        blob = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+        cur = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read()
+                                      for f in blob["sources"])).hexdigest()[:16]
+        if cur != blob["source_hash"] or blob["nodes"] != nodes:
+            return None
+        return blob["per_dispatch"][storage]["valu_instr"] / (CUS * CLOCK_HZ * launch_ms * 1e-3)
+    except (OSError, KeyError, AttributeError, ValueError):
+        return None
+
+
+CUS, CLOCK_HZ = 256, 2.4e9  # MI355X compute units and peak engine clock
+
 REPS = 5  # timed repetitions of every GPU leg; median, min and max reported
 SPINUP_S = 0.25  # untimed steps before the timed repetitions of a sweep leg
 
@@ -714,6 +735,9 @@ def main():
         # pass's rate
         "single_step_equivalent_GBps": per_launch * achieved,
         "single_step_equivalent_frac": per_launch * achieved / HBM_PEAK_GBS,
+        # the roof that binds the multi-step pass: vector-ALU issue (counter
+        # summary's instruction count over this run's launch time)
+        "valu_issue_frac": measured_valu_issue(st, launch_ms, case.nodes),
         "copy_GBps": copy_bandwidth(dev),
     }
     log(f"plain streaming kernel (b = a * 1, 1 GiB f32): {roof['copy_GBps']:.0f} GB/s "

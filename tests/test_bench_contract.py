@@ -48,3 +48,18 @@ def test_traffic_comes_from_the_counter_summary():
 def test_traffic_dropped_for_another_lattice():
     blob = _profile_blob()
     assert bench.measured_traffic("f32", 0.25, blob["nodes"] + 1) == (None, None)
+
+
+def test_valu_issue_from_the_counter_summary():
+    """The vector-ALU issue fraction of a pass comes from the summary's
+    instruction count over the launch time: at the profiled trace average
+    it lies within the issue rate, and it is dropped for another lattice."""
+    blob = _profile_blob()
+    nodes = blob["nodes"]
+    for st in ("f32", "f16", "bf16"):
+        pd = blob["per_dispatch"][st]
+        frac = bench.measured_valu_issue(st, pd["avg_ns"] * 1e-6, nodes)
+        assert frac == pytest.approx(pd["valu_instr"] / (256 * 2.4e9 * pd["avg_ns"] * 1e-9),
+                                     rel=1e-12)
+        assert 0.0 < frac <= 1.0
+    assert bench.measured_valu_issue("f32", 0.25, nodes + 1) is None
