@@ -341,8 +341,8 @@ def time_adjoint(n, steps, ckpt, hist, device):
     case = inputs.shale(n=n, seed=3)
     log(f"shale inputs: {case.nodes} nodes in {time.perf_counter() - t:.1f} s")
     torch.cuda.reset_peak_memory_stats(device)
-    # the forward in the gradient's own pass structure (two-step passes, as
-    # the recording and reverse passes take), timed on 2000 steps and scaled
+    # the forward in two-step passes (the passes the gradient's reverse steps
+    # take), timed on 2000 steps and scaled
     lat2 = Lattice(case.eps, case.k, case.kn0, device=device, pass_mode="two_step",
                    **case.params)
     lat2.step(20)
@@ -398,7 +398,7 @@ def time_adjoint(n, steps, ckpt, hist, device):
         "grad_over_fwd": t_bwd / t_fwd,
         "total_over_fwd": (t_af + t_bwd) / t_fwd,
         # against a forward in two-step passes (the passes the gradient's
-        # recording and reverse steps take), from 2000 steps scaled
+        # reverse steps take), from 2000 steps scaled
         "t_fwd_two_step_ms": t_fwd2,
         "grad_over_fwd_two_step": t_bwd / t_fwd2,
         "total_over_fwd_two_step": (t_af + t_bwd) / t_fwd2,
