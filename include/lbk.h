@@ -72,7 +72,7 @@ typedef enum lbk_correlation {
  * or one step per sweep.  A multi-step pass reads and writes the state
  * once per pass; it pays off on lattices large enough to fill the device. */
 typedef enum lbk_pass_mode {
-    LBK_PASS_AUTO = 0,     /* three-step passes from 2^22 nodes (FP32), 2^24
+    LBK_PASS_AUTO = 0,     /* three-step passes from 2^22 nodes (FP32), 2^23
                               (FP16/BF16); two-step passes from 2^20 (FP32),
                               2^22 (FP16/BF16); single sweeps below */
     LBK_PASS_TWO_STEP = 1, /* two-step passes whatever the size */

@@ -192,14 +192,14 @@ inline bool two_step_pass(const lbk_lattice *lat)
 }
 
 // Lattices from this many nodes on take three-step passes under
-// LBK_PASS_AUTO.  FP32, against two-step passes: 110.6 against 88.0 GLUPS on
-// 4096 x 2048, 94.1 against 80.5 on 2048 x 2048, but 79.9 against 90.2 on
-// 2048 x 1024.  FP16 gains only where bands of 24 rows still leave the
-// device enough waves: 127.4 against 123.0 GLUPS on 4096 x 4096, while on
-// 4096 x 2048 (shorter bands) 112.2 against 115.5.
+// LBK_PASS_AUTO.  FP32, against two-step passes: 116.1 against 88.9 GLUPS on
+// 4096 x 2048, 95.6 against 82.0 on 2048 x 2048, but 81.3 against 93.6 on
+// 2048 x 1024.  FP16: 126.0 against 118.3 on 4096 x 2048, but 104.5 against
+// 110.7 on 2048 x 2048 (bands of 24 rows, shortened there to keep the
+// device filled).
 inline int64_t three_step_nodes(int storage)
 {
-    return storage == LBK_F32 ? (int64_t)1 << 22 : (int64_t)1 << 24;
+    return storage == LBK_F32 ? (int64_t)1 << 22 : (int64_t)1 << 23;
 }
 
 // Whether lbk_step advances this lattice three steps per launch (so do its
