@@ -192,3 +192,23 @@ def test_batch_refuses_three_step_mode(dev):
     b.close()
     for lat in lats + [solo]:
         lat.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_three_step_with_state_checks(dev, storage):
+    """State checks (and, at FP16, the scale re-centring) fall at multiples
+    of check_every in the lattice's time whatever the pass: a check interval
+    of 7 cuts every chunk into two three-step passes and a single sweep,
+    and the state still equals the single sweeps' bitwise."""
+    case = _case(300, 37, 2, 1, 99)
+    a = Lattice(case.eps, case.k, case.kn0, device=dev, storage=storage, check_every=7,
+                pass_mode="single", **case.params)
+    b = Lattice(case.eps, case.k, case.kn0, device=dev, storage=storage, check_every=7,
+                pass_mode="three_step", **case.params)
+    for n in (5, 13, 22):
+        a.step(n)
+        b.step(n)
+    assert a.time == b.time == 40
+    assert torch.equal(a.save_state(), b.save_state())
+    a.close()
+    b.close()
